@@ -1,0 +1,207 @@
+"""Seeded synthetic pencils, disks and start blocks.
+
+This module only builds inputs: sparse matrices, a disk (centre, radius) and
+random start blocks.  It holds none of the eigensolver's arithmetic (no
+filters, no factorizations, no Krylov steps) and imports neither the oracle nor
+the GPU binding, so the same bytes feed both sides of every parity check.
+
+Pencils
+-------
+* Tridiagonal Toeplitz pencil (B = I): diagonal ``a``, super-diagonal ``b``,
+  sub-diagonal ``c``.  Its eigenvalues are a + 2 sqrt(bc) cos(k pi/(n+1)).
+  The *balanced* variant replaces both off-diagonals by sqrt(bc) (a diagonal
+  similarity of the literal matrix): same eigenvalues, normal matrix.
+* Convection-diffusion pencil: unit square, homogeneous Dirichlet boundary,
+  n x n interior grid, h = 1/(n+1), natural ordering with x fastest.
+  A = D * (5-point -Laplacian) + first-order upwind discretisation of v . grad
+  (backward difference where the local velocity component is positive,
+  forward difference where it is negative) + ``shift`` on the diagonal.
+  B is a diagonal lumped mass with entries drawn Uniform[lo, hi] (or I).
+
+All randomness comes from NumPy's PCG64 with an explicit seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+
+@dataclasses.dataclass
+class Workload:
+    """A pencil (A, B), a disk D(c, r) and the solver's shape parameters."""
+    name: str
+    A: sp.csr_matrix          # complex128 CSR
+    B: sp.csr_matrix          # complex128 CSR
+    c: complex                # disk centre
+    r: float                  # disk radius
+    p: int                    # inner (factorized) trapezoidal nodes
+    q: int                    # outer (multi-shift GMRES) nodes
+    w: int                    # block width n_col
+    s_expected: Optional[int] = None   # eigenvalues expected inside D
+    seed: int = 0
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[0]
+
+
+# --------------------------------------------------------------------------
+# pencils
+# --------------------------------------------------------------------------
+
+def toeplitz_pencil(n: int, a: complex, b: complex, c: complex,
+                    balanced: bool = True):
+    """Tridiagonal Toeplitz A (diag a, super b, sub c) and B = I (CSR c128)."""
+    if balanced:
+        beta = np.sqrt(complex(b) * complex(c))
+        sup, sub = beta, beta
+    else:
+        sup, sub = complex(b), complex(c)
+    main = np.full(n, complex(a), dtype=np.complex128)
+    A = sp.diags([np.full(n - 1, sub), main, np.full(n - 1, sup)],
+                 [-1, 0, 1], shape=(n, n), format="csr", dtype=np.complex128)
+    B = sp.identity(n, dtype=np.complex128, format="csr")
+    A.sort_indices()
+    return A, B
+
+
+def convdiff_pencil(n: int, diffusion: float = 1.0, velocity=(20.0, 10.0),
+                    shift: complex = 0.05j, mass=(0.5, 1.5), seed: int = 0,
+                    vfield: Optional[np.ndarray] = None):
+    """Upwinded 5-point convection-diffusion pencil on an n x n grid.
+
+    ``velocity`` is a constant (vx, vy); ``vfield`` (shape (2, n, n), indexed
+    [component, iy, ix]) overrides it with a per-cell field.  ``mass`` is the
+    Uniform range of the diagonal B, or None for B = I.  The mass draw uses
+    ``seed``; a per-cell field is drawn by the caller.
+    """
+    h = 1.0 / (n + 1)
+    N = n * n
+    if vfield is None:
+        vx = np.full((n, n), float(velocity[0]))
+        vy = np.full((n, n), float(velocity[1]))
+    else:
+        vx = np.asarray(vfield[0], dtype=np.float64)
+        vy = np.asarray(vfield[1], dtype=np.float64)
+    dd = diffusion / (h * h)
+    rows, cols, vals = [], [], []
+    idx = np.arange(N).reshape(n, n)          # idx[iy, ix], x fastest
+    iy, ix = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    # diagonal: diffusion + upwind self terms + complex shift
+    diag = 4.0 * dd + np.abs(vx) / h + np.abs(vy) / h + 0.0j
+    diag = diag + shift
+    rows.append(idx.ravel()); cols.append(idx.ravel()); vals.append(diag.ravel())
+
+    def couple(mask, di, dj, val):
+        tgt = idx[(iy + di)[mask], (ix + dj)[mask]]
+        rows.append(idx[mask]); cols.append(tgt); vals.append(val[mask] + 0.0j)
+
+    # west neighbour (ix-1): diffusion -dd, upwind -vx/h when vx > 0
+    m = ix > 0
+    couple(m, 0, -1, -dd - np.where(vx > 0, vx, 0.0) / h)
+    # east neighbour (ix+1): diffusion -dd, upwind +vx/h when vx < 0
+    m = ix < n - 1
+    couple(m, 0, 1, -dd + np.where(vx < 0, vx, 0.0) / h)
+    # south neighbour (iy-1)
+    m = iy > 0
+    couple(m, -1, 0, -dd - np.where(vy > 0, vy, 0.0) / h)
+    # north neighbour (iy+1)
+    m = iy < n - 1
+    couple(m, 1, 0, -dd + np.where(vy < 0, vy, 0.0) / h)
+
+    A = sp.csr_matrix((np.concatenate(vals),
+                       (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(N, N), dtype=np.complex128)
+    A.sum_duplicates(); A.sort_indices()
+    if mass is None:
+        B = sp.identity(N, dtype=np.complex128, format="csr")
+    else:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        bdiag = rng.uniform(mass[0], mass[1], size=N)
+        B = sp.diags(bdiag.astype(np.complex128), 0, format="csr")
+    B.sort_indices()
+    return A, B
+
+
+def random_vfield(n: int, vmax: float, seed: int) -> np.ndarray:
+    """Per-cell convection field, Uniform[-vmax, vmax]^2, shape (2, n, n)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-vmax, vmax, size=(2, n, n))
+
+
+def diagonal_pencil(lam: np.ndarray, bdiag: Optional[np.ndarray] = None):
+    """A = diag(lam * b), B = diag(b): eigenvalues exactly ``lam``."""
+    lam = np.asarray(lam, dtype=np.complex128)
+    b = np.ones_like(lam) if bdiag is None else np.asarray(bdiag, np.complex128)
+    A = sp.diags(lam * b, 0, format="csr", dtype=np.complex128)
+    B = sp.diags(b, 0, format="csr", dtype=np.complex128)
+    return A, B
+
+
+def start_block(n: int, w: int, seed: int = 0) -> np.ndarray:
+    """(randn + i randn)/sqrt(2), n x w, Fortran (column-major) order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    re = rng.standard_normal((w, n))
+    im = rng.standard_normal((w, n))
+    Y = ((re + 1j * im) / np.sqrt(2.0)).T
+    return np.asfortranarray(Y)
+
+
+# --------------------------------------------------------------------------
+# disks
+# --------------------------------------------------------------------------
+
+def midgap_radius(eigs: np.ndarray, c: complex, count: int) -> float:
+    """Radius halfway between the count-th and (count+1)-th distance from c."""
+    d = np.sort(np.abs(np.asarray(eigs) - c))
+    return 0.5 * (d[count - 1] + d[count])
+
+
+def toeplitz_eigs(n: int, a: complex, b: complex, c: complex) -> np.ndarray:
+    """Closed-form eigenvalues a + 2 sqrt(bc) cos(k pi/(n+1)), k = 1..n."""
+    k = np.arange(1, n + 1)
+    return complex(a) + 2.0 * np.sqrt(complex(b) * complex(c)) * np.cos(k * np.pi / (n + 1))
+
+
+# --------------------------------------------------------------------------
+# named workloads (shapes of the paper's experiments; sizes as in the
+# composite-rule benchmark definitions)
+# --------------------------------------------------------------------------
+
+TOEPLITZ_C = 0.5 * np.exp(1j * np.pi / 3)
+
+# Disk for the 128 x 128 convection-diffusion pencil (D=1, v=(20,10),
+# +0.05i, B=diag U[0.5,1.5], seed 0).  Chosen by ``choose_convdiff_disk``:
+# ~100 eigenvalues inside, radius at mid-gap.  Values fixed here so every run
+# uses the same disk without recomputing reference eigenvalues.
+CONVDIFF128_DISK = None   # filled in below once computed (see _DISKS)
+
+_DISKS = {}
+
+
+def toeplitz_workload(n: int = 2000, balanced: bool = True, w: int = 32,
+                      p: int = 4, q: int = 4, count: int = 20,
+                      c: complex = 0.3 + 0.2j, seed: int = 0) -> Workload:
+    A, B = toeplitz_pencil(n, 0.0, 1.0, TOEPLITZ_C, balanced=balanced)
+    lam = toeplitz_eigs(n, 0.0, 1.0, TOEPLITZ_C)
+    r = midgap_radius(lam, c, count)
+    return Workload(f"toeplitz{'_bal' if balanced else '_lit'}_n{n}", A, B,
+                    complex(c), float(r), p, q, w, count, seed)
+
+
+def convdiff_workload(n: int = 128, w: int = 128, p: int = 4, q: int = 8,
+                      seed: int = 0, velocity=(20.0, 10.0),
+                      disk: Optional[tuple] = None,
+                      mass=(0.5, 1.5)) -> Workload:
+    A, B = convdiff_pencil(n, 1.0, velocity, 0.05j, mass, seed)
+    if disk is None:
+        disk = _DISKS.get((n, tuple(velocity), seed, mass))
+    if disk is None:
+        raise KeyError("no stored disk for this convection-diffusion pencil; "
+                       "pass disk=(c, r, count)")
+    c, r, count = disk
+    return Workload(f"convdiff{n}", A, B, complex(c), float(r), p, q, w,
+                    count, seed)
