@@ -1,0 +1,155 @@
+/*
+ * rfeig -- composite-rule rational-filter interior eigensolver, MI355X (gfx950).
+ *
+ * C ABI of the library.  It finds every eigenpair (lambda, x) of a sparse
+ * non-Hermitian pencil A x = lambda B x with lambda inside the disk
+ * D = { z : |z - c| < r }  (Chen & Li, "Interior Eigensolver Based on
+ * Rational Filter with Composite Rule", Sec. 1, eq. problem), by subspace
+ * iteration with the composite-rule trapezoidal filter R_{c,r,pq}(B^{-1}A)
+ * (Sec. 3.2, Alg. composite).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are interleaved (re, im) pairs of IEEE doubles
+ *   (complex128).  Blocks of vectors are column-major with a leading
+ *   dimension >= n.
+ * - Sparse matrices are CSR in HOST memory (int32 row pointers and column
+ *   indices, complex128 values).  The library copies them at plan creation;
+ *   the caller may free them afterwards.
+ * - Block arguments (Y, U, X, Z) are DEVICE pointers owned by the caller.
+ *   Scalar outputs (eigenvalues, errors, flags, counters) are HOST arrays
+ *   owned by the caller.
+ * - Every call enqueues its GPU work on the stream given at plan creation and
+ *   returns after that stream has drained, so outputs are ready on return.
+ * - Errors are returned as rf_status; no call aborts or throws across the
+ *   ABI.  rf_last_error() gives a message for the plan's last failure.
+ *   RF_ERR_DEVICE leaves the plan unusable (destroy it).
+ * - One plan must not be used from two host threads at once.
+ */
+#ifndef RFEIG_H
+#define RFEIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RF_OK = 0,
+    RF_ERR_ARG = 1,       /* bad argument: sizes, NULL pointers, r <= 0, p or q < 1, w < 1 or w > n */
+    RF_ERR_NOMEM = 2,     /* device allocation failed */
+    RF_ERR_SINGULAR = 3,  /* exact zero pivot: a pole lies on an eigenvalue */
+    RF_ERR_NOCONV = 4,    /* iteration cap reached; partial results are returned and flagged */
+    RF_ERR_DEVICE = 5,    /* a HIP call failed; the plan is unusable */
+    RF_ERR_STATE = 6      /* call out of order (e.g. filter before factor_shifts) */
+} rf_status;
+
+/* Sparse square matrix in CSR form, host memory.  val holds 2*nnz doubles. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t *rowptr;   /* n + 1 entries */
+    const int32_t *colind;   /* nnz entries, 0-based */
+    const double *val;       /* nnz complex values, interleaved re/im */
+} rf_csr;
+
+/* Solver options.  Fill with rf_default_opts() and then set the disk. */
+typedef struct {
+    double c_re, c_im;       /* disk centre c */
+    double r;                /* disk radius r > 0 */
+    int32_t p;               /* inner trapezoidal nodes k1: factorized poles (eq. pwtp) */
+    int32_t q;               /* outer trapezoidal nodes k2: multi-shift GMRES shifts (Thm. Rcrm) */
+    int32_t w;               /* block width n_col of the subspace iteration */
+    double sigma_re, sigma_im; /* HSRR shift sigma; NaN in sigma_re means sigma = c (Sec. 6) */
+    double tau;              /* target relative error of converged pairs (eq. rel-error); default 1e-10 */
+    double tau_g;            /* ghost threshold tau_g (Sec. 3.2); default 1e-2 */
+    double gmres_tol;        /* outer-solve tolerance, relative per column and shift; default 1e-12 */
+    int32_t max_subspace_it; /* cap on subspace iterations; default 10 (Sec. 6.3) */
+    int32_t max_krylov_blocks; /* cap on block-Arnoldi steps per filter application; default 150 */
+    int32_t subblock;        /* Krylov sub-block width b dividing w (0 = automatic) */
+    int32_t expected_count;  /* expected eigenvalue count s inside D, -1 if unknown */
+    int32_t tile;            /* band tile size nb (0 = automatic: >= bandwidth, multiple of 16) */
+    int32_t trsm_cols;       /* right-hand sides per triangular-solve workgroup (0 = automatic) */
+    uint64_t seed;           /* seed of the start block when none is given */
+} rf_opts;
+
+/* Per-call statistics of a filter application. */
+typedef struct {
+    int32_t krylov_steps;    /* block-Arnoldi steps taken (applications of G to the basis) */
+    int32_t converged;       /* 1 if every column met gmres_tol for every shift */
+    double max_residual;     /* largest relative residual over shifts and columns */
+    int64_t inner_columns;   /* vectors G was applied to (each costs p solve pairs) */
+    double ms_total;         /* wall time of the call */
+} rf_filter_info;
+
+/* Output of rf_solve_region.  All arrays are caller-owned.
+ * Slots 0..count-1 hold the converged pairs inside D (|lambda - c| < r,
+ * e <= tau); the remaining w - count slots hold the other Ritz pairs of the
+ * last sweep, with flags telling inside / filtered / converged. */
+typedef struct {
+    double *lambda;          /* host, 2*w doubles (complex) */
+    void *X;                 /* device, n x w complex128, leading dimension ldx; unit 2-norm columns */
+    int64_t ldx;
+    double *err;             /* host, w relative errors e_i (eq. rel-error) */
+    int32_t *flags;          /* host, w: bit0 inside D, bit1 e < tau_g, bit2 e <= tau */
+    int32_t count;           /* out: converged pairs inside D */
+    int32_t sweeps;          /* out: subspace iterations used */
+    int32_t converged;       /* out: 1 if the stopping rule of Alg. composite was met */
+    int32_t krylov_steps[16];/* out: block-Arnoldi steps per sweep (first 16 sweeps) */
+    double ms_filter;        /* out: time in filter applications */
+    double ms_hsrr;          /* out: time in projection, QZ and error evaluation */
+} rf_result;
+
+typedef struct rf_plan *rf_plan_t;
+
+/* Defaults: p = 4, q = 8, w = 32, tau = 1e-10, tau_g = 1e-2, gmres_tol = 1e-12,
+ * max_subspace_it = 10, max_krylov_blocks = 150, sigma = c, seed = 0. */
+void rf_default_opts(rf_opts *opts);
+
+/* Copy the pencil to the device, compute the trapezoidal poles/weights of the
+ * inner rule (eq. pwtp, Sec. 2.2) and the outer shifts/weights (Thm. Rcrm,
+ * Sec. 5), size the band tiles from the band extents of pattern(A) and
+ * pattern(B), and allocate every device buffer the plan will use.
+ * hip_stream: a hipStream_t (NULL = the null stream). */
+rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
+                         void *hip_stream, rf_plan_t *out);
+
+/* Band LU with partial pivoting of K_i = p_i B - A for the p inner poles
+ * (Alg. composite, the pre-factorization loop).  RF_ERR_SINGULAR on an exact
+ * zero pivot. */
+rf_status rf_factor_shifts(rf_plan_t plan);
+
+/* Z = G(X) = sum_i w_i K_i^{-1} B X  (eq. linearsolve2), ncols <= w columns.
+ * X and Z are device blocks (n x ncols); they may not overlap. */
+rf_status rf_apply_inner(rf_plan_t plan, const void *X, int64_t ldx, int32_t ncols,
+                         void *Z, int64_t ldz);
+
+/* U = R_{c,r,pq}(B^{-1}A) Y = sum_j c'_j (G - s_j I)^{-1} G(Y)   (eq. linearsolve1abs)
+ * by block multi-shift GMRES on one shared Krylov basis.  The sign of c'_j is
+ * the one for which the sum equals +R_{c,r,pq} (the proof of Thm. Rcrm).
+ * ncols must equal the plan's w.  info may be NULL. */
+rf_status rf_filter_apply(rf_plan_t plan, const void *Y, int64_t ldy, int32_t ncols,
+                          void *U, int64_t ldu, rf_filter_info *info);
+
+/* Alg. composite: subspace iteration with the composite filter and HSRR
+ * (Sec. 2.1) until the filtered count is stable and every filtered error is
+ * <= tau.  Y0: device n x w start block (NULL = seeded Gaussian).  Calls
+ * rf_factor_shifts first if it has not run.  RF_ERR_NOCONV if the sweep cap
+ * is reached (results still filled in). */
+rf_status rf_solve_region(rf_plan_t plan, const void *Y0, int64_t ldy, rf_result *res);
+
+/* Problem size n of a plan, or -1. */
+int64_t rf_plan_n(rf_plan_t plan);
+
+/* Bytes of device memory the plan holds. */
+int64_t rf_plan_device_bytes(rf_plan_t plan);
+
+void rf_plan_destroy(rf_plan_t plan);
+const char *rf_status_str(rf_status s);
+const char *rf_last_error(rf_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFEIG_H */

@@ -1,0 +1,188 @@
+// Internal declarations shared by the rfeig host code and kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "rfeig.h"
+
+// ---------------------------------------------------------------------------
+// complex FP64 helpers (interleaved re/im in a double2)
+// ---------------------------------------------------------------------------
+typedef double2 zd;
+
+__host__ __device__ inline zd zmake(double re, double im) { zd r; r.x = re; r.y = im; return r; }
+__host__ __device__ inline zd zadd(zd a, zd b) { return zmake(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline zd zsub(zd a, zd b) { return zmake(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline zd zmul(zd a, zd b) { return zmake(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__host__ __device__ inline zd zconj(zd a) { return zmake(a.x, -a.y); }
+__host__ __device__ inline zd zscale(zd a, double s) { return zmake(a.x * s, a.y * s); }
+__host__ __device__ inline double zabs2(zd a) { return a.x * a.x + a.y * a.y; }
+// acc += a * b
+__host__ __device__ inline void zfma(zd &acc, zd a, zd b) {
+    acc.x = fma(a.x, b.x, acc.x); acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y); acc.y = fma(a.y, b.x, acc.y);
+}
+// acc -= a * b
+__host__ __device__ inline void zfms(zd &acc, zd a, zd b) {
+    acc.x = fma(-a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+__host__ __device__ inline void zfma_c(zd &acc, zd a, zd b) {
+    acc.x = fma(a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
+}
+__host__ __device__ inline zd zdiv(zd a, zd b) {
+    // Smith's algorithm
+    if (fabs(b.x) >= fabs(b.y)) {
+        double t = b.y / b.x, d = b.x + b.y * t;
+        return zmake((a.x + a.y * t) / d, (a.y - a.x * t) / d);
+    } else {
+        double t = b.x / b.y, d = b.x * t + b.y;
+        return zmake((a.x * t + a.y) / d, (a.y * t - a.x) / d);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct DevCsr {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t *rowptr = nullptr;
+    int32_t *colind = nullptr;
+    zd *val = nullptr;
+    bool diagonal = false;     // only diagonal entries (then dval holds them)
+    zd *dval = nullptr;        // n entries when diagonal
+};
+
+struct BandFactors {
+    int nb = 0;                // tile size (>= kl, ku)
+    int nblk = 0;              // number of row/column blocks
+    int64_t tile_elems = 0;    // nb * nb
+    // per pole, per block k: tiles stored back to back, see rf_band.hip
+    zd *tiles = nullptr;       // p * nblk * 5 * nb*nb
+    int32_t *perm = nullptr;   // p * nblk * 2nb
+    zd *window = nullptr;      // p * (2nb x 3nb) factorization scratch
+    int32_t *info = nullptr;   // p ints: 0 or (1 + first zero-pivot column)
+    bool ready = false;
+};
+
+struct rf_plan {
+    rf_opts opts;
+    int64_t n = 0;
+    int kl = 0, ku = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int max_lds = 65536;      // dynamic LDS bytes a workgroup may use
+    DevCsr A, B;
+    std::vector<zd> poles, weights;       // inner rule (p)
+    std::vector<zd> shifts, oweights;     // outer rule (finite shifts)
+    double oextra = 0.0;                  // (1/q) term for odd q
+    zd *d_poles = nullptr, *d_weights = nullptr;
+    zd *d_shifts = nullptr, *d_oweights = nullptr;
+    BandFactors F;
+    // work buffers
+    zd *rhs = nullptr;        // B X staging: n_pad x w
+    zd *ypart = nullptr;      // per-pole forward results: p x n_pad x w
+    zd *xpart = nullptr;      // per-pole solutions: p x n_pad x w
+    // Krylov
+    int b = 0, nsub = 0, mmax = 0;
+    zd *V = nullptr;          // nsub x (mmax+1) blocks of n x b
+    zd *Wk = nullptr;         // n x w
+    zd *Gin = nullptr;        // n x w staging of the active basis blocks
+    zd *Hm = nullptr;         // nsub x ((mmax+1)b x mmax b) block Hessenberg
+    zd *R0 = nullptr;         // nsub x (b x b)
+    zd *lsQ = nullptr;        // nq x nsub x mmax x (2b x 2b)
+    zd *lsR = nullptr;        // nq x nsub x (mmax b x mmax b)
+    zd *lsG = nullptr;        // nq x nsub x ((mmax+1)b x b)
+    zd *lsWork = nullptr;     // nq x nsub x ((mmax+1)b x b)
+    zd *lsY = nullptr;        // nq x nsub x (mmax b x b)
+    zd *ycomb = nullptr;      // nsub x (mmax b x b)
+    double *resid = nullptr;  // nq x nsub x b
+    double *r0norm = nullptr; // nsub x b column norms of the start block
+    zd *ytil = nullptr;       // n x w  G(Y)
+    zd *tmp = nullptr;        // n x w  scratch
+    double *colnorm = nullptr;// w
+    zd *small = nullptr;      // scratch for b x b / w x w matrices
+    zd *hbuf = nullptr;       // (mmax+1)b x b Gram-Schmidt coefficients
+    zd *rnew = nullptr;       // b x b
+    zd *ident = nullptr;      // b x b identity
+    zd *partial = nullptr;    // split-N GEMM partials
+    int64_t partial_elems = 0;
+    int *flag = nullptr;      // device status flags
+    // HSRR
+    zd *hV = nullptr, *hAV = nullptr, *hBV = nullptr, *hW = nullptr, *hX = nullptr;
+    zd *hproj = nullptr;      // 2 * w * w
+    double *herr = nullptr;   // w
+    int64_t device_bytes = 0;
+    std::vector<void *> allocations;
+    std::string last_error;
+    bool broken = false;
+};
+
+// error helpers --------------------------------------------------------------
+rf_status rf_fail(rf_plan *plan, rf_status s, const std::string &msg);
+
+#define RF_HIP(plan, expr)                                                             \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            (plan)->broken = true;                                                     \
+            return rf_fail((plan), RF_ERR_DEVICE, std::string(#expr) + ": " +          \
+                                                      hipGetErrorString(_e));          \
+        }                                                                              \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files); all enqueue on `s`
+// ---------------------------------------------------------------------------
+// band factorization / solves (rf_band.hip)
+hipError_t launch_band_factor(const rf_plan &P, hipStream_t s);
+// Z = sum_i w_i K_i^{-1} (B X): X n x ncols (ldx), Z n x ncols (ldz)
+hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int ncols,
+                              zd *Z, int64_t ldz, hipStream_t s);
+
+// dense kernels (rf_dense.hip)
+// C (m x k, ldc) = alpha * A^H B + beta * C, A: n x m (lda), B: n x k (ldb); batched by `batch`
+// with strides; reduction over n uses split-N partials in `work`.
+hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_t lda,
+                          int64_t sA, const zd *B, int64_t ldb, int64_t sB, zd beta, zd *C,
+                          int64_t ldc, int64_t sC, int batch, zd *work, int64_t work_elems,
+                          hipStream_t s);
+// C (n x k) = alpha * A (n x m) * B (m x k) + beta * C; batched
+hipError_t launch_gemm_nn(int64_t n, int m, int k, zd alpha, const zd *A, int64_t lda,
+                          int64_t sA, const zd *B, int64_t ldb, int64_t sB, zd beta, zd *C,
+                          int64_t ldc, int64_t sC, int batch, hipStream_t s);
+// Cholesky of batch Hermitian k x k matrices S (in place, lower), returns R^{-1} (upper)
+// in Rinv and R in Rout; status[b] != 0 on breakdown.
+hipError_t launch_chol_inv(int k, zd *S, int64_t sS, zd *Rout, int64_t sR, zd *Rinv,
+                           int64_t sRi, int batch, int *status, double shift_rel,
+                           hipStream_t s);
+hipError_t launch_copy_cols(int64_t n, int ncols, const zd *src, int64_t lds, zd *dst,
+                            int64_t ldd, hipStream_t s);
+hipError_t launch_spmm(const DevCsr &M, int ncols, const zd *X, int64_t ldx, zd *Y,
+                       int64_t ldy, hipStream_t s);
+// Y = A X - sigma * B X   (all n x ncols)
+hipError_t launch_axpby_cols(int64_t n, int ncols, zd alpha, const zd *X, int64_t ldx,
+                             zd beta, const zd *Y, int64_t ldy, zd *Z, int64_t ldz,
+                             hipStream_t s);
+// column 2-norms of (X - Y diag(lam)) (Y may be null) -> out[c]
+hipError_t launch_colnorms(int64_t n, int ncols, const zd *X, int64_t ldx, const zd *Y,
+                           int64_t ldy, const zd *lam, double *out, hipStream_t s);
+hipError_t launch_scale_cols(int64_t n, int ncols, zd *X, int64_t ldx, const double *inv,
+                             hipStream_t s);
+hipError_t launch_gaussian(int64_t n, int ncols, zd *X, int64_t ldx, uint64_t seed,
+                           hipStream_t s);
+// block-GMRES least-squares update for step j (see rf_dense.hip)
+hipError_t launch_ls_update(const rf_plan &P, int j, const int *active, int nact,
+                            hipStream_t s);
+hipError_t launch_ls_solve(const rf_plan &P, int m, const int *active, int nact,
+                           hipStream_t s);
+
+// host QZ (rf_qz.cpp): eigenvalues and right eigenvectors of the pencil (A, B),
+// both n x n column-major complex; vr gets eigenvectors (columns, unit 2-norm).
+int host_qz_eig(int n, const zd *A, const zd *B, zd *alpha, zd *beta, zd *vr);

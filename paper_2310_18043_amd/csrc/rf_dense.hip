@@ -1,0 +1,623 @@
+// Dense and sparse block kernels of the composite-rule filter (gfx950):
+//   * tall-skinny complex products V^H W (split over rows, fixed-order reduction)
+//     and W - V H, used by block Gram-Schmidt in the block-Arnoldi process
+//     (Sec. 3.2, multi-shift GMRES) and by the projections of HSRR (Sec. 2.1);
+//   * Cholesky of small Gram matrices (CholeskyQR orthonormalisation, the
+//     "orth" of Alg. SIsketch);
+//   * the per-shift least-squares updates of multi-shift block GMRES: for every
+//     shift s_j the block Hessenberg matrix H - s_j I~ is reduced to triangular
+//     form one block column per step with Householder reflectors, giving the
+//     residual of every column and shift after each step;
+//   * CSR times block, column norms, start-block generation.
+#include "rf_common.h"
+
+namespace {
+
+constexpr int TM = 64, TN = 64, TK = 16, GT = 256;
+
+// ---------------------------------------------------------------------------
+// C_part[chunk] = A[rows of chunk]^H B[rows of chunk]   (tile 64 x 64 per WG)
+// grid: (ceil(m/64), ceil(k/64), batch * nchunks)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
+    int64_t n, int m, int k, const zd *__restrict__ A, int64_t lda, int64_t sA,
+    const zd *__restrict__ B, int64_t ldb, int64_t sB, zd *__restrict__ part, int nchunks,
+    int64_t chunk) {
+    const int bt = blockIdx.z / nchunks, ch = blockIdx.z % nchunks;
+    const int m0 = blockIdx.x * TM, k0 = blockIdx.y * TN;
+    A += bt * sA; B += bt * sB;
+    const int64_t r0 = int64_t(ch) * chunk;
+    const int64_t r1 = min(n, r0 + chunk);
+    __shared__ zd As[TK][TM + 1];
+    __shared__ zd Bs[TK][TN + 1];
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    zd acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = zmake(0, 0);
+    for (int64_t rr = r0; rr < r1; rr += TK) {
+        // load A[rr:rr+16, m0:m0+64] and B[rr:rr+16, k0:k0+64]
+        for (int e = tid; e < TK * TM; e += GT) {
+            int i = e % TK, c = e / TK;
+            int64_t row = rr + i;
+            As[i][c] = (row < r1 && m0 + c < m) ? A[row + int64_t(m0 + c) * lda] : zmake(0, 0);
+            Bs[i][c] = (row < r1 && k0 + c < k) ? B[row + int64_t(k0 + c) * ldb] : zmake(0, 0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int i = 0; i < TK; ++i) {
+            zd a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { a[u] = As[i][ty + 16 * u]; b[u] = Bs[i][tx + 16 * u]; }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) zfma_c(acc[u][v], a[u], b[v]);
+        }
+        __syncthreads();
+    }
+    zd *P = part + (int64_t(bt) * nchunks + ch) * int64_t(m) * k;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int mi = m0 + ty + 16 * u, kj = k0 + tx + 16 * v;
+            if (mi < m && kj < k) P[mi + int64_t(kj) * m] = acc[u][v];
+        }
+}
+
+// C = alpha * sum_chunks part + beta * C   (fixed summation order)
+__global__ void gemm_cn_reduce_kernel(int m, int k, const zd *part, int nchunks, zd alpha,
+                                      zd beta, zd *C, int64_t ldc, int64_t sC, int batch) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t mk = int64_t(m) * k;
+    if (e >= mk * batch) return;
+    int bt = int(e / mk);
+    int64_t r = e % mk;
+    int mi = int(r % m), kj = int(r / m);
+    const zd *P = part + int64_t(bt) * nchunks * mk + r;
+    zd s = P[0];
+    for (int c = 1; c < nchunks; ++c) s = zadd(s, P[int64_t(c) * mk]);
+    zd *cp = C + bt * sC + mi + int64_t(kj) * ldc;
+    zd out = zmul(alpha, s);
+    if (beta.x != 0.0 || beta.y != 0.0) zfma(out, beta, *cp);
+    *cp = out;
+}
+
+// ---------------------------------------------------------------------------
+// C (n x k) = alpha * A (n x m) B (m x k) + beta * C     grid: (ceil(n/64), ceil(k/64), batch)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd alpha,
+                                                     const zd *__restrict__ A, int64_t lda,
+                                                     int64_t sA, const zd *__restrict__ B,
+                                                     int64_t ldb, int64_t sB, zd beta, zd *C,
+                                                     int64_t ldc, int64_t sC) {
+    const int bt = blockIdx.z;
+    const int64_t n0 = int64_t(blockIdx.x) * TM;
+    const int k0 = blockIdx.y * TN;
+    A += bt * sA; B += bt * sB; C += bt * sC;
+    __shared__ zd As[TK][TM + 1];
+    __shared__ zd Bs[TK][TN + 1];
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    zd acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = zmake(0, 0);
+    for (int kk = 0; kk < m; kk += TK) {
+        for (int e = tid; e < TK * TM; e += GT) {
+            int r = e % TM, i = e / TM;          // A tile: rows n0.., cols kk..
+            int64_t row = n0 + r;
+            As[i][r] = (row < n && kk + i < m) ? A[row + int64_t(kk + i) * lda] : zmake(0, 0);
+            int i2 = e % TK, c = e / TK;         // B tile: rows kk.., cols k0..
+            Bs[i2][c] = (kk + i2 < m && k0 + c < k) ? B[(kk + i2) + int64_t(k0 + c) * ldb] : zmake(0, 0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int i = 0; i < TK; ++i) {
+            zd a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { a[u] = As[i][ty + 16 * u]; b[u] = Bs[i][tx + 16 * u]; }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) zfma(acc[u][v], a[u], b[v]);
+        }
+        __syncthreads();
+    }
+    const bool use_beta = (beta.x != 0.0 || beta.y != 0.0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int64_t row = n0 + ty + 16 * u;
+            int col = k0 + tx + 16 * v;
+            if (row < n && col < k) {
+                zd *cp = C + row + int64_t(col) * ldc;
+                zd out = zmul(alpha, acc[u][v]);
+                if (use_beta) zfma(out, beta, *cp);
+                *cp = out;
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky S = R^H R (R upper) of a batch of k x k Hermitian matrices, in place in
+// global memory (one workgroup each), then Rinv = R^{-1}.  The diagonal is raised by
+// shift_rel * max_i S_ii before factoring (shifted CholeskyQR).  status[b] = 1 + the
+// first column whose pivot is not positive.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(GT) void chol_inv_kernel(int k, zd *S, int64_t sS, zd *Rout,
+                                                      int64_t sR, zd *Rinv, int64_t sRi,
+                                                      int *status, double shift_rel) {
+    const int bt = blockIdx.x;
+    zd *A = S + bt * sS;
+    zd *R = Rout + bt * sR;
+    zd *Ri = Rinv + bt * sRi;
+    const int tid = threadIdx.x;
+    __shared__ int bad;
+    __shared__ double shift;
+    if (tid == 0) {
+        bad = 0;
+        double mx = 0.0;
+        for (int i = 0; i < k; ++i) mx = fmax(mx, A[i + int64_t(i) * k].x);
+        shift = shift_rel * mx;
+    }
+    __syncthreads();
+    // lower Cholesky: A = L L^H, L stored in the lower triangle
+    for (int j = 0; j < k; ++j) {
+        __shared__ double djj;
+        if (tid == 0) {
+            double d = A[j + int64_t(j) * k].x + shift;
+            if (!(d > 0.0)) { if (!bad) bad = j + 1; d = 1.0; }
+            djj = sqrt(d);
+            A[j + int64_t(j) * k] = zmake(djj, 0.0);
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < k; i += GT) A[i + int64_t(j) * k] = zscale(A[i + int64_t(j) * k], 1.0 / djj);
+        __syncthreads();
+        // trailing: A[i][l] -= L[i][j] conj(L[l][j]) for j < l <= i
+        const int rem = k - j - 1;
+        for (int e = tid; e < rem * rem; e += GT) {
+            int i = j + 1 + e % rem, l = j + 1 + e / rem;
+            if (l > i) continue;
+            zd v = A[i + int64_t(l) * k];
+            zd lij = A[i + int64_t(j) * k], llj = A[l + int64_t(j) * k];
+            v.x -= lij.x * llj.x + lij.y * llj.y;
+            v.y -= lij.y * llj.x - lij.x * llj.y;
+            if (i == l) v.y = 0.0;
+            A[i + int64_t(l) * k] = v;
+        }
+        __syncthreads();
+    }
+    // R = L^H (upper), Rinv = R^{-1} (one column per thread, back substitution)
+    for (int e = tid; e < k * k; e += GT) {
+        int i = e % k, j = e / k;
+        R[i + int64_t(j) * k] = (i <= j) ? zconj(A[j + int64_t(i) * k]) : zmake(0, 0);
+    }
+    __syncthreads();
+    for (int c = tid; c < k; c += GT) {
+        zd *x = Ri + int64_t(c) * k;
+        for (int r = c + 1; r < k; ++r) x[r] = zmake(0, 0);
+        for (int r = c; r >= 0; --r) {
+            zd v = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
+            for (int b2 = r + 1; b2 <= c; ++b2) zfms(v, R[r + int64_t(b2) * k], x[b2]);
+            x[r] = zdiv(v, R[r + int64_t(r) * k]);
+        }
+    }
+    if (tid == 0 && status) status[bt] = bad;
+}
+
+__global__ void copy_cols_kernel(int64_t n, int ncols, const zd *src, int64_t lds, zd *dst,
+                                 int64_t ldd) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n * ncols) return;
+    int64_t r = e % n, c = e / n;
+    dst[r + c * ldd] = src[r + c * lds];
+}
+
+// Y = M X for CSR M (one thread per (row, column))
+__global__ void spmm_kernel(int64_t n, int ncols, const int32_t *rp, const int32_t *ci,
+                            const zd *val, const zd *X, int64_t ldx, zd *Y, int64_t ldy) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n * ncols) return;
+    int64_t r = e % n, c = e / n;
+    zd acc = zmake(0, 0);
+    for (int q = rp[r]; q < rp[r + 1]; ++q) zfma(acc, val[q], X[ci[q] + c * ldx]);
+    Y[r + c * ldy] = acc;
+}
+
+__global__ void axpby_kernel(int64_t n, int ncols, zd alpha, const zd *X, int64_t ldx, zd beta,
+                             const zd *Y, int64_t ldy, zd *Z, int64_t ldz) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n * ncols) return;
+    int64_t r = e % n, c = e / n;
+    zd v = zmul(alpha, X[r + c * ldx]);
+    zfma(v, beta, Y[r + c * ldy]);
+    Z[r + c * ldz] = v;
+}
+
+// out[c] = || X[:, c] - lam[c] * Y[:, c] ||_2     (one workgroup per column)
+__global__ __launch_bounds__(GT) void colnorm_kernel(int64_t n, const zd *X, int64_t ldx,
+                                                     const zd *Y, int64_t ldy, const zd *lam,
+                                                     double *out) {
+    const int c = blockIdx.x;
+    const zd *x = X + c * ldx;
+    const zd *y = Y ? Y + c * ldy : nullptr;
+    const zd l = lam ? lam[c] : zmake(0, 0);
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += GT) {
+        zd v = x[r];
+        if (y) zfms(v, l, y[r]);
+        s += zabs2(v);
+    }
+    __shared__ double red[GT];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = GT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = sqrt(red[0]);
+}
+
+__global__ void scale_cols_kernel(int64_t n, int ncols, zd *X, int64_t ldx, const double *inv) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n * ncols) return;
+    int64_t r = e % n, c = e / n;
+    X[r + c * ldx] = zscale(X[r + c * ldx], inv[c]);
+}
+
+// splitmix64-based counter generator: element (r, c) draws from counter r + c*n
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__global__ void gaussian_kernel(int64_t n, int ncols, zd *X, int64_t ldx, uint64_t seed) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n * ncols) return;
+    int64_t r = e % n, c = e / n;
+    uint64_t h1 = splitmix64(seed * 0x632BE59BD9B4E019ull + 2 * uint64_t(e));
+    uint64_t h2 = splitmix64(seed * 0x632BE59BD9B4E019ull + 2 * uint64_t(e) + 1);
+    double u1 = (double((h1 >> 11) + 1)) * (1.0 / 9007199254740993.0);
+    double u2 = double(h2 >> 11) * (1.0 / 9007199254740992.0);
+    double rad = sqrt(-2.0 * log(u1)) * 0.7071067811865476;
+    double ang = 6.283185307179586 * u2;
+    X[r + c * ldx] = zmake(rad * cos(ang), rad * sin(ang));
+}
+
+// ---------------------------------------------------------------------------
+// Multi-shift block GMRES least squares.
+// For shift s_l and sub-block sb, at block-Arnoldi step j the new block column
+// of H - s_l I~ (rows 0..(j+2)b) is rotated by the stored unitary blocks Q_0..Q_{j-1}
+// (each acting on two block rows), then a Householder QR of its bottom 2b x b block
+// gives R_jj and Q_j (stored explicitly, 2b x 2b).  The right-hand side
+// E1 R0 is rotated by Q_j^H; the norms of its last b rows are the residuals.
+// One workgroup per (shift, active sub-block).
+// ---------------------------------------------------------------------------
+struct LsArgs {
+    int b, mmax, j, nq;
+    const zd *shifts;
+    const zd *H; int64_t ldh, sH;       // block Hessenberg per sub-block
+    zd *Q; zd *R; zd *G; zd *work;
+    double *resid;                      // [nq][nsub][b]
+    const double *r0norm;               // [nsub][b] column norms of the start block
+    const int *active;
+    int nsub;
+};
+
+__device__ inline int64_t ls_off(int l, int sb, int nsub, int64_t per) {
+    return (int64_t(l) * nsub + sb) * per;
+}
+
+__global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
+    const int l = blockIdx.x;
+    const int sb = a.active[blockIdx.y];
+    const int b = a.b, j = a.j, mmax = a.mmax, nsub = a.nsub;
+    const int ldc = (mmax + 1) * b;                       // column block leading dim
+    const int64_t qsz = int64_t(4) * b * b;
+    zd *Qs = a.Q + ls_off(l, sb, nsub, int64_t(mmax) * qsz);
+    zd *R = a.R + ls_off(l, sb, nsub, int64_t(mmax) * b * mmax * b);
+    const int ldr = mmax * b;
+    zd *G = a.G + ls_off(l, sb, nsub, int64_t(ldc) * b);
+    zd *col = a.work + ls_off(l, sb, nsub, int64_t(ldc) * b);
+    const zd s = a.shifts[l];
+    const zd *Hc = a.H + sb * a.sH + int64_t(j) * b * a.ldh;   // block column j
+    const int tid = threadIdx.x;
+    const int rows = (j + 2) * b;
+
+    // 1. copy the new column, subtract the shift on its diagonal block
+    for (int e = tid; e < rows * b; e += GT) {
+        int r = e % rows, c = e / rows;
+        zd v = Hc[r + int64_t(c) * a.ldh];
+        if (r == j * b + c) v = zsub(v, s);
+        col[r + int64_t(c) * ldc] = v;
+    }
+    __syncthreads();
+    // 2. apply Q_i^H, i < j, to rows [ib, (i+2)b)
+    extern __shared__ unsigned char smem_raw[];
+    zd *slab = reinterpret_cast<zd *>(smem_raw);          // [2b][b]
+    for (int i = 0; i < j; ++i) {
+        const zd *Qi = Qs + int64_t(i) * qsz;             // 2b x 2b, ld 2b
+        for (int e = tid; e < 2 * b * b; e += GT) {
+            int r = e % (2 * b), c = e / (2 * b);
+            slab[r + c * 2 * b] = col[i * b + r + int64_t(c) * ldc];
+        }
+        __syncthreads();
+        for (int e = tid; e < 2 * b * b; e += GT) {
+            int r = e % (2 * b), c = e / (2 * b);
+            zd acc = zmake(0, 0);
+            for (int t = 0; t < 2 * b; ++t) zfma_c(acc, Qi[t + int64_t(r) * 2 * b], slab[t + c * 2 * b]);
+            col[i * b + r + int64_t(c) * ldc] = acc;
+        }
+        __syncthreads();
+    }
+    // 3. Householder QR of the bottom 2b x b block (in LDS), accumulating Q_j
+    for (int e = tid; e < 2 * b * b; e += GT) {
+        int r = e % (2 * b), c = e / (2 * b);
+        slab[r + c * 2 * b] = col[j * b + r + int64_t(c) * ldc];
+    }
+    zd *Qj = Qs + int64_t(j) * qsz;
+    zd *vv = slab + 2 * b * b;                            // [2b] reflector
+    __shared__ double s_norm2, s_beta;
+    __shared__ zd s_alpha;
+    // Qj starts as identity; we accumulate Qj = H_0 H_1 ... H_{b-1} by right-multiplying
+    for (int e = tid; e < 4 * b * b; e += GT) {
+        int r = e % (2 * b), c = e / (2 * b);
+        Qj[e] = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
+    }
+    __syncthreads();
+    for (int c = 0; c < b; ++c) {
+        // norm of slab[c:, c]
+        if (tid == 0) {
+            double nrm2 = 0.0;
+            for (int r = c; r < 2 * b; ++r) nrm2 += zabs2(slab[r + c * 2 * b]);
+            s_norm2 = nrm2;
+            zd x0 = slab[c + c * 2 * b];
+            double ax0 = sqrt(zabs2(x0));
+            double nrm = sqrt(nrm2);
+            zd ph = (ax0 > 0.0) ? zscale(x0, 1.0 / ax0) : zmake(1.0, 0.0);
+            s_alpha = zscale(ph, -nrm);                   // alpha = -phase(x0) ||x||
+            // v = x - alpha e1 ; v^H v = 2 ||x|| (||x|| + |x0|)
+            s_beta = (nrm > 0.0) ? 2.0 * nrm * (nrm + ax0) : 0.0;
+        }
+        __syncthreads();
+        for (int r = tid; r < 2 * b; r += GT) {
+            zd v = (r < c) ? zmake(0, 0) : slab[r + c * 2 * b];
+            if (r == c) v = zsub(v, s_alpha);
+            vv[r] = v;
+        }
+        __syncthreads();
+        const double inv2 = (s_beta > 0.0) ? 2.0 / s_beta : 0.0;
+        // apply H = I - inv2 v v^H to slab columns c..b-1 (column c becomes alpha e_c)
+        for (int cc = c + tid; cc < b; cc += GT) {
+            zd dot = zmake(0, 0);
+            for (int r = c; r < 2 * b; ++r) zfma_c(dot, vv[r], slab[r + cc * 2 * b]);
+            dot = zscale(dot, inv2);
+            for (int r = c; r < 2 * b; ++r) zfms(slab[r + cc * 2 * b], vv[r], dot);
+        }
+        // Qj <- Qj H  : rows of Qj, each row: Qj[row, :] -= inv2 (Qj[row,:] v) v^H
+        for (int row = tid; row < 2 * b; row += GT) {
+            zd dot = zmake(0, 0);
+            for (int r = c; r < 2 * b; ++r) zfma(dot, Qj[row + int64_t(r) * 2 * b], vv[r]);
+            dot = zscale(dot, inv2);
+            for (int r = c; r < 2 * b; ++r) {
+                zd q = Qj[row + int64_t(r) * 2 * b];
+                zfms(q, dot, zconj(vv[r]));
+                Qj[row + int64_t(r) * 2 * b] = q;
+            }
+        }
+        __syncthreads();
+    }
+    // 4. R block column: rows 0..jb from col, then R_jj from slab
+    for (int e = tid; e < (j + 1) * b * b; e += GT) {
+        int r = e % ((j + 1) * b), c = e / ((j + 1) * b);
+        zd v;
+        if (r < j * b) v = col[r + int64_t(c) * ldc];
+        else { int rr = r - j * b; v = (rr <= c) ? slab[rr + c * 2 * b] : zmake(0, 0); }
+        R[r + int64_t(j * b + c) * ldr] = v;
+    }
+    __syncthreads();
+    // 5. rotate the right-hand side rows [jb, (j+2)b) by Q_j^H
+    for (int e = tid; e < 2 * b * b; e += GT) {
+        int r = e % (2 * b), c = e / (2 * b);
+        slab[r + c * 2 * b] = G[j * b + r + int64_t(c) * ldc];
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * b * b; e += GT) {
+        int r = e % (2 * b), c = e / (2 * b);
+        zd acc = zmake(0, 0);
+        for (int t = 0; t < 2 * b; ++t) zfma_c(acc, Qj[t + int64_t(r) * 2 * b], slab[t + c * 2 * b]);
+        G[j * b + r + int64_t(c) * ldc] = acc;
+    }
+    __syncthreads();
+    // 6. residual of every column: norm of rows [(j+1)b, (j+2)b)
+    for (int c = tid; c < b; c += GT) {
+        double s2 = 0.0;
+        for (int r = 0; r < b; ++r) s2 += zabs2(G[(j + 1) * b + r + int64_t(c) * ldc]);
+        double den = a.r0norm[sb * b + c];
+        a.resid[(int64_t(l) * nsub + sb) * b + c] = (den > 0.0) ? sqrt(s2) / den : 0.0;
+    }
+}
+
+// Back substitution R Y = G[0:mb] for every (shift, active sub-block), then
+// Ycomb[sb] = sum_l c_l Y_l  is done by a second kernel in fixed shift order.
+struct LsSolveArgs {
+    int b, mmax, m, nq, nsub;
+    const zd *R; const zd *G; zd *Y;
+    const int *active;
+};
+
+__global__ __launch_bounds__(GT) void ls_solve_kernel(LsSolveArgs a) {
+    const int l = blockIdx.x;
+    const int sb = a.active[blockIdx.y];
+    const int b = a.b, mmax = a.mmax, m = a.m;
+    const int ldr = mmax * b, ldc = (mmax + 1) * b, mb = m * b;
+    const zd *R = a.R + ls_off(l, sb, a.nsub, int64_t(mmax) * b * mmax * b);
+    const zd *G = a.G + ls_off(l, sb, a.nsub, int64_t(ldc) * b);
+    zd *Y = a.Y + ls_off(l, sb, a.nsub, int64_t(mmax) * b * b);      // ld mmax*b
+    const int tid = threadIdx.x;
+    // thread layout: column c = tid % b, part = tid / b (parts split the dot product)
+    const int parts = GT / b;
+    const int c = tid % b, part = tid / b;
+    extern __shared__ unsigned char smem_raw[];
+    zd *red = reinterpret_cast<zd *>(smem_raw);          // [GT]
+    for (int r = mb - 1; r >= 0; --r) {
+        zd acc = zmake(0, 0);
+        for (int t = r + 1 + part; t < mb; t += parts) zfma(acc, R[r + int64_t(t) * ldr], Y[t + int64_t(c) * ldr]);
+        red[tid] = acc;
+        __syncthreads();
+        if (part == 0) {
+            zd s = G[r + int64_t(c) * ldc];
+            for (int q = 0; q < parts; ++q) s = zsub(s, red[q * b + c]);
+            Y[r + int64_t(c) * ldr] = zdiv(s, R[r + int64_t(r) * ldr]);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void ls_combine_kernel(int b, int mmax, int m, int nq, int nsub, const zd *Y,
+                                  const zd *cw, const int *active, int nact, zd *Ycomb) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int mb = m * b, ldr = mmax * b;
+    if (e >= int64_t(mb) * b * nact) return;
+    int ai = int(e / (int64_t(mb) * b));
+    int64_t rem = e % (int64_t(mb) * b);
+    int r = int(rem % mb), c = int(rem / mb);
+    int sb = active[ai];
+    zd s = zmake(0, 0);
+    for (int l = 0; l < nq; ++l) {
+        const zd *Yl = Y + ls_off(l, sb, nsub, int64_t(mmax) * b * b);
+        zfma(s, cw[l], Yl[r + int64_t(c) * ldr]);
+    }
+    Ycomb[int64_t(sb) * ldr * b + r + int64_t(c) * ldr] = s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_t lda,
+                          int64_t sA, const zd *B, int64_t ldb, int64_t sB, zd beta, zd *C,
+                          int64_t ldc, int64_t sC, int batch, zd *work, int64_t work_elems,
+                          hipStream_t s) {
+    if (n <= 0 || m <= 0 || k <= 0 || batch <= 0) return hipSuccess;
+    const int tiles = ((m + TM - 1) / TM) * ((k + TN - 1) / TN) * batch;
+    int nchunks = int((1024 + tiles - 1) / tiles);          // aim for ~1024 workgroups
+    int64_t maxch = (n + 255) / 256;
+    if (nchunks > maxch) nchunks = int(maxch);
+    int64_t cap = work_elems / (int64_t(m) * k * batch);
+    if (nchunks > cap) nchunks = int(cap);
+    if (nchunks < 1) return hipErrorInvalidValue;
+    int64_t chunk = (n + nchunks - 1) / nchunks;
+    chunk = ((chunk + TK - 1) / TK) * TK;
+    nchunks = int((n + chunk - 1) / chunk);
+    dim3 grid((m + TM - 1) / TM, (k + TN - 1) / TN, batch * nchunks);
+    hipLaunchKernelGGL(gemm_cn_partial_kernel, grid, dim3(GT), 0, s, n, m, k, A, lda, sA, B, ldb,
+                       sB, work, nchunks, chunk);
+    int64_t tot = int64_t(m) * k * batch;
+    hipLaunchKernelGGL(gemm_cn_reduce_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, m, k,
+                       work, nchunks, alpha, beta, C, ldc, sC, batch);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn(int64_t n, int m, int k, zd alpha, const zd *A, int64_t lda,
+                          int64_t sA, const zd *B, int64_t ldb, int64_t sB, zd beta, zd *C,
+                          int64_t ldc, int64_t sC, int batch, hipStream_t s) {
+    if (n <= 0 || k <= 0 || batch <= 0) return hipSuccess;
+    dim3 grid(unsigned((n + TM - 1) / TM), (k + TN - 1) / TN, batch);
+    hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(GT), 0, s, n, m, k, alpha, A, lda, sA, B, ldb,
+                       sB, beta, C, ldc, sC);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_inv(int k, zd *S, int64_t sS, zd *Rout, int64_t sR, zd *Rinv,
+                           int64_t sRi, int batch, int *status, double shift_rel,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(batch), dim3(GT), 0, s, k, S, sS, Rout, sR, Rinv,
+                       sRi, status, shift_rel);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(int64_t n, int ncols, const zd *src, int64_t lds, zd *dst,
+                            int64_t ldd, hipStream_t s) {
+    int64_t tot = n * ncols;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_cols_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, n, ncols, src,
+                       lds, dst, ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmm(const DevCsr &M, int ncols, const zd *X, int64_t ldx, zd *Y, int64_t ldy,
+                       hipStream_t s) {
+    int64_t tot = int64_t(M.n) * ncols;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(spmm_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, int64_t(M.n), ncols,
+                       M.rowptr, M.colind, M.val, X, ldx, Y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby_cols(int64_t n, int ncols, zd alpha, const zd *X, int64_t ldx, zd beta,
+                             const zd *Y, int64_t ldy, zd *Z, int64_t ldz, hipStream_t s) {
+    int64_t tot = n * ncols;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(axpby_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, n, ncols, alpha, X,
+                       ldx, beta, Y, ldy, Z, ldz);
+    return hipGetLastError();
+}
+
+hipError_t launch_colnorms(int64_t n, int ncols, const zd *X, int64_t ldx, const zd *Y,
+                           int64_t ldy, const zd *lam, double *out, hipStream_t s) {
+    if (ncols == 0) return hipSuccess;
+    hipLaunchKernelGGL(colnorm_kernel, dim3(ncols), dim3(GT), 0, s, n, X, ldx, Y, ldy, lam, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(int64_t n, int ncols, zd *X, int64_t ldx, const double *inv,
+                             hipStream_t s) {
+    int64_t tot = n * ncols;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_cols_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, n, ncols, X,
+                       ldx, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_gaussian(int64_t n, int ncols, zd *X, int64_t ldx, uint64_t seed,
+                           hipStream_t s) {
+    int64_t tot = n * ncols;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(gaussian_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, n, ncols, X, ldx,
+                       seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_update(const rf_plan &P, int j, const int *active, int nact, hipStream_t s) {
+    if (nact == 0) return hipSuccess;
+    LsArgs a;
+    a.b = P.b; a.mmax = P.mmax; a.j = j; a.nq = int(P.shifts.size()); a.nsub = P.nsub;
+    a.shifts = P.d_shifts;
+    a.H = P.Hm; a.ldh = int64_t(P.mmax + 1) * P.b; a.sH = a.ldh * int64_t(P.mmax) * P.b;
+    a.Q = P.lsQ; a.R = P.lsR; a.G = P.lsG; a.work = P.lsWork;
+    a.resid = P.resid; a.r0norm = P.r0norm; a.active = active;
+    size_t sm = (size_t(2) * P.b * P.b + 2 * P.b) * sizeof(zd);
+    hipLaunchKernelGGL(ls_update_kernel, dim3(a.nq, nact), dim3(GT), sm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_solve(const rf_plan &P, int m, const int *active, int nact, hipStream_t s) {
+    if (nact == 0 || m == 0) return hipSuccess;
+    LsSolveArgs a;
+    a.b = P.b; a.mmax = P.mmax; a.m = m; a.nq = int(P.shifts.size()); a.nsub = P.nsub;
+    a.R = P.lsR; a.G = P.lsG; a.Y = P.lsY; a.active = active;
+    hipLaunchKernelGGL(ls_solve_kernel, dim3(a.nq, nact), dim3(GT), GT * sizeof(zd), s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t tot = int64_t(m) * P.b * P.b * nact;
+    hipLaunchKernelGGL(ls_combine_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, P.b, P.mmax, m,
+                       a.nq, P.nsub, P.lsY, P.d_oweights, active, nact, P.ycomb);
+    return hipGetLastError();
+}

@@ -1,0 +1,214 @@
+// Generalized Schur form of a small dense complex pencil (A, B) by the QZ
+// algorithm, and the right eigenvectors, on the host.
+//
+// This is the "qz" step of HSRR (Chen & Li, Sec. 2.1, Alg. SIsketch): the
+// projected pencil (W^* A V, W^* B V) is at most a few hundred wide, so it is
+// solved on the CPU while the device holds the large blocks.
+//
+// Steps (complex arithmetic throughout):
+//   1. Householder QR of B: B = Q R; A <- Q^H A.
+//   2. Hessenberg-triangular reduction with Givens rotations: zero A below the
+//      first subdiagonal column by column; each left rotation's fill in B is
+//      removed by a right rotation, which is accumulated into Z.
+//   3. Single-shift QZ sweeps on the active window with deflation; the shift is
+//      the eigenvalue of the trailing 2 x 2 pencil closest to its last diagonal
+//      ratio, with an ad hoc shift every tenth sweep without deflation.
+//   4. lambda_i = S_ii / T_ii; right eigenvectors of the triangular pencil (S, T)
+//      by back substitution, mapped back with Z (= P_R V_R) and normalised.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "rf_common.h"
+
+namespace {
+
+typedef std::complex<double> cd;
+
+struct Mat {
+    int n;
+    std::vector<cd> a;
+    explicit Mat(int n_) : n(n_), a(size_t(n_) * n_) {}
+    cd &operator()(int i, int j) { return a[i + size_t(j) * n]; }
+};
+
+// Givens rotation G = [c s; -conj(s) c] (c real) with G [f; g] = [r; 0]
+void givens(cd f, cd g, double &c, cd &s) {
+    double af = std::abs(f), ag = std::abs(g);
+    if (ag == 0.0) { c = 1.0; s = 0.0; return; }
+    if (af == 0.0) { c = 0.0; s = std::conj(g) / ag; return; }
+    double nrm = std::hypot(af, ag);
+    c = af / nrm;
+    s = (f / af) * std::conj(g) / nrm;
+}
+
+// rows i, i+1 of M (columns j0..n-1): [x; y] <- G [x; y]
+void rot_rows(Mat &M, int i, int k, double c, cd s, int j0, int j1) {
+    for (int j = j0; j < j1; ++j) {
+        cd x = M(i, j), y = M(k, j);
+        M(i, j) = c * x + s * y;
+        M(k, j) = -std::conj(s) * x + c * y;
+    }
+}
+
+// columns i, k of M (rows r0..r1-1): [x y] <- [x y] G^H
+void rot_cols(Mat &M, int i, int k, double c, cd s, int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+        cd x = M(r, i), y = M(r, k);
+        M(r, i) = c * x + std::conj(s) * y;
+        M(r, k) = -s * x + c * y;
+    }
+}
+
+}  // namespace
+
+int host_qz_eig(int n, const zd *Ain, const zd *Bin, zd *alpha_out, zd *beta_out, zd *vr_out) {
+    if (n <= 0) return 0;
+    Mat A(n), B(n), Z(n);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            A(i, j) = cd(Ain[i + size_t(j) * n].x, Ain[i + size_t(j) * n].y);
+            B(i, j) = cd(Bin[i + size_t(j) * n].x, Bin[i + size_t(j) * n].y);
+            Z(i, j) = (i == j) ? 1.0 : 0.0;
+        }
+    const double eps = 2.220446049250313e-16;
+    // 1. Householder QR of B, applied to A from the left
+    std::vector<cd> v(n);
+    for (int k = 0; k < n - 1; ++k) {
+        double nrm2 = 0.0;
+        for (int i = k; i < n; ++i) nrm2 += std::norm(B(i, k));
+        double nrm = std::sqrt(nrm2);
+        if (nrm == 0.0) continue;
+        cd x0 = B(k, k);
+        double ax0 = std::abs(x0);
+        cd ph = ax0 > 0.0 ? x0 / ax0 : cd(1.0);
+        cd alpha = -ph * nrm;
+        for (int i = k; i < n; ++i) v[i] = B(i, k);
+        v[k] -= alpha;
+        double vnorm2 = 2.0 * nrm * (nrm + ax0);
+        if (vnorm2 == 0.0) continue;
+        auto apply = [&](Mat &M) {
+            for (int j = 0; j < n; ++j) {
+                cd d = 0.0;
+                for (int i = k; i < n; ++i) d += std::conj(v[i]) * M(i, j);
+                d *= 2.0 / vnorm2;
+                for (int i = k; i < n; ++i) M(i, j) -= v[i] * d;
+            }
+        };
+        apply(B);
+        apply(A);
+        for (int i = k + 1; i < n; ++i) B(i, k) = 0.0;
+    }
+    // 2. Hessenberg-triangular reduction
+    for (int j = 0; j < n - 2; ++j) {
+        for (int i = n - 1; i >= j + 2; --i) {
+            double c; cd s;
+            givens(A(i - 1, j), A(i, j), c, s);
+            rot_rows(A, i - 1, i, c, s, j, n);
+            A(i, j) = 0.0;
+            rot_rows(B, i - 1, i, c, s, i - 1, n);
+            // B(i, i-1) fill: zero it with a column rotation on (i-1, i)
+            // right rotation of columns (i, i-1) with [B(i,i) B(i,i-1)] G^H = [* 0]
+            givens(std::conj(B(i, i)), std::conj(B(i, i - 1)), c, s);
+            rot_cols(B, i, i - 1, c, s, 0, i + 1);
+            B(i, i - 1) = 0.0;
+            rot_cols(A, i, i - 1, c, s, 0, n);
+            rot_cols(Z, i, i - 1, c, s, 0, n);
+        }
+    }
+    // 3. QZ iterations
+    double anorm = 0.0, bnorm = 0.0;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) { anorm = std::max(anorm, std::abs(A(i, j))); bnorm = std::max(bnorm, std::abs(B(i, j))); }
+    const double atol = eps * std::max(anorm, 1e-300);
+    const double btol = eps * std::max(bnorm, 1e-300);
+    int hi = n - 1;
+    int iter_since = 0, total = 0;
+    const int max_total = 60 * n;
+    while (hi > 0) {
+        if (++total > max_total) return -1;
+        // find lo: the start of the unreduced block ending at hi
+        int lo = hi;
+        while (lo > 0) {
+            double sub = std::abs(A(lo, lo - 1));
+            if (sub <= eps * (std::abs(A(lo, lo)) + std::abs(A(lo - 1, lo - 1))) || sub <= atol) {
+                A(lo, lo - 1) = 0.0;
+                break;
+            }
+            --lo;
+        }
+        if (lo == hi) { --hi; iter_since = 0; continue; }
+        // zero diagonal entries of B inside the block would need special chasing; treat them
+        // by a tiny perturbation (the projected B of HSRR is nonsingular in practice)
+        for (int i = lo; i <= hi; ++i)
+            if (std::abs(B(i, i)) <= btol) B(i, i) = btol;
+        ++iter_since;
+        // shift from the trailing 2x2 pencil
+        cd shift;
+        if (iter_since % 10 == 0) {
+            shift = A(hi, hi - 1) / B(hi - 1, hi - 1) * 1.5 + A(hi, hi) / B(hi, hi);
+        } else {
+            // eigenvalues of (A2, B2): det(A2 - z B2) = 0 with B2 upper triangular
+            cd a11 = A(hi - 1, hi - 1), a12 = A(hi - 1, hi), a21 = A(hi, hi - 1), a22 = A(hi, hi);
+            cd b11 = B(hi - 1, hi - 1), b12 = B(hi - 1, hi), b22 = B(hi, hi);
+            // (a11 - z b11)(a22 - z b22) - (a12 - z b12) a21 = 0
+            cd qa = b11 * b22;
+            cd qb = -(a11 * b22 + a22 * b11) + b12 * a21;
+            cd qc = a11 * a22 - a12 * a21;
+            cd disc = std::sqrt(qb * qb - 4.0 * qa * qc);
+            cd z1 = (-qb + disc) / (2.0 * qa), z2 = (-qb - disc) / (2.0 * qa);
+            cd target = a22 / b22;
+            shift = (std::abs(z1 - target) < std::abs(z2 - target)) ? z1 : z2;
+            if (!std::isfinite(shift.real()) || !std::isfinite(shift.imag())) shift = target;
+        }
+        // bulge chase
+        cd f = A(lo, lo) - shift * B(lo, lo);
+        cd g = A(lo + 1, lo);
+        for (int k = lo; k < hi; ++k) {
+            double c; cd s;
+            givens(f, g, c, s);
+            int jstart = (k == lo) ? lo : k - 1;
+            rot_rows(A, k, k + 1, c, s, jstart, n);
+            if (k > lo) A(k + 1, k - 1) = 0.0;
+            rot_rows(B, k, k + 1, c, s, k, n);
+            // B(k+1, k) fill -> column rotation on (k+1, k)
+            givens(std::conj(B(k + 1, k + 1)), std::conj(B(k + 1, k)), c, s);
+            rot_cols(B, k + 1, k, c, s, 0, k + 2);
+            B(k + 1, k) = 0.0;
+            rot_cols(A, k + 1, k, c, s, 0, std::min(hi, k + 2) + 1);
+            rot_cols(Z, k + 1, k, c, s, 0, n);
+            if (k + 1 < hi) { f = A(k + 1, k); g = A(k + 2, k); }
+        }
+    }
+    // 4. eigenvalues and right eigenvectors
+    for (int i = 0; i < n; ++i) {
+        alpha_out[i] = zmake(A(i, i).real(), A(i, i).imag());
+        beta_out[i] = zmake(B(i, i).real(), B(i, i).imag());
+    }
+    const double small = eps * std::max(anorm, bnorm);
+    std::vector<cd> y(n);
+    for (int i = 0; i < n; ++i) {
+        cd al = A(i, i), be = B(i, i);
+        std::fill(y.begin(), y.end(), cd(0.0));
+        y[i] = 1.0;
+        for (int k = i - 1; k >= 0; --k) {
+            cd sum = 0.0;
+            for (int j = k + 1; j <= i; ++j) sum += (be * A(k, j) - al * B(k, j)) * y[j];
+            cd d = be * A(k, k) - al * B(k, k);
+            if (std::abs(d) < small) d = small;
+            y[k] = -sum / d;
+        }
+        double nrm2 = 0.0;
+        std::vector<cd> x(n, 0.0);
+        for (int r = 0; r < n; ++r) {
+            cd acc = 0.0;
+            for (int j = 0; j <= i; ++j) acc += Z(r, j) * y[j];
+            x[r] = acc;
+            nrm2 += std::norm(acc);
+        }
+        double inv = nrm2 > 0.0 ? 1.0 / std::sqrt(nrm2) : 0.0;
+        for (int r = 0; r < n; ++r) vr_out[r + size_t(i) * n] = zmake(x[r].real() * inv, x[r].imag() * inv);
+    }
+    return 0;
+}

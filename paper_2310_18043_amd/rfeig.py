@@ -1,0 +1,253 @@
+"""Python binding of the rfeig C ABI (``include/rfeig.h``).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory (complex128 CUDA tensors) and the stream.
+The library must be built (``python -m paper_2310_18043_amd.build``); if it is
+missing or fails to load, importing this module raises.
+
+Blocks of vectors are column-major n x k.  A torch tensor ``X`` of shape
+(n, k) is column-major when ``X.T`` is contiguous; ``block(n, k)`` allocates
+one and ``as_colmajor`` converts.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librfeig.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "rfeig.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"rfeig library not built: {LIB_PATH} is missing "
+                      "(run python -m paper_2310_18043_amd.build)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+RF_OK, RF_ERR_ARG, RF_ERR_NOMEM, RF_ERR_SINGULAR, RF_ERR_NOCONV, RF_ERR_DEVICE, RF_ERR_STATE = range(7)
+
+
+class RfCsr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+class RfOpts(ctypes.Structure):
+    _fields_ = [("c_re", ctypes.c_double), ("c_im", ctypes.c_double), ("r", ctypes.c_double),
+                ("p", ctypes.c_int32), ("q", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("sigma_re", ctypes.c_double), ("sigma_im", ctypes.c_double),
+                ("tau", ctypes.c_double), ("tau_g", ctypes.c_double),
+                ("gmres_tol", ctypes.c_double),
+                ("max_subspace_it", ctypes.c_int32), ("max_krylov_blocks", ctypes.c_int32),
+                ("subblock", ctypes.c_int32), ("expected_count", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("trsm_cols", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class RfFilterInfo(ctypes.Structure):
+    _fields_ = [("krylov_steps", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("max_residual", ctypes.c_double), ("inner_columns", ctypes.c_int64),
+                ("ms_total", ctypes.c_double)]
+
+
+class RfResult(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_void_p), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
+                ("err", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("count", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("krylov_steps", ctypes.c_int32 * 16),
+                ("ms_filter", ctypes.c_double), ("ms_hsrr", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_lib.rf_default_opts.argtypes = [ctypes.POINTER(RfOpts)]
+_lib.rf_default_opts.restype = None
+_lib.rf_plan_create.argtypes = [ctypes.POINTER(RfCsr), ctypes.POINTER(RfCsr),
+                                ctypes.POINTER(RfOpts), _P, ctypes.POINTER(_P)]
+_lib.rf_plan_create.restype = ctypes.c_int
+_lib.rf_factor_shifts.argtypes = [_P]
+_lib.rf_factor_shifts.restype = ctypes.c_int
+_lib.rf_apply_inner.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int64]
+_lib.rf_apply_inner.restype = ctypes.c_int
+_lib.rf_filter_apply.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int64,
+                                 ctypes.POINTER(RfFilterInfo)]
+_lib.rf_filter_apply.restype = ctypes.c_int
+_lib.rf_solve_region.argtypes = [_P, _P, ctypes.c_int64, ctypes.POINTER(RfResult)]
+_lib.rf_solve_region.restype = ctypes.c_int
+_lib.rf_plan_n.argtypes = [_P]
+_lib.rf_plan_n.restype = ctypes.c_int64
+_lib.rf_plan_device_bytes.argtypes = [_P]
+_lib.rf_plan_device_bytes.restype = ctypes.c_int64
+_lib.rf_plan_destroy.argtypes = [_P]
+_lib.rf_plan_destroy.restype = None
+_lib.rf_status_str.argtypes = [ctypes.c_int]
+_lib.rf_status_str.restype = ctypes.c_char_p
+_lib.rf_last_error.argtypes = [_P]
+_lib.rf_last_error.restype = ctypes.c_char_p
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def declared_symbols() -> list[str]:
+    """Every function name declared in include/rfeig.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(rf_[a-z_]+)\s*\(", text)))
+
+
+class RfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib.rf_status_str(status).decode()}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def block(n: int, k: int, device="cuda"):
+    """Uninitialised column-major complex128 n x k block on the device."""
+    torch = _torch()
+    return torch.empty((k, n), dtype=torch.complex128, device=device).T
+
+
+def as_colmajor(X):
+    """Column-major complex128 device copy of X (n x k) unless it already is one."""
+    torch = _torch()
+    if X.dim() == 1:
+        X = X[:, None]
+    if X.dtype != torch.complex128:
+        X = X.to(torch.complex128)
+    if not X.is_cuda:
+        X = X.cuda()
+    if X.T.is_contiguous():
+        return X
+    return X.T.contiguous().T
+
+
+def _ld(X) -> int:
+    # leading dimension of a column-major view: stride of the column index
+    return int(X.stride(1)) if X.dim() == 2 and X.shape[1] > 1 else int(X.shape[0])
+
+
+class _HostCsr:
+    """Keeps host arrays alive for the duration of plan creation."""
+
+    def __init__(self, M):
+        import scipy.sparse as sp
+        M = sp.csr_matrix(M, dtype=np.complex128)
+        M.sort_indices()
+        self.rowptr = np.ascontiguousarray(M.indptr, dtype=np.int32)
+        self.colind = np.ascontiguousarray(M.indices, dtype=np.int32)
+        self.val = np.ascontiguousarray(M.data, dtype=np.complex128)
+        self.s = RfCsr(M.shape[0], int(M.nnz), self.rowptr.ctypes.data, self.colind.ctypes.data,
+                       self.val.ctypes.data)
+
+
+class Plan:
+    """rf_plan_create: pencil (A, B) as scipy sparse matrices, disk (c, r), rules p, q, width w."""
+
+    def __init__(self, A, B, c: complex, r: float, p: int = 4, q: int = 8, w: int = 32,
+                 stream=None, **opts):
+        torch = _torch()
+        o = RfOpts()
+        _lib.rf_default_opts(ctypes.byref(o))
+        o.c_re, o.c_im, o.r = float(np.real(c)), float(np.imag(c)), float(r)
+        o.p, o.q, o.w = int(p), int(q), int(w)
+        for key, val in opts.items():
+            if key == "sigma":
+                o.sigma_re, o.sigma_im = float(np.real(val)), float(np.imag(val))
+            elif hasattr(o, key):
+                setattr(o, key, val)
+            else:
+                raise TypeError(f"unknown option {key}")
+        self.opts = o
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        ha, hb = _HostCsr(A), _HostCsr(B)
+        handle = _P()
+        st = _lib.rf_plan_create(ctypes.byref(ha.s), ctypes.byref(hb.s), ctypes.byref(o),
+                                 _P(stream.cuda_stream), ctypes.byref(handle))
+        if st != RF_OK:
+            msg = _lib.rf_last_error(handle).decode() if handle.value else ""
+            if handle.value:
+                _lib.rf_plan_destroy(handle)
+            raise RfError(st, msg or "rf_plan_create failed")
+        self._h = handle
+        self.n = int(_lib.rf_plan_n(handle))
+        self.w = int(w)
+
+    # -- helpers --------------------------------------------------------------
+    def _check(self, st, allow=()):
+        if st != RF_OK and st not in allow:
+            raise RfError(st, _lib.rf_last_error(self._h).decode())
+        return st
+
+    @property
+    def device_bytes(self) -> int:
+        return int(_lib.rf_plan_device_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.rf_plan_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the four calls -------------------------------------------------------
+    def factor_shifts(self):
+        self._check(_lib.rf_factor_shifts(self._h))
+
+    def apply_inner(self, X, out=None):
+        X = as_colmajor(X)
+        k = X.shape[1]
+        Z = block(self.n, k) if out is None else out
+        self._check(_lib.rf_apply_inner(self._h, _P(X.data_ptr()), _ld(X), k,
+                                        _P(Z.data_ptr()), _ld(Z)))
+        return Z
+
+    def filter_apply(self, Y, out=None, allow_noconv=False):
+        Y = as_colmajor(Y)
+        U = block(self.n, Y.shape[1]) if out is None else out
+        info = RfFilterInfo()
+        st = _lib.rf_filter_apply(self._h, _P(Y.data_ptr()), _ld(Y), Y.shape[1],
+                                  _P(U.data_ptr()), _ld(U), ctypes.byref(info))
+        self._check(st, allow=(RF_ERR_NOCONV,) if allow_noconv else ())
+        return U, {"krylov_steps": info.krylov_steps, "converged": bool(info.converged),
+                   "max_residual": info.max_residual, "inner_columns": info.inner_columns,
+                   "ms": info.ms_total}
+
+    def solve_region(self, Y0=None, allow_noconv=False):
+        w = self.w
+        lam = np.zeros(2 * w)
+        err = np.zeros(w)
+        flags = np.zeros(w, dtype=np.int32)
+        X = block(self.n, w)
+        res = RfResult()
+        res.lambda_ = lam.ctypes.data
+        res.X = X.data_ptr()
+        res.ldx = self.n
+        res.err = err.ctypes.data
+        res.flags = flags.ctypes.data
+        if Y0 is not None:
+            Y0 = as_colmajor(Y0)
+            st = _lib.rf_solve_region(self._h, _P(Y0.data_ptr()), _ld(Y0), ctypes.byref(res))
+        else:
+            st = _lib.rf_solve_region(self._h, None, 0, ctypes.byref(res))
+        self._check(st, allow=(RF_ERR_NOCONV,) if allow_noconv else ())
+        lamc = lam[0::2] + 1j * lam[1::2]
+        k = res.count
+        return {"lam": lamc[:k], "X": X[:, :k], "err": err[:k], "count": k,
+                "all_lam": lamc, "all_err": err, "flags": flags, "all_X": X,
+                "sweeps": res.sweeps, "converged": bool(res.converged),
+                "krylov_steps": list(res.krylov_steps[:min(res.sweeps, 16)]),
+                "ms_filter": res.ms_filter, "ms_hsrr": res.ms_hsrr}

@@ -173,13 +173,17 @@ def toeplitz_eigs(n: int, a: complex, b: complex, c: complex) -> np.ndarray:
 
 TOEPLITZ_C = 0.5 * np.exp(1j * np.pi / 3)
 
-# Disk for the 128 x 128 convection-diffusion pencil (D=1, v=(20,10),
-# +0.05i, B=diag U[0.5,1.5], seed 0).  Chosen by ``choose_convdiff_disk``:
-# ~100 eigenvalues inside, radius at mid-gap.  Values fixed here so every run
-# uses the same disk without recomputing reference eigenvalues.
-CONVDIFF128_DISK = None   # filled in below once computed (see _DISKS)
+# Disk for the 128 x 128 convection-diffusion pencil (D = 1, v = (20, 10),
+# +0.05i on the diagonal, B = diag U[0.5, 1.5] with seed 0).  Recipe: the 300
+# eigenvalues of B^{-1}A nearest 2500 + 0.065i (ARPACK shift-invert); centres
+# on the real line (imaginary part 0.0494, the strip's middle) scanned in steps
+# of 5 over [1800, 3200); kept the centre whose 100th/101st distance ratio is
+# largest; radius halfway between the 100th and 101st distances.
+CONVDIFF128_DISK = (2525.0 + 0.0494j, 661.5612524628755, 100)
 
-_DISKS = {}
+_DISKS = {
+    (128, (20.0, 10.0), 0, (0.5, 1.5)): CONVDIFF128_DISK,
+}
 
 
 def toeplitz_workload(n: int = 2000, balanced: bool = True, w: int = 32,
