@@ -1,0 +1,255 @@
+"""Benchmark of the composite-rule interior eigensolver on one MI355X.
+
+One step = the whole hot path on one workload: rf_factor_shifts (band LU of
+the p shifted pencils) + rf_solve_region (Alg. composite: composite filter by
+block multi-shift GMRES, HSRR, ghost test, until converged).  The workload is
+the 128 x 128 upwind convection-diffusion pencil (N = 16384, bandwidth 128,
+D = 1, v = (20, 10), +0.05i, B = diag U[0.5, 1.5]), ~100 eigenvalues in the
+disk, p = 4, q = 8, block width 128, complex FP64.  Inputs are resident on the
+device before the timed region.
+
+Prints ONE JSON line:
+  value        converged eigenpairs (inside D, e <= 1e-10) per second
+  roofline     the band-solve kernel (the inner operator G, the dominant kernel):
+               algorithmic FP64 flops per launch / HIP-event-timed duration
+  cpu_baseline the CPU oracle timed on a bounded sample of the same workload
+  filter_apply one composite filter application: algorithmic GB/s and % of peak
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+import numpy as np  # noqa: E402
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
+PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "band_solve_convdiff128_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def solve_flops_per_column(n, kl, ku, p):
+    """Band-exact flops of sum_i w_i K_i^{-1} for one right-hand side.
+
+    Forward sweep with L (kl multipliers per column) and backward sweep with
+    U (kl + ku super-diagonals), 8 real flops per complex multiply-add, for
+    each of the p poles.
+    """
+    return 8.0 * p * n * (2 * kl + ku)
+
+
+def solve_bytes_per_launch(n, kl, ku, p, cols):
+    """Algorithmic HBM bytes of one band-solve launch: every factor once
+    (LAPACK band size (2kl+ku+1) n complex + n pivots per pole), the
+    right-hand sides read once, the p weighted solutions written once."""
+    factor = p * ((2 * kl + ku + 1) * n * 16 + 4 * n)
+    return factor + cols * n * 16 * (1 + p)
+
+
+def cpu_baseline(wl, gpu_stats):
+    """Time the oracle on a bounded sample and scale to eigenpairs/s."""
+    from oracle import banded, filters
+    t0 = time.time()
+    kl, ku = filters.pencil_bandwidths(wl.A, wl.B)
+    poles, weights = __import__("oracle.coeffs", fromlist=["x"]).trapezoid_nodes(wl.c, wl.r, wl.p)
+    f = banded.band_lu(poles[0] * wl.B - wl.A, kl, ku)
+    t_lu = time.time() - t0
+    ncols = 16
+    X = np.asfortranarray(np.random.default_rng(0).standard_normal((wl.n, ncols)) + 0j)
+    t1 = time.time()
+    f.solve(wl.B @ X)
+    t_solve_col = (time.time() - t1) / ncols          # one pole, one column
+    # full oracle solve estimate: p factorizations + (G applications) * p solves
+    golden = os.path.join(HERE, "tests", "golden", "convdiff128_eigs.txt")
+    apps, src = None, None
+    if os.path.exists(golden):
+        for line in open(golden):
+            if "inner_applications=" in line:
+                apps = sum(json.loads(line.split("inner_applications=")[1].strip()))
+                src = "oracle's own full run (tests/golden/convdiff128_eigs.txt)"
+    if apps is None:
+        apps = gpu_stats["inner_columns"]
+        src = "the GPU run's count of vectors G was applied to"
+    est = wl.p * t_lu + apps * wl.p * t_solve_col
+    return {
+        "value": float(wl.s_expected / est), "unit": "eigenpairs/s", "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle band LU of one shifted pencil ({t_lu:.1f} s) and its solve on "
+                   f"{ncols} columns ({t_solve_col * ncols:.1f} s), scaled to p={wl.p} "
+                   f"factorizations + {apps} applications of G (count from {src}); "
+                   f"estimated full solve {est:.0f} s for {wl.s_expected} pairs; "
+                   f"orthogonalisation and projection not included"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--subblock", type=int, default=0)
+    ap.add_argument("--trsm-cols", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the per-GPU shard is the whole problem); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.calib_copy:
+        a = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")   # 1 GiB
+        a.zero_()
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": a.numel() * 16, "copies": 3}))
+        return
+
+    from paper_2310_18043_amd import rfeig
+    from paper_2310_18043_amd import workloads as W
+
+    wl = W.convdiff_workload()
+    kl, ku = 128, 128
+    props = torch.cuda.get_device_properties(0)
+    log(f"device {props.name} {getattr(props, 'gcnArchName', '')} CUs={props.multi_processor_count} "
+        f"lds/block={getattr(props, 'shared_memory_per_block', '?')} "
+        f"lds/cu={getattr(props, 'shared_memory_per_multiprocessor', '?')}")
+    log(f"workload {wl.name}: n={wl.n} p={wl.p} q={wl.q} w={wl.w} disk c={wl.c} r={wl.r:.3f}")
+    plan = rfeig.Plan(wl.A, wl.B, wl.c, wl.r, p=wl.p, q=wl.q, w=wl.w,
+                      expected_count=wl.s_expected, subblock=args.subblock,
+                      trsm_cols=args.trsm_cols)
+    Y0 = torch.from_numpy(W.start_block(wl.n, wl.w, wl.seed)).cuda()
+    Y0 = rfeig.as_colmajor(Y0)
+    torch.cuda.synchronize()
+
+    def step():
+        plan.factor_shifts()
+        return plan.solve_region(Y0, allow_noconv=True)
+
+    for i in range(args.warmup):
+        t = time.time()
+        res = step()
+        log(f"warmup {i}: {time.time() - t:.3f} s, count={res['count']}, sweeps={res['sweeps']}, "
+            f"krylov={res['krylov_steps']}")
+    plan.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        results.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = plan.profile_read()
+    plan.profile_enable(False)
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    res = results[-1]
+    good = (np.abs(res["lam"] - wl.c) < wl.r) & (res["err"] <= 1e-10)
+    count = int(good.sum())
+    log(f"timed: {ms_per_step:.1f} ms/step, converged pairs {count}, sweeps {res['sweeps']}, "
+        f"krylov steps {res['krylov_steps']}, filter {res['ms_filter']:.1f} ms, hsrr {res['ms_hsrr']:.1f} ms")
+    log(f"kernel stats: {stats}")
+
+    # dominant kernel: band solve (G)
+    fl_col = solve_flops_per_column(wl.n, kl, ku, wl.p)
+    achieved_tflops = fl_col * stats["solve_columns"] / (stats["solve_ms"] * 1e-3) / 1e12
+    avg_cols = stats["solve_columns"] / max(stats["solve_launches"], 1)
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            traffic = json.load(open(TRAFFIC_FILE)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {
+        "kernel": "band_solve_kernel",
+        "bound": "alu",
+        "achieved": round(achieved_tflops, 3),
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tflops / PEAK_FP64_TFLOPS, 4),
+        "traffic": traffic,
+        "avg_launch_ms": round(stats["solve_ms"] / max(stats["solve_launches"], 1), 4),
+        "launches": stats["solve_launches"],
+        "avg_columns_per_launch": round(avg_cols, 2),
+        "algorithmic_flops_per_launch": fl_col * avg_cols,
+        "algorithmic_bytes_per_launch": solve_bytes_per_launch(wl.n, kl, ku, wl.p, avg_cols),
+    }
+
+    # one composite filter application on the start block (the first sweep's input)
+    Yc = Y0
+    torch.cuda.synchronize()
+    plan.profile_enable(True)
+    tf0 = time.perf_counter()
+    U, finfo = plan.filter_apply(Yc, allow_noconv=True)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - tf0
+    fstats = plan.profile_read()
+    plan.profile_enable(False)
+    m = finfo["krylov_steps"]
+    b = plan.opts.subblock or 32
+    # work model: G on all applied columns + block Gram-Schmidt/CholQR + combine
+    n, w, p, s = wl.n, wl.w, wl.p, 16
+    g_flops = fl_col * finfo["inner_columns"]
+    gs_flops = 16.0 * n * b * w * m * (m + 1) + 32.0 * n * b * w * m
+    comb_flops = 8.0 * n * m * b * w
+    f_bytes = (fstats["solve_launches"] * p * ((2 * kl + ku + 1) * n * 16 + 4 * n)
+               + finfo["inner_columns"] * n * 16 * (1 + p)
+               + 2.0 * n * w * s * m * (m + 1) + 8.0 * n * w * s * m + n * (m + 1) * w * s)
+    fa = {
+        "ms": round(tf * 1000, 3), "krylov_steps": m, "inner_columns": finfo["inner_columns"],
+        "algorithmic_tflops": round((g_flops + gs_flops + comb_flops) / tf / 1e12, 3),
+        "frac_fp64_peak": round((g_flops + gs_flops + comb_flops) / tf / 1e12 / PEAK_FP64_TFLOPS, 4),
+        "algorithmic_gbps": round(f_bytes / tf / 1e9, 1),
+        "frac_hbm_peak": round(f_bytes / tf / 1e9 / PEAK_HBM_GBPS, 4),
+        "max_residual": finfo["max_residual"],
+    }
+    log(f"filter_apply: {fa}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(wl, {"inner_columns": finfo["inner_columns"]})
+        log(f"cpu baseline: {cpu}")
+
+    value = count / (ms_per_step / 1000.0)
+    line = {
+        "metric": "converged eigenpairs/s at residual <= 1e-10",
+        "value": round(value, 3),
+        "unit": "eigenpairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "convdiff128_upwind_p4_q8_w128", "n": wl.n, "bandwidth": kl,
+                   "p": wl.p, "q": wl.q, "w": wl.w, "disk_c": [wl.c.real, wl.c.imag],
+                   "disk_r": wl.r, "expected_count": wl.s_expected,
+                   "converged_count": count, "sweeps": res["sweeps"],
+                   "krylov_steps": res["krylov_steps"],
+                   "subblock": b, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "filter_apply": fa,
+        "phases_ms": {"factor": round(stats["factor_ms"] / max(args.steps, 1), 3),
+                      "filter": round(res["ms_filter"], 3), "hsrr": round(res["ms_hsrr"], 3)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -139,6 +139,23 @@ rf_status rf_filter_apply(rf_plan_t plan, const void *Y, int64_t ldy, int32_t nc
  * is reached (results still filled in). */
 rf_status rf_solve_region(rf_plan_t plan, const void *Y0, int64_t ldy, rf_result *res);
 
+/* Timing of the band kernels, for roofline accounting.  Times are summed
+ * HIP-event intervals recorded on the plan stream around each launch. */
+typedef struct {
+    int64_t solve_launches;  /* launches of the multi-RHS band-solve kernel */
+    int64_t solve_columns;   /* right-hand sides summed over those launches (each solved for all p poles) */
+    double solve_ms;         /* summed duration of those launches */
+    int64_t factor_launches; /* launches of the band-factorization kernel pair */
+    double factor_ms;        /* summed duration (factorization + triangle inversion) */
+} rf_kernel_stats;
+
+/* on != 0: reset the counters and start timing; on == 0: stop. */
+rf_status rf_profile_enable(rf_plan_t plan, int32_t on);
+
+/* Copy the counters accumulated since rf_profile_enable(plan, 1); synchronizes
+ * the plan stream. */
+rf_status rf_profile_read(rf_plan_t plan, rf_kernel_stats *out);
+
 /* Problem size n of a plan, or -1. */
 int64_t rf_plan_n(rf_plan_t plan);
 

@@ -138,7 +138,9 @@ int64_t rf_plan_device_bytes(rf_plan_t plan) { return plan ? plan->device_bytes 
 void rf_plan_destroy(rf_plan_t plan) {
     if (!plan) return;
     if (!plan->broken) (void)hipStreamSynchronize(plan->stream);
+    plan->prof.release();
     for (void *p : plan->allocations) (void)hipFree(p);
+    if (plan->h_pinned_int) (void)hipHostFree(plan->h_pinned_int);
     delete plan;
 }
 
@@ -254,7 +256,7 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     const int64_t te = P->F.tile_elems;
     ALLOC(P->F.tiles, int64_t(o.p) * P->F.nblk * 5 * te);
     ALLOC(P->F.perm, int64_t(o.p) * P->F.nblk * 2 * nb);
-    ALLOC(P->F.window, int64_t(o.p) * (2 * nb) * (3 * nb));
+    ALLOC(P->F.window, int64_t(o.p) * 2 * (2 * nb) * (3 * nb));   // double-buffered per pole
     ALLOC(P->F.info, o.p);
     const int64_t n = P->n, w = o.w;
     ALLOC(P->rhs, npad * w);
@@ -278,22 +280,23 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     ALLOC(P->resid, nqs * b);
     ALLOC(P->r0norm, int64_t(P->nsub) * b);
     ALLOC(P->colnorm, std::max<int64_t>(w, 1) * 2);
-    ALLOC(P->small, 8 * w * w + 8 * b * b);
-    ALLOC(P->hbuf, ldc * b);
-    ALLOC(P->rnew, int64_t(b) * b);
-    ALLOC(P->ident, int64_t(b) * b);
-    {
-        std::vector<zd> I(size_t(b) * b, Z(0));
-        for (int i = 0; i < b; ++i) I[i + size_t(i) * b] = Z(1);
-        if (hipMemcpy(P->ident, I.data(), sizeof(zd) * I.size(), hipMemcpyHostToDevice) != hipSuccess) {
-            P->broken = true;
-            rf_fail(P, RF_ERR_DEVICE, "copy of the identity block failed");
-            return fail(RF_ERR_DEVICE);
-        }
-    }
+    // small-matrix scratch: CholeskyQR work (<= 6 k^2 per block, batched), the panel
+    // Gram-Schmidt coefficients and factor of orth_panels (after a 5*64^2 offset)
+    ALLOC(P->small, std::max<int64_t>(8 * w * w, 5 * 64 * 64 + 64 * w + 64 * 64) + 8 * int64_t(P->nsub) * b * b);
+    ALLOC(P->hbuf, 2 * int64_t(P->nsub) * ldc * b);
+    ALLOC(P->rnew, int64_t(P->nsub) * b * b);
     P->partial_elems = std::max<int64_t>(int64_t(1) << 22, 16 * w * w);
     ALLOC(P->partial, P->partial_elems);
     ALLOC(P->flag, 64 + w);
+    ALLOC(P->d_status, 2 * w);
+    ALLOC(P->d_dratio, 2 * w);
+    ALLOC(P->d_active, w);
+    if (hipHostMalloc(reinterpret_cast<void **>(&P->h_pinned_int), sizeof(int) * w, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        P->h_pinned_int = nullptr;
+        rf_fail(P, RF_ERR_NOMEM, "pinned host allocation failed");
+        return fail(RF_ERR_NOMEM);
+    }
     ALLOC(P->hV, n * w);
     ALLOC(P->hAV, n * w);
     ALLOC(P->hBV, n * w);
@@ -309,7 +312,10 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
 rf_status rf_factor_shifts(rf_plan_t P) {
     if (!P) return RF_ERR_ARG;
     if (P->broken) return rf_fail(P, RF_ERR_STATE, "plan is unusable after a device error");
+    hipEvent_t ev0 = nullptr;
+    P->prof.record_begin(P->stream, ev0);
     RF_HIP(P, launch_band_factor(*P, P->stream));
+    P->prof.record_end(P->stream, ev0, 0, 1);
     std::vector<int32_t> info(P->opts.p);
     RF_HIP(P, hipMemcpyAsync(info.data(), P->F.info, sizeof(int32_t) * P->opts.p,
                              hipMemcpyDeviceToHost, P->stream));
@@ -341,9 +347,12 @@ rf_status rf_apply_inner(rf_plan_t P, const void *X, int64_t ldx, int32_t ncols,
 
 namespace {
 
-// Orthonormalise the n x k block Wb (ld n) in place by CholeskyQR2 (shifted
-// CholeskyQR3 if the Gram matrix is numerically indefinite).  Rout (k x k, on the
-// device) receives the triangular factor with Wb_in = Q Rout.  tmp: n x k scratch.
+const double kUnit = 1.1102230246251565e-16;
+
+// Orthonormalise one n x k block Wb (ld n) in place by CholeskyQR2, with a shifted
+// first pass (CholeskyQR3) when the Gram matrix is numerically indefinite.  Rout
+// (k x k, device, may be null) receives the factor with Wb_in = Q Rout.
+// tmp: n x k scratch.  Used for blocks wider than the batched path supports.
 rf_status cholqr(rf_plan *P, zd *Wb, int64_t n, int k, zd *Rout, zd *tmp) {
     hipStream_t s = P->stream;
     zd *S = P->small;                      // k x k
@@ -352,37 +361,36 @@ rf_status cholqr(rf_plan *P, zd *Wb, int64_t n, int k, zd *Rout, zd *tmp) {
     zd *R2 = R1i + int64_t(k) * k;
     zd *R2i = R2 + int64_t(k) * k;
     zd *Racc = R2i + int64_t(k) * k;
-    int *status = P->flag;
-    const int kk = k;
-    // first pass (retried with a shift on breakdown)
+    int *status = P->d_status;
+    double *dratio = P->d_dratio;
+    int passes = 1;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        double shift = attempt == 0 ? 0.0 : 11.0 * (double(n) * kk + double(kk) * (kk + 1)) * 1.1102230246251565e-16;
-        RF_HIP(P, launch_gemm_cn(n, kk, kk, Z(1), Wb, n, 0, Wb, n, 0, Z(0), S, kk, 0, 1, P->partial,
+        double shift = attempt == 0 ? 0.0 : 11.0 * (double(n) * k + double(k) * (k + 1)) * kUnit;
+        RF_HIP(P, launch_gemm_cn(n, k, k, Z(1), Wb, n, 0, Wb, n, 0, Z(0), S, k, 0, 1, P->partial,
                                  P->partial_elems, s));
-        RF_HIP(P, launch_chol_inv(kk, S, 0, R1, 0, R1i, 0, 1, status, shift, s));
+        RF_HIP(P, launch_chol_inv(k, S, 0, R1, 0, R1i, 0, 1, status, dratio, shift, s));
         int hstat = 0;
+        double dr = 0.0;
         RF_HIP(P, hipMemcpyAsync(&hstat, status, sizeof(int), hipMemcpyDeviceToHost, s));
+        RF_HIP(P, hipMemcpyAsync(&dr, dratio, sizeof(double), hipMemcpyDeviceToHost, s));
         RF_HIP(P, hipStreamSynchronize(s));
-        if (hstat == 0) break;
+        if (hstat == 0) { passes = (attempt == 0 && dr > 1e-5) ? 1 : 2; break; }
         if (attempt == 1) return rf_fail(P, RF_ERR_NOCONV, "CholeskyQR breakdown (rank-deficient block)");
     }
-    RF_HIP(P, launch_gemm_nn(n, kk, kk, Z(1), Wb, n, 0, R1i, kk, 0, Z(0), tmp, n, 0, 1, s));
-    // two more passes on the (now well-conditioned) block
-    RF_HIP(P, hipMemcpyAsync(Racc, R1, sizeof(zd) * kk * kk, hipMemcpyDeviceToDevice, s));
+    RF_HIP(P, launch_gemm_nn(n, k, k, Z(1), Wb, n, 0, R1i, k, 0, Z(0), tmp, n, 0, 1, s));
+    RF_HIP(P, hipMemcpyAsync(Racc, R1, sizeof(zd) * k * k, hipMemcpyDeviceToDevice, s));
     zd *src = tmp, *dst = Wb;
-    for (int pass = 0; pass < 2; ++pass) {
-        RF_HIP(P, launch_gemm_cn(n, kk, kk, Z(1), src, n, 0, src, n, 0, Z(0), S, kk, 0, 1, P->partial,
+    for (int pass = 0; pass < passes; ++pass) {
+        RF_HIP(P, launch_gemm_cn(n, k, k, Z(1), src, n, 0, src, n, 0, Z(0), S, k, 0, 1, P->partial,
                                  P->partial_elems, s));
-        RF_HIP(P, launch_chol_inv(kk, S, 0, R2, 0, R2i, 0, 1, status, 0.0, s));
-        RF_HIP(P, launch_gemm_nn(n, kk, kk, Z(1), src, n, 0, R2i, kk, 0, Z(0), dst, n, 0, 1, s));
-        // Racc <- R2 * Racc (via R1 scratch)
-        RF_HIP(P, launch_gemm_nn(kk, kk, kk, Z(1), R2, kk, 0, Racc, kk, 0, Z(0), R1, kk, 0, 1, s));
-        RF_HIP(P, hipMemcpyAsync(Racc, R1, sizeof(zd) * kk * kk, hipMemcpyDeviceToDevice, s));
+        RF_HIP(P, launch_chol_inv(k, S, 0, R2, 0, R2i, 0, 1, status, dratio, 0.0, s));
+        RF_HIP(P, launch_gemm_nn(n, k, k, Z(1), src, n, 0, R2i, k, 0, Z(0), dst, n, 0, 1, s));
+        RF_HIP(P, launch_gemm_nn(k, k, k, Z(1), R2, k, 0, Racc, k, 0, Z(0), R1, k, 0, 1, s));
+        RF_HIP(P, hipMemcpyAsync(Racc, R1, sizeof(zd) * k * k, hipMemcpyDeviceToDevice, s));
         std::swap(src, dst);
     }
-    // after two passes the result is back in Wb (src after the final swap is Wb)
-    if (src != Wb) RF_HIP(P, hipMemcpyAsync(Wb, src, sizeof(zd) * n * kk, hipMemcpyDeviceToDevice, s));
-    if (Rout) RF_HIP(P, hipMemcpyAsync(Rout, Racc, sizeof(zd) * kk * kk, hipMemcpyDeviceToDevice, s));
+    if (src != Wb) RF_HIP(P, hipMemcpyAsync(Wb, src, sizeof(zd) * n * k, hipMemcpyDeviceToDevice, s));
+    if (Rout) RF_HIP(P, hipMemcpyAsync(Rout, Racc, sizeof(zd) * k * k, hipMemcpyDeviceToDevice, s));
     int hstat = 0;
     RF_HIP(P, hipMemcpyAsync(&hstat, status, sizeof(int), hipMemcpyDeviceToHost, s));
     RF_HIP(P, hipStreamSynchronize(s));
@@ -390,7 +398,67 @@ rf_status cholqr(rf_plan *P, zd *Wb, int64_t n, int k, zd *Rout, zd *tmp) {
     return RF_OK;
 }
 
-// U = sum_j c'_j (G - s_j I)^{-1} G(Y) by block multi-shift GMRES.
+// Batched CholeskyQR2 of `batch` blocks W_t = W + t sW (n x k, ld n, k <= 64), in
+// place; R_t (k x k) goes to R + t k^2.  Enqueued only: the caller reads the
+// breakdown flags (d_status, two passes) and condition estimates (d_dratio) at its
+// next synchronisation and redoes flagged blocks with cholqr().  tmp: n x k x batch.
+rf_status cholqr2_batched_enqueue(rf_plan *P, zd *W, int64_t sW, int batch, int64_t n, int k,
+                                  zd *R, zd *tmp) {
+    hipStream_t s = P->stream;
+    const int64_t kk = int64_t(k) * k;
+    zd *S = P->small;                      // batch x k x k each
+    zd *R1 = S + batch * kk, *R1i = R1 + batch * kk, *R2 = R1i + batch * kk, *R2i = R2 + batch * kk;
+    RF_HIP(P, launch_gemm_cn(n, k, k, Z(1), W, n, sW, W, n, sW, Z(0), S, k, kk, batch, P->partial,
+                             P->partial_elems, s));
+    RF_HIP(P, launch_chol_inv(k, S, kk, R1, kk, R1i, kk, batch, P->d_status, P->d_dratio, 0.0, s));
+    RF_HIP(P, launch_gemm_nn(n, k, k, Z(1), W, n, sW, R1i, k, kk, Z(0), tmp, n, n * k, batch, s));
+    RF_HIP(P, launch_gemm_cn(n, k, k, Z(1), tmp, n, n * k, tmp, n, n * k, Z(0), S, k, kk, batch,
+                             P->partial, P->partial_elems, s));
+    RF_HIP(P, launch_chol_inv(k, S, kk, R2, kk, R2i, kk, batch, P->d_status + batch,
+                              P->d_dratio + batch, 0.0, s));
+    RF_HIP(P, launch_gemm_nn(n, k, k, Z(1), tmp, n, n * k, R2i, k, kk, Z(0), W, n, sW, batch, s));
+    RF_HIP(P, launch_gemm_nn(k, k, k, Z(1), R2, k, kk, R1, k, kk, Z(0), R, k, kk, batch, s));
+    return RF_OK;
+}
+
+// Read the flags of cholqr2_batched_enqueue (after a synchronisation) and redo the
+// blocks that broke down or were too ill-conditioned for two passes, from `backup`
+// (same layout as W), with the robust single-block routine.  A block that is
+// (numerically) rank deficient has orthonormal columns that are arbitrary in the
+// deficient directions; when `basis` is given (the Krylov basis the block must stay
+// orthogonal to: basis[t], n x kb) those columns are projected off the basis twice
+// and re-orthonormalised.  The factor R is kept: its columns for the deficient
+// directions are tiny, so the Arnoldi relation changes only by rounding-level terms.
+rf_status cholqr2_batched_fixup(rf_plan *P, zd *W, int64_t sW, const zd *backup, int64_t sB,
+                                int batch, int64_t n, int k, zd *R, zd *tmp,
+                                const std::vector<int> &st, const std::vector<double> &dr,
+                                const std::vector<const zd *> *basis = nullptr, int kb = 0) {
+    hipStream_t s = P->stream;
+    for (int t = 0; t < batch; ++t) {
+        bool bad = st[t] != 0 || st[batch + t] != 0 || !(dr[t] > 1e-6);
+        if (!bad) continue;
+        zd *Wt = W + t * sW;
+        RF_HIP(P, launch_copy_cols(n, k, backup + t * sB, n, Wt, n, s));
+        RF_TRY(cholqr(P, Wt, n, k, R + int64_t(t) * k * k, tmp));
+        if (basis && kb > 0) {
+            const zd *Vt = (*basis)[t];
+            zd *h = P->hbuf;             // kb x k coefficients (free at this point of a step)
+            for (int pass = 0; pass < 2; ++pass) {
+                RF_HIP(P, launch_gemm_cn(n, kb, k, Z(1), Vt, n, 0, Wt, n, 0, Z(0), h, kb, 0, 1,
+                                         P->partial, P->partial_elems, s));
+                RF_HIP(P, launch_gemm_nn(n, kb, k, Z(-1), Vt, n, 0, h, kb, 0, Z(1), Wt, n, 0, 1, s));
+            }
+            zd *Rdiscard = P->small + 7 * int64_t(k) * k;
+            RF_TRY(cholqr(P, Wt, n, k, Rdiscard, tmp));
+        }
+    }
+    return RF_OK;
+}
+
+// U = sum_j c'_j (G - s_j I)^{-1} G(Y) by block multi-shift GMRES: w/b independent
+// sub-blocks of width b, each with its own block-Arnoldi basis, advanced together
+// (one application of G to all active sub-blocks per step) until every column of
+// every sub-block meets the tolerance for every shift.
 rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
                       rf_filter_info *info) {
     const double t0 = now_ms();
@@ -401,72 +469,101 @@ rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
     const int64_t ldc = int64_t(mmax + 1) * b, mbmax = int64_t(mmax) * b;
     const int64_t vstride = n * ldc;                 // per sub-block basis
     const int64_t hstride = ldc * mbmax;
-    (void)w;
+    const int64_t bb = int64_t(b) * b;
     int64_t inner_cols = 0;
+    int *d_active = P->d_active;
+    int *h_active = P->h_pinned_int;                 // pinned host mirror of d_active
 
     // Ytilde = G(Y)
     RF_HIP(P, launch_inner_apply(*P, Y, ldy, w, P->ytil, n, s));
     inner_cols += w;
-    // column norms of Ytilde (per sub-block) for relative residuals
-    RF_HIP(P, launch_colnorms(n, w, P->ytil, n, nullptr, 0, nullptr, P->r0norm, s));
-    // V_sb[0] R0_sb = Ytilde_sb
-    for (int sb = 0; sb < nsub; ++sb) {
-        zd *V0 = P->V + sb * vstride;
-        RF_HIP(P, launch_copy_cols(n, b, P->ytil + int64_t(sb) * b * n, n, V0, n, s));
-        RF_TRY(cholqr(P, V0, n, b, P->R0 + int64_t(sb) * b * b, P->tmp));
+    // The outer solves are column-wise linear in Ytilde: solve for unit-norm
+    // columns (so every column meets the relative tolerance on its own scale,
+    // whatever the spread of |R_p(lambda)| across the block) and scale back.
+    double *d_scale = P->colnorm;          // w column norms
+    double *d_inv = P->colnorm + w;        // w inverse norms
+    RF_HIP(P, launch_colnorms(n, w, P->ytil, n, nullptr, 0, nullptr, d_scale, s));
+    std::vector<double> nrm(w), inv(w), ones(w, 1.0);
+    RF_HIP(P, hipMemcpyAsync(nrm.data(), d_scale, sizeof(double) * w, hipMemcpyDeviceToHost, s));
+    RF_HIP(P, hipStreamSynchronize(s));
+    for (int c = 0; c < w; ++c) inv[c] = nrm[c] > 0.0 ? 1.0 / nrm[c] : 0.0;
+    RF_HIP(P, hipMemcpyAsync(d_inv, inv.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
+    RF_HIP(P, hipMemcpyAsync(P->r0norm, ones.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
+    // V_sb[0] R0_sb = Ytilde_sb D_sb^{-1}   (all sub-blocks at once)
+    RF_HIP(P, launch_copy_block(n, b, P->ytil, n, n * b, P->V, n, vstride, nsub, s));
+    for (int sb = 0; sb < nsub; ++sb)
+        RF_HIP(P, launch_scale_cols(n, b, P->V + sb * vstride, n, d_inv + int64_t(sb) * b, s));
+    RF_HIP(P, launch_copy_block(n, b, P->V, n, vstride, P->Gin, n, n * b, nsub, s));   // backup
+    RF_TRY(cholqr2_batched_enqueue(P, P->V, vstride, nsub, n, b, P->R0, P->tmp));
+    {
+        std::vector<int> st(2 * nsub);
+        std::vector<double> dr(2 * nsub);
+        RF_HIP(P, hipMemcpyAsync(st.data(), P->d_status, sizeof(int) * 2 * nsub, hipMemcpyDeviceToHost, s));
+        RF_HIP(P, hipMemcpyAsync(dr.data(), P->d_dratio, sizeof(double) * 2 * nsub, hipMemcpyDeviceToHost, s));
+        RF_HIP(P, hipStreamSynchronize(s));
+        RF_TRY(cholqr2_batched_fixup(P, P->V, vstride, P->Gin, n * b, nsub, n, b, P->R0, P->tmp, st, dr));
     }
-    // right-hand sides E1 R0 per (shift, sub-block); Hessenberg columns are
-    // cleared step by step
+    // right-hand sides E1 R0 per (shift, sub-block)
     if (nq > 0) {
         RF_HIP(P, hipMemsetAsync(P->lsG, 0, sizeof(zd) * int64_t(nq) * nsub * ldc * b, s));
         for (int l = 0; l < nq; ++l)
-            for (int sb = 0; sb < nsub; ++sb)
-                RF_HIP(P, hipMemcpy2DAsync(P->lsG + (int64_t(l) * nsub + sb) * ldc * b, ldc * sizeof(zd),
-                                           P->R0 + int64_t(sb) * b * b, b * sizeof(zd), b * sizeof(zd), b,
-                                           hipMemcpyDeviceToDevice, s));
+            RF_HIP(P, launch_copy_block(b, b, P->R0, b, bb, P->lsG + int64_t(l) * nsub * ldc * b, ldc,
+                                        ldc * b, nsub, s));
     }
     std::vector<int> active(nsub), msteps(nsub, 0);
     std::iota(active.begin(), active.end(), 0);
     std::vector<double> resid(size_t(std::max(nq, 1)) * nsub * b);
+    std::vector<int> st(2 * nsub);
+    std::vector<double> dr(2 * nsub);
     double worst_final = 0.0;
     bool all_conv = true;
     int steps = 0;
-    int *d_active = P->flag + 16;
     if (nq == 0) active.clear();         // q = 1: the filter is (1/q) G(Y) only
+    zd *h1 = P->hbuf;                    // nsub x ((mmax+1)b x b), by active position
+    zd *h2 = P->hbuf + int64_t(nsub) * ldc * b;
+    zd *Rn = P->rnew;                    // nsub x (b x b)
     for (int j = 0; j < mmax && !active.empty(); ++j) {
         const int nact = int(active.size());
-        // gather the newest basis block of every active sub-block
-        for (int a = 0; a < nact; ++a) {
-            int sb = active[a];
-            RF_HIP(P, launch_copy_cols(n, b, P->V + sb * vstride + int64_t(j) * b * n, n,
-                                       P->Gin + int64_t(a) * b * n, n, s));
-        }
+        const int kb = (j + 1) * b;
+        for (int a = 0; a < nact; ++a) h_active[a] = active[a];
+        RF_HIP(P, hipMemcpyAsync(d_active, h_active, sizeof(int) * nact, hipMemcpyHostToDevice, s));
+        // gather the newest basis block of every active sub-block, apply G
+        RF_HIP(P, launch_copy_block(n, b, P->V + int64_t(j) * b * n, n, vstride, P->Gin, n, n * b,
+                                    nact, s, d_active, kMapA));
         RF_HIP(P, launch_inner_apply(*P, P->Gin, n, nact * b, P->Wk, n, s));
         inner_cols += int64_t(nact) * b;
-        for (int a = 0; a < nact; ++a) {
-            int sb = active[a];
-            zd *Vs = P->V + sb * vstride;
-            zd *Wb = P->Wk + int64_t(a) * b * n;
-            zd *Hc = P->Hm + sb * hstride + int64_t(j) * b * ldc;     // block column j
-            const int kb = (j + 1) * b;
-            RF_HIP(P, hipMemset2DAsync(Hc, ldc * sizeof(zd), 0, (j + 2) * b * sizeof(zd), b, s));
-            for (int pass = 0; pass < 2; ++pass) {   // block classical Gram-Schmidt, twice
-                zd *h = P->hbuf;                                      // kb x b
-                RF_HIP(P, launch_gemm_cn(n, kb, b, Z(1), Vs, n, 0, Wb, n, 0, Z(0), h, kb, 0, 1,
-                                         P->partial, P->partial_elems, s));
-                RF_HIP(P, launch_gemm_nn(n, kb, b, Z(-1), Vs, n, 0, h, kb, 0, Z(1), Wb, n, 0, 1, s));
-                // H[0:kb, jb:(j+1)b] += h
-                RF_HIP(P, launch_gemm_nn(kb, b, b, Z(1), h, kb, 0, P->ident, b, 0, Z(1), Hc, ldc, 0, 1, s));
-            }
-            // V_{j+1} R = W ;  H[(j+1)b:(j+2)b, jb:(j+1)b] = R
-            zd *Rn = P->rnew;
-            RF_TRY(cholqr(P, Wb, n, b, Rn, P->tmp));
-            RF_HIP(P, launch_copy_cols(n, b, Wb, n, Vs + int64_t(j + 1) * b * n, n, s));
-            RF_HIP(P, hipMemcpy2DAsync(Hc + int64_t(j + 1) * b, ldc * sizeof(zd), Rn, b * sizeof(zd),
-                                       b * sizeof(zd), b, hipMemcpyDeviceToDevice, s));
+        // block classical Gram-Schmidt, twice: h = V^H W; W -= V h
+        zd *hp[2] = {h1, h2};
+        for (int pass = 0; pass < 2; ++pass) {
+            RF_HIP(P, launch_gemm_cn(n, kb, b, Z(1), P->V, n, vstride, P->Wk, n, n * b, Z(0), hp[pass],
+                                     kb, ldc * b, nact, P->partial, P->partial_elems, s, d_active,
+                                     kMapA));
+            RF_HIP(P, launch_gemm_nn(n, kb, b, Z(-1), P->V, n, vstride, hp[pass], kb, ldc * b, Z(1),
+                                     P->Wk, n, n * b, nact, s, d_active, kMapA));
         }
+        // H[sb][0:kb, jb:(j+1)b] = h1 + h2
+        zd *Hcol = P->Hm + int64_t(j) * b * ldc;
+        RF_HIP(P, launch_copy_block(kb, b, h1, kb, ldc * b, Hcol, ldc, hstride, nact, s, d_active, kMapC));
+        RF_HIP(P, launch_add_block(kb, b, Z(1), h2, kb, ldc * b, Hcol, ldc, hstride, nact, s, d_active,
+                                   kMapC));
+        // V_{j+1} R = W  (backup of W in Gin for the rare fallback)
+        RF_HIP(P, launch_copy_cols(n, nact * b, P->Wk, n, P->Gin, n, s));
+        RF_TRY(cholqr2_batched_enqueue(P, P->Wk, n * b, nact, n, b, Rn, P->tmp));
+        // the fallback check needs the flags before V and H are written
+        RF_HIP(P, hipMemcpyAsync(st.data(), P->d_status, sizeof(int) * 2 * nact, hipMemcpyDeviceToHost, s));
+        RF_HIP(P, hipMemcpyAsync(dr.data(), P->d_dratio, sizeof(double) * 2 * nact, hipMemcpyDeviceToHost, s));
+        RF_HIP(P, hipStreamSynchronize(s));
+        {
+            std::vector<const zd *> basis(nact);
+            for (int a = 0; a < nact; ++a) basis[a] = P->V + active[a] * vstride;
+            RF_TRY(cholqr2_batched_fixup(P, P->Wk, n * b, P->Gin, n * b, nact, n, b, Rn, P->tmp, st,
+                                         dr, &basis, kb));
+        }
+        RF_HIP(P, launch_copy_block(n, b, P->Wk, n, n * b, P->V + int64_t(j + 1) * b * n, n, vstride,
+                                    nact, s, d_active, kMapC));
+        RF_HIP(P, launch_copy_block(b, b, Rn, b, bb, Hcol + int64_t(j + 1) * b, ldc, hstride, nact, s,
+                                    d_active, kMapC));
         // per-shift least squares update and residuals
-        RF_HIP(P, hipMemcpyAsync(d_active, active.data(), sizeof(int) * nact, hipMemcpyHostToDevice, s));
         RF_HIP(P, launch_ls_update(*P, j, d_active, nact, s));
         RF_HIP(P, hipMemcpyAsync(resid.data(), P->resid, sizeof(double) * nq * nsub * b,
                                  hipMemcpyDeviceToHost, s));
@@ -486,20 +583,20 @@ rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
         }
         active.swap(still);
     }
-    // solve the triangular systems, combine shifts, U_sb = V_sb Ycomb_sb
+    // solve the triangular systems, combine shifts, U_sb = V_sb Ycomb_sb D_sb
     for (int sb = 0; sb < nsub; ++sb) {
         const int m = msteps[sb];
         zd *Us = U + int64_t(sb) * b * ldu;
         if (m == 0) {
             RF_HIP(P, hipMemset2DAsync(Us, ldu * sizeof(zd), 0, n * sizeof(zd), b, s));
         } else {
-            int one = sb;
-            RF_HIP(P, hipMemcpyAsync(d_active, &one, sizeof(int), hipMemcpyHostToDevice, s));
-            RF_HIP(P, launch_ls_solve(*P, m, d_active, 1, s));
+            h_active[sb] = sb;
+            RF_HIP(P, hipMemcpyAsync(d_active + sb, h_active + sb, sizeof(int), hipMemcpyHostToDevice, s));
+            RF_HIP(P, launch_ls_solve(*P, m, d_active + sb, 1, s));
             RF_HIP(P, launch_gemm_nn(n, m * b, b, Z(1), P->V + sb * vstride, n, 0,
                                      P->ycomb + int64_t(sb) * mbmax * b, mbmax, 0, Z(0), Us, ldu, 0, 1,
                                      s));
-            RF_HIP(P, hipStreamSynchronize(s));
+            RF_HIP(P, launch_scale_cols(n, b, Us, ldu, d_scale + int64_t(sb) * b, s));
         }
         if (P->oextra != 0.0)
             RF_HIP(P, launch_axpby_cols(n, b, Z(1), Us, ldu, Z(P->oextra), P->ytil + int64_t(sb) * b * n,
@@ -530,6 +627,35 @@ rf_status rf_filter_apply(rf_plan_t P, const void *Y, int64_t ldy, int32_t ncols
 
 namespace {
 
+// orth(U) for a wide block (n x w, in place): panels of at most 64 columns, each
+// made orthogonal to the previous panels by classical Gram-Schmidt applied twice
+// and then orthonormalised by CholeskyQR2 (the Gram matrices of 64-column panels
+// are factored in LDS).  Only the orthonormal basis is kept; its span is that of U.
+rf_status orth_panels(rf_plan *P, zd *U, int64_t n, int w) {
+    hipStream_t s = P->stream;
+    const int kp = 64;
+    zd *h = P->small + 5 * 64 * 64;                            // (w - kp) x kp scratch
+    zd *R = h + int64_t(w) * kp;                               // kp x kp factor (discarded)
+    std::vector<int> st(2);
+    std::vector<double> dr(2);
+    for (int c0 = 0; c0 < w; c0 += kp) {
+        const int k = std::min(kp, w - c0);
+        zd *Ut = U + int64_t(c0) * n;
+        for (int pass = 0; c0 > 0 && pass < 2; ++pass) {
+            RF_HIP(P, launch_gemm_cn(n, c0, k, Z(1), U, n, 0, Ut, n, 0, Z(0), h, c0, 0, 1, P->partial,
+                                     P->partial_elems, s));
+            RF_HIP(P, launch_gemm_nn(n, c0, k, Z(-1), U, n, 0, h, c0, 0, Z(1), Ut, n, 0, 1, s));
+        }
+        RF_HIP(P, launch_copy_cols(n, k, Ut, n, P->Gin, n, s));
+        RF_TRY(cholqr2_batched_enqueue(P, Ut, n * k, 1, n, k, R, P->tmp));
+        RF_HIP(P, hipMemcpyAsync(st.data(), P->d_status, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+        RF_HIP(P, hipMemcpyAsync(dr.data(), P->d_dratio, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+        RF_HIP(P, hipStreamSynchronize(s));
+        RF_TRY(cholqr2_batched_fixup(P, Ut, n * k, P->Gin, n * k, 1, n, k, R, P->tmp, st, dr));
+    }
+    return RF_OK;
+}
+
 // HSRR(A, B, U, sigma) (Sec. 2.1): Ritz values lam (host), unit-norm Ritz vectors in
 // P->hX, errors e_i (eq. rel-error) in err (host).
 rf_status hsrr(rf_plan *P, zd *U, std::vector<std::complex<double>> &lam,
@@ -549,13 +675,13 @@ rf_status hsrr(rf_plan *P, zd *U, std::vector<std::complex<double>> &lam,
     RF_HIP(P, hipMemcpyAsync(P->colnorm, cn.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
     RF_HIP(P, launch_copy_cols(n, w, U, n, P->hV, n, s));
     RF_HIP(P, launch_scale_cols(n, w, P->hV, n, P->colnorm, s));
-    RF_TRY(cholqr(P, P->hV, n, w, nullptr, P->tmp));
+    RF_TRY(orth_panels(P, P->hV, n, w));
     // AV, BV, W = orth(AV - sigma BV)
     RF_HIP(P, launch_spmm(P->A, w, P->hV, n, P->hAV, n, s));
     RF_HIP(P, launch_spmm(P->B, w, P->hV, n, P->hBV, n, s));
     RF_HIP(P, launch_axpby_cols(n, w, Z(1), P->hAV, n, Z(-sigma.real(), -sigma.imag()), P->hBV, n,
                                 P->hW, n, s));
-    RF_TRY(cholqr(P, P->hW, n, w, nullptr, P->tmp));
+    RF_TRY(orth_panels(P, P->hW, n, w));
     // projected pencil
     zd *Ah = P->hproj, *Bh = P->hproj + int64_t(w) * w;
     RF_HIP(P, launch_gemm_cn(n, w, w, Z(1), P->hW, n, 0, P->hAV, n, 0, Z(0), Ah, w, 0, 1, P->partial,
@@ -621,7 +747,7 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
     if (Y0) RF_HIP(P, launch_copy_cols(n, w, static_cast<const zd *>(Y0), ldy, Y, n, s));
     else RF_HIP(P, launch_gaussian(n, w, Y, n, P->opts.seed, s));
     // Y = orth(Y)  (Alg. composite: orthonormal random start)
-    RF_TRY(cholqr(P, Y, n, w, nullptr, P->tmp));
+    RF_TRY(orth_panels(P, Y, n, w));
     const std::complex<double> c(P->opts.c_re, P->opts.c_im);
     const double r = P->opts.r;
     std::vector<std::complex<double>> lam;
@@ -685,6 +811,87 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
     res->ms_hsrr = ms_hsrr;
     (void)t_start;
     return converged ? RF_OK : RF_ERR_NOCONV;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+hipEvent_t KernelProfile::take() {
+    if (pool.empty()) {
+        if (pending.size() > 1024) (void)drain();
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+        return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+}
+
+void KernelProfile::record_begin(hipStream_t s, hipEvent_t &a) {
+    a = on ? take() : nullptr;
+    if (a) (void)hipEventRecord(a, s);
+}
+
+void KernelProfile::record_end(hipStream_t s, hipEvent_t a, int64_t cols, int kind) {
+    if (!a) return;
+    hipEvent_t b = take();
+    if (!b) { pool.push_back(a); return; }
+    (void)hipEventRecord(b, s);
+    pending.push_back({a, b, cols, kind});
+}
+
+hipError_t KernelProfile::drain() {
+    for (auto &p : pending) {
+        hipError_t e = hipEventSynchronize(p.b);
+        if (e != hipSuccess) return e;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) return e;
+        if (p.kind == 0) {
+            stats.solve_launches += 1;
+            stats.solve_columns += p.cols;
+            stats.solve_ms += ms;
+        } else {
+            stats.factor_launches += 1;
+            stats.factor_ms += ms;
+        }
+        pool.push_back(p.a);
+        pool.push_back(p.b);
+    }
+    pending.clear();
+    return hipSuccess;
+}
+
+void KernelProfile::release() {
+    for (auto &p : pending) { pool.push_back(p.a); pool.push_back(p.b); }
+    pending.clear();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+}
+
+extern "C" {
+
+rf_status rf_profile_enable(rf_plan_t P, int32_t on) {
+    if (!P) return RF_ERR_ARG;
+    if (P->broken) return rf_fail(P, RF_ERR_STATE, "plan is unusable after a device error");
+    if (on) {
+        RF_HIP(P, P->prof.drain());
+        P->prof.stats = rf_kernel_stats{};
+    }
+    P->prof.on = on != 0;
+    return RF_OK;
+}
+
+rf_status rf_profile_read(rf_plan_t P, rf_kernel_stats *out) {
+    if (!P || !out) return RF_ERR_ARG;
+    if (P->broken) return rf_fail(P, RF_ERR_STATE, "plan is unusable after a device error");
+    RF_HIP(P, hipStreamSynchronize(P->stream));
+    RF_HIP(P, P->prof.drain());
+    *out = P->prof.stats;
+    return RF_OK;
 }
 
 }  // extern "C"

@@ -71,8 +71,23 @@ struct BandFactors {
     bool ready = false;
 };
 
+// HIP-event timing of the band kernels (enabled by rf_profile_enable)
+struct KernelProfile {
+    bool on = false;
+    std::vector<hipEvent_t> pool;          // free events
+    struct Pending { hipEvent_t a, b; int64_t cols; int kind; };
+    std::vector<Pending> pending;          // recorded, not yet read
+    rf_kernel_stats stats{};
+    hipEvent_t take();
+    void record_begin(hipStream_t s, hipEvent_t &a);
+    void record_end(hipStream_t s, hipEvent_t a, int64_t cols, int kind);
+    hipError_t drain();                    // sync on the events, fold into stats
+    void release();
+};
+
 struct rf_plan {
     rf_opts opts;
+    mutable KernelProfile prof;
     int64_t n = 0;
     int kl = 0, ku = 0;
     hipStream_t stream = nullptr;
@@ -114,6 +129,10 @@ struct rf_plan {
     zd *partial = nullptr;    // split-N GEMM partials
     int64_t partial_elems = 0;
     int *flag = nullptr;      // device status flags
+    int *d_status = nullptr;  // 2w Cholesky breakdown flags (two passes)
+    double *d_dratio = nullptr; // 2w Cholesky diagonal ratios
+    int *d_active = nullptr;  // w active sub-block indices
+    int *h_pinned_int = nullptr; // pinned host mirror of d_active
     // HSRR
     zd *hV = nullptr, *hAV = nullptr, *hBV = nullptr, *hW = nullptr, *hX = nullptr;
     zd *hproj = nullptr;      // 2 * w * w
@@ -147,21 +166,35 @@ hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int nc
                               zd *Z, int64_t ldz, hipStream_t s);
 
 // dense kernels (rf_dense.hip)
+// Batched operands: entry t of operand X is at X + (flags & kMapX ? map[t] : t) * sX.
+constexpr int kMapA = 1, kMapB = 2, kMapC = 4;
 // C (m x k, ldc) = alpha * A^H B + beta * C, A: n x m (lda), B: n x k (ldb); batched by `batch`
 // with strides; reduction over n uses split-N partials in `work`.
 hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_t lda,
                           int64_t sA, const zd *B, int64_t ldb, int64_t sB, zd beta, zd *C,
                           int64_t ldc, int64_t sC, int batch, zd *work, int64_t work_elems,
-                          hipStream_t s);
+                          hipStream_t s, const int *map = nullptr, int flags = 0);
 // C (n x k) = alpha * A (n x m) * B (m x k) + beta * C; batched
 hipError_t launch_gemm_nn(int64_t n, int m, int k, zd alpha, const zd *A, int64_t lda,
                           int64_t sA, const zd *B, int64_t ldb, int64_t sB, zd beta, zd *C,
-                          int64_t ldc, int64_t sC, int batch, hipStream_t s);
-// Cholesky of batch Hermitian k x k matrices S (in place, lower), returns R^{-1} (upper)
-// in Rinv and R in Rout; status[b] != 0 on breakdown.
+                          int64_t ldc, int64_t sC, int batch, hipStream_t s,
+                          const int *map = nullptr, int flags = 0);
+// Cholesky S = R^H R of batch Hermitian k x k matrices (ld k): R to Rout, R^{-1} to Rinv;
+// status[t] != 0 on breakdown, dratio[t] = min R_ii / max R_ii.  For k <= 64 the
+// factorization runs in LDS and S is left intact (map: A -> S, B -> Rout, C -> Rinv);
+// for k > 64 S is overwritten and no map is allowed.
 hipError_t launch_chol_inv(int k, zd *S, int64_t sS, zd *Rout, int64_t sR, zd *Rinv,
-                           int64_t sRi, int batch, int *status, double shift_rel,
-                           hipStream_t s);
+                           int64_t sRi, int batch, int *status, double *dratio,
+                           double shift_rel, hipStream_t s, const int *map = nullptr,
+                           int flags = 0);
+// C (m x k) += alpha * A (m x k); batched (map: A, C)
+hipError_t launch_add_block(int m, int k, zd alpha, const zd *A, int64_t lda, int64_t sA, zd *C,
+                            int64_t ldc, int64_t sC, int batch, hipStream_t s,
+                            const int *map = nullptr, int flags = 0);
+// dst (n x ncols) = src; batched (map: A -> src, C -> dst)
+hipError_t launch_copy_block(int64_t n, int ncols, const zd *src, int64_t lds, int64_t sS,
+                             zd *dst, int64_t ldd, int64_t sD, int batch, hipStream_t s,
+                             const int *map = nullptr, int flags = 0);
 hipError_t launch_copy_cols(int64_t n, int ncols, const zd *src, int64_t lds, zd *dst,
                             int64_t ldd, hipStream_t s);
 hipError_t launch_spmm(const DevCsr &M, int ncols, const zd *X, int64_t ldx, zd *Y,

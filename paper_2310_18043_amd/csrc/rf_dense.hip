@@ -9,11 +9,19 @@
 //     form one block column per step with Householder reflectors, giving the
 //     residual of every column and shift after each step;
 //   * CSR times block, column norms, start-block generation.
+//
+// Batched kernels take an optional index map: operand X of batch entry t lives at
+// base_X + (mapped_X ? map[t] : t) * stride_X.  The Krylov sub-blocks that are
+// still active are addressed this way without compacting their storage.
 #include "rf_common.h"
 
 namespace {
 
 constexpr int TM = 64, TN = 64, TK = 16, GT = 256;
+
+__device__ inline int64_t bidx(const int *map, int flags, int bit, int t) {
+    return (map && (flags & bit)) ? map[t] : t;
+}
 
 // ---------------------------------------------------------------------------
 // C_part[chunk] = A[rows of chunk]^H B[rows of chunk]   (tile 64 x 64 per WG)
@@ -22,10 +30,11 @@ constexpr int TM = 64, TN = 64, TK = 16, GT = 256;
 __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
     int64_t n, int m, int k, const zd *__restrict__ A, int64_t lda, int64_t sA,
     const zd *__restrict__ B, int64_t ldb, int64_t sB, zd *__restrict__ part, int nchunks,
-    int64_t chunk) {
+    int64_t chunk, const int *map, int flags) {
     const int bt = blockIdx.z / nchunks, ch = blockIdx.z % nchunks;
     const int m0 = blockIdx.x * TM, k0 = blockIdx.y * TN;
-    A += bt * sA; B += bt * sB;
+    A += bidx(map, flags, kMapA, bt) * sA;
+    B += bidx(map, flags, kMapB, bt) * sB;
     const int64_t r0 = int64_t(ch) * chunk;
     const int64_t r1 = min(n, r0 + chunk);
     __shared__ zd As[TK][TM + 1];
@@ -37,7 +46,6 @@ __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = zmake(0, 0);
     for (int64_t rr = r0; rr < r1; rr += TK) {
-        // load A[rr:rr+16, m0:m0+64] and B[rr:rr+16, k0:k0+64]
         for (int e = tid; e < TK * TM; e += GT) {
             int i = e % TK, c = e / TK;
             int64_t row = rr + i;
@@ -47,13 +55,13 @@ __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
         __syncthreads();
 #pragma unroll 4
         for (int i = 0; i < TK; ++i) {
-            zd a[4], b[4];
+            zd av[4], bv[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) { a[u] = As[i][ty + 16 * u]; b[u] = Bs[i][tx + 16 * u]; }
+            for (int u = 0; u < 4; ++u) { av[u] = As[i][ty + 16 * u]; bv[u] = Bs[i][tx + 16 * u]; }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) zfma_c(acc[u][v], a[u], b[v]);
+                for (int v = 0; v < 4; ++v) zfma_c(acc[u][v], av[u], bv[v]);
         }
         __syncthreads();
     }
@@ -69,7 +77,8 @@ __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
 
 // C = alpha * sum_chunks part + beta * C   (fixed summation order)
 __global__ void gemm_cn_reduce_kernel(int m, int k, const zd *part, int nchunks, zd alpha,
-                                      zd beta, zd *C, int64_t ldc, int64_t sC, int batch) {
+                                      zd beta, zd *C, int64_t ldc, int64_t sC, int batch,
+                                      const int *map, int flags) {
     int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     int64_t mk = int64_t(m) * k;
     if (e >= mk * batch) return;
@@ -79,7 +88,7 @@ __global__ void gemm_cn_reduce_kernel(int m, int k, const zd *part, int nchunks,
     const zd *P = part + int64_t(bt) * nchunks * mk + r;
     zd s = P[0];
     for (int c = 1; c < nchunks; ++c) s = zadd(s, P[int64_t(c) * mk]);
-    zd *cp = C + bt * sC + mi + int64_t(kj) * ldc;
+    zd *cp = C + bidx(map, flags, kMapC, bt) * sC + mi + int64_t(kj) * ldc;
     zd out = zmul(alpha, s);
     if (beta.x != 0.0 || beta.y != 0.0) zfma(out, beta, *cp);
     *cp = out;
@@ -92,11 +101,14 @@ __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd
                                                      const zd *__restrict__ A, int64_t lda,
                                                      int64_t sA, const zd *__restrict__ B,
                                                      int64_t ldb, int64_t sB, zd beta, zd *C,
-                                                     int64_t ldc, int64_t sC) {
+                                                     int64_t ldc, int64_t sC, const int *map,
+                                                     int flags) {
     const int bt = blockIdx.z;
     const int64_t n0 = int64_t(blockIdx.x) * TM;
     const int k0 = blockIdx.y * TN;
-    A += bt * sA; B += bt * sB; C += bt * sC;
+    A += bidx(map, flags, kMapA, bt) * sA;
+    B += bidx(map, flags, kMapB, bt) * sB;
+    C += bidx(map, flags, kMapC, bt) * sC;
     __shared__ zd As[TK][TM + 1];
     __shared__ zd Bs[TK][TN + 1];
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
@@ -116,13 +128,13 @@ __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd
         __syncthreads();
 #pragma unroll 4
         for (int i = 0; i < TK; ++i) {
-            zd a[4], b[4];
+            zd av[4], bv[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) { a[u] = As[i][ty + 16 * u]; b[u] = Bs[i][tx + 16 * u]; }
+            for (int u = 0; u < 4; ++u) { av[u] = As[i][ty + 16 * u]; bv[u] = Bs[i][tx + 16 * u]; }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) zfma(acc[u][v], a[u], b[v]);
+                for (int v = 0; v < 4; ++v) zfma(acc[u][v], av[u], bv[v]);
         }
         __syncthreads();
     }
@@ -143,14 +155,90 @@ __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky S = R^H R (R upper) of a batch of k x k Hermitian matrices, in place in
-// global memory (one workgroup each), then Rinv = R^{-1}.  The diagonal is raised by
-// shift_rel * max_i S_ii before factoring (shifted CholeskyQR).  status[b] = 1 + the
-// first column whose pivot is not positive.
+// Cholesky S = R^H R (R upper) of a batch of k x k Hermitian matrices (leading
+// dimension k), then Rinv = R^{-1}.  The diagonal is raised by shift_rel * max_i S_ii
+// before factoring (shifted CholeskyQR).  status[t] = 1 + the first column whose
+// pivot is not positive; dratio[t] = min_i R_ii / max_i R_ii (condition estimate).
+// LDS version (k <= 64): the whole matrix, its factor and its inverse stay in LDS.
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(GT) void chol_inv_lds_kernel(int k, const zd *S, int64_t sS,
+                                                          zd *Rout, int64_t sR, zd *Rinv,
+                                                          int64_t sRi, int *status,
+                                                          double *dratio, double shift_rel,
+                                                          const int *map, int flags) {
+    const int bt = blockIdx.x;
+    const zd *Sg = S + bidx(map, flags, kMapA, bt) * sS;
+    zd *Rg = Rout + bidx(map, flags, kMapB, bt) * sR;
+    zd *Rig = Rinv + bidx(map, flags, kMapC, bt) * sRi;
+    extern __shared__ unsigned char smem_raw[];
+    zd *L = reinterpret_cast<zd *>(smem_raw);      // [k][k] column-major lower factor
+    zd *X = L + k * k;                             // [k][k] inverse of L (lower)
+    __shared__ int bad;
+    __shared__ double shift;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < k * k; e += GT) L[e] = Sg[e];
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int i = 0; i < k; ++i) mx = fmax(mx, L[i + i * k].x);
+        shift = shift_rel * mx;
+    }
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        if (tid == 0) {
+            double d = L[j + j * k].x + shift;
+            if (!(d > 0.0)) { if (!bad) bad = j + 1; d = 1.0; }
+            L[j + j * k] = zmake(sqrt(d), 0.0);
+        }
+        __syncthreads();
+        const double inv = 1.0 / L[j + j * k].x;
+        for (int i = j + 1 + tid; i < k; i += GT) L[i + j * k] = zscale(L[i + j * k], inv);
+        __syncthreads();
+        const int rem = k - j - 1;
+        for (int e = tid; e < rem * rem; e += GT) {
+            int i = j + 1 + e % rem, l = j + 1 + e / rem;
+            if (l > i) continue;
+            zd v = L[i + l * k];
+            zd lij = L[i + j * k], llj = L[l + j * k];
+            v.x -= lij.x * llj.x + lij.y * llj.y;
+            v.y -= lij.y * llj.x - lij.x * llj.y;
+            if (i == l) v.y = 0.0;
+            L[i + l * k] = v;
+        }
+        __syncthreads();
+    }
+    // X = L^{-1} (lower), column c by thread group; forward substitution row by row
+    for (int e = tid; e < k * k; e += GT) X[e] = zmake(0, 0);
+    __syncthreads();
+    for (int r = 0; r < k; ++r) {
+        // X[r][c] = (delta_rc - sum_{q<r} L[r][q] X[q][c]) / L[r][r], c <= r
+        for (int c = tid; c <= r; c += GT) {
+            zd v = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
+            for (int q = c; q < r; ++q) zfms(v, L[r + q * k], X[q + c * k]);
+            X[r + c * k] = zscale(v, 1.0 / L[r + r * k].x);
+        }
+        __syncthreads();
+    }
+    // R = L^H (upper), Rinv = X^H
+    for (int e = tid; e < k * k; e += GT) {
+        int i = e % k, j = e / k;
+        Rg[e] = (i <= j) ? zconj(L[j + i * k]) : zmake(0, 0);
+        Rig[e] = (i <= j) ? zconj(X[j + i * k]) : zmake(0, 0);
+    }
+    if (tid == 0) {
+        double mn = 1e300, mx = 0.0;
+        for (int i = 0; i < k; ++i) { mn = fmin(mn, L[i + i * k].x); mx = fmax(mx, L[i + i * k].x); }
+        if (status) status[bt] = bad;
+        if (dratio) dratio[bt] = (mx > 0.0) ? mn / mx : 0.0;
+    }
+}
+
+// Global-memory version for k > 64 (one workgroup per matrix, S overwritten).
 __global__ __launch_bounds__(GT) void chol_inv_kernel(int k, zd *S, int64_t sS, zd *Rout,
                                                       int64_t sR, zd *Rinv, int64_t sRi,
-                                                      int *status, double shift_rel) {
+                                                      int *status, double *dratio,
+                                                      double shift_rel) {
     const int bt = blockIdx.x;
     zd *A = S + bt * sS;
     zd *R = Rout + bt * sR;
@@ -158,6 +246,7 @@ __global__ __launch_bounds__(GT) void chol_inv_kernel(int k, zd *S, int64_t sS, 
     const int tid = threadIdx.x;
     __shared__ int bad;
     __shared__ double shift;
+    __shared__ double djj;
     if (tid == 0) {
         bad = 0;
         double mx = 0.0;
@@ -165,9 +254,7 @@ __global__ __launch_bounds__(GT) void chol_inv_kernel(int k, zd *S, int64_t sS, 
         shift = shift_rel * mx;
     }
     __syncthreads();
-    // lower Cholesky: A = L L^H, L stored in the lower triangle
     for (int j = 0; j < k; ++j) {
-        __shared__ double djj;
         if (tid == 0) {
             double d = A[j + int64_t(j) * k].x + shift;
             if (!(d > 0.0)) { if (!bad) bad = j + 1; d = 1.0; }
@@ -177,7 +264,6 @@ __global__ __launch_bounds__(GT) void chol_inv_kernel(int k, zd *S, int64_t sS, 
         __syncthreads();
         for (int i = j + 1 + tid; i < k; i += GT) A[i + int64_t(j) * k] = zscale(A[i + int64_t(j) * k], 1.0 / djj);
         __syncthreads();
-        // trailing: A[i][l] -= L[i][j] conj(L[l][j]) for j < l <= i
         const int rem = k - j - 1;
         for (int e = tid; e < rem * rem; e += GT) {
             int i = j + 1 + e % rem, l = j + 1 + e / rem;
@@ -191,22 +277,57 @@ __global__ __launch_bounds__(GT) void chol_inv_kernel(int k, zd *S, int64_t sS, 
         }
         __syncthreads();
     }
-    // R = L^H (upper), Rinv = R^{-1} (one column per thread, back substitution)
     for (int e = tid; e < k * k; e += GT) {
         int i = e % k, j = e / k;
         R[i + int64_t(j) * k] = (i <= j) ? zconj(A[j + int64_t(i) * k]) : zmake(0, 0);
+        Ri[i + int64_t(j) * k] = zmake(0, 0);
     }
     __syncthreads();
-    for (int c = tid; c < k; c += GT) {
-        zd *x = Ri + int64_t(c) * k;
-        for (int r = c + 1; r < k; ++r) x[r] = zmake(0, 0);
-        for (int r = c; r >= 0; --r) {
+    // Rinv: row by row from the bottom, all columns in parallel
+    for (int r = k - 1; r >= 0; --r) {
+        for (int c = r + tid; c < k; c += GT) {
             zd v = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
-            for (int b2 = r + 1; b2 <= c; ++b2) zfms(v, R[r + int64_t(b2) * k], x[b2]);
-            x[r] = zdiv(v, R[r + int64_t(r) * k]);
+            for (int q = r + 1; q <= c; ++q) zfms(v, R[r + int64_t(q) * k], Ri[q + int64_t(c) * k]);
+            Ri[r + int64_t(c) * k] = zscale(v, 1.0 / R[r + int64_t(r) * k].x);
         }
+        __syncthreads();
     }
-    if (tid == 0 && status) status[bt] = bad;
+    if (tid == 0) {
+        double mn = 1e300, mx = 0.0;
+        for (int i = 0; i < k; ++i) { double d = R[i + int64_t(i) * k].x; mn = fmin(mn, d); mx = fmax(mx, d); }
+        if (status) status[bt] = bad;
+        if (dratio) dratio[bt] = (mx > 0.0) ? mn / mx : 0.0;
+    }
+}
+
+// C[map] (m x k block, ldc) += alpha * Aop (m x k, lda), batched
+__global__ void add_block_kernel(int m, int k, zd alpha, const zd *A, int64_t lda, int64_t sA,
+                                 zd *C, int64_t ldc, int64_t sC, int batch, const int *map,
+                                 int flags) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t mk = int64_t(m) * k;
+    if (e >= mk * batch) return;
+    int bt = int(e / mk);
+    int64_t r = e % mk;
+    int i = int(r % m), j = int(r / m);
+    const zd *ap = A + bidx(map, flags, kMapA, bt) * sA + i + int64_t(j) * lda;
+    zd *cp = C + bidx(map, flags, kMapC, bt) * sC + i + int64_t(j) * ldc;
+    zd v = *cp;
+    zfma(v, alpha, *ap);
+    *cp = v;
+}
+
+// dst[map] (n x ncols) = src[map]   (batched column-block copy)
+__global__ void copy_block_kernel(int64_t n, int ncols, const zd *src, int64_t lds, int64_t sS,
+                                  zd *dst, int64_t ldd, int64_t sD, int batch, const int *map,
+                                  int flags) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t per = n * ncols;
+    if (e >= per * batch) return;
+    int bt = int(e / per);
+    int64_t r = e % per;
+    int64_t i = r % n, c = r / n;
+    dst[bidx(map, flags, kMapC, bt) * sD + i + c * ldd] = src[bidx(map, flags, kMapA, bt) * sS + i + c * lds];
 }
 
 __global__ void copy_cols_kernel(int64_t n, int ncols, const zd *src, int64_t lds, zd *dst,
@@ -294,9 +415,10 @@ __global__ void gaussian_kernel(int64_t n, int ncols, zd *X, int64_t ldx, uint64
 // For shift s_l and sub-block sb, at block-Arnoldi step j the new block column
 // of H - s_l I~ (rows 0..(j+2)b) is rotated by the stored unitary blocks Q_0..Q_{j-1}
 // (each acting on two block rows), then a Householder QR of its bottom 2b x b block
-// gives R_jj and Q_j (stored explicitly, 2b x 2b).  The right-hand side
-// E1 R0 is rotated by Q_j^H; the norms of its last b rows are the residuals.
-// One workgroup per (shift, active sub-block).
+// gives R_jj and Q_j (stored explicitly, 2b x 2b).  The right-hand side E1 R0 is
+// rotated by Q_j^H; the norms of its last b rows are the residuals.
+// One workgroup per (shift, active sub-block); the column being rotated and each
+// Q_i are staged in LDS.
 // ---------------------------------------------------------------------------
 struct LsArgs {
     int b, mmax, j, nq;
@@ -311,6 +433,19 @@ struct LsArgs {
 
 __device__ inline int64_t ls_off(int l, int sb, int nsub, int64_t per) {
     return (int64_t(l) * nsub + sb) * per;
+}
+
+// out (2b x b, LDS) = Q^H (2b x 2b, LDS) * in (2b x b, LDS)
+__device__ inline void apply_qh(const zd *Qs, const zd *in, zd *out, int b) {
+    const int m2 = 2 * b;
+    for (int e = threadIdx.x; e < m2 * b; e += GT) {
+        int r = e % m2, c = e / m2;
+        zd acc = zmake(0, 0);
+        const zd *qc = Qs + r * m2;      // column r of Q (conjugated on use)
+        const zd *ic = in + c * m2;
+        for (int t = 0; t < m2; ++t) zfma_c(acc, qc[t], ic[t]);
+        out[r + c * m2] = acc;
+    }
 }
 
 __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
@@ -328,6 +463,13 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
     const zd *Hc = a.H + sb * a.sH + int64_t(j) * b * a.ldh;   // block column j
     const int tid = threadIdx.x;
     const int rows = (j + 2) * b;
+    const int m2 = 2 * b;
+
+    extern __shared__ unsigned char smem_raw[];
+    zd *Ql = reinterpret_cast<zd *>(smem_raw);            // [2b][2b]
+    zd *slab = Ql + m2 * m2;                              // [2b][b]
+    zd *slab2 = slab + m2 * b;                            // [2b][b]
+    zd *vv = slab2 + m2 * b;                              // [2b]
 
     // 1. copy the new column, subtract the shift on its diagonal block
     for (int e = tid; e < rows * b; e += GT) {
@@ -337,107 +479,107 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
         col[r + int64_t(c) * ldc] = v;
     }
     __syncthreads();
-    // 2. apply Q_i^H, i < j, to rows [ib, (i+2)b)
-    extern __shared__ unsigned char smem_raw[];
-    zd *slab = reinterpret_cast<zd *>(smem_raw);          // [2b][b]
+    // 2. apply Q_i^H, i < j, to rows [ib, (i+2)b); rows i*b..(i+1)*b are final after step i
+    if (j > 0) {
+        for (int e = tid; e < m2 * b; e += GT) {
+            int r = e % m2, c = e / m2;
+            slab[r + c * m2] = col[r + int64_t(c) * ldc];
+        }
+    }
     for (int i = 0; i < j; ++i) {
-        const zd *Qi = Qs + int64_t(i) * qsz;             // 2b x 2b, ld 2b
-        for (int e = tid; e < 2 * b * b; e += GT) {
-            int r = e % (2 * b), c = e / (2 * b);
-            slab[r + c * 2 * b] = col[i * b + r + int64_t(c) * ldc];
-        }
+        const zd *Qi = Qs + int64_t(i) * qsz;
+        for (int e = tid; e < m2 * m2; e += GT) Ql[e] = Qi[e];
         __syncthreads();
-        for (int e = tid; e < 2 * b * b; e += GT) {
-            int r = e % (2 * b), c = e / (2 * b);
-            zd acc = zmake(0, 0);
-            for (int t = 0; t < 2 * b; ++t) zfma_c(acc, Qi[t + int64_t(r) * 2 * b], slab[t + c * 2 * b]);
-            col[i * b + r + int64_t(c) * ldc] = acc;
+        apply_qh(Ql, slab, slab2, b);
+        __syncthreads();
+        // top b rows are final: store; bottom b rows move up, next block row comes in
+        for (int e = tid; e < b * b; e += GT) {
+            int r = e % b, c = e / b;
+            col[i * b + r + int64_t(c) * ldc] = slab2[r + c * m2];
+            slab[r + c * m2] = slab2[b + r + c * m2];
+            slab[b + r + c * m2] = col[(i + 2) * b + r + int64_t(c) * ldc];
         }
         __syncthreads();
     }
-    // 3. Householder QR of the bottom 2b x b block (in LDS), accumulating Q_j
-    for (int e = tid; e < 2 * b * b; e += GT) {
-        int r = e % (2 * b), c = e / (2 * b);
-        slab[r + c * 2 * b] = col[j * b + r + int64_t(c) * ldc];
+    // 3. Householder QR of the bottom 2b x b block (in LDS), accumulating Q_j in LDS
+    if (j == 0) {
+        for (int e = tid; e < m2 * b; e += GT) {
+            int r = e % m2, c = e / m2;
+            slab[r + c * m2] = col[r + int64_t(c) * ldc];
+        }
     }
-    zd *Qj = Qs + int64_t(j) * qsz;
-    zd *vv = slab + 2 * b * b;                            // [2b] reflector
-    __shared__ double s_norm2, s_beta;
+    for (int e = tid; e < m2 * m2; e += GT) {
+        int r = e % m2, c = e / m2;
+        Ql[e] = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
+    }
+    __shared__ double s_beta;
     __shared__ zd s_alpha;
-    // Qj starts as identity; we accumulate Qj = H_0 H_1 ... H_{b-1} by right-multiplying
-    for (int e = tid; e < 4 * b * b; e += GT) {
-        int r = e % (2 * b), c = e / (2 * b);
-        Qj[e] = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
-    }
     __syncthreads();
     for (int c = 0; c < b; ++c) {
-        // norm of slab[c:, c]
         if (tid == 0) {
             double nrm2 = 0.0;
-            for (int r = c; r < 2 * b; ++r) nrm2 += zabs2(slab[r + c * 2 * b]);
-            s_norm2 = nrm2;
-            zd x0 = slab[c + c * 2 * b];
+            for (int r = c; r < m2; ++r) nrm2 += zabs2(slab[r + c * m2]);
+            zd x0 = slab[c + c * m2];
             double ax0 = sqrt(zabs2(x0));
             double nrm = sqrt(nrm2);
             zd ph = (ax0 > 0.0) ? zscale(x0, 1.0 / ax0) : zmake(1.0, 0.0);
             s_alpha = zscale(ph, -nrm);                   // alpha = -phase(x0) ||x||
-            // v = x - alpha e1 ; v^H v = 2 ||x|| (||x|| + |x0|)
-            s_beta = (nrm > 0.0) ? 2.0 * nrm * (nrm + ax0) : 0.0;
+            s_beta = (nrm > 0.0) ? 2.0 * nrm * (nrm + ax0) : 0.0;   // v^H v
         }
         __syncthreads();
-        for (int r = tid; r < 2 * b; r += GT) {
-            zd v = (r < c) ? zmake(0, 0) : slab[r + c * 2 * b];
+        for (int r = tid; r < m2; r += GT) {
+            zd v = (r < c) ? zmake(0, 0) : slab[r + c * m2];
             if (r == c) v = zsub(v, s_alpha);
             vv[r] = v;
         }
         __syncthreads();
         const double inv2 = (s_beta > 0.0) ? 2.0 / s_beta : 0.0;
-        // apply H = I - inv2 v v^H to slab columns c..b-1 (column c becomes alpha e_c)
+        // H = I - inv2 v v^H on slab columns c..b-1
         for (int cc = c + tid; cc < b; cc += GT) {
             zd dot = zmake(0, 0);
-            for (int r = c; r < 2 * b; ++r) zfma_c(dot, vv[r], slab[r + cc * 2 * b]);
+            for (int r = c; r < m2; ++r) zfma_c(dot, vv[r], slab[r + cc * m2]);
             dot = zscale(dot, inv2);
-            for (int r = c; r < 2 * b; ++r) zfms(slab[r + cc * 2 * b], vv[r], dot);
+            for (int r = c; r < m2; ++r) zfms(slab[r + cc * m2], vv[r], dot);
         }
-        // Qj <- Qj H  : rows of Qj, each row: Qj[row, :] -= inv2 (Qj[row,:] v) v^H
-        for (int row = tid; row < 2 * b; row += GT) {
+        // Qj <- Qj H (rows of Qj)
+        for (int row = tid; row < m2; row += GT) {
             zd dot = zmake(0, 0);
-            for (int r = c; r < 2 * b; ++r) zfma(dot, Qj[row + int64_t(r) * 2 * b], vv[r]);
+            for (int r = c; r < m2; ++r) zfma(dot, Ql[row + r * m2], vv[r]);
             dot = zscale(dot, inv2);
-            for (int r = c; r < 2 * b; ++r) {
-                zd q = Qj[row + int64_t(r) * 2 * b];
+            for (int r = c; r < m2; ++r) {
+                zd q = Ql[row + r * m2];
                 zfms(q, dot, zconj(vv[r]));
-                Qj[row + int64_t(r) * 2 * b] = q;
+                Ql[row + r * m2] = q;
             }
         }
         __syncthreads();
     }
+    zd *Qj = Qs + int64_t(j) * qsz;
+    for (int e = tid; e < m2 * m2; e += GT) Qj[e] = Ql[e];
     // 4. R block column: rows 0..jb from col, then R_jj from slab
     for (int e = tid; e < (j + 1) * b * b; e += GT) {
         int r = e % ((j + 1) * b), c = e / ((j + 1) * b);
         zd v;
         if (r < j * b) v = col[r + int64_t(c) * ldc];
-        else { int rr = r - j * b; v = (rr <= c) ? slab[rr + c * 2 * b] : zmake(0, 0); }
+        else { int rr = r - j * b; v = (rr <= c) ? slab[rr + c * m2] : zmake(0, 0); }
         R[r + int64_t(j * b + c) * ldr] = v;
     }
-    __syncthreads();
     // 5. rotate the right-hand side rows [jb, (j+2)b) by Q_j^H
-    for (int e = tid; e < 2 * b * b; e += GT) {
-        int r = e % (2 * b), c = e / (2 * b);
-        slab[r + c * 2 * b] = G[j * b + r + int64_t(c) * ldc];
+    for (int e = tid; e < m2 * b; e += GT) {
+        int r = e % m2, c = e / m2;
+        slab2[r + c * m2] = G[j * b + r + int64_t(c) * ldc];
     }
     __syncthreads();
-    for (int e = tid; e < 2 * b * b; e += GT) {
-        int r = e % (2 * b), c = e / (2 * b);
-        zd acc = zmake(0, 0);
-        for (int t = 0; t < 2 * b; ++t) zfma_c(acc, Qj[t + int64_t(r) * 2 * b], slab[t + c * 2 * b]);
-        G[j * b + r + int64_t(c) * ldc] = acc;
-    }
+    apply_qh(Ql, slab2, slab, b);
     __syncthreads();
+    for (int e = tid; e < m2 * b; e += GT) {
+        int r = e % m2, c = e / m2;
+        G[j * b + r + int64_t(c) * ldc] = slab[r + c * m2];
+    }
     // 6. residual of every column: norm of rows [(j+1)b, (j+2)b)
     for (int c = tid; c < b; c += GT) {
         double s2 = 0.0;
-        for (int r = 0; r < b; ++r) s2 += zabs2(G[(j + 1) * b + r + int64_t(c) * ldc]);
+        for (int r = 0; r < b; ++r) s2 += zabs2(slab[b + r + c * m2]);
         double den = a.r0norm[sb * b + c];
         a.resid[(int64_t(l) * nsub + sb) * b + c] = (den > 0.0) ? sqrt(s2) / den : 0.0;
     }
@@ -451,29 +593,43 @@ struct LsSolveArgs {
     const int *active;
 };
 
+// Blocked by b rows: Y_I = R_II^{-1} (G_I - sum_{J > I} R_IJ Y_J), with R_II solved by
+// substitution in LDS.
 __global__ __launch_bounds__(GT) void ls_solve_kernel(LsSolveArgs a) {
     const int l = blockIdx.x;
     const int sb = a.active[blockIdx.y];
     const int b = a.b, mmax = a.mmax, m = a.m;
-    const int ldr = mmax * b, ldc = (mmax + 1) * b, mb = m * b;
+    const int ldr = mmax * b, ldc = (mmax + 1) * b;
     const zd *R = a.R + ls_off(l, sb, a.nsub, int64_t(mmax) * b * mmax * b);
     const zd *G = a.G + ls_off(l, sb, a.nsub, int64_t(ldc) * b);
     zd *Y = a.Y + ls_off(l, sb, a.nsub, int64_t(mmax) * b * b);      // ld mmax*b
     const int tid = threadIdx.x;
-    // thread layout: column c = tid % b, part = tid / b (parts split the dot product)
-    const int parts = GT / b;
-    const int c = tid % b, part = tid / b;
     extern __shared__ unsigned char smem_raw[];
-    zd *red = reinterpret_cast<zd *>(smem_raw);          // [GT]
-    for (int r = mb - 1; r >= 0; --r) {
-        zd acc = zmake(0, 0);
-        for (int t = r + 1 + part; t < mb; t += parts) zfma(acc, R[r + int64_t(t) * ldr], Y[t + int64_t(c) * ldr]);
-        red[tid] = acc;
+    zd *T = reinterpret_cast<zd *>(smem_raw);             // [b][b] right-hand side block
+    zd *D = T + b * b;                                    // [b][b] diagonal block of R
+    for (int I = m - 1; I >= 0; --I) {
+        const int r0 = I * b;
+        // T = G_I - sum_{J>I} R_IJ Y_J
+        for (int e = tid; e < b * b; e += GT) {
+            int r = e % b, c = e / b;
+            zd v = G[r0 + r + int64_t(c) * ldc];
+            for (int t = r0 + b; t < m * b; ++t) zfms(v, R[r0 + r + int64_t(t) * ldr], Y[t + int64_t(c) * ldr]);
+            T[r + c * b] = v;
+            D[r + c * b] = R[r0 + r + int64_t(r0 + c) * ldr];
+        }
         __syncthreads();
-        if (part == 0) {
-            zd s = G[r + int64_t(c) * ldc];
-            for (int q = 0; q < parts; ++q) s = zsub(s, red[q * b + c]);
-            Y[r + int64_t(c) * ldr] = zdiv(s, R[r + int64_t(r) * ldr]);
+        // back substitution with the upper triangular D, one column per thread
+        for (int c = tid; c < b; c += GT) {
+            for (int r = b - 1; r >= 0; --r) {
+                zd v = T[r + c * b];
+                for (int q = r + 1; q < b; ++q) zfms(v, D[r + q * b], T[q + c * b]);
+                T[r + c * b] = zdiv(v, D[r + r * b]);
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < b * b; e += GT) {
+            int r = e % b, c = e / b;
+            Y[r0 + r + int64_t(c) * ldr] = T[r + c * b];
         }
         __syncthreads();
     }
@@ -504,7 +660,7 @@ __global__ void ls_combine_kernel(int b, int mmax, int m, int nq, int nsub, cons
 hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_t lda,
                           int64_t sA, const zd *B, int64_t ldb, int64_t sB, zd beta, zd *C,
                           int64_t ldc, int64_t sC, int batch, zd *work, int64_t work_elems,
-                          hipStream_t s) {
+                          hipStream_t s, const int *map, int flags) {
     if (n <= 0 || m <= 0 || k <= 0 || batch <= 0) return hipSuccess;
     const int tiles = ((m + TM - 1) / TM) * ((k + TN - 1) / TN) * batch;
     int nchunks = int((1024 + tiles - 1) / tiles);          // aim for ~1024 workgroups
@@ -518,28 +674,56 @@ hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_
     nchunks = int((n + chunk - 1) / chunk);
     dim3 grid((m + TM - 1) / TM, (k + TN - 1) / TN, batch * nchunks);
     hipLaunchKernelGGL(gemm_cn_partial_kernel, grid, dim3(GT), 0, s, n, m, k, A, lda, sA, B, ldb,
-                       sB, work, nchunks, chunk);
+                       sB, work, nchunks, chunk, map, flags);
     int64_t tot = int64_t(m) * k * batch;
     hipLaunchKernelGGL(gemm_cn_reduce_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, m, k,
-                       work, nchunks, alpha, beta, C, ldc, sC, batch);
+                       work, nchunks, alpha, beta, C, ldc, sC, batch, map, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm_nn(int64_t n, int m, int k, zd alpha, const zd *A, int64_t lda,
                           int64_t sA, const zd *B, int64_t ldb, int64_t sB, zd beta, zd *C,
-                          int64_t ldc, int64_t sC, int batch, hipStream_t s) {
+                          int64_t ldc, int64_t sC, int batch, hipStream_t s, const int *map,
+                          int flags) {
     if (n <= 0 || k <= 0 || batch <= 0) return hipSuccess;
     dim3 grid(unsigned((n + TM - 1) / TM), (k + TN - 1) / TN, batch);
     hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(GT), 0, s, n, m, k, alpha, A, lda, sA, B, ldb,
-                       sB, beta, C, ldc, sC);
+                       sB, beta, C, ldc, sC, map, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_chol_inv(int k, zd *S, int64_t sS, zd *Rout, int64_t sR, zd *Rinv,
-                           int64_t sRi, int batch, int *status, double shift_rel,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(batch), dim3(GT), 0, s, k, S, sS, Rout, sR, Rinv,
-                       sRi, status, shift_rel);
+                           int64_t sRi, int batch, int *status, double *dratio, double shift_rel,
+                           hipStream_t s, const int *map, int flags) {
+    if (batch <= 0) return hipSuccess;
+    if (k <= 64) {
+        hipLaunchKernelGGL(chol_inv_lds_kernel, dim3(batch), dim3(GT), size_t(2) * k * k * sizeof(zd),
+                           s, k, S, sS, Rout, sR, Rinv, sRi, status, dratio, shift_rel, map, flags);
+    } else {
+        if (map) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(chol_inv_kernel, dim3(batch), dim3(GT), 0, s, k, S, sS, Rout, sR, Rinv,
+                           sRi, status, dratio, shift_rel);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_add_block(int m, int k, zd alpha, const zd *A, int64_t lda, int64_t sA, zd *C,
+                            int64_t ldc, int64_t sC, int batch, hipStream_t s, const int *map,
+                            int flags) {
+    int64_t tot = int64_t(m) * k * batch;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(add_block_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, m, k, alpha, A,
+                       lda, sA, C, ldc, sC, batch, map, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_block(int64_t n, int ncols, const zd *src, int64_t lds, int64_t sS,
+                             zd *dst, int64_t ldd, int64_t sD, int batch, hipStream_t s,
+                             const int *map, int flags) {
+    int64_t tot = n * ncols * batch;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_block_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, n, ncols, src,
+                       lds, sS, dst, ldd, sD, batch, map, flags);
     return hipGetLastError();
 }
 
@@ -603,7 +787,8 @@ hipError_t launch_ls_update(const rf_plan &P, int j, const int *active, int nact
     a.H = P.Hm; a.ldh = int64_t(P.mmax + 1) * P.b; a.sH = a.ldh * int64_t(P.mmax) * P.b;
     a.Q = P.lsQ; a.R = P.lsR; a.G = P.lsG; a.work = P.lsWork;
     a.resid = P.resid; a.r0norm = P.r0norm; a.active = active;
-    size_t sm = (size_t(2) * P.b * P.b + 2 * P.b) * sizeof(zd);
+    const int b = P.b;
+    size_t sm = (size_t(4) * b * b + 4 * b * b + 2 * b) * sizeof(zd);
     hipLaunchKernelGGL(ls_update_kernel, dim3(a.nq, nact), dim3(GT), sm, s, a);
     return hipGetLastError();
 }
@@ -613,7 +798,8 @@ hipError_t launch_ls_solve(const rf_plan &P, int m, const int *active, int nact,
     LsSolveArgs a;
     a.b = P.b; a.mmax = P.mmax; a.m = m; a.nq = int(P.shifts.size()); a.nsub = P.nsub;
     a.R = P.lsR; a.G = P.lsG; a.Y = P.lsY; a.active = active;
-    hipLaunchKernelGGL(ls_solve_kernel, dim3(a.nq, nact), dim3(GT), GT * sizeof(zd), s, a);
+    hipLaunchKernelGGL(ls_solve_kernel, dim3(a.nq, nact), dim3(GT),
+                       size_t(2) * P.b * P.b * sizeof(zd), s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int64_t tot = int64_t(m) * P.b * P.b * nact;

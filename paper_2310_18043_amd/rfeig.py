@@ -61,7 +61,17 @@ class RfResult(ctypes.Structure):
                 ("ms_filter", ctypes.c_double), ("ms_hsrr", ctypes.c_double)]
 
 
+class RfKernelStats(ctypes.Structure):
+    _fields_ = [("solve_launches", ctypes.c_int64), ("solve_columns", ctypes.c_int64),
+                ("solve_ms", ctypes.c_double), ("factor_launches", ctypes.c_int64),
+                ("factor_ms", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
+_lib.rf_profile_enable.argtypes = [_P, ctypes.c_int32]
+_lib.rf_profile_enable.restype = ctypes.c_int
+_lib.rf_profile_read.argtypes = [_P, ctypes.POINTER(RfKernelStats)]
+_lib.rf_profile_read.restype = ctypes.c_int
 _lib.rf_default_opts.argtypes = [ctypes.POINTER(RfOpts)]
 _lib.rf_default_opts.restype = None
 _lib.rf_plan_create.argtypes = [ctypes.POINTER(RfCsr), ctypes.POINTER(RfCsr),
@@ -202,6 +212,14 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def profile_enable(self, on: bool = True):
+        self._check(_lib.rf_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        st = RfKernelStats()
+        self._check(_lib.rf_profile_read(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in RfKernelStats._fields_}
 
     # -- the four calls -------------------------------------------------------
     def factor_shifts(self):

@@ -29,6 +29,8 @@ def main():
     res = solver.solve_region(wl.A, wl.B, wl.c, wl.r, wl.p, wl.q, Y0, tau=1e-10,
                               gmres_tol=1e-12, s_expected=wl.s_expected)
     dt = time.time() - t0
+    # G applications (vectors): n_col for G(Y) plus one per Arnoldi step per column
+    apps = [int(wl.w + it.sum()) for it in res.gmres_iters]
     order = np.argsort(res.lam.real)
     out = os.path.join(HERE, "convdiff128_eigs.txt")
     with open(out, "w") as f:
@@ -36,7 +38,8 @@ def main():
         f.write(f"# 128x128 convection-diffusion workload: c={wl.c}, r={wl.r!r}, p={wl.p}, "
                 f"q={wl.q}, w={wl.w}, seed={wl.seed}\n")
         f.write(f"# sweeps={res.sweeps} converged={res.converged} seconds={dt:.0f} "
-                f"gmres_steps_max={[int(i.max()) for i in res.gmres_iters]}\n")
+                f"gmres_steps_max={[int(i.max()) for i in res.gmres_iters]} "
+                f"inner_applications={apps}\n")
         f.write("# re im rel_error\n")
         for k in order:
             f.write(f"{res.lam[k].real!r} {res.lam[k].imag!r} {res.err[k]!r}\n")

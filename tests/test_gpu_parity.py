@@ -172,3 +172,27 @@ def test_solve_region_small_convdiff_vs_oracle(rf, torch_cuda):
     # residuals re-evaluated by the oracle's definition on the returned vectors
     e = hsrr.rel_errors(A, B, res["lam"], _to_host(res["X"]), c, r)
     assert e.max() <= 1e-10
+
+
+@pytest.mark.parametrize("subblock", [8, 16])
+def test_filter_apply_on_converged_ritz_vectors(rf, torch_cuda, subblock):
+    # After solve_region the Ritz block is nearly invariant; the outer solves must
+    # still converge and the filter must still match the simple rule.
+    from oracle import filters
+    n = 24
+    A, B = W.convdiff_pencil(n, mass=(0.5, 1.5), seed=3)
+    import scipy.linalg as sl
+    lam = sl.eigvals(A.toarray(), B.toarray())
+    c = np.sort(lam.real)[200] + 0.05j
+    r = W.midgap_radius(lam, c, 24)
+    _say(f"filter on ritz vectors subblock={subblock}")
+    plan = rf.Plan(A, B, c, r, p=4, q=8, w=32, subblock=subblock, gmres_tol=1e-12,
+                   max_krylov_blocks=60, expected_count=24)
+    res = plan.solve_region(torch_cuda.from_numpy(W.start_block(n * n, 32, 0)).cuda())
+    Xr = res["all_X"]
+    U, info = plan.filter_apply(Xr, allow_noconv=True)
+    ref = filters.simple_filter(A, B, c, r, 32, _to_host(Xr))
+    print("krylov steps", info["krylov_steps"], "max residual", info["max_residual"],
+          "relerr", _relerr(_to_host(U), ref))
+    assert info["converged"], info
+    assert _relerr(_to_host(U), ref) <= 1e-10
