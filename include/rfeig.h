@@ -156,6 +156,16 @@ rf_status rf_profile_enable(rf_plan_t plan, int32_t on);
  * the plan stream. */
 rf_status rf_profile_read(rf_plan_t plan, rf_kernel_stats *out);
 
+/* Generalized eigenvalues and right eigenvectors of a small dense pencil (A, B),
+ * the "qz" step of HSRR (Sec. 2.1): complex QZ to the generalized Schur form,
+ * then back-substitution on the triangular pencil and back-transformation.
+ * Host memory: A, B are n x n column-major complex128 (2 n^2 doubles each, not
+ * modified); alpha, beta get n complex values with lambda_i = alpha_i / beta_i;
+ * vr gets n unit-2-norm eigenvectors (columns, n x n complex128).  Runs on the
+ * CPU only.  Returns 0, or -1 if the QZ iteration did not converge. */
+int rf_dense_eig(int32_t n, const double *A, const double *B, double *alpha, double *beta,
+                 double *vr);
+
 /* Problem size n of a plan, or -1. */
 int64_t rf_plan_n(rf_plan_t plan);
 

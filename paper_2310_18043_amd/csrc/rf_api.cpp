@@ -258,6 +258,8 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     ALLOC(P->F.perm, int64_t(o.p) * P->F.nblk * 2 * nb);
     ALLOC(P->F.window, int64_t(o.p) * 2 * (2 * nb) * (3 * nb));   // double-buffered per pole
     ALLOC(P->F.info, o.p);
+    ALLOC(P->F.rows, int64_t(o.p) * P->F.nblk * te * 3);
+    ALLOC(P->F.subperm, int64_t(o.p) * 2 * nb);
     const int64_t n = P->n, w = o.w;
     ALLOC(P->rhs, npad * w);
     ALLOC(P->ypart, int64_t(o.p) * npad * w);

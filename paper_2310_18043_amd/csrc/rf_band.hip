@@ -35,7 +35,9 @@ struct FactorArgs {
     const zd *poles;
     zd *tiles;          // [pole][k][5][nb*nb]
     int32_t *perm;      // [pole][k][2nb]
-    zd *window;         // [pole][2nb x 3nb], ld 2nb
+    zd *window;         // [pole][2][2nb x 3nb], ld 2nb (double-buffered)
+    zd *rows;           // [pole][nblk][nb x 3nb], ld nb: prepared row blocks
+    int32_t *subperm;   // [pole][2nb]: row order of the current sub-panel
     int32_t *info;      // [pole]
 };
 
@@ -74,290 +76,386 @@ __device__ void scatter_rows(const FactorArgs &a, zd z, zd *W, int ldw, int h, i
     }
 }
 
-// The factorization runs as a sequence of launches per block step k, all p poles
-// at once:
-//   band_panel_kernel  (one workgroup per pole): LU with partial pivoting of the
-//       2nb x nb panel (column block k of the window), chunk by chunk in LDS;
-//       stores the row permutation, the packed L11 \ U11 block and L21;
-//   band_update_kernel (2nb/CPW workgroups per pole, CPW columns each): applies
-//       the permutation to the U part of the window (column blocks k+1, k+2),
-//       U_top = L11^{-1} (top rows) by blocked substitution in LDS, bottom rows
-//       minus L21 U_top, stores U1/U2 and writes the updated bottom rows into the
-//       next window; workgroup 0 of each pole also loads the next row block.
-// Kernel boundaries order the steps, so no workgroup ever waits on another.
-// The window of each pole is double-buffered (current / next).
-
 __device__ inline zd *pole_window(zd *base, int pole, int buf, int nb) {
     return base + (int64_t(pole) * 2 + buf) * (2 * nb) * (3 * nb);
 }
 
-// zero window rows [h*nb, h*nb+nb) and load row block rb of K = z B - A into them
-__device__ void load_row_block(const FactorArgs &a, zd z, zd *W, int h, int rb, int cbase) {
-    const int nb = a.nb, ldw = 2 * nb;
-    for (int e = threadIdx.x; e < nb * 3 * nb; e += blockDim.x) {
-        int r = e % nb, c = e / nb;
-        W[h * nb + r + int64_t(c) * ldw] = zmake(0, 0);
-    }
+// Row block rb of K = z B - A for every pole, prepared once per factorization:
+// nb x 3nb, column-major (ld nb), column 0 = global column (rb - 1) nb.
+// grid: (nblk, p)
+__global__ __launch_bounds__(256) void rowblock_prep_kernel(FactorArgs a) {
+    const int rb = blockIdx.x, pole = blockIdx.y;
+    const int nb = a.nb;
+    const int64_t tot = int64_t(nb) * 3 * nb;
+    zd *Pb = a.rows + (int64_t(pole) * a.nblk + rb) * tot;
+    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) Pb[e] = zmake(0, 0);
     __syncthreads();
-    scatter_rows(a, z, W, ldw, h, rb, cbase);
-    __syncthreads();
+    scatter_rows(a, a.poles[pole], Pb, nb, 0, rb, (rb - 1) * nb);
 }
 
+// First window of every pole: row blocks 0 and 1, window column 0 = global column 0.
 __global__ __launch_bounds__(256) void band_window_init_kernel(FactorArgs a) {
     const int pole = blockIdx.x;
-    zd *W = pole_window(a.window, pole, 0, a.nb);
-    const zd z = a.poles[pole];
-    load_row_block(a, z, W, 0, 0, 0);
-    if (a.nblk > 1) load_row_block(a, z, W, 1, 1, 0);
-    else {
-        for (int e = threadIdx.x; e < a.nb * 3 * a.nb; e += blockDim.x) {
-            int r = e % a.nb, c = e / a.nb;
-            W[a.nb + r + int64_t(c) * 2 * a.nb] = zmake(0, 0);
-        }
+    const int nb = a.nb, ldw = 2 * nb;
+    zd *W = pole_window(a.window, pole, 0, nb);
+    const int64_t tot = int64_t(nb) * 3 * nb;
+    const zd *P0 = a.rows + int64_t(pole) * a.nblk * tot;
+    const zd *P1 = P0 + tot;
+    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+        int r = int(e % nb), c = int(e / nb);
+        // row block 0 is stored from global column -nb
+        W[r + int64_t(c) * ldw] = (c < 2 * nb) ? P0[r + int64_t(c + nb) * nb] : zmake(0, 0);
+        W[nb + r + int64_t(c) * ldw] = (a.nblk > 1) ? P1[e] : zmake(0, 0);
     }
     if (threadIdx.x == 0) a.info[pole] = 0;
 }
 
-template <int NC>
-__global__ __launch_bounds__(kThreads) void band_panel_kernel(FactorArgs a, int k, int buf) {
-    const int pole = blockIdx.x;
-    const int nb = a.nb, nblk = a.nblk;
-    const int ldw = 2 * nb;
-    const int64_t te = int64_t(nb) * nb;
-    zd *W = pole_window(a.window, pole, buf, nb);
-    const int tid = threadIdx.x;
-    extern __shared__ unsigned char smem_raw[];
-    zd *C = reinterpret_cast<zd *>(smem_raw);                    // [2nb][NC], row-major
-    zd *U12 = C + 2 * nb * NC;                                   // [NC][nb]
-    int *pivrow = reinterpret_cast<int *>(U12 + NC * nb);        // [nb]
-    int *srcrow = pivrow + nb;                                   // [2 NC]
-    int *dstrow = srcrow + 2 * NC;                               // [2 NC]
-    double *redv = reinterpret_cast<double *>(dstrow + 2 * NC);  // [kThreads/64]
-    int *redi = reinterpret_cast<int *>(redv + kThreads / 64);   // [kThreads/64]
-    __shared__ int s_info, s_nmoved;
-    if (tid == 0) s_info = 0;
-    const int rows = (k + 1 < nblk) ? 2 * nb : nb;
-    for (int jc = 0; jc < nb; jc += NC) {
-        for (int e = tid; e < rows * NC; e += kThreads) {
-            int r = e % rows, cc = e / rows;
-            C[r * NC + cc] = W[r + int64_t(jc + cc) * ldw];
-        }
-        __syncthreads();
-        // ---- unblocked LU with partial pivoting of the chunk, in LDS
-        for (int cc = 0; cc < NC; ++cc) {
-            const int j = jc + cc;
-            double best = -1.0; int bi = j;
-            for (int r = j + tid; r < rows; r += kThreads) {
-                double v = zabs2(C[r * NC + cc]);
-                if (v > best) { best = v; bi = r; }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                double ov = __shfl_down(best, off, 64);
-                int oi = __shfl_down(bi, off, 64);
-                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-            }
-            if ((tid & 63) == 0) { redv[tid >> 6] = best; redi[tid >> 6] = bi; }
-            __syncthreads();
-            if (tid == 0) {
-                double bv = redv[0]; int bidx = redi[0];
-                for (int wv = 1; wv < kThreads / 64; ++wv)
-                    if (redv[wv] > bv || (redv[wv] == bv && redi[wv] < bidx)) { bv = redv[wv]; bidx = redi[wv]; }
-                if (!(bv > 0.0)) { if (s_info == 0) s_info = k * nb + j + 1; bidx = j; }
-                pivrow[j] = bidx;
-            }
-            __syncthreads();
-            const int pr = pivrow[j];
-            if (pr != j && tid < NC) {
-                zd t = C[j * NC + tid]; C[j * NC + tid] = C[pr * NC + tid]; C[pr * NC + tid] = t;
-            }
-            __syncthreads();
-            const zd piv = C[j * NC + cc];
-            const zd inv = (zabs2(piv) > 0.0) ? zdiv(zmake(1.0, 0.0), piv) : zmake(0, 0);
-            for (int r = j + 1 + tid; r < rows; r += kThreads) {
-                zd l = zmul(C[r * NC + cc], inv);
-                C[r * NC + cc] = l;
+// The factorization of block step k runs as nb/SW sub-steps of SW columns
+// (right-looking, blocked), each one pair of launches for all p poles:
+//   band_panel_kernel (one workgroup per pole): LU with partial pivoting of the
+//       R x SW sub-panel (window columns c0..c0+SW-1) held in registers, column c
+//       owned by wave c % 8, rows spread over the lanes (NS per lane).  The owner
+//       of column j+1 applies pivot step j to it first and finds the next pivot at
+//       once, so each column costs one barrier.  Writes the sub-panel back, its
+//       row permutation (subperm) and the running permutation of the block step.
+//   band_trail_kernel (one wave per window column, many workgroups per pole):
+//       columns right of the sub-panel: gather in the sub-panel's row order, solve
+//       with its unit lower SW x SW block, subtract L * U from the rows below;
+//       columns left of it: apply the permutation.  The last sub-step writes the
+//       tiles (packed L11\U11, L21, U1, U2), the top half of the next window, and
+//       copies the prepared row block k+2 into its bottom half.
+// Kernel boundaries order the sub-steps, so no workgroup ever waits on another.
+constexpr int kFacThreads = 512;
+constexpr int kFacWaves = kFacThreads / 64;
+
+// lane ln's value of x (ln wave-uniform); readlane moves 32 bits at a time
+__device__ inline double dlane_get(double x, int ln) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), ln);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), ln);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline zd lane_get(zd x, int ln) {
+    return zmake(dlane_get(x.x, ln), dlane_get(x.y, ln));
+}
+
+// value of row `row` (wave-uniform) of a column spread as v[s] = row lane + 64 s
+// (every slot is read out with readlane and the slot chosen among the results, so
+// the register array is never indexed dynamically)
+template <int NS>
+__device__ inline zd row_get(const zd (&v)[NS], int row) {
+    const int sl = row >> 6, ln = row & 63;
+    zd x = lane_get(v[0], ln);
 #pragma unroll
-                for (int c2 = 0; c2 < NC; ++c2)
-                    if (c2 > cc) zfms(C[r * NC + c2], l, C[j * NC + c2]);
-            }
-            __syncthreads();
-        }
-        // ---- the chunk's interchanges as one permutation of at most 2 NC rows
-        if (tid == 0) {
-            int m = 0;
-            for (int cc = 0; cc < NC; ++cc) {
-                int j = jc + cc, pr = pivrow[j];
-                bool hj = false, hp = false;
-                for (int q = 0; q < m; ++q) { hj |= (dstrow[q] == j); hp |= (dstrow[q] == pr); }
-                if (!hj) { dstrow[m] = j; srcrow[m] = j; ++m; }
-                if (!hp && pr != j) { dstrow[m] = pr; srcrow[m] = pr; ++m; }
-                // swap the contents (sources) held by rows j and pr
-                int qj = -1, qp = -1;
-                for (int q = 0; q < m; ++q) { if (dstrow[q] == j) qj = q; if (dstrow[q] == pr) qp = q; }
-                if (qj >= 0 && qp >= 0) { int t = srcrow[qj]; srcrow[qj] = srcrow[qp]; srcrow[qp] = t; }
-            }
-            s_nmoved = m;
-        }
-        // ---- write the chunk back
-        for (int e = tid; e < rows * NC; e += kThreads) {
-            int r = e % rows, cc = e / rows;
-            W[r + int64_t(jc + cc) * ldw] = C[r * NC + cc];
-        }
-        __syncthreads();
-        // ---- apply the permutation to the other panel columns (independent loads)
-        {
-            const int m = s_nmoved;
-            for (int col = tid; col < nb; col += kThreads) {
-                if (col >= jc && col < jc + NC) continue;
-                zd *wc = W + int64_t(col) * ldw;
-                zd vals[2 * NC];
-#pragma unroll
-                for (int q = 0; q < 2 * NC; ++q) vals[q] = (q < m) ? wc[srcrow[q]] : zmake(0, 0);
-#pragma unroll
-                for (int q = 0; q < 2 * NC; ++q) if (q < m) wc[dstrow[q]] = vals[q];
-            }
-        }
-        __syncthreads();
-        // ---- U12 inside the panel: one column per thread, values loaded at once
-        for (int col = jc + NC + tid; col < nb; col += kThreads) {
-            zd *wc = W + int64_t(col) * ldw;
-            zd u[NC];
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc) u[cc] = wc[jc + cc];
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc) {
-#pragma unroll
-                for (int c2 = 0; c2 < NC; ++c2)
-                    if (c2 < cc) zfms(u[cc], C[(jc + cc) * NC + c2], u[c2]);
-            }
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc) { wc[jc + cc] = u[cc]; U12[cc * nb + col] = u[cc]; }
-        }
-        __syncthreads();
-        // ---- trailing update inside the panel (multipliers and U12 from LDS)
-        {
-            const int r0 = jc + NC, c0 = jc + NC;
-            const int nr = rows - r0, ncl = nb - c0;
-            const int tot = nr * ncl;
-            for (int e0 = tid; e0 < tot; e0 += 4 * kThreads) {
-                zd acc[4];
-                int rr[4], cl[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    int e = e0 + q * kThreads;
-                    rr[q] = r0 + (e < tot ? e % nr : 0);
-                    cl[q] = c0 + (e < tot ? e / nr : 0);
-                    acc[q] = (e < tot) ? W[rr[q] + int64_t(cl[q]) * ldw] : zmake(0, 0);
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    int e = e0 + q * kThreads;
-                    if (e < tot) {
-#pragma unroll
-                        for (int cc = 0; cc < NC; ++cc) zfms(acc[q], C[rr[q] * NC + cc], U12[cc * nb + cl[q]]);
-                        W[rr[q] + int64_t(cl[q]) * ldw] = acc[q];
-                    }
-                }
-            }
-        }
-        __syncthreads();
+    for (int s = 1; s < NS; ++s) {
+        zd y = lane_get(v[s], ln);
+        if (s == sl) x = y;
     }
-    // permutation of the window rows: new row i = old row perm[i]
-    int32_t *pm = a.perm + (int64_t(pole) * nblk + k) * (2 * nb);
-    if (tid == 0) {
-        for (int i = 0; i < 2 * nb; ++i) pm[i] = i;
-        for (int j = 0; j < nb; ++j) {
-            int pr = pivrow[j];
-            int t = pm[j]; pm[j] = pm[pr]; pm[pr] = t;
+    return x;
+}
+
+// Pivot step (pivot row p, column gj, multipliers l) applied to a column right of it.
+template <int NS>
+__device__ __attribute__((always_inline)) inline void step_update(zd (&x)[NS], const zd (&l)[NS],
+                                                                  int p, int gj, int lane) {
+    const zd u = row_get<NS>(x, p), t = row_get<NS>(x, gj);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int r = lane + 64 * s;
+        zd y = x[s];
+        if (r == gj) y = u;
+        else if (r > gj) {
+            if (r == p) y = t;
+            zfms(y, l[s], u);
         }
-        if (s_info != 0 && a.info[pole] == 0) a.info[pole] = s_info;
-    }
-    // packed L11 \ U11 to both diagonal slots (inverted later), L21
-    zd *T0 = a.tiles + tile_index(pole, k, 0, nblk, te);
-    zd *T1 = T0 + te, *T2 = T1 + te;
-    for (int64_t e = tid; e < te; e += kThreads) {
-        int r = int(e % nb), c = int(e / nb);
-        zd v = W[r + int64_t(c) * ldw];
-        T0[e] = v;
-        T2[e] = v;
-        T1[e] = (k + 1 < nblk) ? W[nb + r + int64_t(c) * ldw] : zmake(0, 0);
+        x[s] = y;
     }
 }
 
-// CPW columns of the U part per workgroup.  grid: (2nb/CPW, p)
-template <int CPW>
-__global__ __launch_bounds__(kThreads) void band_update_kernel(FactorArgs a, int k, int buf) {
-    const int pole = blockIdx.y, rank = blockIdx.x;
+// Pivot step on a column held as x[s] = row lane + 64 s (sub-panel column j, panel
+// column gj): partial pivoting by largest |.|^2 (ties: smallest row), swap, scale by
+// 1 / pivot, publish the multipliers in lc and the pivot row in s_piv[j]; lane 0
+// records the interchange in the sub-panel order idxl and the step order pmf.
+template <int NS>
+__device__ __attribute__((always_inline)) inline void panel_pivot(
+        zd (&x)[NS], int j, int gj, int R, int lane, zd *lc, int *s_piv, int *idxl, int *pmf,
+        int *s_info, int info_base) {
+    double best = -1.0;
+    int bi = gj;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int r = lane + 64 * s;
+        double m = zabs2(x[s]);
+        if (r >= gj && r < R && m > best) { best = m; bi = r; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        double ob = __shfl_xor(best, off, 64);
+        int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const bool sing = !(best > 0.0);
+    const int p = __builtin_amdgcn_readfirstlane(sing ? gj : bi);
+    const zd ap = row_get<NS>(x, p), a0 = row_get<NS>(x, gj);
+    const zd inv = sing ? zmake(0, 0) : zdiv(zmake(1.0, 0.0), ap);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int r = lane + 64 * s;
+        zd y = x[s];
+        if (r == gj) y = ap;
+        else if (r > gj) y = zmul((r == p) ? a0 : y, inv);
+        x[s] = y;
+        if (r < R) lc[r] = y;
+    }
+    if (lane == 0) {
+        s_piv[j] = p;
+        int t = idxl[gj]; idxl[gj] = idxl[p]; idxl[p] = t;
+        t = pmf[gj]; pmf[gj] = pmf[p]; pmf[p] = t;
+        if (sing && *s_info == 0) *s_info = info_base + gj + 1;
+    }
+}
+
+template <int NS, int SW>
+__global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, int k, int buf,
+                                                                int c0) {
+    constexpr int CPT = SW / kFacWaves;                  // columns per wave
+    const int pole = blockIdx.x;
     const int nb = a.nb, nblk = a.nblk, ldw = 2 * nb;
-    const int64_t te = int64_t(nb) * nb;
-    const zd *W = pole_window(a.window, pole, buf, nb);
-    zd *Wn = pole_window(a.window, pole, buf ^ 1, nb);
-    const int tid = threadIdx.x;
-    const int rows = (k + 1 < nblk) ? 2 * nb : nb;
-    const int cols = min(3 * nb, (nblk - k) * nb);          // window columns that exist
-    const int32_t *pm = a.perm + (int64_t(pole) * nblk + k) * (2 * nb);
-    zd *T3 = a.tiles + tile_index(pole, k, 3, nblk, te);   // U1
-    zd *T4 = T3 + te;                                      // U2
-    extern __shared__ unsigned char smem_raw[];
-    zd *S = reinterpret_cast<zd *>(smem_raw);              // [2nb][CPW]
-    const int cbeg = nb + rank * CPW;                      // first window column of this WG
-    // 1. permuted columns into LDS (zeros for columns beyond the matrix)
-    for (int e = tid; e < rows * CPW; e += kThreads) {
-        int r = e / CPW, c = e % CPW;
-        int col = cbeg + c;
-        S[e] = (col < cols) ? W[pm[r] + int64_t(col) * ldw] : zmake(0, 0);
+    zd *W = pole_window(a.window, pole, buf, nb);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int R = (k + 1 < nblk) ? 2 * nb : nb;
+    __shared__ zd Lcol[2][2 * 256];                       // multipliers, double-buffered
+    __shared__ int idxl[2 * 256], pmf[2 * 256], s_piv[SW];
+    __shared__ int s_info;
+    int32_t *pm = a.perm + (int64_t(pole) * nblk + k) * (2 * nb);
+    for (int r = tid; r < 2 * nb; r += kFacThreads) {
+        idxl[r] = r;
+        pmf[r] = (c0 == 0) ? r : pm[r];
+    }
+    if (tid == 0) s_info = 0;
+    zd v[CPT][NS];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        const int col = c0 + wave + kFacWaves * i;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            int r = lane + 64 * s;
+            v[i][s] = (r < R) ? W[r + int64_t(col) * ldw] : zmake(0, 0);
+        }
     }
     __syncthreads();
-    // 2. top rows: U = L11^{-1} S_top, blocks of 16 rows (unit lower L11 from the window)
-    zd *Lb = S + 2 * nb * CPW;                             // [2nb][16] L column block
-    for (int r0 = 0; r0 < nb; r0 += 16) {
-        // stage the 16 multiplier columns r0..r0+15 (rows r0..rows) in LDS
-        for (int e = tid; e < (rows - r0) * 16; e += kThreads) {
-            int r = r0 + e % (rows - r0), q = e / (rows - r0);
-            Lb[r * 16 + q] = W[r + int64_t(r0 + q) * ldw];
+    if (wave == 0)
+        panel_pivot<NS>(v[0], 0, c0, R, lane, Lcol[0], s_piv, idxl, pmf, &s_info, k * nb);
+    __syncthreads();
+    for (int j = 0; j < SW; ++j) {
+        const int gj = c0 + j;
+        const int p = __builtin_amdgcn_readfirstlane(s_piv[j]);
+        const zd *lc = Lcol[j & 1];
+        zd l[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            int r = lane + 64 * s;
+            l[s] = (r < R) ? lc[r] : zmake(0, 0);
         }
-        __syncthreads();
-        // solve the 16 x 16 unit lower diagonal block: one thread per column
-        if (tid < CPW) {
-            const int c = tid;
-            for (int r = r0 + 1; r < r0 + 16; ++r) {
-                zd v = S[r * CPW + c];
-                for (int q = r0; q < r; ++q) zfms(v, Lb[r * 16 + (q - r0)], S[q * CPW + c]);
-                S[r * CPW + c] = v;
+        // the owner of column j+1 updates it first and finds the next pivot
+        const bool owner = (j + 1 < SW) && wave == ((j + 1) % kFacWaves);
+        const int ii = (j + 1) / kFacWaves;
+        if (owner) {
+            // constant register indices in every branch (no dynamically indexed arrays)
+#define RF_OWNER_STEP(I_)                                                                       \
+            case I_:                                                                            \
+                step_update<NS>(v[I_], l, p, gj, lane);                                         \
+                panel_pivot<NS>(v[I_], j + 1, gj + 1, R, lane, Lcol[(j + 1) & 1], s_piv, idxl,  \
+                                pmf, &s_info, k * nb);                                          \
+                break;
+            switch (ii) {
+                RF_OWNER_STEP(0)
+                RF_OWNER_STEP(1)
+                default:
+                if constexpr (CPT > 2) {
+                    if (ii == 2) {
+                        step_update<NS>(v[CPT > 2 ? 2 : 0], l, p, gj, lane);
+                        panel_pivot<NS>(v[CPT > 2 ? 2 : 0], j + 1, gj + 1, R, lane, Lcol[(j + 1) & 1],
+                                        s_piv, idxl, pmf, &s_info, k * nb);
+                    } else {
+                        step_update<NS>(v[CPT > 3 ? 3 : 0], l, p, gj, lane);
+                        panel_pivot<NS>(v[CPT > 3 ? 3 : 0], j + 1, gj + 1, R, lane, Lcol[(j + 1) & 1],
+                                        s_piv, idxl, pmf, &s_info, k * nb);
+                    }
+                }
+            }
+#undef RF_OWNER_STEP
+        }
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+            const int c = wave + kFacWaves * i;
+            if (owner && i == ii) continue;
+            if (c > j) {
+                step_update<NS>(v[i], l, p, gj, lane);
+            } else if (c < j && p != gj) {
+                const zd u = row_get<NS>(v[i], p), t = row_get<NS>(v[i], gj);
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    int r = lane + 64 * s;
+                    if (r == gj) v[i][s] = u;
+                    else if (r == p) v[i][s] = t;
+                }
             }
         }
         __syncthreads();
-        // rows below the block (all rows of the window, top and bottom): minus L(:, block) U(block)
-        for (int e = tid; e < (rows - r0 - 16) * CPW; e += kThreads) {
-            int r = r0 + 16 + e / CPW, c = e % CPW;
-            zd v = S[r * CPW + c];
+    }
 #pragma unroll
-            for (int q = 0; q < 16; ++q) zfms(v, Lb[r * 16 + q], S[(r0 + q) * CPW + c]);
-            S[r * CPW + c] = v;
+    for (int i = 0; i < CPT; ++i) {
+        const int col = c0 + wave + kFacWaves * i;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            int r = lane + 64 * s;
+            if (r < R) W[r + int64_t(col) * ldw] = v[i][s];
         }
-        __syncthreads();
     }
-    // 3. store U1/U2 (top rows) and the updated bottom rows into the next window
-    for (int e = tid; e < nb * CPW; e += kThreads) {
-        int r = e % nb, c = e / nb;
-        int col = cbeg + c;
-        if (col < 2 * nb) T3[r + int64_t(col - nb) * nb] = S[r * CPW + c];
-        else T4[r + int64_t(col - 2 * nb) * nb] = S[r * CPW + c];
-        if (k + 1 < nblk) Wn[r + int64_t(col - nb) * ldw] = S[(nb + r) * CPW + c];
+    int32_t *sp = a.subperm + int64_t(pole) * 2 * nb;
+    for (int r = tid; r < 2 * nb; r += kFacThreads) {
+        sp[r] = idxl[r];
+        pm[r] = pmf[r];
     }
-    // 4. workgroup 0: clear the last column block of the next window's top half and
-    //    load the fresh row block k+2 into its bottom half
-    if (rank == 0 && k + 1 < nblk) {
-        for (int e = tid; e < nb * nb; e += kThreads) {
-            int r = e % nb, c = e / nb;
+    if (tid == 0 && s_info != 0 && a.info[pole] == 0) a.info[pole] = s_info;
+}
+
+// grid: (ceil(columns / 8), p); one window column per wave.
+template <int NS, int SW>
+__global__ __launch_bounds__(kFacThreads) void band_trail_kernel(FactorArgs a, int k, int buf,
+                                                                int c0) {
+    const int pole = blockIdx.y;
+    const int nb = a.nb, nblk = a.nblk, ldw = 2 * nb;
+    const int64_t te = int64_t(nb) * nb;
+    zd *W = pole_window(a.window, pole, buf, nb);
+    zd *Wn = pole_window(a.window, pole, buf ^ 1, nb);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int R = (k + 1 < nblk) ? 2 * nb : nb;
+    const int cols = min(3 * nb, (nblk - k) * nb);       // window columns that exist
+    const bool fin = (c0 + SW == nb);
+    const int nleft = fin ? nb : c0;
+    const int right0 = fin ? nb : c0 + SW;
+    const int total = nleft + 3 * nb - right0;
+    extern __shared__ unsigned char smem_raw[];
+    zd *Ls = reinterpret_cast<zd *>(smem_raw);            // [SW][2nb]
+    int *sp = reinterpret_cast<int *>(Ls + SW * ldw);     // [2nb]
+    const int32_t *spg = a.subperm + int64_t(pole) * 2 * nb;
+    for (int r = tid; r < R; r += kFacThreads) sp[r] = spg[r];
+    const bool need_l = int(blockIdx.x) * kFacWaves + kFacWaves - 1 >= nleft;
+    if (need_l) {
+        // L of the sub-panel, rows c0..R-1 (rows above are not read)
+        const int rr = R - c0, tot = rr * SW;
+        for (int e0 = tid; e0 < tot; e0 += 4 * kFacThreads) {
+            zd t[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int e = e0 + i * kFacThreads;
+                t[i] = (e < tot) ? W[c0 + e % rr + int64_t(c0 + e / rr) * ldw] : zmake(0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int e = e0 + i * kFacThreads;
+                if (e < tot) Ls[(e / rr) * ldw + c0 + e % rr] = t[i];
+            }
+        }
+    }
+    __syncthreads();
+    const int slot = blockIdx.x * kFacWaves + wave;
+    zd *T0 = a.tiles + tile_index(pole, k, 0, nblk, te);
+    zd *T1 = T0 + te, *T2 = T1 + te, *T3 = T2 + te, *T4 = T3 + te;
+    if (slot < total) {
+        zd v[NS];
+        if (slot < nleft) {
+            const int col = slot;
+            const bool perm_it = col < c0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                int r = lane + 64 * s;
+                v[s] = (r < R) ? W[(perm_it ? sp[r] : r) + int64_t(col) * ldw] : zmake(0, 0);
+            }
+            if (fin) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    int r = lane + 64 * s;
+                    if (r < nb) { T0[r + int64_t(col) * nb] = v[s]; T2[r + int64_t(col) * nb] = v[s]; }
+                    else if (r < 2 * nb) T1[(r - nb) + int64_t(col) * nb] = (r < R) ? v[s] : zmake(0, 0);
+                }
+            } else if (perm_it) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    int r = lane + 64 * s;
+                    if (r < R) W[r + int64_t(col) * ldw] = v[s];
+                }
+            }
+        } else {
+            const int col = right0 + (slot - nleft);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                int r = lane + 64 * s;
+                v[s] = (r < R && col < cols) ? W[sp[r] + int64_t(col) * ldw] : zmake(0, 0);
+            }
+            const int sl = c0 >> 6, base = c0 & 63;
+            zd vt = v[0];
+#pragma unroll
+            for (int s = 1; s < NS; ++s) if (s == sl) vt = v[s];
+            for (int q = 0; q < SW; ++q) {
+                zd u = zmake(__shfl(vt.x, base + q, 64), __shfl(vt.y, base + q, 64));
+                if (lane > base + q && lane < base + SW) zfms(vt, Ls[q * ldw + sl * 64 + lane], u);
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) if (s == sl) v[s] = vt;
+            for (int q = 0; q < SW; ++q) {
+                zd u = zmake(__shfl(vt.x, base + q, 64), __shfl(vt.y, base + q, 64));
+                const zd *lq = Ls + q * ldw;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    int r = lane + 64 * s;
+                    if (r >= c0 + SW && r < R) zfms(v[s], lq[r], u);
+                }
+            }
+            if (fin) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    int r = lane + 64 * s;
+                    if (r < nb) {
+                        if (col < 2 * nb) T3[r + int64_t(col - nb) * nb] = v[s];
+                        else T4[r + int64_t(col - 2 * nb) * nb] = v[s];
+                    } else if (r < R && k + 1 < nblk) {
+                        Wn[(r - nb) + int64_t(col - nb) * ldw] = v[s];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    int r = lane + 64 * s;
+                    if (r < R) W[r + int64_t(col) * ldw] = v[s];
+                }
+            }
+        }
+    }
+    // last sub-step: next window's last column block of the top half is zero, its
+    // bottom half is the prepared row block k+2 (column 0 = window column 0)
+    if (fin && k + 1 < nblk) {
+        const int64_t nthr = int64_t(gridDim.x) * kFacThreads;
+        const int64_t gid = int64_t(blockIdx.x) * kFacThreads + tid;
+        for (int64_t e = gid; e < te; e += nthr) {
+            int r = int(e % nb), c = int(e / nb);
             Wn[r + int64_t(2 * nb + c) * ldw] = zmake(0, 0);
         }
-        __syncthreads();
-        if (k + 2 < nblk) load_row_block(a, a.poles[pole], Wn, 1, k + 2, (k + 1) * nb);
-        else {
-            for (int e = tid; e < nb * 3 * nb; e += kThreads) {
-                int r = e % nb, c = e / nb;
-                Wn[nb + r + int64_t(c) * ldw] = zmake(0, 0);
+        const int64_t tot = 3 * te;
+        const zd *Pb = a.rows + (int64_t(pole) * nblk + (k + 2)) * tot;
+        const bool have = k + 2 < nblk;
+        for (int64_t e0 = gid; e0 < tot; e0 += 4 * nthr) {
+            zd t[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int64_t e = e0 + i * nthr;
+                t[i] = (have && e < tot) ? Pb[e] : zmake(0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int64_t e = e0 + i * nthr;
+                if (e < tot) Wn[nb + int(e % nb) + (e / nb) * ldw] = t[i];
             }
         }
     }
@@ -687,27 +785,42 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
     a.info = P.F.info;
     const int nb = a.nb;
     const int p = P.opts.p;
-    auto panel_lds = [&](int nc) {
-        return size_t(2 * nb * nc + nc * nb) * sizeof(zd) + (nb + 4 * nc) * sizeof(int) +
-               (kThreads / 64) * (sizeof(double) + sizeof(int));
+    // sub-steps of 32 columns when the trail kernel's L staging fits, else 16
+    auto trail_lds = [&](int sw) {
+        return size_t(sw) * 2 * nb * sizeof(zd) + size_t(2 * nb) * sizeof(int);
     };
-    const int nc = panel_lds(16) <= size_t(P.max_lds) ? 16 : (panel_lds(8) <= size_t(P.max_lds) ? 8 : 4);
-    // update kernel LDS: permuted columns [2nb][cpw] + one L column block [2nb][16]
-    const int cpw = (size_t(2 * nb) * (16 + 16) * sizeof(zd) <= size_t(P.max_lds)) ? 16 : 8;
-    const size_t upd_lds = size_t(2 * nb) * (cpw + 16) * sizeof(zd);
+    const int sw = (nb % 32 == 0 && trail_lds(32) <= size_t(P.max_lds)) ? 32 : 16;
+    const int ns = (2 * nb + 63) / 64;
+    if (trail_lds(sw) > size_t(P.max_lds) || nb > 256) return hipErrorInvalidValue;
+    a.rows = P.F.rows;
+    a.subperm = P.F.subperm;
+    hipLaunchKernelGGL(rowblock_prep_kernel, dim3(a.nblk, p), dim3(256), 0, s, a);
     hipLaunchKernelGGL(band_window_init_kernel, dim3(p), dim3(256), 0, s, a);
     int buf = 0;
     for (int k = 0; k < a.nblk; ++k) {
-        if (nc == 16)
-            hipLaunchKernelGGL(band_panel_kernel<16>, dim3(p), dim3(kThreads), panel_lds(16), s, a, k, buf);
-        else if (nc == 8)
-            hipLaunchKernelGGL(band_panel_kernel<8>, dim3(p), dim3(kThreads), panel_lds(8), s, a, k, buf);
-        else
-            hipLaunchKernelGGL(band_panel_kernel<4>, dim3(p), dim3(kThreads), panel_lds(4), s, a, k, buf);
-        if (cpw == 16)
-            hipLaunchKernelGGL(band_update_kernel<16>, dim3(2 * nb / 16, p), dim3(kThreads), upd_lds, s, a, k, buf);
-        else
-            hipLaunchKernelGGL(band_update_kernel<8>, dim3(2 * nb / 8, p), dim3(kThreads), upd_lds, s, a, k, buf);
+        for (int c0 = 0; c0 < nb; c0 += sw) {
+            const bool fin = c0 + sw == nb;
+            const int total = (fin ? nb : c0) + 3 * nb - (fin ? nb : c0 + sw);
+            const dim3 tg((total + kFacWaves - 1) / kFacWaves, p);
+            const size_t tl = trail_lds(sw);
+#define RF_FAC_LAUNCH(NS_, SW_)                                                                   \
+            hipLaunchKernelGGL((band_panel_kernel<NS_, SW_>), dim3(p), dim3(kFacThreads), 0, s, a, \
+                               k, buf, c0);                                                      \
+            hipLaunchKernelGGL((band_trail_kernel<NS_, SW_>), tg, dim3(kFacThreads), tl, s, a, k,  \
+                               buf, c0)
+            if (sw == 32) {
+                if (ns <= 1) { RF_FAC_LAUNCH(1, 32); }
+                else if (ns <= 2) { RF_FAC_LAUNCH(2, 32); }
+                else if (ns <= 4) { RF_FAC_LAUNCH(4, 32); }
+                else { RF_FAC_LAUNCH(8, 32); }
+            } else {
+                if (ns <= 1) { RF_FAC_LAUNCH(1, 16); }
+                else if (ns <= 2) { RF_FAC_LAUNCH(2, 16); }
+                else if (ns <= 4) { RF_FAC_LAUNCH(4, 16); }
+                else { RF_FAC_LAUNCH(8, 16); }
+            }
+#undef RF_FAC_LAUNCH
+        }
         buf ^= 1;
     }
     hipError_t e = hipGetLastError();
@@ -730,7 +843,7 @@ template <int CW>
 static hipError_t launch_solve_cw(const SolveArgs &a, hipStream_t s) {
     const int slices = (a.ncols + CW - 1) / CW;
     // more columns per workgroup -> more accumulator registers -> fewer threads
-    constexpr int NT = CW <= 2 ? 1024 : 512;
+    constexpr int NT = CW == 1 ? 1024 : 512;
     hipLaunchKernelGGL((band_solve_kernel<CW, NT>), dim3(slices * a.p), dim3(NT),
                        solve_lds(a.nb, CW), s, a);
     return hipGetLastError();

@@ -66,7 +66,9 @@ struct BandFactors {
     // per pole, per block k: tiles stored back to back, see rf_band.hip
     zd *tiles = nullptr;       // p * nblk * 5 * nb*nb
     int32_t *perm = nullptr;   // p * nblk * 2nb
-    zd *window = nullptr;      // p * (2nb x 3nb) factorization scratch
+    zd *window = nullptr;      // p * 2 * (2nb x 3nb) factorization scratch (double-buffered)
+    zd *rows = nullptr;        // p * nblk * (nb x 3nb): row blocks of p_i B - A, dense
+    int32_t *subperm = nullptr; // p * 2nb: row order of the current sub-panel
     int32_t *info = nullptr;   // p ints: 0 or (1 + first zero-pivot column)
     bool ready = false;
 };

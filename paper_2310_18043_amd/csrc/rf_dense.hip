@@ -435,17 +435,27 @@ __device__ inline int64_t ls_off(int l, int sb, int nsub, int64_t per) {
     return (int64_t(l) * nsub + sb) * per;
 }
 
-// out (2b x b, LDS) = Q^H (2b x 2b, LDS) * in (2b x b, LDS)
-__device__ inline void apply_qh(const zd *Qs, const zd *in, zd *out, int b) {
+// out (2b x b, LDS, ld 2b) = Q^H in, Q in LDS with padded leading dimension ldq
+// (conjugated on use), in (2b x b, LDS, ld 2b).
+__device__ inline void apply_qh(const zd *Qs, int ldq, const zd *in, zd *out, int b) {
     const int m2 = 2 * b;
     for (int e = threadIdx.x; e < m2 * b; e += GT) {
         int r = e % m2, c = e / m2;
         zd acc = zmake(0, 0);
-        const zd *qc = Qs + r * m2;      // column r of Q (conjugated on use)
+        const zd *qc = Qs + r * ldq;     // column r of Q
         const zd *ic = in + c * m2;
         for (int t = 0; t < m2; ++t) zfma_c(acc, qc[t], ic[t]);
         out[r + c * m2] = acc;
     }
+}
+
+// wave-wide sum (all lanes get the result)
+__device__ inline zd wave_sum(zd v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        v.x += __shfl_xor(v.x, off, 64);
+        v.y += __shfl_xor(v.y, off, 64);
+    }
+    return v;
 }
 
 __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
@@ -462,12 +472,14 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
     const zd s = a.shifts[l];
     const zd *Hc = a.H + sb * a.sH + int64_t(j) * b * a.ldh;   // block column j
     const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64;
     const int rows = (j + 2) * b;
     const int m2 = 2 * b;
+    const int ldq = m2 + 1;                               // padded: conflict-free columns
 
     extern __shared__ unsigned char smem_raw[];
-    zd *Ql = reinterpret_cast<zd *>(smem_raw);            // [2b][2b]
-    zd *slab = Ql + m2 * m2;                              // [2b][b]
+    zd *Ql = reinterpret_cast<zd *>(smem_raw);            // [2b][2b+1]
+    zd *slab = Ql + m2 * ldq;                             // [2b][b]
     zd *slab2 = slab + m2 * b;                            // [2b][b]
     zd *vv = slab2 + m2 * b;                              // [2b]
 
@@ -488,9 +500,9 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
     }
     for (int i = 0; i < j; ++i) {
         const zd *Qi = Qs + int64_t(i) * qsz;
-        for (int e = tid; e < m2 * m2; e += GT) Ql[e] = Qi[e];
+        for (int e = tid; e < m2 * m2; e += GT) Ql[(e % m2) + (e / m2) * ldq] = Qi[e];
         __syncthreads();
-        apply_qh(Ql, slab, slab2, b);
+        apply_qh(Ql, ldq, slab, slab2, b);
         __syncthreads();
         // top b rows are final: store; bottom b rows move up, next block row comes in
         for (int e = tid; e < b * b; e += GT) {
@@ -501,7 +513,8 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
         }
         __syncthreads();
     }
-    // 3. Householder QR of the bottom 2b x b block (in LDS), accumulating Q_j in LDS
+    // 3. Householder QR of the bottom 2b x b block (in LDS), accumulating Q_j in LDS.
+    //    One wave per reduction: lane r holds row r (2b <= 64).
     if (j == 0) {
         for (int e = tid; e < m2 * b; e += GT) {
             int r = e % m2, c = e / m2;
@@ -510,52 +523,46 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
     }
     for (int e = tid; e < m2 * m2; e += GT) {
         int r = e % m2, c = e / m2;
-        Ql[e] = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
+        Ql[r + c * ldq] = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
     }
     __shared__ double s_beta;
-    __shared__ zd s_alpha;
     __syncthreads();
+    const int nwaves = GT / 64;
     for (int c = 0; c < b; ++c) {
-        if (tid == 0) {
-            double nrm2 = 0.0;
-            for (int r = c; r < m2; ++r) nrm2 += zabs2(slab[r + c * m2]);
-            zd x0 = slab[c + c * m2];
+        if (wave == 0) {
+            zd x = (lane >= c && lane < m2) ? slab[lane + c * m2] : zmake(0, 0);
+            double nrm2 = wave_sum(zmake(zabs2(x), 0.0)).x;
+            zd x0 = zmake(__shfl(x.x, c, 64), __shfl(x.y, c, 64));
             double ax0 = sqrt(zabs2(x0));
             double nrm = sqrt(nrm2);
             zd ph = (ax0 > 0.0) ? zscale(x0, 1.0 / ax0) : zmake(1.0, 0.0);
-            s_alpha = zscale(ph, -nrm);                   // alpha = -phase(x0) ||x||
-            s_beta = (nrm > 0.0) ? 2.0 * nrm * (nrm + ax0) : 0.0;   // v^H v
-        }
-        __syncthreads();
-        for (int r = tid; r < m2; r += GT) {
-            zd v = (r < c) ? zmake(0, 0) : slab[r + c * m2];
-            if (r == c) v = zsub(v, s_alpha);
-            vv[r] = v;
+            zd alpha = zscale(ph, -nrm);                  // alpha = -phase(x0) ||x||
+            if (lane < m2) vv[lane] = (lane == c) ? zsub(x, alpha) : x;
+            if (lane == 0) s_beta = (nrm > 0.0) ? 2.0 * nrm * (nrm + ax0) : 0.0;   // v^H v
         }
         __syncthreads();
         const double inv2 = (s_beta > 0.0) ? 2.0 / s_beta : 0.0;
-        // H = I - inv2 v v^H on slab columns c..b-1
-        for (int cc = c + tid; cc < b; cc += GT) {
-            zd dot = zmake(0, 0);
-            for (int r = c; r < m2; ++r) zfma_c(dot, vv[r], slab[r + cc * m2]);
-            dot = zscale(dot, inv2);
-            for (int r = c; r < m2; ++r) zfms(slab[r + cc * m2], vv[r], dot);
+        const zd vr = (lane < m2) ? vv[lane] : zmake(0, 0);
+        // H = I - inv2 v v^H on slab columns c..b-1: one wave per column
+        for (int cc = c + wave; cc < b; cc += nwaves) {
+            zd y = (lane < m2) ? slab[lane + cc * m2] : zmake(0, 0);
+            zd d = zmake(0, 0);
+            zfma_c(d, vr, y);
+            d = zscale(wave_sum(d), inv2);
+            if (lane < m2) { zfms(y, vr, d); slab[lane + cc * m2] = y; }
         }
-        // Qj <- Qj H (rows of Qj)
-        for (int row = tid; row < m2; row += GT) {
-            zd dot = zmake(0, 0);
-            for (int r = c; r < m2; ++r) zfma(dot, Ql[row + r * m2], vv[r]);
-            dot = zscale(dot, inv2);
-            for (int r = c; r < m2; ++r) {
-                zd q = Ql[row + r * m2];
-                zfms(q, dot, zconj(vv[r]));
-                Ql[row + r * m2] = q;
-            }
+        // Qj <- Qj H: one wave per row of Qj (lanes over columns r)
+        for (int row = wave; row < m2; row += nwaves) {
+            zd q = (lane < m2) ? Ql[row + lane * ldq] : zmake(0, 0);
+            zd d = zmake(0, 0);
+            zfma(d, q, vr);
+            d = zscale(wave_sum(d), inv2);
+            if (lane < m2) { zfms(q, d, zconj(vr)); Ql[row + lane * ldq] = q; }
         }
         __syncthreads();
     }
     zd *Qj = Qs + int64_t(j) * qsz;
-    for (int e = tid; e < m2 * m2; e += GT) Qj[e] = Ql[e];
+    for (int e = tid; e < m2 * m2; e += GT) Qj[e] = Ql[(e % m2) + (e / m2) * ldq];
     // 4. R block column: rows 0..jb from col, then R_jj from slab
     for (int e = tid; e < (j + 1) * b * b; e += GT) {
         int r = e % ((j + 1) * b), c = e / ((j + 1) * b);
@@ -570,7 +577,7 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
         slab2[r + c * m2] = G[j * b + r + int64_t(c) * ldc];
     }
     __syncthreads();
-    apply_qh(Ql, slab2, slab, b);
+    apply_qh(Ql, ldq, slab2, slab, b);
     __syncthreads();
     for (int e = tid; e < m2 * b; e += GT) {
         int r = e % m2, c = e / m2;
@@ -588,48 +595,71 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
 // Back substitution R Y = G[0:mb] for every (shift, active sub-block), then
 // Ycomb[sb] = sum_l c_l Y_l  is done by a second kernel in fixed shift order.
 struct LsSolveArgs {
-    int b, mmax, m, nq, nsub;
+    int b, mmax, m, nq, nsub, cpw;
     const zd *R; const zd *G; zd *Y;
     const int *active;
 };
 
-// Blocked by b rows: Y_I = R_II^{-1} (G_I - sum_{J > I} R_IJ Y_J), with R_II solved by
-// substitution in LDS.
+// Right-looking block back substitution, columns split over blockIdx.z in groups of
+// cpw (the columns of Y are independent).  The running right-hand side lives in LDS;
+// once diagonal block I is solved, its contribution is removed from every row above
+// it in parallel.
 __global__ __launch_bounds__(GT) void ls_solve_kernel(LsSolveArgs a) {
     const int l = blockIdx.x;
     const int sb = a.active[blockIdx.y];
-    const int b = a.b, mmax = a.mmax, m = a.m;
+    const int b = a.b, mmax = a.mmax, m = a.m, cpw = a.cpw;
+    const int c0 = blockIdx.z * cpw;
+    const int mb = m * b;
     const int ldr = mmax * b, ldc = (mmax + 1) * b;
     const zd *R = a.R + ls_off(l, sb, a.nsub, int64_t(mmax) * b * mmax * b);
     const zd *G = a.G + ls_off(l, sb, a.nsub, int64_t(ldc) * b);
     zd *Y = a.Y + ls_off(l, sb, a.nsub, int64_t(mmax) * b * b);      // ld mmax*b
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    constexpr int nwaves = GT / 64;
     extern __shared__ unsigned char smem_raw[];
-    zd *T = reinterpret_cast<zd *>(smem_raw);             // [b][b] right-hand side block
-    zd *D = T + b * b;                                    // [b][b] diagonal block of R
+    zd *acc = reinterpret_cast<zd *>(smem_raw);           // [cpw][mb] running right-hand side
+    zd *yb = acc + cpw * mb;                               // [cpw][b] solved block
+    zd *D = yb + cpw * b;                                  // [b][b+1] diagonal block of R
+    const int ldd = b + 1;
+    for (int e = tid; e < mb * cpw; e += GT) {
+        int r = e % mb, c = e / mb;
+        acc[r + c * mb] = G[r + int64_t(c0 + c) * ldc];
+    }
     for (int I = m - 1; I >= 0; --I) {
         const int r0 = I * b;
-        // T = G_I - sum_{J>I} R_IJ Y_J
         for (int e = tid; e < b * b; e += GT) {
             int r = e % b, c = e / b;
-            zd v = G[r0 + r + int64_t(c) * ldc];
-            for (int t = r0 + b; t < m * b; ++t) zfms(v, R[r0 + r + int64_t(t) * ldr], Y[t + int64_t(c) * ldr]);
-            T[r + c * b] = v;
-            D[r + c * b] = R[r0 + r + int64_t(r0 + c) * ldr];
+            D[r + c * ldd] = R[r0 + r + int64_t(r0 + c) * ldr];
         }
         __syncthreads();
-        // back substitution with the upper triangular D, one column per thread
-        for (int c = tid; c < b; c += GT) {
-            for (int r = b - 1; r >= 0; --r) {
-                zd v = T[r + c * b];
-                for (int q = r + 1; q < b; ++q) zfms(v, D[r + q * b], T[q + c * b]);
-                T[r + c * b] = zdiv(v, D[r + r * b]);
+        // diagonal block: one wave per column, lane = row (b <= 64)
+        for (int c = wave; c < cpw; c += nwaves) {
+            zd v = (lane < b) ? acc[r0 + lane + c * mb] : zmake(0, 0);
+            for (int k = b - 1; k >= 0; --k) {
+                zd vk = zmake(__shfl(v.x, k, 64), __shfl(v.y, k, 64));
+                zd yk = zdiv(vk, D[k + k * ldd]);
+                if (lane == k) v = yk;
+                else if (lane < k) zfms(v, D[lane + k * ldd], yk);
+            }
+            if (lane < b) {
+                yb[lane + c * b] = v;
+                Y[r0 + lane + int64_t(c0 + c) * ldr] = v;
             }
         }
         __syncthreads();
-        for (int e = tid; e < b * b; e += GT) {
-            int r = e % b, c = e / b;
-            Y[r0 + r + int64_t(c) * ldr] = T[r + c * b];
+        // rows above: acc[0:r0] -= R[0:r0, block I] * yb
+        for (int row = tid; row < r0; row += GT) {
+            zd s[8];
+            for (int c = 0; c < 8; ++c) s[c] = zmake(0, 0);
+            for (int k = 0; k < b; ++k) {
+                const zd rv = R[row + int64_t(r0 + k) * ldr];
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (c < cpw) zfma(s[c], rv, yb[k + c * b]);
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < cpw) acc[row + c * mb] = zsub(acc[row + c * mb], s[c]);
         }
         __syncthreads();
     }
@@ -788,7 +818,7 @@ hipError_t launch_ls_update(const rf_plan &P, int j, const int *active, int nact
     a.Q = P.lsQ; a.R = P.lsR; a.G = P.lsG; a.work = P.lsWork;
     a.resid = P.resid; a.r0norm = P.r0norm; a.active = active;
     const int b = P.b;
-    size_t sm = (size_t(4) * b * b + 4 * b * b + 2 * b) * sizeof(zd);
+    size_t sm = (size_t(2 * b) * (2 * b + 1) + 4 * b * b + 2 * b) * sizeof(zd);
     hipLaunchKernelGGL(ls_update_kernel, dim3(a.nq, nact), dim3(GT), sm, s, a);
     return hipGetLastError();
 }
@@ -798,8 +828,16 @@ hipError_t launch_ls_solve(const rf_plan &P, int m, const int *active, int nact,
     LsSolveArgs a;
     a.b = P.b; a.mmax = P.mmax; a.m = m; a.nq = int(P.shifts.size()); a.nsub = P.nsub;
     a.R = P.lsR; a.G = P.lsG; a.Y = P.lsY; a.active = active;
-    hipLaunchKernelGGL(ls_solve_kernel, dim3(a.nq, nact), dim3(GT),
-                       size_t(2) * P.b * P.b * sizeof(zd), s, a);
+    // columns per workgroup: up to 4 (more workgroups), as LDS allows
+    const int mb = m * P.b;
+    a.cpw = 0;
+    for (int c = 4; c >= 1; c /= 2) {
+        size_t sm = (size_t(c) * (mb + P.b) + size_t(P.b) * (P.b + 1)) * sizeof(zd);
+        if (P.b % c == 0 && sm <= size_t(P.max_lds)) { a.cpw = c; break; }
+    }
+    if (a.cpw == 0) return hipErrorInvalidValue;
+    size_t sm = (size_t(a.cpw) * (mb + P.b) + size_t(P.b) * (P.b + 1)) * sizeof(zd);
+    hipLaunchKernelGGL(ls_solve_kernel, dim3(a.nq, nact, P.b / a.cpw), dim3(GT), sm, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int64_t tot = int64_t(m) * P.b * P.b * nact;

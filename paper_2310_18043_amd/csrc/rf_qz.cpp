@@ -212,3 +212,11 @@ int host_qz_eig(int n, const zd *Ain, const zd *Bin, zd *alpha_out, zd *beta_out
     }
     return 0;
 }
+
+extern "C" int rf_dense_eig(int32_t n, const double *A, const double *B, double *alpha, double *beta,
+                            double *vr) {
+    if (n < 0 || (n > 0 && (!A || !B || !alpha || !beta || !vr))) return -2;
+    return host_qz_eig(n, reinterpret_cast<const zd *>(A), reinterpret_cast<const zd *>(B),
+                       reinterpret_cast<zd *>(alpha), reinterpret_cast<zd *>(beta),
+                       reinterpret_cast<zd *>(vr));
+}
