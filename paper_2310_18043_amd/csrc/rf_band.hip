@@ -542,75 +542,138 @@ struct SolveArgs {
     int64_t npad;
 };
 
-// Solve kernel.  One workgroup of NT threads owns one pole and a slice of CW
-// right-hand sides and runs the whole forward and backward sweep.  Each nb x nb
-// tile product out = T v is done by G threads per output row (G a power of two,
-// the G threads of a row sit in adjacent lanes of one wave): thread (i, g) loads
-// its contiguous segment of row i of T -- its loads of a tile are issued in
-// batches of kSeg, so a tile costs few memory latencies -- multiplies by the
-// matching rows of v (LDS, [nb][CW]) and the G partial sums are combined with
-// cross-lane shuffles.  Triangular tiles (Linv lower, Uinv upper, U2 lower) are
-// read only inside their triangle.  Tiles are read straight from global memory:
-// the column slices of one pole run on the same XCD (workgroup id modulo p
-// selects the pole) and share each tile through its L2.
-constexpr int kSeg = 16;             // tile loads in flight per thread and batch
+// Solve kernel.  One workgroup of kSolveThreads threads owns one pole and a slice
+// of CW right-hand sides and runs the whole forward and backward sweep.  Each
+// nb x nb tile product out = T v is done by G threads per output row (G a power
+// of two, the G threads of a row sit in one wave, 64 / G lanes apart): thread (i, g)
+// takes the columns k = j G + g of row i, multiplies them by the matching rows of
+// v (LDS, [nb][CW]; the G lanes of a row read adjacent rows of v, so a wave's
+// reads fall in distinct banks or are broadcasts) and the G partial sums are
+// combined with cross-lane shuffles.  Triangular tiles (Linv lower, Uinv upper,
+// U2 lower) are read only inside their triangle.
+//
+// The tile reads of the whole solve form one fixed sequence -- forward: Linv_k,
+// L21_k per block; backward: U1_k, U2_k, Uinv_k -- independent of the data, so
+// they are software-pipelined: every thread's part of a tile is split into
+// batches of kSeg elements held in two register buffers, and as soon as a batch
+// has been consumed the batch two places further down the sequence (usually the
+// same part of the next tile) is requested.  The tile loads of the next product
+// are thus in flight across the reductions and barriers of the current one.  In
+// addition the workgroups of a pole touch the next block's tiles so that they are
+// in L2.
+constexpr int kSolveThreads = 512;
+constexpr int kSeg = 16;             // tile elements per thread and batch
 
 enum TileShape { kFull = 0, kLower = 1, kUpper = 2 };
 
-struct SolveGeom {
-    int G, rows_per_wave, klen;
-};
-
-__host__ __device__ inline SolveGeom solve_geom(int nb, int nthreads) {
-    SolveGeom g;
+// lanes per output row for tile size nb: the largest power of two <= 32 with
+// G * nb <= kSolveThreads
+__host__ __device__ inline int solve_lanes(int nb) {
     int G = 1;
-    while (G * 2 <= 64 && G * 2 * nb <= nthreads) G *= 2;
-    g.G = G;
-    g.rows_per_wave = 64 / G;
-    g.klen = (nb + G - 1) / G;
-    return g;
+    while (G * 2 <= 32 && G * 2 * nb <= kSolveThreads) G *= 2;
+    return G;
 }
 
-// acc[c] = sum_k T[i, k] v[k, c] over this thread's k-segment (clipped to the
-// tile's triangle), reduced over the G lanes of row i; valid in lane g == 0.
-// Threads with i >= nb contribute zeros but still take part in the shuffles.
-template <int CW>
-__device__ inline void tile_prod(const zd *__restrict__ T, const zd *v, int nb,
-                                 const SolveGeom &sg, int i, int g, int shape, zd *acc) {
+// The tile-read sequence: phases 0 .. 2 nblk - 2 are the forward products
+// (even: Linv_k, odd: L21_k, k = phase / 2), then 3 per backward block
+// (U1_k, U2_k, Uinv_k for k = nblk - 1 down to 0).
+template <int G>
+struct TileStream {
+    const zd *tiles;     // this pole's tiles
+    int64_t te;
+    int nb, nblk, nF, nph, nbat;   // nbat: batches per tile (even)
+    int i, g;            // this thread's row and column residue
+
+    __device__ const zd *phase_tile(int ph, int &shape) const {
+        int k, slot;
+        if (ph < nF) {
+            k = ph >> 1;
+            if (ph & 1) { slot = 1; shape = kFull; } else { slot = 0; shape = kLower; }
+        } else {
+            const int q = ph - nF, j = q / 3, t = q - 3 * j;
+            k = nblk - 1 - j;
+            slot = (t == 0) ? 3 : (t == 1) ? 4 : 2;
+            shape = (t == 0) ? kFull : (t == 1) ? kLower : kUpper;
+        }
+        return tiles + (int64_t(k) * 5 + slot) * te;
+    }
+    // this thread's range [j0, j1) of j (column k = j G + g) in a tile of `shape`
+    __device__ void jrange(int shape, int &j0, int &j1) const {
+        j0 = 0;
+        j1 = (nb - g + G - 1) / G;
+        if (i >= nb) j1 = 0;
+        else if (shape == kLower) j1 = min(j1, i >= g ? (i - g) / G + 1 : 0);
+        else if (shape == kUpper) j0 = i > g ? (i - g + G - 1) / G : 0;
+    }
+    // request batch s of the sequence into t (zeros outside the tile's part)
+    __device__ void issue(int s, zd (&t)[kSeg]) const {
+        const int ph = s / nbat, b = s - ph * nbat;
+        int j0 = 0, j1 = 0;
+        const zd *T = tiles;
+        if (ph < nph) {
+            int shape;
+            T = phase_tile(ph, shape);
+            jrange(shape, j0, j1);
+        }
+        const int jb = b * kSeg;
+        const int64_t stride = int64_t(G) * nb;
+        const zd *pt = T + i + int64_t(g) * nb + jb * stride;
+        if (jb >= j0 && jb + kSeg <= j1) {
 #pragma unroll
-    for (int c = 0; c < CW; ++c) acc[c] = zmake(0, 0);
-    if (i < nb) {
-        int k0 = g * sg.klen;
-        int k1 = min(nb, k0 + sg.klen);
-        if (shape == kLower) k1 = min(k1, i + 1);
-        else if (shape == kUpper) k0 = max(k0, i);
-        const zd *tp = T + i;
-        for (int kb = k0; kb < k1; kb += kSeg) {
-            zd t[kSeg];
-#pragma unroll
-            for (int u = 0; u < kSeg; ++u)
-                t[u] = (kb + u < k1) ? tp[int64_t(kb + u) * nb] : zmake(0, 0);
+            for (int u = 0; u < kSeg; ++u) t[u] = pt[u * stride];
+        } else {
 #pragma unroll
             for (int u = 0; u < kSeg; ++u) {
-                if (kb + u < k1) {
-                    const zd *vr = v + (kb + u) * CW;
-#pragma unroll
-                    for (int c = 0; c < CW; ++c) zfma(acc[c], t[u], vr[c]);
-                }
+                const int j = jb + u;
+                t[u] = (j >= j0 && j < j1) ? pt[u * stride] : zmake(0, 0);
             }
         }
     }
-    for (int off = sg.G / 2; off > 0; off >>= 1) {
+};
+
+// acc[c] += sum over batch s (part of a tile of `shape`) of T[i, k] v[k, c]
+// (elements outside the tile's part were loaded as zeros)
+template <int CW, int G>
+__device__ __attribute__((always_inline)) inline void consume(const TileStream<G> &ts, int s,
+                                                              const zd (&t)[kSeg], const zd *v,
+                                                              zd *acc) {
+    const int b = s % ts.nbat;
+    const int jb = b * kSeg;
+    const int kmax = ts.nb - 1;
+    const zd *vb = v + (jb * G + ts.g) * CW;
+    if ((jb + kSeg - 1) * G + ts.g <= kmax) {
 #pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            acc[c].x += __shfl_xor(acc[c].x, off, 64);
-            acc[c].y += __shfl_xor(acc[c].y, off, 64);
+        for (int u = 0; u < kSeg; ++u) {
+#pragma unroll
+            for (int c = 0; c < CW; ++c) zfma(acc[c], t[u], vb[u * G * CW + c]);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kSeg; ++u) {
+            if ((jb + u) * G + ts.g <= kmax) {
+#pragma unroll
+                for (int c = 0; c < CW; ++c) zfma(acc[c], t[u], vb[u * G * CW + c]);
+            }
         }
     }
 }
 
-template <int CW, int NT>
-__global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
+// sum over the G lanes of a row (lanes lane % (64 / G) equal)
+template <int CW, int G>
+__device__ inline void reduce_rows(zd *acc) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            acc[c].x += __shfl_xor(acc[c].x, off * (64 / G), 64);
+            acc[c].y += __shfl_xor(acc[c].y, off * (64 / G), 64);
+        }
+    }
+}
+
+template <int CW, int G>
+__global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) {
+    constexpr int NT = kSolveThreads;
     const int p = a.p;
     const int pole = blockIdx.x % p;             // slices of one pole share an XCD
     const int slice = blockIdx.x / p;
@@ -621,10 +684,11 @@ __global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
     const int64_t te = int64_t(nb) * nb;
     const int tid = threadIdx.x;
     const zd wgt = a.weights[pole];
-    const SolveGeom sg = solve_geom(nb, NT);
     const int wave = tid / 64, lane = tid % 64;
-    const int i = wave * sg.rows_per_wave + lane / sg.G;    // output row of this thread
-    const int g = lane % sg.G;
+    // lanes of one wave: row-fastest, so each load instruction reads G runs of
+    // 64 / G consecutive rows of a tile column
+    const int i = wave * (64 / G) + lane % (64 / G);         // output row of this thread
+    const int g = lane / (64 / G);
     const bool writer = (g == 0) && (i < nb);
 
     extern __shared__ unsigned char smem_raw[];
@@ -637,6 +701,12 @@ __global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
     zd *xp = a.xpart + int64_t(pole) * a.npad * a.ncols;
     const zd *tiles = a.tiles + int64_t(pole) * nblk * 5 * te;
     const int32_t *perm = a.perm + int64_t(pole) * nblk * 2 * nb;
+
+    TileStream<G> ts;
+    ts.tiles = tiles; ts.te = te; ts.nb = nb; ts.nblk = nblk;
+    ts.nF = 2 * nblk - 1; ts.nph = ts.nF + 3 * nblk;
+    ts.nbat = 2 * (((nb + G - 1) / G + 2 * kSeg - 1) / (2 * kSeg));
+    ts.i = i; ts.g = g;
 
     // L2 prefetch: the workgroups of this pole that share an XCD (workgroups are
     // dealt to the 8 XCDs round-robin) split the next step's tiles between them and
@@ -681,7 +751,26 @@ __global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
         }
     };
 
+    // the pipelined tile stream: s = next batch to consume
+    zd bufA[kSeg], bufB[kSeg];
+    int s = 0;
+    ts.issue(0, bufA);
+    ts.issue(1, bufB);
     zd acc[CW];
+    auto run_phase = [&](const zd *v) {
+        for (int bp = 0; bp < ts.nbat; bp += 2) {
+            consume<CW, G>(ts, s, bufA, v, acc);
+            ts.issue(s + 2, bufA);
+            consume<CW, G>(ts, s + 1, bufB, v, acc);
+            ts.issue(s + 3, bufB);
+            s += 2;
+        }
+    };
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int c = 0; c < CW; ++c) acc[c] = zmake(0, 0);
+    };
+
     // ---------------- forward sweep
     prefetch_rhs(0);
     store_rhs(win);
@@ -699,8 +788,9 @@ __global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
             win2[e] = win[pk[r] * CW + c];
         }
         __syncthreads();
-        const zd *Tk = tiles + int64_t(k) * 5 * te;
-        tile_prod<CW>(Tk, win2, nb, sg, i, g, kLower, acc);      // y_k = Linv w_top
+        zero_acc();
+        run_phase(win2);                             // y_k = Linv w_top
+        reduce_rows<CW, G>(acc);
         if (writer) {
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
@@ -710,7 +800,9 @@ __global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
         }
         __syncthreads();
         if (!last) {
-            tile_prod<CW>(Tk + te, ybuf, nb, sg, i, g, kFull, acc);   // t_{k+1} = w_bot - L21 y_k
+            zero_acc();
+            run_phase(ybuf);                          // t_{k+1} = w_bot - L21 y_k
+            reduce_rows<CW, G>(acc);
             if (writer) {
 #pragma unroll
                 for (int c = 0; c < CW; ++c) win[i * CW + c] = zsub(win2[(nb + i) * CW + c], acc[c]);
@@ -734,22 +826,24 @@ __global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
         zd *xk = ring + (k % 3) * nb * CW;
         const zd *xk1 = ring + ((k + 1) % 3) * nb * CW;
         const zd *xk2 = ring + ((k + 2) % 3) * nb * CW;
-        const zd *Tk = tiles + int64_t(k) * 5 * te;
         zd y[CW];
 #pragma unroll
         for (int c = 0; c < CW; ++c) y[c] = ynext[c];
         load_y(k - 1, ynext);                                       // y_{k-1}, used next step
         if (k > 0) touch(tiles + int64_t(k - 1) * 5 * te + 2 * te, 3 * te);   // Uinv, U1, U2 of k-1
         // v = y_k - U1 x_{k+1} - U2 x_{k+2}
-        zd acc2[CW];
-        tile_prod<CW>(Tk + 3 * te, xk1, nb, sg, i, g, kFull, acc);
-        tile_prod<CW>(Tk + 4 * te, xk2, nb, sg, i, g, kLower, acc2);
+        zero_acc();
+        run_phase(xk1);
+        run_phase(xk2);
+        reduce_rows<CW, G>(acc);
         if (writer) {
 #pragma unroll
-            for (int c = 0; c < CW; ++c) ybuf[i * CW + c] = zsub(zsub(y[c], acc[c]), acc2[c]);
+            for (int c = 0; c < CW; ++c) ybuf[i * CW + c] = zsub(y[c], acc[c]);
         }
         __syncthreads();
-        tile_prod<CW>(Tk + 2 * te, ybuf, nb, sg, i, g, kUpper, acc);     // x_k = Uinv v
+        zero_acc();
+        run_phase(ybuf);                                    // x_k = Uinv v
+        reduce_rows<CW, G>(acc);
         if (writer) {
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
@@ -839,14 +933,24 @@ static size_t solve_lds(int nb, int cw) {
     return size_t(2 * nb * cw * 2 + nb * cw + 3 * nb * cw) * sizeof(zd);
 }
 
-template <int CW>
-static hipError_t launch_solve_cw(const SolveArgs &a, hipStream_t s) {
+template <int CW, int G>
+static hipError_t launch_solve_g(const SolveArgs &a, hipStream_t s) {
     const int slices = (a.ncols + CW - 1) / CW;
-    // more columns per workgroup -> more accumulator registers -> fewer threads
-    constexpr int NT = CW == 1 ? 1024 : 512;
-    hipLaunchKernelGGL((band_solve_kernel<CW, NT>), dim3(slices * a.p), dim3(NT),
+    hipLaunchKernelGGL((band_solve_kernel<CW, G>), dim3(slices * a.p), dim3(kSolveThreads),
                        solve_lds(a.nb, CW), s, a);
     return hipGetLastError();
+}
+
+template <int CW>
+static hipError_t launch_solve_cw(const SolveArgs &a, hipStream_t s) {
+    switch (solve_lanes(a.nb)) {
+        case 2: return launch_solve_g<CW, 2>(a, s);
+        case 4: return launch_solve_g<CW, 4>(a, s);
+        case 8: return launch_solve_g<CW, 8>(a, s);
+        case 16: return launch_solve_g<CW, 16>(a, s);
+        case 32: return launch_solve_g<CW, 32>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int ncols, zd *Z,
@@ -867,10 +971,10 @@ hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int nc
     int cw = P.opts.trsm_cols;
     if (cw <= 0) {
         // enough workgroups to cover the chip, at most 8 columns each
-        cw = 8;
+        cw = 4;
         while (cw > 1 && (int64_t(ncols + cw - 1) / cw) * a.p < 256) cw /= 2;
     }
-    if (cw > 4) cw = 8; else if (cw > 2) cw = 4;
+    if (cw > 2) cw = 4;
     while (cw > 1 && solve_lds(a.nb, cw) > size_t(P.max_lds)) cw /= 2;
     hipError_t e;
     hipEvent_t ev0 = nullptr;
@@ -878,8 +982,7 @@ hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int nc
     switch (cw) {
         case 1: e = launch_solve_cw<1>(a, s); break;
         case 2: e = launch_solve_cw<2>(a, s); break;
-        case 4: e = launch_solve_cw<4>(a, s); break;
-        default: e = launch_solve_cw<8>(a, s); break;
+        default: e = launch_solve_cw<4>(a, s); break;
     }
     if (e != hipSuccess) return e;
     P.prof.record_end(s, ev0, ncols, 0);
