@@ -42,7 +42,7 @@ def main():
                 f"inner_applications={apps}\n")
         f.write("# re im rel_error\n")
         for k in order:
-            f.write(f"{res.lam[k].real!r} {res.lam[k].imag!r} {res.err[k]!r}\n")
+            f.write(f"{float(res.lam[k].real)!r} {float(res.lam[k].imag)!r} {float(res.err[k])!r}\n")
     print(out, len(res.lam), res.sweeps, res.converged, f"{dt:.0f}s")
 
 

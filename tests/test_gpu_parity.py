@@ -196,3 +196,79 @@ def test_filter_apply_on_converged_ritz_vectors(rf, torch_cuda, subblock):
           "relerr", _relerr(_to_host(U), ref))
     assert info["converged"], info
     assert _relerr(_to_host(U), ref) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# full size: the 128 x 128 convection-diffusion workload the benchmark times
+# (N = 16384, bandwidth 128, p = 4, q = 8, w = 128)
+# ---------------------------------------------------------------------------
+def _golden_convdiff128():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "convdiff128_eigs.txt")
+    lam, err = [], []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        re_, im_, e_ = (float(x) for x in line.split())
+        lam.append(complex(re_, im_))
+        err.append(e_)
+    return np.array(lam), np.array(err)
+
+
+@pytest.fixture(scope="module")
+def convdiff128(rf, torch_cuda):
+    wl = W.convdiff_workload()
+    plan = rf.Plan(wl.A, wl.B, wl.c, wl.r, p=wl.p, q=wl.q, w=wl.w,
+                   expected_count=wl.s_expected, gmres_tol=1e-13)
+    plan.factor_shifts()
+    return wl, plan
+
+
+def test_full_size_inner_apply_sampled_columns(rf, torch_cuda, convdiff128):
+    # G on all 128 columns in the benchmark's launch shape; the oracle checks 3 of them
+    from oracle import filters
+    wl, plan = convdiff128
+    _say("convdiff128 apply_inner, 128 columns")
+    X = W.start_block(wl.n, wl.w, seed=11)
+    Z = _to_host(plan.apply_inner(torch_cuda.from_numpy(X).cuda()))
+    cols = [0, 77, 127]
+    ref = filters.InnerOperator(wl.A, wl.B, wl.c, wl.r, wl.p)(X[:, cols])
+    assert _relerr(Z[:, cols], ref) <= 1e-12, _relerr(Z[:, cols], ref)
+
+
+def test_full_size_filter_apply_sampled_columns(rf, torch_cuda, convdiff128):
+    # one composite filter application on the 128-column start block; the oracle's
+    # simple rule with pq = 32 poles on 2 of the columns
+    from oracle import filters
+    wl, plan = convdiff128
+    _say("convdiff128 filter_apply, 128 columns")
+    Y = W.start_block(wl.n, wl.w, wl.seed)
+    U, info = plan.filter_apply(torch_cuda.from_numpy(Y).cuda())
+    assert info["converged"], info
+    cols = [5, 100]
+    ref = filters.simple_filter(wl.A, wl.B, wl.c, wl.r, wl.p * wl.q, Y[:, cols])
+    e = _relerr(_to_host(U)[:, cols], ref)
+    print("filter relerr", e, "krylov steps", info["krylov_steps"])
+    assert e <= 1e-11, e
+
+
+def test_full_size_solve_region_matches_oracle(rf, torch_cuda, convdiff128):
+    # eigenpairs of the benchmark workload vs the oracle's own full Alg. composite run
+    # (tests/golden/convdiff128_eigs.txt, written by tests/golden/make_convdiff128.py)
+    from oracle import hsrr
+    from scipy.optimize import linear_sum_assignment
+    wl, plan = convdiff128
+    ref_lam, ref_err = _golden_convdiff128()
+    _say("convdiff128 solve_region")
+    Y0 = torch_cuda.from_numpy(W.start_block(wl.n, wl.w, wl.seed)).cuda()
+    res = plan.solve_region(Y0)
+    assert res["converged"]
+    assert res["count"] == len(ref_lam) == wl.s_expected
+    cost = np.abs(res["lam"][:, None] - ref_lam[None, :])
+    r, c = linear_sum_assignment(cost)
+    rel = cost[r, c] / np.abs(ref_lam[c])
+    print("max |dlambda|/|lambda|", rel.max(), "median", np.median(rel))
+    assert rel.max() <= 1e-10, rel.max()
+    e = hsrr.rel_errors(wl.A, wl.B, res["lam"], _to_host(res["X"]), wl.c, wl.r)
+    print("max residual (oracle's definition)", e.max())
+    assert e.max() <= 1e-10
