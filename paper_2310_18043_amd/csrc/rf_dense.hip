@@ -417,8 +417,10 @@ __global__ void gaussian_kernel(int64_t n, int ncols, zd *X, int64_t ldx, uint64
 // (each acting on two block rows), then a Householder QR of its bottom 2b x b block
 // gives R_jj and Q_j (stored explicitly, 2b x 2b).  The right-hand side E1 R0 is
 // rotated by Q_j^H; the norms of its last b rows are the residuals.
-// One workgroup per (shift, active sub-block); the column being rotated and each
-// Q_i are staged in LDS.
+// One workgroup per (shift, active sub-block).  The column is streamed through a
+// 2b x b window in LDS: rows come straight from H (the shift subtracted on the fly),
+// each rotation's finished top block row goes straight into R, and Q_{i+1} is
+// loaded into registers while Q_i is applied.
 // ---------------------------------------------------------------------------
 struct LsArgs {
     int b, mmax, j, nq;
@@ -435,17 +437,45 @@ __device__ inline int64_t ls_off(int l, int sb, int nsub, int64_t per) {
     return (int64_t(l) * nsub + sb) * per;
 }
 
-// out (2b x b, LDS, ld 2b) = Q^H in, Q in LDS with padded leading dimension ldq
-// (conjugated on use), in (2b x b, LDS, ld 2b).
+// out (2b x b, LDS, ld 2b) = Q^H in, with Q in LDS (ld ldq, conjugated on use) and
+// in (2b x b, LDS, ld 2b).  Each thread computes a 2 x 4 block of out (rows r, r + b;
+// columns 4q..4q+3), so every LDS read feeds several multiply-adds (b < 4: one
+// element per thread).
 __device__ inline void apply_qh(const zd *Qs, int ldq, const zd *in, zd *out, int b) {
     const int m2 = 2 * b;
-    for (int e = threadIdx.x; e < m2 * b; e += GT) {
-        int r = e % m2, c = e / m2;
-        zd acc = zmake(0, 0);
-        const zd *qc = Qs + r * ldq;     // column r of Q
-        const zd *ic = in + c * m2;
-        for (int t = 0; t < m2; ++t) zfma_c(acc, qc[t], ic[t]);
-        out[r + c * m2] = acc;
+    if (b % 4 != 0) {
+        for (int e = threadIdx.x; e < m2 * b; e += GT) {
+            const int r = e % m2, c = e / m2;
+            zd acc = zmake(0, 0);
+            for (int t = 0; t < m2; ++t) zfma_c(acc, Qs[r * ldq + t], in[c * m2 + t]);
+            out[r + c * m2] = acc;
+        }
+        return;
+    }
+    const int ncg = b / 4;                       // column groups
+    for (int e = threadIdx.x; e < b * ncg; e += GT) {
+        const int r = e % b, cg = e / b;
+        zd acc[2][4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = zmake(0, 0);
+        const zd *q0 = Qs + r * ldq, *q1 = Qs + (r + b) * ldq;     // columns r, r+b of Q
+        const zd *ic = in + (4 * cg) * m2;
+        for (int t = 0; t < m2; ++t) {
+            const zd a0 = q0[t], a1 = q1[t];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const zd x = ic[v * m2 + t];
+                zfma_c(acc[0][v], a0, x);
+                zfma_c(acc[1][v], a1, x);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            out[r + (4 * cg + v) * m2] = acc[0][v];
+            out[r + b + (4 * cg + v) * m2] = acc[1][v];
+        }
     }
 }
 
@@ -458,6 +488,8 @@ __device__ inline zd wave_sum(zd v) {
     return v;
 }
 
+constexpr int kQPer = (64 * 64 + GT - 1) / GT;   // Q elements per thread (2b <= 64)
+
 __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
     const int l = blockIdx.x;
     const int sb = a.active[blockIdx.y];
@@ -468,12 +500,10 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
     zd *R = a.R + ls_off(l, sb, nsub, int64_t(mmax) * b * mmax * b);
     const int ldr = mmax * b;
     zd *G = a.G + ls_off(l, sb, nsub, int64_t(ldc) * b);
-    zd *col = a.work + ls_off(l, sb, nsub, int64_t(ldc) * b);
     const zd s = a.shifts[l];
     const zd *Hc = a.H + sb * a.sH + int64_t(j) * b * a.ldh;   // block column j
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
-    const int rows = (j + 2) * b;
     const int m2 = 2 * b;
     const int ldq = m2 + 1;                               // padded: conflict-free columns
 
@@ -483,44 +513,65 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
     zd *slab2 = slab + m2 * b;                            // [2b][b]
     zd *vv = slab2 + m2 * b;                              // [2b]
 
-    // 1. copy the new column, subtract the shift on its diagonal block
-    for (int e = tid; e < rows * b; e += GT) {
-        int r = e % rows, c = e / rows;
+    // element (r, c) of the new column block of H - s I~ (r < (j+2) b)
+    auto hval = [&](int r, int c) {
         zd v = Hc[r + int64_t(c) * a.ldh];
         if (r == j * b + c) v = zsub(v, s);
-        col[r + int64_t(c) * ldc] = v;
+        return v;
+    };
+    // 1. window = rows [0, 2b)
+    for (int e = tid; e < m2 * b; e += GT) {
+        int r = e % m2, c = e / m2;
+        slab[e] = hval(r, c);
     }
-    __syncthreads();
-    // 2. apply Q_i^H, i < j, to rows [ib, (i+2)b); rows i*b..(i+1)*b are final after step i
+    // 2. rotations by Q_0 .. Q_{j-1}; Q_i arrives in registers one step ahead
+    zd qn[kQPer];
     if (j > 0) {
-        for (int e = tid; e < m2 * b; e += GT) {
-            int r = e % m2, c = e / m2;
-            slab[r + c * m2] = col[r + int64_t(c) * ldc];
+#pragma unroll
+        for (int q = 0; q < kQPer; ++q) {
+            const int e = tid + q * GT;
+            qn[q] = (e < m2 * m2) ? Qs[e] : zmake(0, 0);
         }
     }
     for (int i = 0; i < j; ++i) {
-        const zd *Qi = Qs + int64_t(i) * qsz;
-        for (int e = tid; e < m2 * m2; e += GT) Ql[(e % m2) + (e / m2) * ldq] = Qi[e];
+#pragma unroll
+        for (int q = 0; q < kQPer; ++q) {
+            const int e = tid + q * GT;
+            if (e < m2 * m2) Ql[(e % m2) + (e / m2) * ldq] = qn[q];
+        }
+        // next rows of the column and the next Q, in flight during the product
+        zd hn[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * GT;
+            hn[q] = (e < b * b) ? hval((i + 2) * b + e % b, e / b) : zmake(0, 0);
+        }
+        if (i + 1 < j) {
+            const zd *Qn = Qs + int64_t(i + 1) * qsz;
+#pragma unroll
+            for (int q = 0; q < kQPer; ++q) {
+                const int e = tid + q * GT;
+                qn[q] = (e < m2 * m2) ? Qn[e] : zmake(0, 0);
+            }
+        }
         __syncthreads();
         apply_qh(Ql, ldq, slab, slab2, b);
         __syncthreads();
-        // top b rows are final: store; bottom b rows move up, next block row comes in
+        // top b rows are final (block row i of R); bottom b rows move up, new rows below
         for (int e = tid; e < b * b; e += GT) {
             int r = e % b, c = e / b;
-            col[i * b + r + int64_t(c) * ldc] = slab2[r + c * m2];
+            R[i * b + r + int64_t(j * b + c) * ldr] = slab2[r + c * m2];
             slab[r + c * m2] = slab2[b + r + c * m2];
-            slab[b + r + c * m2] = col[(i + 2) * b + r + int64_t(c) * ldc];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * GT;
+            if (e < b * b) slab[b + e % b + (e / b) * m2] = hn[q];
         }
         __syncthreads();
     }
     // 3. Householder QR of the bottom 2b x b block (in LDS), accumulating Q_j in LDS.
     //    One wave per reduction: lane r holds row r (2b <= 64).
-    if (j == 0) {
-        for (int e = tid; e < m2 * b; e += GT) {
-            int r = e % m2, c = e / m2;
-            slab[r + c * m2] = col[r + int64_t(c) * ldc];
-        }
-    }
     for (int e = tid; e < m2 * m2; e += GT) {
         int r = e % m2, c = e / m2;
         Ql[r + c * ldq] = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
@@ -563,13 +614,10 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
     }
     zd *Qj = Qs + int64_t(j) * qsz;
     for (int e = tid; e < m2 * m2; e += GT) Qj[e] = Ql[(e % m2) + (e / m2) * ldq];
-    // 4. R block column: rows 0..jb from col, then R_jj from slab
-    for (int e = tid; e < (j + 1) * b * b; e += GT) {
-        int r = e % ((j + 1) * b), c = e / ((j + 1) * b);
-        zd v;
-        if (r < j * b) v = col[r + int64_t(c) * ldc];
-        else { int rr = r - j * b; v = (rr <= c) ? slab[rr + c * m2] : zmake(0, 0); }
-        R[r + int64_t(j * b + c) * ldr] = v;
+    // 4. diagonal block R_jj (upper triangle of the reduced window)
+    for (int e = tid; e < b * b; e += GT) {
+        int r = e % b, c = e / b;
+        R[j * b + r + int64_t(j * b + c) * ldr] = (r <= c) ? slab[r + c * m2] : zmake(0, 0);
     }
     // 5. rotate the right-hand side rows [jb, (j+2)b) by Q_j^H
     for (int e = tid; e < m2 * b; e += GT) {
