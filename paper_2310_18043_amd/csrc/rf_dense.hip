@@ -571,14 +571,17 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
         __syncthreads();
     }
     // 3. Householder QR of the bottom 2b x b block (in LDS), accumulating Q_j in LDS.
-    //    One wave per reduction: lane r holds row r (2b <= 64).
+    //    Per column: wave 0 forms the reflector v (one wave reduction); the dot
+    //    products v^H slab(:, cc) and Q_j v are plain loops, one thread each (the
+    //    column loop starts at a different row per thread, so the reads of a wave fall
+    //    in distinct banks); then both rank-one updates run over all threads.
     for (int e = tid; e < m2 * m2; e += GT) {
         int r = e % m2, c = e / m2;
         Ql[r + c * ldq] = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
     }
     __shared__ double s_beta;
+    __shared__ zd s_dcol[32], s_dq[64];
     __syncthreads();
-    const int nwaves = GT / 64;
     for (int c = 0; c < b; ++c) {
         if (wave == 0) {
             zd x = (lane >= c && lane < m2) ? slab[lane + c * m2] : zmake(0, 0);
@@ -593,22 +596,43 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
         }
         __syncthreads();
         const double inv2 = (s_beta > 0.0) ? 2.0 / s_beta : 0.0;
-        const zd vr = (lane < m2) ? vv[lane] : zmake(0, 0);
-        // H = I - inv2 v v^H on slab columns c..b-1: one wave per column
-        for (int cc = c + wave; cc < b; cc += nwaves) {
-            zd y = (lane < m2) ? slab[lane + cc * m2] : zmake(0, 0);
+        if (tid < m2) {
+            // (Q_j v)[row]
             zd d = zmake(0, 0);
-            zfma_c(d, vr, y);
-            d = zscale(wave_sum(d), inv2);
-            if (lane < m2) { zfms(y, vr, d); slab[lane + cc * m2] = y; }
+            for (int t = 0; t < m2; ++t) zfma(d, Ql[tid + t * ldq], vv[t]);
+            s_dq[tid] = zscale(d, inv2);
+        } else if (tid >= 64 && tid < 64 + b) {
+            // (v^H slab)[cc] for cc > c
+            const int cc = tid - 64;
+            zd d = zmake(0, 0);
+            if (cc > c) {
+                for (int k = 0; k < m2; ++k) {
+                    int r = k + cc;
+                    if (r >= m2) r -= m2;
+                    zfma_c(d, vv[r], slab[r + cc * m2]);
+                }
+            }
+            s_dcol[cc] = zscale(d, inv2);
         }
-        // Qj <- Qj H: one wave per row of Qj (lanes over columns r)
-        for (int row = wave; row < m2; row += nwaves) {
-            zd q = (lane < m2) ? Ql[row + lane * ldq] : zmake(0, 0);
-            zd d = zmake(0, 0);
-            zfma(d, q, vr);
-            d = zscale(wave_sum(d), inv2);
-            if (lane < m2) { zfms(q, d, zconj(vr)); Ql[row + lane * ldq] = q; }
+        __syncthreads();
+        for (int e = tid; e < m2 * (b - c - 1); e += GT) {
+            const int r = e % m2, cc = c + 1 + e / m2;
+            zfms(slab[r + cc * m2], vv[r], s_dcol[cc]);
+        }
+        if (tid < m2) {
+            // column c itself becomes (alpha, 0, ..., 0)
+            zd y = slab[tid + c * m2];
+            if (tid == c) {
+                const zd vc = vv[c];
+                y = zsub(y, vc);                          // x_c - v_c = alpha
+            } else if (tid > c) {
+                y = zmake(0, 0);
+            }
+            slab[tid + c * m2] = y;
+        }
+        for (int e = tid; e < m2 * m2; e += GT) {
+            const int row = e % m2, t = e / m2;
+            zfms(Ql[row + t * ldq], s_dq[row], zconj(vv[t]));
         }
         __syncthreads();
     }
