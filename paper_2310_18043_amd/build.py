@@ -28,6 +28,11 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-munsafe-fp-atomics"]
 
 
+# per-source flags: the host QZ uses plain complex multiply/divide (its operands
+# are finite; no Annex-G infinity recovery calls in the inner loops)
+EXTRA = {"rf_qz.cpp": ["-fcx-limited-range"]}
+
+
 def _obj(src: str) -> str:
     return os.path.join(CSRC, "_build", os.path.splitext(src)[0] + ".o")
 
@@ -38,7 +43,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         # every source includes HIP headers: compile all of them as HIP for gfx950
-        cmd = [HIPCC] + COMMON + DEVICE + ["-x", "hip", "-c", path, "-o", _obj(src)]
+        cmd = [HIPCC] + COMMON + DEVICE + EXTRA.get(src, []) + ["-x", "hip", "-c", path, "-o", _obj(src)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,

@@ -1,8 +1,8 @@
 """The C-ABI library loads and exports every entry point include/rfeig.h declares.
 
-Runs on the CPU: no compute call is made, only symbol lookup, the pure host
-helpers (option defaults, status strings) and argument checks that fail before
-any device work.
+Runs on the CPU: no device compute call is made, only symbol lookup, the pure
+host helpers (option defaults, status strings, the host QZ of the projected
+pencil) and argument checks that fail before any device work.
 """
 import ctypes
 import math
@@ -85,3 +85,55 @@ def test_plan_create_rejects_bad_arguments_before_device_work(lib):
     assert lib.rf_plan_create(ctypes.byref(An), ctypes.byref(A), ctypes.byref(o), None,
                               ctypes.byref(out)) == rfeig.RF_ERR_ARG
     assert out.value is None
+
+
+def _dense_eig(lib, A, B):
+    import numpy as np
+    f = lib.rf_dense_eig
+    f.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 5
+    f.restype = ctypes.c_int
+    n = A.shape[0]
+    A = np.asfortranarray(A, dtype=np.complex128)
+    B = np.asfortranarray(B, dtype=np.complex128)
+    al = np.zeros(n, np.complex128)
+    be = np.zeros(n, np.complex128)
+    vr = np.zeros((n, n), np.complex128, order="F")
+    st = f(n, A.ctypes.data, B.ctypes.data, al.ctypes.data, be.ctypes.data, vr.ctypes.data)
+    return st, al, be, vr
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (64, 3), (128, 4)])
+def test_host_qz_matches_lapack_and_residuals(lib, n, seed):
+    # the host QZ of HSRR: eigenvalues against LAPACK's generalized eigensolver and
+    # ||A v - lambda B v|| small for every returned (unit) vector
+    import numpy as np
+    import scipy.linalg as sl
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    B = np.eye(n) + 0.2 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    st, al, be, vr = _dense_eig(lib, A, B)
+    assert st == 0
+    lam = al / be
+    ref = sl.eigvals(A, B)
+    d = np.abs(lam[:, None] - ref[None, :])
+    from scipy.optimize import linear_sum_assignment
+    r, c = linear_sum_assignment(d)
+    scale = np.linalg.norm(A, 2) * np.linalg.norm(np.linalg.inv(B), 2)
+    assert d[r, c].max() <= 1e-11 * scale, d[r, c].max()
+    assert np.allclose(np.linalg.norm(vr, axis=0), 1.0)
+    res = np.linalg.norm(A @ vr - (B @ vr) * lam[None, :], axis=0)
+    assert res.max() <= 1e-11 * np.linalg.norm(A, 2) * max(1.0, np.abs(lam).max()), res.max()
+
+
+def test_host_qz_diagonal_and_triangular_pencils(lib):
+    # already-triangular input: the eigenvalues are the diagonal ratios exactly
+    import numpy as np
+    rng = np.random.default_rng(9)
+    n = 12
+    A = np.triu(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    B = np.triu(rng.standard_normal((n, n))) + 3 * np.eye(n)
+    st, al, be, vr = _dense_eig(lib, A, B)
+    assert st == 0
+    ref = np.diag(A) / np.diag(B)
+    lam = al / be
+    assert np.max(np.min(np.abs(lam[:, None] - ref[None, :]), axis=1)) <= 1e-13 * np.abs(ref).max()
