@@ -69,7 +69,7 @@ typedef struct {
     int32_t max_krylov_blocks; /* cap on block-Arnoldi steps per filter application; default 150 */
     int32_t subblock;        /* Krylov sub-block width b dividing w (0 = automatic) */
     int32_t expected_count;  /* expected eigenvalue count s inside D, -1 if unknown */
-    int32_t tile;            /* band tile size nb (0 = automatic: >= bandwidth, multiple of 16) */
+    int32_t tile;            /* band tile size nb: 16, 32, 64, 128 or 256, >= the bandwidth (0 = automatic: the smallest such) */
     int32_t trsm_cols;       /* right-hand sides per band-solve workgroup: 1, 2 or 4 (0 = automatic, 3 and 5..8 act as 4) */
     uint64_t seed;           /* seed of the start block when none is given */
 } rf_opts;

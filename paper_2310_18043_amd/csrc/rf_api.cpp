@@ -158,7 +158,8 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     if (o.subblock < 0 || (o.subblock > 0 && (o.w % o.subblock != 0 || o.subblock > 32 ||
                                               (256 % o.subblock) != 0)))
         return RF_ERR_ARG;
-    if (o.tile < 0 || o.tile > 256 || (o.tile > 0 && o.tile % 16 != 0)) return RF_ERR_ARG;
+    if (o.tile < 0 || o.tile > 256 || (o.tile > 0 && (o.tile < 16 || (o.tile & (o.tile - 1)) != 0)))
+        return RF_ERR_ARG;
     if (o.trsm_cols < 0 || o.trsm_cols > 8) return RF_ERR_ARG;
 
     rf_plan *P = new rf_plan();
@@ -191,7 +192,11 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     band_extent(B, kl, ku);
     P->kl = kl; P->ku = ku;
     int nb = o.tile;
-    if (nb == 0) nb = std::max(16, ((std::max(std::max(kl, ku), 1) + 15) / 16) * 16);
+    if (nb == 0) {
+        // tile: the smallest power of two >= max(16, kl, ku)
+        nb = 16;
+        while (nb < std::max(kl, ku)) nb *= 2;
+    }
     if (nb < std::max(kl, ku)) {
         rf_fail(P, RF_ERR_ARG, "tile smaller than the bandwidth");
         return fail(RF_ERR_ARG);

@@ -543,312 +543,292 @@ struct SolveArgs {
 };
 
 // Solve kernel.  One workgroup of kSolveThreads threads owns one pole and a slice
-// of CW right-hand sides and runs the whole forward and backward sweep.  Each
-// nb x nb tile product out = T v is done by G threads per output row (G a power
-// of two, the G threads of a row sit in one wave, 64 / G lanes apart): thread (i, g)
-// takes the columns k = j G + g of row i, multiplies them by the matching rows of
-// v (LDS, [nb][CW]; the G lanes of a row read adjacent rows of v, so a wave's
-// reads fall in distinct banks or are broadcasts) and the G partial sums are
-// combined with cross-lane shuffles.  Triangular tiles (Linv lower, Uinv upper,
-// U2 lower) are read only inside their triangle.
+// of CW right-hand sides and runs the whole forward and backward sweep as nb x nb
+// tile products out = T v.  Tiles are stored whole (the inverted triangles carry
+// explicit zeros), so every product reads its full tile and every thread issues the
+// same loads on every path.  Layout (template on the tile size NB, a power of two):
+// the NB rows are spread over SLOTS row slots with R rows each (rows s, s + SLOTS,
+// ...), the columns over G lanes (column k = j G + g), so a thread holds an R x KL
+// piece of the tile and each LDS read of v feeds R multiply-adds; the G partial sums
+// of a row are combined with cross-lane shuffles.  Lanes are slot-fastest, so one
+// load instruction reads G runs of 64/G consecutive rows of a tile column.
 //
 // The tile reads of the whole solve form one fixed sequence -- forward: Linv_k,
 // L21_k per block; backward: U1_k, U2_k, Uinv_k -- independent of the data, so
-// they are software-pipelined: every thread's part of a tile is split into
-// batches of kSeg elements held in two register buffers, and as soon as a batch
-// has been consumed the batch two places further down the sequence (usually the
-// same part of the next tile) is requested.  The tile loads of the next product
-// are thus in flight across the reductions and barriers of the current one.  In
-// addition the workgroups of a pole touch the next block's tiles so that they are
+// they are software-pipelined: a thread's piece of a tile is split into NBAT
+// batches held in two register buffers, and as soon as a batch has been consumed
+// the batch two places further down the sequence is requested, so the next
+// product's loads are in flight across the reductions and barriers of the current
+// one.  The workgroups of a pole also touch the next block's tiles so that they are
 // in L2.
 constexpr int kSolveThreads = 512;
-constexpr int kSeg = 16;             // tile elements per thread and batch
 
-enum TileShape { kFull = 0, kLower = 1, kUpper = 2 };
-
-// lanes per output row for tile size nb: the largest power of two <= 32 with
-// G * nb <= kSolveThreads
-__host__ __device__ inline int solve_lanes(int nb) {
-    int G = 1;
-    while (G * 2 <= 32 && G * 2 * nb <= kSolveThreads) G *= 2;
-    return G;
-}
-
-// The tile-read sequence: phases 0 .. 2 nblk - 2 are the forward products
-// (even: Linv_k, odd: L21_k, k = phase / 2), then 3 per backward block
-// (U1_k, U2_k, Uinv_k for k = nblk - 1 down to 0).
-template <int G>
-struct TileStream {
-    const zd *tiles;     // this pole's tiles
-    int64_t te;
-    int nb, nblk, nF, nph, nbat;   // nbat: batches per tile (even)
-    int i, g;            // this thread's row and column residue
-
-    __device__ const zd *phase_tile(int ph, int &shape) const {
-        int k, slot;
-        if (ph < nF) {
-            k = ph >> 1;
-            if (ph & 1) { slot = 1; shape = kFull; } else { slot = 0; shape = kLower; }
-        } else {
-            const int q = ph - nF, j = q / 3, t = q - 3 * j;
-            k = nblk - 1 - j;
-            slot = (t == 0) ? 3 : (t == 1) ? 4 : 2;
-            shape = (t == 0) ? kFull : (t == 1) ? kLower : kUpper;
-        }
-        return tiles + (int64_t(k) * 5 + slot) * te;
-    }
-    // this thread's range [j0, j1) of j (column k = j G + g) in a tile of `shape`
-    __device__ void jrange(int shape, int &j0, int &j1) const {
-        j0 = 0;
-        j1 = (nb - g + G - 1) / G;
-        if (i >= nb) j1 = 0;
-        else if (shape == kLower) j1 = min(j1, i >= g ? (i - g) / G + 1 : 0);
-        else if (shape == kUpper) j0 = i > g ? (i - g + G - 1) / G : 0;
-    }
-    // request batch s of the sequence into t (zeros outside the tile's part)
-    __device__ void issue(int s, zd (&t)[kSeg]) const {
-        const int ph = s / nbat, b = s - ph * nbat;
-        int j0 = 0, j1 = 0;
-        const zd *T = tiles;
-        if (ph < nph) {
-            int shape;
-            T = phase_tile(ph, shape);
-            jrange(shape, j0, j1);
-        }
-        const int jb = b * kSeg;
-        const int64_t stride = int64_t(G) * nb;
-        const zd *pt = T + i + int64_t(g) * nb + jb * stride;
-        if (jb >= j0 && jb + kSeg <= j1) {
-#pragma unroll
-            for (int u = 0; u < kSeg; ++u) t[u] = pt[u * stride];
-        } else {
-#pragma unroll
-            for (int u = 0; u < kSeg; ++u) {
-                const int j = jb + u;
-                t[u] = (j >= j0 && j < j1) ? pt[u * stride] : zmake(0, 0);
-            }
-        }
-    }
+template <int NB>
+struct SolveShape {
+    static constexpr int R = NB >= 64 ? NB / 64 : 1;                  // rows per thread
+    static constexpr int SLOTS = NB / R;
+    static constexpr int G0 = kSolveThreads / SLOTS;
+    static constexpr int G = G0 < NB / 2 ? G0 : NB / 2;               // lanes per slot
+    static constexpr int KL = NB / G;                                 // columns per thread
+    static constexpr int L = R * KL;                                  // tile elements per thread
+    static constexpr int S = L / 2 < 8 ? L / 2 : 8;                   // batch size
+    static constexpr int NBAT = L / S;                                // batches per tile (even)
+    static constexpr int RPW = 64 / G;                                // slots per wave
+    static constexpr int ACTIVE = SLOTS * G;                          // threads with rows
+    static_assert(NBAT % 2 == 0 && S >= 1 && ACTIVE <= kSolveThreads, "solve shape");
 };
 
-// acc[c] += sum over batch s (part of a tile of `shape`) of T[i, k] v[k, c]
-// (elements outside the tile's part were loaded as zeros)
-template <int CW, int G>
-__device__ __attribute__((always_inline)) inline void consume(const TileStream<G> &ts, int s,
-                                                              const zd (&t)[kSeg], const zd *v,
-                                                              zd *acc) {
-    const int b = s % ts.nbat;
-    const int jb = b * kSeg;
-    const int kmax = ts.nb - 1;
-    const zd *vb = v + (jb * G + ts.g) * CW;
-    if ((jb + kSeg - 1) * G + ts.g <= kmax) {
+// Load batch b of this thread's piece of tile T (thread corner tp = T + slot + g NB;
+// the element offsets are compile-time constants).
+template <int NB>
+__device__ __attribute__((always_inline)) inline void issue_batch(const zd *tp, int b,
+                                                                  zd (&t)[SolveShape<NB>::S]) {
+    using SH = SolveShape<NB>;
 #pragma unroll
-        for (int u = 0; u < kSeg; ++u) {
+    for (int e = 0; e < SH::S; ++e) {
+        const int E = b * SH::S + e, j = E / SH::R, q = E % SH::R;
+        t[e] = tp[SH::SLOTS * q + j * SH::G * NB];
+    }
+}
+
+// acc[q][c] += sum over batch b of a tile of T[row_q, k] v[k, c]
+template <int CW, int NB>
+__device__ __attribute__((always_inline)) inline void consume(int g, int b,
+                                                              const zd (&t)[SolveShape<NB>::S],
+                                                              const zd *v,
+                                                              zd (&acc)[SolveShape<NB>::R][CW]) {
+    using SH = SolveShape<NB>;
 #pragma unroll
-            for (int c = 0; c < CW; ++c) zfma(acc[c], t[u], vb[u * G * CW + c]);
-        }
-    } else {
+    for (int e = 0; e < SH::S; ++e) {
+        const int E = b * SH::S + e, j = E / SH::R, q = E % SH::R;
+        const zd *vr = v + (j * SH::G + g) * CW;
 #pragma unroll
-        for (int u = 0; u < kSeg; ++u) {
-            if ((jb + u) * G + ts.g <= kmax) {
+        for (int c = 0; c < CW; ++c) zfma(acc[q][c], t[e], vr[c]);
+    }
+}
+
+template <int CW, int NB>
+__device__ inline void reduce_rows(zd (&acc)[SolveShape<NB>::R][CW]) {
+    using SH = SolveShape<NB>;
 #pragma unroll
-                for (int c = 0; c < CW; ++c) zfma(acc[c], t[u], vb[u * G * CW + c]);
+    for (int off = SH::G / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < SH::R; ++q)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                acc[q][c].x += __shfl_xor(acc[q][c].x, off * SH::RPW, 64);
+                acc[q][c].y += __shfl_xor(acc[q][c].y, off * SH::RPW, 64);
             }
-        }
     }
 }
 
-// sum over the G lanes of a row (lanes lane % (64 / G) equal)
-template <int CW, int G>
-__device__ inline void reduce_rows(zd *acc) {
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) {
-#pragma unroll
-        for (int c = 0; c < CW; ++c) {
-            acc[c].x += __shfl_xor(acc[c].x, off * (64 / G), 64);
-            acc[c].y += __shfl_xor(acc[c].y, off * (64 / G), 64);
-        }
-    }
-}
-
-template <int CW, int G>
+template <int CW, int NB>
 __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) {
+    using SH = SolveShape<NB>;
     constexpr int NT = kSolveThreads;
+    constexpr int R = SH::R;
     const int p = a.p;
     const int pole = blockIdx.x % p;             // slices of one pole share an XCD
     const int slice = blockIdx.x / p;
     const int c0 = slice * CW;
     if (c0 >= a.ncols) return;
     const int ncw = min(CW, a.ncols - c0);
-    const int nb = a.nb, nblk = a.nblk;
-    const int64_t te = int64_t(nb) * nb;
+    const int nblk = a.nblk;
+    constexpr int64_t te = int64_t(NB) * NB;
     const int tid = threadIdx.x;
     const zd wgt = a.weights[pole];
     const int wave = tid / 64, lane = tid % 64;
-    // lanes of one wave: row-fastest, so each load instruction reads G runs of
-    // 64 / G consecutive rows of a tile column
-    const int i = wave * (64 / G) + lane % (64 / G);         // output row of this thread
-    const int g = lane / (64 / G);
-    const bool writer = (g == 0) && (i < nb);
+    const int g = lane / SH::RPW;
+    const int slot_raw = wave * SH::RPW + lane % SH::RPW;
+    const bool active = tid < SH::ACTIVE;
+    const int slot = active ? slot_raw : 0;                  // idle threads read row 0
+    const bool writer = active && g == 0;
 
     extern __shared__ unsigned char smem_raw[];
-    zd *win = reinterpret_cast<zd *>(smem_raw);   // [2nb][CW]
-    zd *win2 = win + 2 * nb * CW;                 // [2nb][CW]
-    zd *ybuf = win2 + 2 * nb * CW;                // [nb][CW]
-    zd *ring = ybuf + nb * CW;                    // [3][nb][CW]
+    zd *win = reinterpret_cast<zd *>(smem_raw);   // [2NB][CW]
+    zd *win2 = win + 2 * NB * CW;                 // [2NB][CW]
+    zd *ybuf = win2 + 2 * NB * CW;                // [NB][CW]
+    zd *ring = ybuf + NB * CW;                    // [3][NB][CW]
 
     zd *yp = a.ypart + int64_t(pole) * a.npad * a.ncols;
     zd *xp = a.xpart + int64_t(pole) * a.npad * a.ncols;
     const zd *tiles = a.tiles + int64_t(pole) * nblk * 5 * te;
-    const int32_t *perm = a.perm + int64_t(pole) * nblk * 2 * nb;
+    const int32_t *perm = a.perm + int64_t(pole) * nblk * 2 * NB;
 
-    TileStream<G> ts;
-    ts.tiles = tiles; ts.te = te; ts.nb = nb; ts.nblk = nblk;
-    ts.nF = 2 * nblk - 1; ts.nph = ts.nF + 3 * nblk;
-    ts.nbat = 2 * (((nb + G - 1) / G + 2 * kSeg - 1) / (2 * kSeg));
-    ts.i = i; ts.g = g;
+    // tile of block k, slot t (0 Linv, 1 L21, 2 Uinv, 3 U1, 4 U2), at this thread's corner
+    const int64_t corner = slot + int64_t(g) * NB;
+    auto tile_at = [&](int k, int t) __attribute__((always_inline)) {
+        return tiles + (int64_t(k) * 5 + t) * te + corner;
+    };
 
     // L2 prefetch: the workgroups of this pole that share an XCD (workgroups are
     // dealt to the 8 XCDs round-robin) split the next step's tiles between them and
-    // touch one element per 128-byte line, so the tile reads of the next step hit L2.
+    // each thread touches one 128-byte line.
     const int nslices = (a.ncols + CW - 1) / CW;
     const int spread = (8 % p == 0) ? 8 / p : 1;          // XCDs one pole is spread over
     const int prank = slice / spread;
     const int pcount = (nslices + spread - 1) / spread;
     double sink = 0.0;
-    auto touch = [&](const zd *base, int64_t elems) {
+    auto touch = [&](const zd *base, int64_t elems) __attribute__((always_inline)) {
         const int64_t lines = (elems + 7) / 8;              // 8 complex per 128-byte line
         const int64_t per = (lines + pcount - 1) / pcount;
-        const int64_t l0 = int64_t(prank) * per, l1 = min(lines, l0 + per);
-        for (int64_t ln = l0 + tid; ln < l1; ln += NT) sink += base[ln * 8].x;
+        const int64_t ln = int64_t(prank) * per + tid;
+        const bool ok = tid < per && ln < lines;
+        sink += base[ok ? ln * 8 : 0].x;
     };
 
-    // right-hand-side rows of block blk for element e of the [nb][CW] block
-    auto rhs_elem = [&](int blk, int e) {
-        int r = e / CW, c = e % CW;
-        int64_t row = int64_t(blk) * nb + r;
-        zd v = zmake(0, 0);
-        if (row < a.n && c < ncw) {
-            v = a.X[row + int64_t(c0 + c) * a.ldx];
-            if (a.bdiag) v = zmul(a.bdiag[row], v);
-        }
-        return v;
-    };
-    constexpr int RPT = (256 * CW + NT - 1) / NT;        // rhs elements per thread (nb <= 256)
+    // right-hand sides: rows of block blk, element e of the [NB][CW] block
+    constexpr int RPT = (NB * CW + NT - 1) / NT;
     zd pre[RPT];
-    auto prefetch_rhs = [&](int blk) {
+    auto prefetch_rhs = [&](int blk) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
-            int e = tid + q * NT;
-            pre[q] = (blk < nblk && e < nb * CW) ? rhs_elem(blk, e) : zmake(0, 0);
+            const int e = tid + q * NT;
+            const int r = e / CW, c = e % CW;
+            const int64_t row = int64_t(blk) * NB + r;
+            const bool ok = blk < nblk && e < NB * CW && row < a.n && c < ncw;
+            zd x = a.X[ok ? row + int64_t(c0 + c) * a.ldx : 0];
+            if (a.bdiag) x = zmul(a.bdiag[ok ? row : 0], x);
+            pre[q] = ok ? x : zmake(0, 0);
         }
     };
-    auto store_rhs = [&](zd *dst) {
+    auto store_rhs = [&](zd *dst) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             int e = tid + q * NT;
-            if (e < nb * CW) dst[e] = pre[q];
+            if (e < NB * CW) dst[e] = pre[q];
         }
     };
 
-    // the pipelined tile stream: s = next batch to consume
-    zd bufA[kSeg], bufB[kSeg];
-    int s = 0;
-    ts.issue(0, bufA);
-    ts.issue(1, bufB);
-    zd acc[CW];
-    auto run_phase = [&](const zd *v) {
-        for (int bp = 0; bp < ts.nbat; bp += 2) {
-            consume<CW, G>(ts, s, bufA, v, acc);
-            ts.issue(s + 2, bufA);
-            consume<CW, G>(ts, s + 1, bufB, v, acc);
-            ts.issue(s + 3, bufB);
-            s += 2;
-        }
-    };
-    auto zero_acc = [&]() {
+    // the pipelined tile stream: bufA / bufB hold the even / odd batches of the tile
+    // being consumed; each consumed batch is replaced by the one two places further
+    // down the sequence (the same tile, or the next one)
+    zd bufA[SH::S], bufB[SH::S];
+    issue_batch<NB>(tile_at(0, 0), 0, bufA);
+    issue_batch<NB>(tile_at(0, 0), 1, bufB);
+    zd acc[R][CW];
+    auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
-        for (int c = 0; c < CW; ++c) acc[c] = zmake(0, 0);
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) acc[q][c] = zmake(0, 0);
+    };
+    auto run_phase = [&](const zd *v, const zd *tcur, const zd *tnext) __attribute__((always_inline)) {
+#pragma unroll
+        for (int bp = 0; bp < SH::NBAT; bp += 2) {
+            consume<CW, NB>(g, bp, bufA, v, acc);
+            if (bp + 2 < SH::NBAT) issue_batch<NB>(tcur, bp + 2, bufA);
+            else issue_batch<NB>(tnext, bp + 2 - SH::NBAT, bufA);
+            consume<CW, NB>(g, bp + 1, bufB, v, acc);
+            if (bp + 3 < SH::NBAT) issue_batch<NB>(tcur, bp + 3, bufB);
+            else issue_batch<NB>(tnext, bp + 3 - SH::NBAT, bufB);
+        }
     };
 
     // ---------------- forward sweep
+    constexpr int GPT = (2 * NB * CW + NT - 1) / NT;     // gathered elements per thread
     prefetch_rhs(0);
     store_rhs(win);
     prefetch_rhs(1);
     for (int k = 0; k < nblk; ++k) {
         const bool last = (k + 1 == nblk);
-        if (!last) store_rhs(win + nb * CW);                 // b_{k+1}
+        if (!last) store_rhs(win + NB * CW);                 // b_{k+1}
         prefetch_rhs(k + 2);                                 // b_{k+2}, used next step
-        if (!last) touch(tiles + int64_t(k + 1) * 5 * te, 2 * te);   // Linv, L21 of step k+1
+        touch(tiles + int64_t(min(k + 1, nblk - 1)) * 5 * te, 2 * te);   // Linv, L21 of step k+1
+        const int rows = last ? NB : 2 * NB;
+        const int32_t *pk = perm + int64_t(k) * 2 * NB;
+        int pr[GPT];
+#pragma unroll
+        for (int q = 0; q < GPT; ++q) pr[q] = pk[min(tid + q * NT, rows * CW - 1) / CW];
         __syncthreads();
-        const int rows = last ? nb : 2 * nb;
-        const int32_t *pk = perm + int64_t(k) * 2 * nb;
-        for (int e = tid; e < rows * CW; e += NT) {
-            int r = e / CW, c = e % CW;
-            win2[e] = win[pk[r] * CW + c];
+#pragma unroll
+        for (int q = 0; q < GPT; ++q) {
+            const int e = min(tid + q * NT, rows * CW - 1);  // past the end: same value again
+            win2[e] = win[pr[q] * CW + e % CW];
         }
         __syncthreads();
         zero_acc();
-        run_phase(win2);                             // y_k = Linv w_top
-        reduce_rows<CW, G>(acc);
+        run_phase(win2, tile_at(k, 0), tile_at(k, 1));       // y_k = Linv w_top
+        reduce_rows<CW, NB>(acc);
         if (writer) {
 #pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                ybuf[i * CW + c] = acc[c];
-                if (c < ncw) yp[int64_t(k) * nb + i + int64_t(c0 + c) * a.npad] = acc[c];
+            for (int q = 0; q < R; ++q) {
+                const int row = slot + SH::SLOTS * q;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    ybuf[row * CW + c] = acc[q][c];
+                    if (c < ncw) yp[int64_t(k) * NB + row + int64_t(c0 + c) * a.npad] = acc[q][c];
+                }
             }
         }
         __syncthreads();
-        if (!last) {
-            zero_acc();
-            run_phase(ybuf);                          // t_{k+1} = w_bot - L21 y_k
-            reduce_rows<CW, G>(acc);
-            if (writer) {
+        zero_acc();
+        // next: Linv_{k+1}, or U1 of the last block to start the backward sweep
+        run_phase(ybuf, tile_at(k, 1), last ? tile_at(k, 3) : tile_at(k + 1, 0));   // t_{k+1} = w_bot - L21 y_k
+        reduce_rows<CW, NB>(acc);
+        if (writer && !last) {
 #pragma unroll
-                for (int c = 0; c < CW; ++c) win[i * CW + c] = zsub(win2[(nb + i) * CW + c], acc[c]);
+            for (int q = 0; q < R; ++q) {
+                const int row = slot + SH::SLOTS * q;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) win[row * CW + c] = zsub(win2[(NB + row) * CW + c], acc[q][c]);
             }
         }
         __syncthreads();
     }
     // ---------------- backward sweep
-    for (int e = tid; e < 3 * nb * CW; e += NT) ring[e] = zmake(0, 0);
+    for (int e = tid; e < 3 * NB * CW; e += NT) ring[e] = zmake(0, 0);
     touch(tiles + int64_t(nblk - 1) * 5 * te + 2 * te, 3 * te);
-    zd ynext[CW];
-    auto load_y = [&](int k, zd *dst) {
+    zd ynext[R][CW];
+    auto load_y = [&](int k, zd (&dst)[R][CW]) {
 #pragma unroll
-        for (int c = 0; c < CW; ++c)
-            dst[c] = (writer && k >= 0 && c < ncw) ? yp[int64_t(k) * nb + i + int64_t(c0 + c) * a.npad]
-                                                  : zmake(0, 0);
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const bool ok = writer && k >= 0 && c < ncw;
+                const zd x = yp[ok ? int64_t(k) * NB + slot + SH::SLOTS * q + int64_t(c0 + c) * a.npad : 0];
+                dst[q][c] = ok ? x : zmake(0, 0);
+            }
     };
     load_y(nblk - 1, ynext);
     __syncthreads();
     for (int k = nblk - 1; k >= 0; --k) {
-        zd *xk = ring + (k % 3) * nb * CW;
-        const zd *xk1 = ring + ((k + 1) % 3) * nb * CW;
-        const zd *xk2 = ring + ((k + 2) % 3) * nb * CW;
-        zd y[CW];
+        zd *xk = ring + (k % 3) * NB * CW;
+        const zd *xk1 = ring + ((k + 1) % 3) * NB * CW;
+        const zd *xk2 = ring + ((k + 2) % 3) * NB * CW;
+        zd y[R][CW];
 #pragma unroll
-        for (int c = 0; c < CW; ++c) y[c] = ynext[c];
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) y[q][c] = ynext[q][c];
         load_y(k - 1, ynext);                                       // y_{k-1}, used next step
-        if (k > 0) touch(tiles + int64_t(k - 1) * 5 * te + 2 * te, 3 * te);   // Uinv, U1, U2 of k-1
+        touch(tiles + int64_t(max(k - 1, 0)) * 5 * te + 2 * te, 3 * te);   // Uinv, U1, U2 of k-1
         // v = y_k - U1 x_{k+1} - U2 x_{k+2}
         zero_acc();
-        run_phase(xk1);
-        run_phase(xk2);
-        reduce_rows<CW, G>(acc);
+        run_phase(xk1, tile_at(k, 3), tile_at(k, 4));
+        run_phase(xk2, tile_at(k, 4), tile_at(k, 2));
+        reduce_rows<CW, NB>(acc);
         if (writer) {
 #pragma unroll
-            for (int c = 0; c < CW; ++c) ybuf[i * CW + c] = zsub(y[c], acc[c]);
+            for (int q = 0; q < R; ++q) {
+                const int row = slot + SH::SLOTS * q;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) ybuf[row * CW + c] = zsub(y[q][c], acc[q][c]);
+            }
         }
         __syncthreads();
         zero_acc();
-        run_phase(ybuf);                                    // x_k = Uinv v
-        reduce_rows<CW, G>(acc);
+        run_phase(ybuf, tile_at(k, 2), tile_at(max(k - 1, 0), 3));   // x_k = Uinv v
+        reduce_rows<CW, NB>(acc);
         if (writer) {
 #pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                xk[i * CW + c] = acc[c];
-                if (c < ncw) xp[int64_t(k) * nb + i + int64_t(c0 + c) * a.npad] = zmul(wgt, acc[c]);
+            for (int q = 0; q < R; ++q) {
+                const int row = slot + SH::SLOTS * q;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    xk[row * CW + c] = acc[q][c];
+                    if (c < ncw) xp[int64_t(k) * NB + row + int64_t(c0 + c) * a.npad] = zmul(wgt, acc[q][c]);
+                }
             }
         }
         __syncthreads();
@@ -933,22 +913,22 @@ static size_t solve_lds(int nb, int cw) {
     return size_t(2 * nb * cw * 2 + nb * cw + 3 * nb * cw) * sizeof(zd);
 }
 
-template <int CW, int G>
-static hipError_t launch_solve_g(const SolveArgs &a, hipStream_t s) {
+template <int CW, int NB>
+static hipError_t launch_solve_nb(const SolveArgs &a, hipStream_t s) {
     const int slices = (a.ncols + CW - 1) / CW;
-    hipLaunchKernelGGL((band_solve_kernel<CW, G>), dim3(slices * a.p), dim3(kSolveThreads),
-                       solve_lds(a.nb, CW), s, a);
+    hipLaunchKernelGGL((band_solve_kernel<CW, NB>), dim3(slices * a.p), dim3(kSolveThreads),
+                       solve_lds(NB, CW), s, a);
     return hipGetLastError();
 }
 
 template <int CW>
 static hipError_t launch_solve_cw(const SolveArgs &a, hipStream_t s) {
-    switch (solve_lanes(a.nb)) {
-        case 2: return launch_solve_g<CW, 2>(a, s);
-        case 4: return launch_solve_g<CW, 4>(a, s);
-        case 8: return launch_solve_g<CW, 8>(a, s);
-        case 16: return launch_solve_g<CW, 16>(a, s);
-        case 32: return launch_solve_g<CW, 32>(a, s);
+    switch (a.nb) {
+        case 16: return launch_solve_nb<CW, 16>(a, s);
+        case 32: return launch_solve_nb<CW, 32>(a, s);
+        case 64: return launch_solve_nb<CW, 64>(a, s);
+        case 128: return launch_solve_nb<CW, 128>(a, s);
+        case 256: return launch_solve_nb<CW, 256>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

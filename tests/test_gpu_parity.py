@@ -88,7 +88,7 @@ def test_inner_apply_tile_override_and_column_slices(rf, torch_cuda):
     A, B = W.convdiff_pencil(12, mass=(0.5, 1.5), seed=5)           # kl = 12
     X = W.start_block(A.shape[0], 16, seed=2)
     ref = filters.InnerOperator(A, B, 300 + 0.05j, 100.0, 3)(X)
-    for tile, cols in [(16, 1), (32, 2), (48, 4), (64, 8)]:
+    for tile, cols in [(16, 1), (32, 2), (64, 4), (128, 8)]:
         _say(f"inner_apply tile={tile} trsm_cols={cols}")
         plan = rf.Plan(A, B, 300 + 0.05j, 100.0, p=3, q=4, w=16, tile=tile, trsm_cols=cols)
         plan.factor_shifts()

@@ -84,6 +84,12 @@ def test_plan_create_rejects_bad_arguments_before_device_work(lib):
     An = rfeig.RfCsr(2, 2, rowptr.ctypes.data, col.ctypes.data, nanval.ctypes.data)
     assert lib.rf_plan_create(ctypes.byref(An), ctypes.byref(A), ctypes.byref(o), None,
                               ctypes.byref(out)) == rfeig.RF_ERR_ARG
+    # tile sizes other than 16, 32, 64, 128, 256
+    for bad in (8, 48, 96, 512):
+        o.tile = bad
+        assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None,
+                                  ctypes.byref(out)) == rfeig.RF_ERR_ARG
+    o.tile = 0
     assert out.value is None
 
 
