@@ -545,8 +545,9 @@ struct SolveArgs {
 // Solve kernel.  One workgroup of kSolveThreads threads owns one pole and a slice
 // of CW right-hand sides and runs the whole forward and backward sweep as nb x nb
 // tile products out = T v.  Tiles are stored whole (the inverted triangles carry
-// explicit zeros), so every product reads its full tile and every thread issues the
-// same loads on every path.  Layout (template on the tile size NB, a power of two):
+// explicit zeros); the parts of a thread's piece that are structurally zero in a
+// triangular tile are skipped at compile time, so every thread issues the same
+// loads on every path.  Layout (template on the tile size NB, a power of two):
 // the NB rows are spread over SLOTS row slots with R rows each (rows s, s + SLOTS,
 // ...), the columns over G lanes (column k = j G + g), so a thread holds an R x KL
 // piece of the tile and each LDS read of v feeds R multiply-adds; the G partial sums
@@ -578,21 +579,33 @@ struct SolveShape {
     static_assert(NBAT % 2 == 0 && S >= 1 && ACTIVE <= kSolveThreads, "solve shape");
 };
 
+// Shape of a tile: full, or triangular with structural zeros (Linv and U2 lower,
+// Uinv upper).  Element (q, j) of a thread's piece covers rows [q SLOTS, (q+1) SLOTS)
+// and columns [j G, j G + G) of the tile; it is skipped when all of it is zero.
+enum : int { kFull = 0, kLower = 1, kUpper = 2 };
+
+template <int NB, int SHAPE>
+__device__ constexpr bool piece_zero(int q, int j) {
+    using SH = SolveShape<NB>;
+    return SHAPE == kLower ? ((q + 1) * SH::SLOTS - 1 < j * SH::G)
+         : SHAPE == kUpper ? (q * SH::SLOTS > j * SH::G + SH::G - 1) : false;
+}
+
 // Load batch b of this thread's piece of tile T (thread corner tp = T + slot + g NB;
 // the element offsets are compile-time constants).
-template <int NB>
+template <int NB, int SHAPE>
 __device__ __attribute__((always_inline)) inline void issue_batch(const zd *tp, int b,
                                                                   zd (&t)[SolveShape<NB>::S]) {
     using SH = SolveShape<NB>;
 #pragma unroll
     for (int e = 0; e < SH::S; ++e) {
         const int E = b * SH::S + e, j = E / SH::R, q = E % SH::R;
-        t[e] = tp[SH::SLOTS * q + j * SH::G * NB];
+        if (!piece_zero<NB, SHAPE>(q, j)) t[e] = tp[SH::SLOTS * q + j * SH::G * NB];
     }
 }
 
 // acc[q][c] += sum over batch b of a tile of T[row_q, k] v[k, c]
-template <int CW, int NB>
+template <int CW, int NB, int SHAPE>
 __device__ __attribute__((always_inline)) inline void consume(int g, int b,
                                                               const zd (&t)[SolveShape<NB>::S],
                                                               const zd *v,
@@ -601,9 +614,30 @@ __device__ __attribute__((always_inline)) inline void consume(int g, int b,
 #pragma unroll
     for (int e = 0; e < SH::S; ++e) {
         const int E = b * SH::S + e, j = E / SH::R, q = E % SH::R;
+        if (piece_zero<NB, SHAPE>(q, j)) continue;
         const zd *vr = v + (j * SH::G + g) * CW;
 #pragma unroll
         for (int c = 0; c < CW; ++c) zfma(acc[q][c], t[e], vr[c]);
+    }
+}
+
+// One tile product of the stream: consume the tile of shape SC held in bufA / bufB
+// (even / odd batches) and request, batch by batch, the rest of it and then the
+// first batches of the next tile, read as shape SN.  A consumer never uses an
+// element its producer skipped: SN is the next tile's shape or kFull.
+template <int CW, int NB, int SC, int SN>
+__device__ __attribute__((always_inline)) inline void run_phase(
+        int g, zd (&bufA)[SolveShape<NB>::S], zd (&bufB)[SolveShape<NB>::S],
+        zd (&acc)[SolveShape<NB>::R][CW], const zd *v, const zd *tcur, const zd *tnext) {
+    using SH = SolveShape<NB>;
+#pragma unroll
+    for (int bp = 0; bp < SH::NBAT; bp += 2) {
+        consume<CW, NB, SC>(g, bp, bufA, v, acc);
+        if (bp + 2 < SH::NBAT) issue_batch<NB, SC>(tcur, bp + 2, bufA);
+        else issue_batch<NB, SN>(tnext, bp + 2 - SH::NBAT, bufA);
+        consume<CW, NB, SC>(g, bp + 1, bufB, v, acc);
+        if (bp + 3 < SH::NBAT) issue_batch<NB, SC>(tcur, bp + 3, bufB);
+        else issue_batch<NB, SN>(tnext, bp + 3 - SH::NBAT, bufB);
     }
 }
 
@@ -704,25 +738,14 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
     // being consumed; each consumed batch is replaced by the one two places further
     // down the sequence (the same tile, or the next one)
     zd bufA[SH::S], bufB[SH::S];
-    issue_batch<NB>(tile_at(0, 0), 0, bufA);
-    issue_batch<NB>(tile_at(0, 0), 1, bufB);
+    issue_batch<NB, kFull>(tile_at(0, 0), 0, bufA);
+    issue_batch<NB, kFull>(tile_at(0, 0), 1, bufB);
     zd acc[R][CW];
     auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < R; ++q)
 #pragma unroll
             for (int c = 0; c < CW; ++c) acc[q][c] = zmake(0, 0);
-    };
-    auto run_phase = [&](const zd *v, const zd *tcur, const zd *tnext) __attribute__((always_inline)) {
-#pragma unroll
-        for (int bp = 0; bp < SH::NBAT; bp += 2) {
-            consume<CW, NB>(g, bp, bufA, v, acc);
-            if (bp + 2 < SH::NBAT) issue_batch<NB>(tcur, bp + 2, bufA);
-            else issue_batch<NB>(tnext, bp + 2 - SH::NBAT, bufA);
-            consume<CW, NB>(g, bp + 1, bufB, v, acc);
-            if (bp + 3 < SH::NBAT) issue_batch<NB>(tcur, bp + 3, bufB);
-            else issue_batch<NB>(tnext, bp + 3 - SH::NBAT, bufB);
-        }
     };
 
     // ---------------- forward sweep
@@ -748,7 +771,8 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         }
         __syncthreads();
         zero_acc();
-        run_phase(win2, tile_at(k, 0), tile_at(k, 1));       // y_k = Linv w_top
+        run_phase<CW, NB, kLower, kFull>(g, bufA, bufB, acc, win2, tile_at(k, 0),
+                                         tile_at(k, 1));          // y_k = Linv w_top
         reduce_rows<CW, NB>(acc);
         if (writer) {
 #pragma unroll
@@ -764,7 +788,8 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         __syncthreads();
         zero_acc();
         // next: Linv_{k+1}, or U1 of the last block to start the backward sweep
-        run_phase(ybuf, tile_at(k, 1), last ? tile_at(k, 3) : tile_at(k + 1, 0));   // t_{k+1} = w_bot - L21 y_k
+        run_phase<CW, NB, kFull, kFull>(g, bufA, bufB, acc, ybuf, tile_at(k, 1),
+                                        last ? tile_at(k, 3) : tile_at(k + 1, 0));   // t_{k+1} = w_bot - L21 y_k
         reduce_rows<CW, NB>(acc);
         if (writer && !last) {
 #pragma unroll
@@ -805,8 +830,8 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         touch(tiles + int64_t(max(k - 1, 0)) * 5 * te + 2 * te, 3 * te);   // Uinv, U1, U2 of k-1
         // v = y_k - U1 x_{k+1} - U2 x_{k+2}
         zero_acc();
-        run_phase(xk1, tile_at(k, 3), tile_at(k, 4));
-        run_phase(xk2, tile_at(k, 4), tile_at(k, 2));
+        run_phase<CW, NB, kFull, kLower>(g, bufA, bufB, acc, xk1, tile_at(k, 3), tile_at(k, 4));
+        run_phase<CW, NB, kLower, kUpper>(g, bufA, bufB, acc, xk2, tile_at(k, 4), tile_at(k, 2));
         reduce_rows<CW, NB>(acc);
         if (writer) {
 #pragma unroll
@@ -818,7 +843,8 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         }
         __syncthreads();
         zero_acc();
-        run_phase(ybuf, tile_at(k, 2), tile_at(max(k - 1, 0), 3));   // x_k = Uinv v
+        run_phase<CW, NB, kUpper, kFull>(g, bufA, bufB, acc, ybuf, tile_at(k, 2),
+                                         tile_at(max(k - 1, 0), 3));   // x_k = Uinv v
         reduce_rows<CW, NB>(acc);
         if (writer) {
 #pragma unroll
