@@ -139,17 +139,22 @@ __device__ inline zd lane_get(zd x, int ln) {
     return zmake(dlane_get(x.x, ln), dlane_get(x.y, ln));
 }
 
-// value of row `row` (wave-uniform) of a column spread as v[s] = row lane + 64 s
-// (every slot is read out with readlane and the slot chosen among the results, so
-// the register array is never indexed dynamically)
+// value of row `row` (wave-uniform) of a column spread as v[s] = row lane + 64 s:
+// a uniform branch picks the slot, so only that slot is read out with readlane
+// (and the register array is never indexed dynamically)
 template <int NS>
-__device__ inline zd row_get(const zd (&v)[NS], int row) {
-    const int sl = row >> 6, ln = row & 63;
-    zd x = lane_get(v[0], ln);
-#pragma unroll
-    for (int s = 1; s < NS; ++s) {
-        zd y = lane_get(v[s], ln);
-        if (s == sl) x = y;
+__device__ __attribute__((always_inline)) inline zd row_get(const zd (&v)[NS], int row) {
+    const int sl = __builtin_amdgcn_readfirstlane(row >> 6), ln = row & 63;
+    zd x;
+    switch (sl) {
+        case 0: x = lane_get(v[0], ln); break;
+        case 1: x = lane_get(v[NS > 1 ? 1 : 0], ln); break;
+        case 2: x = lane_get(v[NS > 2 ? 2 : 0], ln); break;
+        case 3: x = lane_get(v[NS > 3 ? 3 : 0], ln); break;
+        case 4: x = lane_get(v[NS > 4 ? 4 : 0], ln); break;
+        case 5: x = lane_get(v[NS > 5 ? 5 : 0], ln); break;
+        case 6: x = lane_get(v[NS > 6 ? 6 : 0], ln); break;
+        default: x = lane_get(v[NS > 7 ? 7 : 0], ln); break;
     }
     return x;
 }
@@ -172,6 +177,30 @@ __device__ __attribute__((always_inline)) inline void step_update(zd (&x)[NS], c
     }
 }
 
+// Wave-wide argmax of (m, i) by largest m, ties to the smallest i (a total order, so
+// the combination order does not matter), with DPP moves: within each row of 16
+// lanes by shifts of 1, 2, 4, 8, then across rows by the row-15 and row-31
+// broadcasts; lane 63 ends with the result.  Lanes whose DPP source does not exist
+// keep their own value.
+__device__ __attribute__((always_inline)) inline void wave_argmax(double &m, int &i) {
+#define RF_ARGMAX_STEP(CTRL, ROWMASK)                                                         \
+    {                                                                                         \
+        const int lo = __double2loint(m), hi = __double2hiint(m);                             \
+        const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);       \
+        const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);       \
+        const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROWMASK, 0xF, false);          \
+        const double om = __hiloint2double(ohi, olo);                                         \
+        if (om > m || (om == m && oi < i)) { m = om; i = oi; }                                \
+    }
+    RF_ARGMAX_STEP(0x111, 0xF)     // row_shr:1
+    RF_ARGMAX_STEP(0x112, 0xF)     // row_shr:2
+    RF_ARGMAX_STEP(0x114, 0xF)     // row_shr:4
+    RF_ARGMAX_STEP(0x118, 0xF)     // row_shr:8
+    RF_ARGMAX_STEP(0x142, 0xA)     // row_bcast:15 into rows 1 and 3
+    RF_ARGMAX_STEP(0x143, 0xC)     // row_bcast:31 into rows 2 and 3
+#undef RF_ARGMAX_STEP
+}
+
 // Pivot step on a column held as x[s] = row lane + 64 s (sub-panel column j, panel
 // column gj): partial pivoting by largest |.|^2 (ties: smallest row), swap, scale by
 // 1 / pivot, publish the multipliers in lc and the pivot row in s_piv[j]; lane 0
@@ -188,13 +217,26 @@ __device__ __attribute__((always_inline)) inline void panel_pivot(
         double m = zabs2(x[s]);
         if (r >= gj && r < R && m > best) { best = m; bi = r; }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        double ob = __shfl_xor(best, off, 64);
-        int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    wave_argmax(best, bi);                               // lane 63 holds the result
+    const double bmax = dlane_get(best, 63);
+    const bool sing = !(bmax > 0.0);
+    const int p = sing ? gj : __builtin_amdgcn_readlane(bi, 63);
+#ifdef RF_CHECK_ARGMAX
+    {   // cross-check against a butterfly over all lanes (diagnostic builds only)
+        double b2 = -1.0; int i2 = gj;
+        for (int s = 0; s < NS; ++s) {
+            int r = lane + 64 * s;
+            double m = zabs2(x[s]);
+            if (r >= gj && r < R && m > b2) { b2 = m; i2 = r; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            double ob = __shfl_xor(b2, off, 64);
+            int oi = __shfl_xor(i2, off, 64);
+            if (ob > b2 || (ob == b2 && oi < i2)) { b2 = ob; i2 = oi; }
+        }
+        if (lane == 0 && (b2 > 0.0 ? i2 : gj) != p) *s_info = 1;
     }
-    const bool sing = !(best > 0.0);
-    const int p = __builtin_amdgcn_readfirstlane(sing ? gj : bi);
+#endif
     const zd ap = row_get<NS>(x, p), a0 = row_get<NS>(x, gj);
     const zd inv = sing ? zmake(0, 0) : zdiv(zmake(1.0, 0.0), ap);
 #pragma unroll
