@@ -328,7 +328,12 @@ rf_status rf_factor_shifts(rf_plan_t P) {
                              hipMemcpyDeviceToHost, P->stream));
     RF_HIP(P, hipStreamSynchronize(P->stream));
     for (int i = 0; i < P->opts.p; ++i)
-        if (info[i] != 0) {
+        if (info[i] < 0) {
+            P->F.ready = false;
+            return rf_fail(P, RF_ERR_DEVICE,
+                           "band factorization of pole " + std::to_string(i) +
+                               ": a pivot step was not published in time");
+        } else if (info[i] != 0) {
             P->F.ready = false;
             return rf_fail(P, RF_ERR_SINGULAR,
                            "zero pivot in the factorization of pole " + std::to_string(i) +

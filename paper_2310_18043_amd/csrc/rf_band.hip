@@ -208,7 +208,7 @@ __device__ __attribute__((always_inline)) inline void wave_argmax(double &m, int
 template <int NS>
 __device__ __attribute__((always_inline)) inline void panel_pivot(
         zd (&x)[NS], int j, int gj, int R, int lane, zd *lc, int *s_piv, int *idxl, int *pmf,
-        int *s_info, int info_base) {
+        int *s_info, int info_base, int *s_flag) {
     double best = -1.0;
     int bi = gj;
 #pragma unroll
@@ -254,6 +254,24 @@ __device__ __attribute__((always_inline)) inline void panel_pivot(
         t = pmf[gj]; pmf[gj] = pmf[p]; pmf[p] = t;
         if (sing && *s_info == 0) *s_info = info_base + gj + 1;
     }
+    // publish: the wave's multipliers and lane 0's records reach LDS before the flag
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) __hip_atomic_store(&s_flag[j], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Wait until pivot step j has been published.  The wait is bounded: past the bound
+// the step is taken as failed (s_info = -1) and the wave goes on, so no wave can
+// hang; the host reports the failure.
+__device__ __attribute__((always_inline)) inline void wait_flag(int *flag, int *s_info) {
+    int it = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+        if (++it > (1 << 20)) {
+            if (__lane_id() == 0) *s_info = -1;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 template <int NS, int SW>
@@ -265,14 +283,19 @@ __global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, i
     zd *W = pole_window(a.window, pole, buf, nb);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int R = (k + 1 < nblk) ? 2 * nb : nb;
-    __shared__ zd Lcol[2][2 * 256];                       // multipliers, double-buffered
-    __shared__ int idxl[2 * 256], pmf[2 * 256], s_piv[SW];
+    // multipliers of every pivot step of the sub-panel (kept, so that no wave waits
+    // for another to finish reading them)
+    extern __shared__ unsigned char smem_raw[];
+    zd *Lh = reinterpret_cast<zd *>(smem_raw);            // [SW][2nb]
+    const int ldl = 2 * nb;
+    __shared__ int idxl[2 * 256], pmf[2 * 256], s_piv[SW], s_flag[SW];
     __shared__ int s_info;
     int32_t *pm = a.perm + (int64_t(pole) * nblk + k) * (2 * nb);
     for (int r = tid; r < 2 * nb; r += kFacThreads) {
         idxl[r] = r;
         pmf[r] = (c0 == 0) ? r : pm[r];
     }
+    if (tid < SW) s_flag[tid] = 0;
     if (tid == 0) s_info = 0;
     zd v[CPT][NS];
 #pragma unroll
@@ -285,13 +308,17 @@ __global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, i
         }
     }
     __syncthreads();
+    // Pivot steps without workgroup barriers: step j is published by the owner of
+    // column j (flag, pivot row, multipliers); every wave waits only for that.  The
+    // owner of column j+1 applies step j to it first and publishes step j+1, so the
+    // other columns' updates stay off the critical path.
     if (wave == 0)
-        panel_pivot<NS>(v[0], 0, c0, R, lane, Lcol[0], s_piv, idxl, pmf, &s_info, k * nb);
-    __syncthreads();
+        panel_pivot<NS>(v[0], 0, c0, R, lane, Lh, s_piv, idxl, pmf, &s_info, k * nb, s_flag);
     for (int j = 0; j < SW; ++j) {
         const int gj = c0 + j;
+        wait_flag(&s_flag[j], &s_info);
         const int p = __builtin_amdgcn_readfirstlane(s_piv[j]);
-        const zd *lc = Lcol[j & 1];
+        const zd *lc = Lh + j * ldl;
         zd l[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -301,13 +328,14 @@ __global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, i
         // the owner of column j+1 updates it first and finds the next pivot
         const bool owner = (j + 1 < SW) && wave == ((j + 1) % kFacWaves);
         const int ii = (j + 1) / kFacWaves;
+        zd *lnext = Lh + (j + 1) * ldl;
         if (owner) {
             // constant register indices in every branch (no dynamically indexed arrays)
 #define RF_OWNER_STEP(I_)                                                                       \
             case I_:                                                                            \
                 step_update<NS>(v[I_], l, p, gj, lane);                                         \
-                panel_pivot<NS>(v[I_], j + 1, gj + 1, R, lane, Lcol[(j + 1) & 1], s_piv, idxl,  \
-                                pmf, &s_info, k * nb);                                          \
+                panel_pivot<NS>(v[I_], j + 1, gj + 1, R, lane, lnext, s_piv, idxl, pmf,         \
+                                &s_info, k * nb, s_flag);                                       \
                 break;
             switch (ii) {
                 RF_OWNER_STEP(0)
@@ -316,12 +344,12 @@ __global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, i
                 if constexpr (CPT > 2) {
                     if (ii == 2) {
                         step_update<NS>(v[CPT > 2 ? 2 : 0], l, p, gj, lane);
-                        panel_pivot<NS>(v[CPT > 2 ? 2 : 0], j + 1, gj + 1, R, lane, Lcol[(j + 1) & 1],
-                                        s_piv, idxl, pmf, &s_info, k * nb);
+                        panel_pivot<NS>(v[CPT > 2 ? 2 : 0], j + 1, gj + 1, R, lane, lnext, s_piv,
+                                        idxl, pmf, &s_info, k * nb, s_flag);
                     } else {
                         step_update<NS>(v[CPT > 3 ? 3 : 0], l, p, gj, lane);
-                        panel_pivot<NS>(v[CPT > 3 ? 3 : 0], j + 1, gj + 1, R, lane, Lcol[(j + 1) & 1],
-                                        s_piv, idxl, pmf, &s_info, k * nb);
+                        panel_pivot<NS>(v[CPT > 3 ? 3 : 0], j + 1, gj + 1, R, lane, lnext, s_piv,
+                                        idxl, pmf, &s_info, k * nb, s_flag);
                     }
                 }
             }
@@ -343,8 +371,8 @@ __global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, i
                 }
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
         const int col = c0 + wave + kFacWaves * i;
@@ -946,7 +974,8 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
             const dim3 tg((total + kFacWaves - 1) / kFacWaves, p);
             const size_t tl = trail_lds(sw);
 #define RF_FAC_LAUNCH(NS_, SW_)                                                                   \
-            hipLaunchKernelGGL((band_panel_kernel<NS_, SW_>), dim3(p), dim3(kFacThreads), 0, s, a, \
+            hipLaunchKernelGGL((band_panel_kernel<NS_, SW_>), dim3(p), dim3(kFacThreads),          \
+                               size_t(SW_) * 2 * nb * sizeof(zd), s, a, \
                                k, buf, c0);                                                      \
             hipLaunchKernelGGL((band_trail_kernel<NS_, SW_>), tg, dim3(kFacThreads), tl, s, a, k,  \
                                buf, c0)
