@@ -72,6 +72,7 @@ typedef struct {
     int32_t tile;            /* band tile size nb: 16, 32, 64, 128 or 256, >= the bandwidth (0 = automatic: the smallest such) */
     int32_t trsm_cols;       /* right-hand sides per band-solve workgroup: 1, 2 or 4 (0 = automatic, 3 and 5..8 act as 4) */
     uint64_t seed;           /* seed of the start block when none is given */
+    int32_t q_max;           /* largest outer node count of rf_solve_region_adaptive (0 = q) */
 } rf_opts;
 
 /* Per-call statistics of a filter application. */
@@ -104,7 +105,7 @@ typedef struct {
 typedef struct rf_plan *rf_plan_t;
 
 /* Defaults: p = 4, q = 8, w = 32, tau = 1e-10, tau_g = 1e-2, gmres_tol = 1e-12,
- * max_subspace_it = 10, max_krylov_blocks = 150, sigma = c, seed = 0. */
+ * max_subspace_it = 10, max_krylov_blocks = 150, sigma = c, seed = 0, q_max = 0. */
 void rf_default_opts(rf_opts *opts);
 
 /* Copy the pencil to the device, compute the trapezoidal poles/weights of the
@@ -138,6 +139,19 @@ rf_status rf_filter_apply(rf_plan_t plan, const void *Y, int64_t ldy, int32_t nc
  * rf_factor_shifts first if it has not run.  RF_ERR_NOCONV if the sweep cap
  * is reached (results still filled in). */
 rf_status rf_solve_region(rf_plan_t plan, const void *Y0, int64_t ldy, rf_result *res);
+
+/* Alg. composite2 (Sec. 3.2): the composite filter without subspace iteration.
+ * Y0 (device n x w, NULL = seeded Gaussian) is orthonormalised once and
+ * Ytilde = G(Y0) is formed once; then for k2 = q, 2q, 4q, ... <= q_max the outer
+ * solves (G - s_j I) U_j = Ytilde are solved for ALL k2 shifts on the one shared,
+ * growing Krylov basis (the shifts of 2 k2 nodes do not contain those of k2, so
+ * none are reused), U = sum_j c'_j U_j = R_{c,r,p k2}(B^{-1}A) Y0, and HSRR with the
+ * ghost test runs on U; the loop stops when the filtered count repeats (or equals
+ * expected_count at the first level) and every filtered error is <= tau.
+ * res->sweeps = levels used, res->krylov_steps[t] = basis depth at level t.
+ * q_max of the plan must be >= q (the plan sizes the per-shift storage by it).
+ * RF_ERR_NOCONV when q_max is reached first (results still filled in). */
+rf_status rf_solve_region_adaptive(rf_plan_t plan, const void *Y0, int64_t ldy, rf_result *res);
 
 /* Timing of the band kernels, for roofline accounting.  Times are summed
  * HIP-event intervals recorded on the plan stream around each launch. */

@@ -72,3 +72,45 @@ def solve_region(A, B, c: complex, r: float, p: int, q: int, Y0: np.ndarray,
     filt = (np.abs(lam - c) < r) & (err < tau_g)
     return SolveResult(lam[filt], X[:, filt], err[filt], lam, err, t, its,
                        converged)
+
+
+def solve_region_adaptive(A, B, c: complex, r: float, p: int, q: int, q_max: int,
+                          Y0: np.ndarray, tau: float = 1e-10, tau_g: float = 1e-2,
+                          sigma=None, s_expected=None) -> SolveResult:
+    """Alg. composite2 (Sec. 3.2): no subspace iteration; the outer node count k2
+    doubles from q while the block stays Y = orth(Y0).
+
+    At level k2 the algorithm forms U = sum_j c_j^{(k2)} (G - s_j^{(k2)} I)^{-1} G(Y)
+    over all k2 outer nodes.  (The shortcut of reusing the k2 solutions and adding
+    only the new nodes relies on s^{(k2)} being a subset of s^{(2 k2)}, which does not
+    hold for the nodes theta_j = (2j - 1) pi / k2; every node is re-solved.)  By the
+    composite identity that sum equals the simple-rule filter with p k2 poles applied
+    to Y, which is what this oracle computes, with direct band solves.  Then HSRR,
+    the ghost test, and the same stopping rule as Alg. composite (the level plays the
+    role of the sweep).  Levels stop at q_max.
+    """
+    A = A.tocsr(); B = B.tocsr()
+    sigma = complex(c) if sigma is None else complex(sigma)
+    Y = hsrr.orth(Y0)
+    prev = None
+    lam = X = err = None
+    converged = False
+    levels = 0
+    k2 = q
+    while k2 <= q_max:
+        levels += 1
+        U = filters.simple_filter(A, B, c, r, p * k2, Y)
+        _, lam, X = hsrr.hsrr(A, B, U, sigma)
+        err = hsrr.rel_errors(A, B, lam, X, c, r)
+        inside = np.abs(lam - c) < r
+        filt = inside & (err < tau_g)
+        count = int(filt.sum())
+        all_small = bool(np.all(err[filt] <= tau))
+        if all_small and (count == prev or (levels == 1 and s_expected is not None
+                                            and count == s_expected)):
+            converged = True
+            break
+        prev = count
+        k2 *= 2
+    filt = (np.abs(lam - c) < r) & (err < tau_g)
+    return SolveResult(lam[filt], X[:, filt], err[filt], lam, err, levels, [], converged)

@@ -61,6 +61,22 @@ bool csr_ok(const rf_csr *M) {
     return true;
 }
 
+// Outer trapezoidal rule with q nodes (Thm. Rcrm, sign as in its proof): sigma_j the
+// roots of z^q = -1, shifts s_j = 1/(1+sigma_j), weights c'_j = sigma_j/(q(1+sigma_j));
+// the root -1 (odd q) contributes the term (1/q) G instead of a shift.
+void outer_rule(int q, std::vector<zd> &shifts, std::vector<zd> &weights, double &extra) {
+    shifts.clear();
+    weights.clear();
+    extra = 0.0;
+    for (int j = 1; j <= q; ++j) {
+        std::complex<double> sg = std::polar(1.0, (2.0 * j - 1.0) * kPi / q);
+        if (std::abs(1.0 + sg) < 1e-12) { extra = 1.0 / q; continue; }
+        std::complex<double> sj = 1.0 / (1.0 + sg), cj = sg / (double(q) * (1.0 + sg));
+        shifts.push_back(Z(sj.real(), sj.imag()));
+        weights.push_back(Z(cj.real(), cj.imag()));
+    }
+}
+
 void band_extent(const rf_csr *M, int &kl, int &ku) {
     for (int32_t i = 0; i < M->n; ++i)
         for (int64_t e = M->rowptr[i]; e < M->rowptr[i + 1]; ++e) {
@@ -114,6 +130,7 @@ void rf_default_opts(rf_opts *o) {
     o->tile = 0;
     o->trsm_cols = 0;
     o->seed = 0;
+    o->q_max = 0;
 }
 
 const char *rf_status_str(rf_status s) {
@@ -161,6 +178,7 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     if (o.tile < 0 || o.tile > 256 || (o.tile > 0 && (o.tile < 16 || (o.tile & (o.tile - 1)) != 0)))
         return RF_ERR_ARG;
     if (o.trsm_cols < 0 || o.trsm_cols > 8) return RF_ERR_ARG;
+    if (o.q_max < 0 || o.q_max > 256) return RF_ERR_ARG;
 
     rf_plan *P = new rf_plan();
     P->opts = o;
@@ -219,16 +237,13 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
         P->poles.push_back(Z(pole.real(), pole.imag()));
         P->weights.push_back(Z(wgt.real(), wgt.imag()));
     }
-    // outer rule: sigma_j roots of z^q = -1; s_j = 1/(1+sigma_j),
-    // c'_j = (1/q) sigma_j/(1+sigma_j); the root -1 (odd q) contributes (1/q) G.
-    for (int j = 1; j <= o.q; ++j) {
-        std::complex<double> sg = std::polar(1.0, (2.0 * j - 1.0) * kPi / o.q);
-        if (std::abs(1.0 + sg) < 1e-12) { P->oextra = 1.0 / o.q; continue; }
-        std::complex<double> sj = 1.0 / (1.0 + sg), cj = sg / (double(o.q) * (1.0 + sg));
-        P->shifts.push_back(Z(sj.real(), sj.imag()));
-        P->oweights.push_back(Z(cj.real(), cj.imag()));
-    }
+    outer_rule(o.q, P->shifts, P->oweights, P->oextra);
     const int nq = int(P->shifts.size());
+    // least-squares storage covers the largest outer rule the plan may use
+    std::vector<zd> sh_max, ow_max;
+    double ex_max = 0.0;
+    outer_rule(std::max(o.q, o.q_max), sh_max, ow_max, ex_max);
+    const int nq_alloc = std::max(nq, int(sh_max.size()));
 
     // Krylov sub-block width
     int b = o.subblock;
@@ -248,8 +263,8 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     st = upload_csr(P, B, P->B); if (st != RF_OK) return fail(st);
     ALLOC(P->d_poles, o.p);
     ALLOC(P->d_weights, o.p);
-    ALLOC(P->d_shifts, std::max(nq, 1));
-    ALLOC(P->d_oweights, std::max(nq, 1));
+    ALLOC(P->d_shifts, std::max(nq_alloc, 1));
+    ALLOC(P->d_oweights, std::max(nq_alloc, 1));
     if (hipMemcpy(P->d_poles, P->poles.data(), sizeof(zd) * o.p, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(P->d_weights, P->weights.data(), sizeof(zd) * o.p, hipMemcpyHostToDevice) != hipSuccess ||
         (nq > 0 && hipMemcpy(P->d_shifts, P->shifts.data(), sizeof(zd) * nq, hipMemcpyHostToDevice) != hipSuccess) ||
@@ -277,7 +292,7 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     ALLOC(P->V, int64_t(P->nsub) * n * ldc);
     ALLOC(P->Hm, int64_t(P->nsub) * ldc * mb);
     ALLOC(P->R0, int64_t(P->nsub) * b * b);
-    const int64_t nqs = int64_t(std::max(nq, 1)) * P->nsub;
+    const int64_t nqs = int64_t(std::max(nq_alloc, 1)) * P->nsub;
     ALLOC(P->lsQ, nqs * P->mmax * 4 * b * b);
     ALLOC(P->lsR, nqs * mb * mb);
     ALLOC(P->lsG, nqs * ldc * b);
@@ -467,38 +482,47 @@ rf_status cholqr2_batched_fixup(rf_plan *P, zd *W, int64_t sW, const zd *backup,
     return RF_OK;
 }
 
-// U = sum_j c'_j (G - s_j I)^{-1} G(Y) by block multi-shift GMRES: w/b independent
-// sub-blocks of width b, each with its own block-Arnoldi basis, advanced together
-// (one application of G to all active sub-blocks per step) until every column of
-// every sub-block meets the tolerance for every shift.
-rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
-                      rf_filter_info *info) {
-    const double t0 = now_ms();
+// Block multi-shift GMRES on w/b independent sub-blocks of width b, each with its own
+// block-Arnoldi basis of G; the basis of Ytilde = G(Y) is shared by every shift
+// (the shift invariance of the Krylov space, Sec. 3.2).  The work is split so that
+// the basis can outlive one outer rule (Alg. composite2):
+//   krylov_start    Ytilde = G(Y), unit columns, first basis block;
+//   krylov_rule     install an outer rule: E1 R0 right-hand sides and the least
+//                   squares of every shift replayed over the existing depth;
+//   krylov_advance  block-Arnoldi steps until every column of every sub-block meets
+//                   the tolerance for every shift;
+//   krylov_combine  U = sum_j c'_j (G - s_j I)^{-1} Ytilde (+ (1/q) Ytilde, odd q).
+struct KrylovState {
+    std::vector<int> msteps;   // basis depth (blocks) per sub-block
+    std::vector<double> scale; // column norms of Ytilde
+    int64_t inner_cols = 0;
+    int steps = 0;
+    double worst = 0.0;
+    bool converged = true;
+};
+
+rf_status krylov_start(rf_plan *P, const zd *Y, int64_t ldy, KrylovState &K) {
     hipStream_t s = P->stream;
     const int64_t n = P->n;
     const int w = P->opts.w, b = P->b, nsub = P->nsub, mmax = P->mmax;
-    const int nq = int(P->shifts.size());
-    const int64_t ldc = int64_t(mmax + 1) * b, mbmax = int64_t(mmax) * b;
-    const int64_t vstride = n * ldc;                 // per sub-block basis
-    const int64_t hstride = ldc * mbmax;
-    const int64_t bb = int64_t(b) * b;
-    int64_t inner_cols = 0;
-    int *d_active = P->d_active;
-    int *h_active = P->h_pinned_int;                 // pinned host mirror of d_active
-
+    const int64_t ldc = int64_t(mmax + 1) * b;
+    const int64_t vstride = n * ldc;
+    K = KrylovState();
+    K.msteps.assign(nsub, 0);
     // Ytilde = G(Y)
     RF_HIP(P, launch_inner_apply(*P, Y, ldy, w, P->ytil, n, s));
-    inner_cols += w;
+    K.inner_cols += w;
     // The outer solves are column-wise linear in Ytilde: solve for unit-norm
     // columns (so every column meets the relative tolerance on its own scale,
     // whatever the spread of |R_p(lambda)| across the block) and scale back.
     double *d_scale = P->colnorm;          // w column norms
     double *d_inv = P->colnorm + w;        // w inverse norms
     RF_HIP(P, launch_colnorms(n, w, P->ytil, n, nullptr, 0, nullptr, d_scale, s));
-    std::vector<double> nrm(w), inv(w), ones(w, 1.0);
-    RF_HIP(P, hipMemcpyAsync(nrm.data(), d_scale, sizeof(double) * w, hipMemcpyDeviceToHost, s));
+    std::vector<double> inv(w), ones(w, 1.0);
+    K.scale.resize(w);
+    RF_HIP(P, hipMemcpyAsync(K.scale.data(), d_scale, sizeof(double) * w, hipMemcpyDeviceToHost, s));
     RF_HIP(P, hipStreamSynchronize(s));
-    for (int c = 0; c < w; ++c) inv[c] = nrm[c] > 0.0 ? 1.0 / nrm[c] : 0.0;
+    for (int c = 0; c < w; ++c) inv[c] = K.scale[c] > 0.0 ? 1.0 / K.scale[c] : 0.0;
     RF_HIP(P, hipMemcpyAsync(d_inv, inv.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
     RF_HIP(P, hipMemcpyAsync(P->r0norm, ones.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
     // V_sb[0] R0_sb = Ytilde_sb D_sb^{-1}   (all sub-blocks at once)
@@ -507,34 +531,86 @@ rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
         RF_HIP(P, launch_scale_cols(n, b, P->V + sb * vstride, n, d_inv + int64_t(sb) * b, s));
     RF_HIP(P, launch_copy_block(n, b, P->V, n, vstride, P->Gin, n, n * b, nsub, s));   // backup
     RF_TRY(cholqr2_batched_enqueue(P, P->V, vstride, nsub, n, b, P->R0, P->tmp));
-    {
-        std::vector<int> st(2 * nsub);
-        std::vector<double> dr(2 * nsub);
-        RF_HIP(P, hipMemcpyAsync(st.data(), P->d_status, sizeof(int) * 2 * nsub, hipMemcpyDeviceToHost, s));
-        RF_HIP(P, hipMemcpyAsync(dr.data(), P->d_dratio, sizeof(double) * 2 * nsub, hipMemcpyDeviceToHost, s));
+    std::vector<int> st(2 * nsub);
+    std::vector<double> dr(2 * nsub);
+    RF_HIP(P, hipMemcpyAsync(st.data(), P->d_status, sizeof(int) * 2 * nsub, hipMemcpyDeviceToHost, s));
+    RF_HIP(P, hipMemcpyAsync(dr.data(), P->d_dratio, sizeof(double) * 2 * nsub, hipMemcpyDeviceToHost, s));
+    RF_HIP(P, hipStreamSynchronize(s));
+    RF_TRY(cholqr2_batched_fixup(P, P->V, vstride, P->Gin, n * b, nsub, n, b, P->R0, P->tmp, st, dr));
+    return RF_OK;
+}
+
+// worst residual of sub-block sb over all shifts and columns (host copy)
+double krylov_worst(const rf_plan *P, const std::vector<double> &resid, int sb) {
+    const int nq = int(P->shifts.size()), nsub = P->nsub, b = P->b;
+    double worst = 0.0;
+    for (int l = 0; l < nq; ++l)
+        for (int c = 0; c < b; ++c) worst = std::max(worst, resid[(size_t(l) * nsub + sb) * b + c]);
+    return worst;
+}
+
+// Install the plan's current outer rule (P->shifts / P->oweights) on the existing
+// basis: right-hand sides E1 R0 and the least squares replayed step by step.
+// `open` gets the sub-blocks that do not yet meet the tolerance for every shift.
+rf_status krylov_rule(rf_plan *P, KrylovState &K, std::vector<int> &open) {
+    hipStream_t s = P->stream;
+    const int b = P->b, nsub = P->nsub, mmax = P->mmax;
+    const int nq = int(P->shifts.size());
+    const int64_t ldc = int64_t(mmax + 1) * b, bb = int64_t(b) * b;
+    open.clear();
+    if (nq == 0) return RF_OK;              // q = 1: the filter is (1/q) G(Y) only
+    RF_HIP(P, hipMemcpyAsync(P->d_shifts, P->shifts.data(), sizeof(zd) * nq, hipMemcpyHostToDevice, s));
+    RF_HIP(P, hipMemcpyAsync(P->d_oweights, P->oweights.data(), sizeof(zd) * nq, hipMemcpyHostToDevice, s));
+    RF_HIP(P, hipMemsetAsync(P->lsG, 0, sizeof(zd) * int64_t(nq) * nsub * ldc * b, s));
+    for (int l = 0; l < nq; ++l)
+        RF_HIP(P, launch_copy_block(b, b, P->R0, b, bb, P->lsG + int64_t(l) * nsub * ldc * b, ldc,
+                                    ldc * b, nsub, s));
+    int depth = 0;
+    for (int sb = 0; sb < nsub; ++sb) depth = std::max(depth, K.msteps[sb]);
+    int *h_active = P->h_pinned_int;
+    for (int j = 0; j < depth; ++j) {
+        int nact = 0;
+        for (int sb = 0; sb < nsub; ++sb)
+            if (K.msteps[sb] > j) h_active[nact++] = sb;
+        RF_HIP(P, hipMemcpyAsync(P->d_active, h_active, sizeof(int) * nact, hipMemcpyHostToDevice, s));
+        RF_HIP(P, launch_ls_update(*P, j, P->d_active, nact, s));
+        RF_HIP(P, hipStreamSynchronize(s));    // h_active is reused by the next step
+    }
+    std::vector<double> resid(size_t(nq) * nsub * b);
+    if (depth > 0) {
+        RF_HIP(P, hipMemcpyAsync(resid.data(), P->resid, sizeof(double) * nq * nsub * b,
+                                 hipMemcpyDeviceToHost, s));
         RF_HIP(P, hipStreamSynchronize(s));
-        RF_TRY(cholqr2_batched_fixup(P, P->V, vstride, P->Gin, n * b, nsub, n, b, P->R0, P->tmp, st, dr));
     }
-    // right-hand sides E1 R0 per (shift, sub-block)
-    if (nq > 0) {
-        RF_HIP(P, hipMemsetAsync(P->lsG, 0, sizeof(zd) * int64_t(nq) * nsub * ldc * b, s));
-        for (int l = 0; l < nq; ++l)
-            RF_HIP(P, launch_copy_block(b, b, P->R0, b, bb, P->lsG + int64_t(l) * nsub * ldc * b, ldc,
-                                        ldc * b, nsub, s));
-    }
-    std::vector<int> active(nsub), msteps(nsub, 0);
-    std::iota(active.begin(), active.end(), 0);
+    for (int sb = 0; sb < nsub; ++sb)
+        if (K.msteps[sb] == 0 || !(krylov_worst(P, resid, sb) <= P->opts.gmres_tol)) open.push_back(sb);
+    return RF_OK;
+}
+
+// Block-Arnoldi steps for the sub-blocks in `active` until each meets the tolerance.
+// uniform: every sub-block of `active` keeps stepping until all of them meet it
+// (their depths stay equal, as the adaptive form needs); otherwise each stops on
+// its own.  The sub-blocks of `active` must all be at the same depth.
+rf_status krylov_advance(rf_plan *P, KrylovState &K, std::vector<int> active, bool uniform) {
+    hipStream_t s = P->stream;
+    const int64_t n = P->n;
+    const int b = P->b, nsub = P->nsub, mmax = P->mmax;
+    const int nq = int(P->shifts.size());
+    const int64_t ldc = int64_t(mmax + 1) * b, mbmax = int64_t(mmax) * b;
+    const int64_t vstride = n * ldc;
+    const int64_t hstride = ldc * mbmax;
+    const int64_t bb = int64_t(b) * b;
+    int *d_active = P->d_active;
+    int *h_active = P->h_pinned_int;                 // pinned host mirror of d_active
     std::vector<double> resid(size_t(std::max(nq, 1)) * nsub * b);
     std::vector<int> st(2 * nsub);
     std::vector<double> dr(2 * nsub);
-    double worst_final = 0.0;
-    bool all_conv = true;
-    int steps = 0;
-    if (nq == 0) active.clear();         // q = 1: the filter is (1/q) G(Y) only
+    if (nq == 0) active.clear();
     zd *h1 = P->hbuf;                    // nsub x ((mmax+1)b x b), by active position
     zd *h2 = P->hbuf + int64_t(nsub) * ldc * b;
     zd *Rn = P->rnew;                    // nsub x (b x b)
-    for (int j = 0; j < mmax && !active.empty(); ++j) {
+    int j0 = active.empty() ? 0 : K.msteps[active[0]];
+    for (int j = j0; j < mmax && !active.empty(); ++j) {
         const int nact = int(active.size());
         const int kb = (j + 1) * b;
         for (int a = 0; a < nact; ++a) h_active[a] = active[a];
@@ -543,7 +619,7 @@ rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
         RF_HIP(P, launch_copy_block(n, b, P->V + int64_t(j) * b * n, n, vstride, P->Gin, n, n * b,
                                     nact, s, d_active, kMapA));
         RF_HIP(P, launch_inner_apply(*P, P->Gin, n, nact * b, P->Wk, n, s));
-        inner_cols += int64_t(nact) * b;
+        K.inner_cols += int64_t(nact) * b;
         // block classical Gram-Schmidt, twice: h = V^H W; W -= V h
         zd *hp[2] = {h1, h2};
         for (int pass = 0; pass < 2; ++pass) {
@@ -580,31 +656,47 @@ rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
         RF_HIP(P, hipMemcpyAsync(resid.data(), P->resid, sizeof(double) * nq * nsub * b,
                                  hipMemcpyDeviceToHost, s));
         RF_HIP(P, hipStreamSynchronize(s));
-        steps = j + 1;
+        K.steps = std::max(K.steps, j + 1);
         std::vector<int> still;
+        bool any_open = false;
         for (int sb : active) {
-            double worst = 0.0;
-            for (int l = 0; l < nq; ++l)
-                for (int c = 0; c < b; ++c) worst = std::max(worst, resid[(size_t(l) * nsub + sb) * b + c]);
-            msteps[sb] = j + 1;
-            if (!(worst <= P->opts.gmres_tol) && j + 1 < mmax) still.push_back(sb);
+            K.msteps[sb] = j + 1;
+            if (!(krylov_worst(P, resid, sb) <= P->opts.gmres_tol)) any_open = true;
+        }
+        for (int sb : active) {
+            const double worst = krylov_worst(P, resid, sb);
+            const bool open = uniform ? any_open : !(worst <= P->opts.gmres_tol);
+            if (open && j + 1 < mmax) still.push_back(sb);
             else {
-                if (!(worst <= P->opts.gmres_tol)) all_conv = false;
-                worst_final = std::max(worst_final, worst);
+                if (!(worst <= P->opts.gmres_tol)) K.converged = false;
+                K.worst = std::max(K.worst, worst);
             }
         }
         active.swap(still);
     }
-    // solve the triangular systems, combine shifts, U_sb = V_sb Ycomb_sb D_sb
+    return RF_OK;
+}
+
+// solve the triangular systems, combine shifts, U_sb = V_sb Ycomb_sb D_sb
+rf_status krylov_combine(rf_plan *P, KrylovState &K, zd *U, int64_t ldu) {
+    hipStream_t s = P->stream;
+    const int64_t n = P->n;
+    const int b = P->b, nsub = P->nsub, mmax = P->mmax;
+    const int64_t ldc = int64_t(mmax + 1) * b, mbmax = int64_t(mmax) * b;
+    const int64_t vstride = n * ldc;
+    const double *d_scale = P->colnorm;
+    int *h_active = P->h_pinned_int;
+    RF_HIP(P, hipMemcpyAsync(P->colnorm, K.scale.data(), sizeof(double) * P->opts.w,
+                             hipMemcpyHostToDevice, s));
     for (int sb = 0; sb < nsub; ++sb) {
-        const int m = msteps[sb];
+        const int m = K.msteps[sb];
         zd *Us = U + int64_t(sb) * b * ldu;
-        if (m == 0) {
+        if (m == 0 || P->shifts.empty()) {
             RF_HIP(P, hipMemset2DAsync(Us, ldu * sizeof(zd), 0, n * sizeof(zd), b, s));
         } else {
             h_active[sb] = sb;
-            RF_HIP(P, hipMemcpyAsync(d_active + sb, h_active + sb, sizeof(int), hipMemcpyHostToDevice, s));
-            RF_HIP(P, launch_ls_solve(*P, m, d_active + sb, 1, s));
+            RF_HIP(P, hipMemcpyAsync(P->d_active + sb, h_active + sb, sizeof(int), hipMemcpyHostToDevice, s));
+            RF_HIP(P, launch_ls_solve(*P, m, P->d_active + sb, 1, s));
             RF_HIP(P, launch_gemm_nn(n, m * b, b, Z(1), P->V + sb * vstride, n, 0,
                                      P->ycomb + int64_t(sb) * mbmax * b, mbmax, 0, Z(0), Us, ldu, 0, 1,
                                      s));
@@ -615,14 +707,28 @@ rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
                                         n, Us, ldu, s));
     }
     RF_HIP(P, hipStreamSynchronize(s));
+    return RF_OK;
+}
+
+// U = sum_j c'_j (G - s_j I)^{-1} G(Y) (Alg. composite's filter): a fresh basis,
+// every sub-block stopping on its own.
+rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
+                      rf_filter_info *info) {
+    const double t0 = now_ms();
+    KrylovState K;
+    RF_TRY(krylov_start(P, Y, ldy, K));
+    std::vector<int> open;
+    RF_TRY(krylov_rule(P, K, open));
+    RF_TRY(krylov_advance(P, K, open, false));
+    RF_TRY(krylov_combine(P, K, U, ldu));
     if (info) {
-        info->krylov_steps = steps;
-        info->converged = all_conv ? 1 : 0;
-        info->max_residual = worst_final;
-        info->inner_columns = inner_cols;
+        info->krylov_steps = K.steps;
+        info->converged = K.converged ? 1 : 0;
+        info->max_residual = K.worst;
+        info->inner_columns = K.inner_cols;
         info->ms_total = now_ms() - t0;
     }
-    return all_conv ? RF_OK : RF_ERR_NOCONV;
+    return K.converged ? RF_OK : RF_ERR_NOCONV;
 }
 
 }  // namespace
@@ -742,6 +848,35 @@ rf_status hsrr(rf_plan *P, zd *U, std::vector<std::complex<double>> &lam,
     return RF_OK;
 }
 
+// Copy the last Ritz pairs into the caller's result, converged pairs inside D first.
+rf_status fill_result(rf_plan *P, const std::vector<std::complex<double>> &lam,
+                      const std::vector<double> &err, const std::vector<int> &flags,
+                      rf_result *res) {
+    hipStream_t s = P->stream;
+    const int64_t n = P->n;
+    const int w = P->opts.w;
+    std::vector<int> order(w);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b2) {
+        bool ga = (flags[a] & 7) == 7, gb = (flags[b2] & 7) == 7;
+        return ga > gb;
+    });
+    int count = 0;
+    for (int i = 0; i < w; ++i) {
+        int k = order[i];
+        res->lambda[2 * i] = lam[k].real();
+        res->lambda[2 * i + 1] = lam[k].imag();
+        res->err[i] = err[k];
+        res->flags[i] = flags[k];
+        if ((flags[k] & 7) == 7) ++count;
+        RF_HIP(P, hipMemcpyAsync(static_cast<zd *>(res->X) + int64_t(i) * res->ldx, P->hX + int64_t(k) * n,
+                                 sizeof(zd) * n, hipMemcpyDeviceToDevice, s));
+    }
+    RF_HIP(P, hipStreamSynchronize(s));
+    res->count = count;
+    return RF_OK;
+}
+
 }  // namespace
 
 rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *res) {
@@ -797,31 +932,82 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
         prev = count;
     }
     if (t > P->opts.max_subspace_it) t = P->opts.max_subspace_it;
-    // order: converged pairs inside D first, then the rest
-    std::vector<int> order(w);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b2) {
-        bool ga = (flags[a] & 7) == 7, gb = (flags[b2] & 7) == 7;
-        return ga > gb;
-    });
-    int count = 0;
-    for (int i = 0; i < w; ++i) {
-        int k = order[i];
-        res->lambda[2 * i] = lam[k].real();
-        res->lambda[2 * i + 1] = lam[k].imag();
-        res->err[i] = err[k];
-        res->flags[i] = flags[k];
-        if ((flags[k] & 7) == 7) ++count;
-        RF_HIP(P, hipMemcpyAsync(static_cast<zd *>(res->X) + int64_t(i) * res->ldx, P->hX + int64_t(k) * n,
-                                 sizeof(zd) * n, hipMemcpyDeviceToDevice, s));
-    }
-    RF_HIP(P, hipStreamSynchronize(s));
-    res->count = count;
+    RF_TRY(fill_result(P, lam, err, flags, res));
     res->sweeps = t;
     res->converged = converged ? 1 : 0;
     res->ms_filter = ms_filter;
     res->ms_hsrr = ms_hsrr;
     (void)t_start;
+    return converged ? RF_OK : RF_ERR_NOCONV;
+}
+
+rf_status rf_solve_region_adaptive(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *res) {
+    if (!P) return RF_ERR_ARG;
+    if (P->broken) return rf_fail(P, RF_ERR_STATE, "plan is unusable after a device error");
+    if (!res || !res->lambda || !res->X || !res->err || !res->flags || res->ldx < P->n)
+        return rf_fail(P, RF_ERR_ARG, "bad result buffers");
+    if (Y0 && ldy < P->n) return rf_fail(P, RF_ERR_ARG, "bad start block");
+    if (P->opts.q_max < P->opts.q)
+        return rf_fail(P, RF_ERR_ARG, "q_max of the plan must be at least q");
+    if (!P->F.ready) RF_TRY(rf_factor_shifts(P));
+    hipStream_t s = P->stream;
+    const int64_t n = P->n;
+    const int w = P->opts.w, nsub = P->nsub;
+    zd *Y = P->hX;
+    if (Y0) RF_HIP(P, launch_copy_cols(n, w, static_cast<const zd *>(Y0), ldy, Y, n, s));
+    else RF_HIP(P, launch_gaussian(n, w, Y, n, P->opts.seed, s));
+    RF_TRY(orth_panels(P, Y, n, w));
+    const std::complex<double> c(P->opts.c_re, P->opts.c_im);
+    const double r = P->opts.r;
+    double ms_filter = 0.0, ms_hsrr = 0.0;
+    double t1 = now_ms();
+    KrylovState K;
+    RF_TRY(krylov_start(P, Y, n, K));           // Ytilde = G(Y) once; the basis is kept
+    ms_filter += now_ms() - t1;
+    std::vector<int> all(nsub), open, flags(w);
+    std::iota(all.begin(), all.end(), 0);
+    std::vector<std::complex<double>> lam;
+    std::vector<double> err;
+    int prev = -1, t = 0;
+    bool converged = false;
+    rf_status out = RF_OK;
+    for (int k2 = P->opts.q; k2 <= P->opts.q_max; k2 *= 2, ++t) {
+        t1 = now_ms();
+        outer_rule(k2, P->shifts, P->oweights, P->oextra);
+        out = krylov_rule(P, K, open);
+        if (out == RF_OK && !open.empty()) out = krylov_advance(P, K, all, true);
+        if (out == RF_OK) out = krylov_combine(P, K, P->Wk, n);
+        if (out != RF_OK) break;
+        if (t < 16) res->krylov_steps[t] = K.msteps.empty() ? 0 : K.msteps[0];
+        double t2 = now_ms();
+        ms_filter += t2 - t1;
+        out = hsrr(P, P->Wk, lam, err);
+        ms_hsrr += now_ms() - t2;
+        if (out != RF_OK) break;
+        int count = 0;
+        bool all_small = true;
+        for (int i = 0; i < w; ++i) {
+            bool inside = std::abs(lam[i] - c) < r;
+            bool filt = inside && err[i] < P->opts.tau_g;
+            flags[i] = (inside ? 1 : 0) | (filt ? 2 : 0) | (err[i] <= P->opts.tau ? 4 : 0);
+            if (filt) { ++count; if (!(err[i] <= P->opts.tau)) all_small = false; }
+        }
+        if (all_small && (count == prev || (t == 0 && P->opts.expected_count >= 0 &&
+                                            count == P->opts.expected_count))) {
+            converged = true;
+            ++t;
+            break;
+        }
+        prev = count;
+    }
+    // the plan's own outer rule (q) for later calls
+    outer_rule(P->opts.q, P->shifts, P->oweights, P->oextra);
+    if (out != RF_OK) return out;
+    RF_TRY(fill_result(P, lam, err, flags, res));
+    res->sweeps = t;
+    res->converged = converged ? 1 : 0;
+    res->ms_filter = ms_filter;
+    res->ms_hsrr = ms_hsrr;
     return converged ? RF_OK : RF_ERR_NOCONV;
 }
 

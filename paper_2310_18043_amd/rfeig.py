@@ -44,7 +44,7 @@ class RfOpts(ctypes.Structure):
                 ("max_subspace_it", ctypes.c_int32), ("max_krylov_blocks", ctypes.c_int32),
                 ("subblock", ctypes.c_int32), ("expected_count", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("trsm_cols", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("q_max", ctypes.c_int32)]
 
 
 class RfFilterInfo(ctypes.Structure):
@@ -86,6 +86,8 @@ _lib.rf_filter_apply.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, cty
 _lib.rf_filter_apply.restype = ctypes.c_int
 _lib.rf_solve_region.argtypes = [_P, _P, ctypes.c_int64, ctypes.POINTER(RfResult)]
 _lib.rf_solve_region.restype = ctypes.c_int
+_lib.rf_solve_region_adaptive.argtypes = [_P, _P, ctypes.c_int64, ctypes.POINTER(RfResult)]
+_lib.rf_solve_region_adaptive.restype = ctypes.c_int
 _lib.rf_plan_n.argtypes = [_P]
 _lib.rf_plan_n.restype = ctypes.c_int64
 _lib.rf_plan_device_bytes.argtypes = [_P]
@@ -245,6 +247,15 @@ class Plan:
                    "ms": info.ms_total}
 
     def solve_region(self, Y0=None, allow_noconv=False):
+        """Alg. composite: subspace iteration with the composite filter."""
+        return self._region(_lib.rf_solve_region, Y0, allow_noconv)
+
+    def solve_region_adaptive(self, Y0=None, allow_noconv=False):
+        """Alg. composite2: no subspace iteration, the outer node count doubles from q
+        to the plan's q_max on one shared Krylov basis."""
+        return self._region(_lib.rf_solve_region_adaptive, Y0, allow_noconv)
+
+    def _region(self, fn, Y0, allow_noconv):
         w = self.w
         lam = np.zeros(2 * w)
         err = np.zeros(w)
@@ -258,9 +269,9 @@ class Plan:
         res.flags = flags.ctypes.data
         if Y0 is not None:
             Y0 = as_colmajor(Y0)
-            st = _lib.rf_solve_region(self._h, _P(Y0.data_ptr()), _ld(Y0), ctypes.byref(res))
+            st = fn(self._h, _P(Y0.data_ptr()), _ld(Y0), ctypes.byref(res))
         else:
-            st = _lib.rf_solve_region(self._h, None, 0, ctypes.byref(res))
+            st = fn(self._h, None, 0, ctypes.byref(res))
         self._check(st, allow=(RF_ERR_NOCONV,) if allow_noconv else ())
         lamc = lam[0::2] + 1j * lam[1::2]
         k = res.count

@@ -272,3 +272,47 @@ def test_full_size_solve_region_matches_oracle(rf, torch_cuda, convdiff128):
     e = hsrr.rel_errors(wl.A, wl.B, res["lam"], _to_host(res["X"]), wl.c, wl.r)
     print("max residual (oracle's definition)", e.max())
     assert e.max() <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Alg. composite2: no subspace iteration, outer node count doubling on one basis
+# ---------------------------------------------------------------------------
+def test_solve_region_adaptive_small_convdiff_vs_oracle(rf, torch_cuda):
+    from oracle import hsrr, solver
+    import scipy.linalg as sl
+    n = 20
+    A, B = W.convdiff_pencil(n, mass=(0.5, 1.5), seed=6)
+    lam_all = sl.eigvals(A.toarray(), B.toarray())
+    c = np.sort(lam_all.real)[150] + 0.05j
+    r = W.midgap_radius(lam_all, c, 12)
+    Y0 = W.start_block(n * n, 16, 1)
+    _say("solve_region_adaptive convdiff20")
+    plan = rf.Plan(A, B, c, r, p=4, q=4, q_max=64, w=16, expected_count=12, gmres_tol=1e-13)
+    res = plan.solve_region_adaptive(torch_cuda.from_numpy(Y0).cuda())
+    ref = solver.solve_region_adaptive(A, B, c, r, 4, 4, 64, Y0, s_expected=12)
+    print("levels", res["sweeps"], ref.sweeps, "basis depth", res["krylov_steps"])
+    assert res["converged"] and ref.converged
+    assert res["count"] == len(ref.lam) == 12
+    assert res["sweeps"] == ref.sweeps
+    d = np.abs(res["lam"][:, None] - ref.lam[None, :]).min(axis=1)
+    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+    e = hsrr.rel_errors(A, B, res["lam"], _to_host(res["X"]), c, r)
+    assert e.max() <= 1e-10
+    # the plan's own rule is back in place: filter_apply still matches the simple rule
+    from oracle import filters
+    Y = W.start_block(n * n, 16, seed=3)
+    U, info = plan.filter_apply(torch_cuda.from_numpy(Y).cuda())
+    assert _relerr(_to_host(U), filters.simple_filter(A, B, c, r, 16, Y)) <= 1e-11
+
+
+def test_solve_region_adaptive_toeplitz_closed_form(rf, torch_cuda):
+    wl = W.toeplitz_workload(n=2000, w=32, count=20)
+    _say("solve_region_adaptive toeplitz2000")
+    plan = rf.Plan(wl.A, wl.B, wl.c, wl.r, p=4, q=4, q_max=64, w=32, expected_count=20)
+    res = plan.solve_region_adaptive(torch_cuda.from_numpy(W.start_block(wl.n, 32, 0)).cuda())
+    exact = W.toeplitz_eigs(wl.n, 0, 1, W.TOEPLITZ_C)
+    inside = exact[np.abs(exact - wl.c) < wl.r]
+    assert res["converged"] and res["count"] == len(inside) == 20
+    d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
+    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+    assert res["err"].max() <= 1e-10

@@ -96,3 +96,32 @@ def test_solve_region_random_mass_vs_dense_qz(seed):
     assert res.converged and len(res.lam) == len(inside) == 10
     assert _match(res.lam, inside) <= 1e-9 * abs(c)
     assert res.err.max() <= 1e-10
+
+
+def test_solve_region_adaptive_vs_dense_qz():
+    # Alg. composite2 on a small random-mass pencil: every pair inside the disk,
+    # against dense QZ
+    import scipy.linalg as sl
+    n = 20
+    A, B = W.convdiff_pencil(n, mass=(0.5, 1.5), seed=6)
+    lam_all = sl.eigvals(A.toarray(), B.toarray())
+    c = np.sort(lam_all.real)[150] + 0.05j
+    r = W.midgap_radius(lam_all, c, 12)
+    res = solver.solve_region_adaptive(A, B, c, r, 4, 4, 64, W.start_block(n * n, 16, 1),
+                                       s_expected=12)
+    inside = lam_all[np.abs(lam_all - c) < r]
+    assert res.converged and len(res.lam) == len(inside) == 12
+    d = np.abs(res.lam[:, None] - inside[None, :]).min(axis=1)
+    assert np.all(d <= 1e-11 * np.abs(res.lam)), d.max()
+    assert res.err.max() <= 1e-10
+
+
+def test_solve_region_adaptive_balanced_toeplitz_closed_form():
+    wl = W.toeplitz_workload(n=200, w=16, count=8)
+    res = solver.solve_region_adaptive(wl.A, wl.B, wl.c, wl.r, 4, 4, 64,
+                                       W.start_block(wl.n, 16, 0), s_expected=8)
+    exact = W.toeplitz_eigs(wl.n, 0, 1, W.TOEPLITZ_C)
+    inside = exact[np.abs(exact - wl.c) < wl.r]
+    assert res.converged and len(res.lam) == len(inside)
+    d = np.abs(res.lam[:, None] - inside[None, :]).min(axis=1)
+    assert np.all(d <= 1e-10 * np.abs(inside).max()), d.max()
