@@ -101,6 +101,77 @@ def cpu_baseline(wl, cols_per_step):
     }
 
 
+def batched_form(ndisks, reps):
+    """Many adjacent disks of one pencil (128 x 128 constant-velocity convection-
+    diffusion, B = I, closed-form spectrum): all disks' poles factorized in one
+    launch sequence and the disks solved concurrently, against the same disks run
+    one after another with a plan each.  Counts are checked against the closed form."""
+    import torch
+    from paper_2310_18043_amd import rfeig
+    from paper_2310_18043_amd import workloads as W
+    A, B, disks, exact = W.disk_batch(n=128, ndisks=ndisks)
+    specs = [{"c": d["c"], "r": d["r"], "w": d["w"], "expected_count": d["count"]}
+             for d in disks]
+    common = dict(p=4, q=8, max_krylov_blocks=60)
+    Y0 = [torch.from_numpy(W.start_block(A.shape[0], s["w"], 100 + d)).cuda()
+          for d, s in enumerate(specs)]
+
+    def good(res, s):
+        inside = exact[np.abs(exact - s["c"]) < s["r"]]
+        lam = res["lam"][res["err"] <= 1e-10]
+        if len(lam) == 0:
+            return 0
+        dist = np.abs(lam[:, None] - inside[None, :]).min(axis=1)
+        return int(np.sum(dist <= 1e-10 * np.abs(lam)))
+
+    batch = rfeig.Batch(A, B, specs, **common)
+
+    def step_batched():
+        batch.factor()
+        return batch.solve(Y0, allow_noconv=True)
+
+    step_batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        outs = step_batched()
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) * 1000.0 / reps
+    found_b = sum(good(r, s) for r, s in zip(outs, specs))
+    mem_b = batch.device_bytes
+    batch.close()
+    del batch
+
+    plans = [rfeig.Plan(A, B, s["c"], s["r"], w=s["w"], expected_count=s["expected_count"],
+                        **common) for s in specs]
+
+    def step_seq():
+        res = []
+        for P, y in zip(plans, Y0):
+            P.factor_shifts()
+            res.append(P.solve_region(y, allow_noconv=True))
+        return res
+
+    step_seq()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        outs_s = step_seq()
+    torch.cuda.synchronize()
+    ms_s = (time.perf_counter() - t0) * 1000.0 / reps
+    found_s = sum(good(r, s) for r, s in zip(outs_s, specs))
+    for P in plans:
+        P.close()
+    expected = sum(s["expected_count"] for s in specs)
+    return {"workload": f"convdiff128_I_{ndisks}disks_p4_q8", "disks": ndisks,
+            "widths": [s["w"] for s in specs], "expected_count": expected,
+            "ms_per_step": round(ms_b, 3), "value": round(found_b / (ms_b / 1000.0), 3),
+            "unit": "eigenpairs/s", "converged_count": found_b,
+            "sweeps": [r["sweeps"] for r in outs], "device_gb": round(mem_b / 1e9, 2),
+            "sequential": {"ms_per_step": round(ms_s, 3), "converged_count": found_s,
+                           "value": round(found_s / (ms_s / 1000.0), 3)}}
+
+
 def W_start_block(wl):
     from paper_2310_18043_amd import workloads as W
     return W.start_block(wl.n, wl.w, wl.seed)
@@ -114,6 +185,10 @@ def main():
     ap.add_argument("--subblock", type=int, default=0)
     ap.add_argument("--trsm-cols", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adaptive-qmax", type=int, default=64,
+                    help="also time Alg. composite2 up to this outer node count (0: skip)")
+    ap.add_argument("--batch-disks", type=int, default=16,
+                    help="also time the batched form on this many disks (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -233,6 +308,41 @@ def main():
     }
     log(f"filter_apply: {fa}")
 
+    # Alg. composite2 on the same workload and start block: outer node count doubling
+    # from q to q_max on one Krylov basis, no subspace iteration
+    c2 = None
+    if args.adaptive_qmax > 0:
+        plan2 = rfeig.Plan(wl.A, wl.B, wl.c, wl.r, p=wl.p, q=wl.q, w=wl.w,
+                           expected_count=wl.s_expected, q_max=args.adaptive_qmax,
+                           max_krylov_blocks=60, subblock=args.subblock)
+
+        def step2():
+            plan2.factor_shifts()
+            return plan2.solve_region_adaptive(Y0, allow_noconv=True)
+
+        step2()
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
+        reps2 = max(1, min(args.steps, 2))
+        for _ in range(reps2):
+            r2 = step2()
+        torch.cuda.synchronize()
+        ms2 = (time.perf_counter() - tc0) * 1000.0 / reps2
+        good2 = (np.abs(r2["lam"] - wl.c) < wl.r) & (r2["err"] <= 1e-10)
+        c2 = {"ms_per_step": round(ms2, 3),
+              "value": round(int(good2.sum()) / (ms2 / 1000.0), 3), "unit": "eigenpairs/s",
+              "converged_count": int(good2.sum()), "levels": r2["sweeps"],
+              "q_levels": [wl.q * 2 ** i for i in range(r2["sweeps"])],
+              "basis_depth": r2["krylov_steps"], "q_max": args.adaptive_qmax,
+              "ms_filter": round(r2["ms_filter"], 3), "ms_hsrr": round(r2["ms_hsrr"], 3)}
+        log(f"composite2: {c2}")
+        del plan2
+
+    bt = None
+    if args.batch_disks > 0:
+        bt = batched_form(args.batch_disks, min(args.steps, 2))
+        log(f"batched: {bt}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -257,6 +367,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "filter_apply": fa,
+        "composite2": c2,
+        "batched": bt,
         "phases_ms": {"factor": round(stats["factor_ms"] / max(args.steps, 1), 3),
                       "filter": round(res["ms_filter"], 3), "hsrr": round(res["ms_hsrr"], 3)},
     }

@@ -180,6 +180,57 @@ rf_status rf_profile_read(rf_plan_t plan, rf_kernel_stats *out);
 int rf_dense_eig(int32_t n, const double *A, const double *B, double *alpha, double *beta,
                  double *vr);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: many disks D_d = { |z - c_d| < r_d } of ONE pencil, solved
+ * independently (Sec. 1: the solver covers several regions in parallel to build
+ * up a partial or full eigen-decomposition).  All disks' poles are factorized
+ * together, so the band factorization runs with sum_d p_d independent chains in
+ * one launch sequence, and the disks' subspace iterations run concurrently, each
+ * on a stream and host thread of its own.
+ * ------------------------------------------------------------------------- */
+typedef struct rf_batch *rf_batch_t;
+
+/* opts: host array of ndisks option sets, one per disk (its own c, r, p, q, w,
+ * tolerances); every entry must give the same tile (0 = automatic).  The device
+ * memory is the factor storage of sum_d p_d poles plus each disk's Krylov and
+ * HSRR buffers; the library creates one non-blocking stream per disk and runs
+ * the factorization on hip_stream.  On failure *out may still be set: read
+ * rf_batch_last_error, then rf_batch_destroy it. */
+rf_status rf_batch_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts, int32_t ndisks,
+                          void *hip_stream, rf_batch_t *out);
+
+/* Factorize K_i = p_i B - A for every pole of every disk (the disks' step 2 of
+ * Alg. composite, batched).  RF_ERR_SINGULAR names the first disk with an exactly
+ * singular shifted pencil; then no disk is usable until a later call succeeds. */
+rf_status rf_batch_factor(rf_batch_t batch);
+
+/* The plan of disk d (0 <= d < ndisks; NULL if out of range), owned by the batch:
+ * every per-plan call works on it (rf_filter_apply, rf_solve_region,
+ * rf_solve_region_adaptive, profiling) on the disk's own stream, except
+ * rf_factor_shifts, which returns RF_ERR_STATE: its factors come from
+ * rf_batch_factor. */
+rf_plan_t rf_batch_plan(rf_batch_t batch, int32_t d);
+
+/* Number of disks, or -1. */
+int32_t rf_batch_size(rf_batch_t batch);
+
+/* rf_solve_region for every disk, at most `threads` disks at a time (<= 0: all),
+ * each on its own host thread and stream.  Y0: host array of ndisks device start
+ * blocks (NULL, or a NULL entry: seeded Gaussian), ldy: host array of their leading
+ * dimensions (may be NULL when Y0 is); res: host array of ndisks rf_result, filled
+ * as by rf_solve_region; status: host array of ndisks per-disk return codes.
+ * Returns RF_OK if every disk returned RF_OK, else the code of the first disk that
+ * did not (its message in rf_batch_last_error).  Start blocks written on another
+ * stream must be complete before the call. */
+rf_status rf_batch_solve(rf_batch_t batch, const void *const *Y0, const int64_t *ldy,
+                         rf_result *res, rf_status *status, int32_t threads);
+
+/* Bytes of device memory the batch holds (factor storage and every disk plan). */
+int64_t rf_batch_device_bytes(rf_batch_t batch);
+
+const char *rf_batch_last_error(rf_batch_t batch);
+void rf_batch_destroy(rf_batch_t batch);
+
 /* Problem size n of a plan, or -1. */
 int64_t rf_plan_n(rf_plan_t plan);
 

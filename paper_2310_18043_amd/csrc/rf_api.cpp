@@ -2,6 +2,7 @@
 // subspace iteration (Chen & Li, Alg. composite, Sec. 3.2).  Host code; every
 // step on the n-sized data runs in the kernels of rf_band.hip and rf_dense.hip.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -9,6 +10,7 @@
 #include <limits>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rf_common.h"
@@ -161,8 +163,16 @@ void rf_plan_destroy(rf_plan_t plan) {
     delete plan;
 }
 
-rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
-                         void *hip_stream, rf_plan_t *out) {
+}  // extern "C"
+
+namespace {
+
+// Plan creation.  owner != null: the plan's band factors live in owner's storage,
+// starting at pole `pole_offset` (batched disks); poles != null: factor exactly these
+// poles instead of the disk's trapezoidal nodes (the batch's factor owner).
+rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
+                           void *hip_stream, rf_plan_t *out, const rf_plan *owner,
+                           int pole_offset, const std::vector<zd> *poles) {
     if (!out) return RF_ERR_ARG;
     *out = nullptr;
     if (!opts || !csr_ok(A) || !csr_ok(B) || A->n != B->n) return RF_ERR_ARG;
@@ -237,6 +247,15 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
         P->poles.push_back(Z(pole.real(), pole.imag()));
         P->weights.push_back(Z(wgt.real(), wgt.imag()));
     }
+    if (poles) {
+        if (int(poles->size()) != o.p) return fail(RF_ERR_ARG);
+        P->poles = *poles;
+    }
+    if (owner && (owner->F.nb != nb || owner->n != P->n || pole_offset < 0 ||
+                  pole_offset + o.p > owner->opts.p)) {
+        rf_fail(P, RF_ERR_ARG, "disk does not fit the shared factor storage");
+        return fail(RF_ERR_ARG);
+    }
     outer_rule(o.q, P->shifts, P->oweights, P->oextra);
     const int nq = int(P->shifts.size());
     // least-squares storage covers the largest outer rule the plan may use
@@ -274,12 +293,20 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
         return fail(RF_ERR_DEVICE);
     }
     const int64_t te = P->F.tile_elems;
-    ALLOC(P->F.tiles, int64_t(o.p) * P->F.nblk * 5 * te);
-    ALLOC(P->F.perm, int64_t(o.p) * P->F.nblk * 2 * nb);
-    ALLOC(P->F.window, int64_t(o.p) * 2 * (2 * nb) * (3 * nb));   // double-buffered per pole
-    ALLOC(P->F.info, o.p);
-    ALLOC(P->F.rows, int64_t(o.p) * P->F.nblk * te * 3);
-    ALLOC(P->F.subperm, int64_t(o.p) * 2 * nb);
+    if (owner) {
+        // factors of poles pole_offset .. pole_offset + p - 1 of the owner
+        P->shared_factors = true;
+        P->F.tiles = owner->F.tiles + int64_t(pole_offset) * P->F.nblk * 5 * te;
+        P->F.perm = owner->F.perm + int64_t(pole_offset) * P->F.nblk * 2 * nb;
+        P->F.info = owner->F.info + pole_offset;
+    } else {
+        ALLOC(P->F.tiles, int64_t(o.p) * P->F.nblk * 5 * te);
+        ALLOC(P->F.perm, int64_t(o.p) * P->F.nblk * 2 * nb);
+        ALLOC(P->F.window, int64_t(o.p) * 2 * (2 * nb) * (3 * nb));   // double-buffered per pole
+        ALLOC(P->F.info, o.p);
+        ALLOC(P->F.rows, int64_t(o.p) * P->F.nblk * te * 3);
+        ALLOC(P->F.subperm, int64_t(o.p) * 2 * nb);
+    }
     const int64_t n = P->n, w = o.w;
     ALLOC(P->rhs, npad * w);
     ALLOC(P->ypart, int64_t(o.p) * npad * w);
@@ -331,9 +358,20 @@ rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     return RF_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
+                         void *hip_stream, rf_plan_t *out) {
+    return plan_create_impl(A, B, opts, hip_stream, out, nullptr, 0, nullptr);
+}
+
 rf_status rf_factor_shifts(rf_plan_t P) {
     if (!P) return RF_ERR_ARG;
     if (P->broken) return rf_fail(P, RF_ERR_STATE, "plan is unusable after a device error");
+    if (P->shared_factors)
+        return rf_fail(P, RF_ERR_STATE, "the factors of a batched disk come from rf_batch_factor");
     hipEvent_t ev0 = nullptr;
     P->prof.record_begin(P->stream, ev0);
     RF_HIP(P, launch_band_factor(*P, P->stream));
@@ -1090,6 +1128,177 @@ rf_status rf_profile_read(rf_plan_t P, rf_kernel_stats *out) {
     RF_HIP(P, P->prof.drain());
     *out = P->prof.stats;
     return RF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form: several disks of one pencil (Sec. 1: regions handled in parallel).
+// One factor owner holds the band factors of every disk's poles and factorizes
+// them with one launch sequence; each disk is an ordinary plan whose factor
+// pointers address its slice of that storage and which runs on a stream of its own.
+// ---------------------------------------------------------------------------
+struct rf_batch {
+    rf_plan *owner = nullptr;
+    std::vector<rf_plan *> disks;
+    std::vector<hipStream_t> streams;
+    std::string last_error;
+};
+
+namespace {
+
+rf_status batch_fail(rf_batch *Bt, rf_status s, const std::string &msg) {
+    Bt->last_error = msg;
+    return s;
+}
+
+void batch_free(rf_batch *Bt) {
+    for (rf_plan *d : Bt->disks) rf_plan_destroy(d);
+    if (Bt->owner) rf_plan_destroy(Bt->owner);
+    for (hipStream_t s : Bt->streams) (void)hipStreamDestroy(s);
+    delete Bt;
+}
+
+}  // namespace
+
+extern "C" {
+
+rf_status rf_batch_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts, int32_t ndisks,
+                          void *hip_stream, rf_batch_t *out) {
+    if (!out) return RF_ERR_ARG;
+    *out = nullptr;
+    if (!opts || ndisks < 1 || !csr_ok(A) || !csr_ok(B) || A->n != B->n) return RF_ERR_ARG;
+    int64_t ptot = 0;
+    for (int d = 0; d < ndisks; ++d) {
+        if (opts[d].p < 1 || opts[d].tile != opts[0].tile) return RF_ERR_ARG;
+        ptot += opts[d].p;
+    }
+    if (ptot > (int64_t(1) << 20)) return RF_ERR_ARG;
+    rf_batch *Bt = new rf_batch();
+    auto fail = [&](rf_status s) {
+        *out = Bt;  // kept so the caller can read rf_batch_last_error, then destroy
+        return s;
+    };
+    // the owner's poles: every disk's trapezoidal nodes, disk after disk (eq. pwtp)
+    std::vector<zd> poles;
+    for (int d = 0; d < ndisks; ++d) {
+        const rf_opts &o = opts[d];
+        for (int i = 1; i <= o.p; ++i) {
+            std::complex<double> pole = std::complex<double>(o.c_re, o.c_im) +
+                                        o.r * std::polar(1.0, (2.0 * i - 1.0) * kPi / o.p);
+            poles.push_back(Z(pole.real(), pole.imag()));
+        }
+    }
+    // the owner only factorizes: one column, one Krylov block
+    rf_opts oo = opts[0];
+    oo.p = int32_t(ptot);
+    oo.q = 1;
+    oo.q_max = 0;
+    oo.w = 1;
+    oo.subblock = 0;
+    oo.max_krylov_blocks = 1;
+    rf_status st = plan_create_impl(A, B, &oo, hip_stream, &Bt->owner, nullptr, 0, &poles);
+    if (st != RF_OK) {
+        return fail(batch_fail(Bt, st, std::string("factor storage: ") +
+                                           (Bt->owner ? Bt->owner->last_error : rf_status_str(st))));
+    }
+    int off = 0;
+    for (int d = 0; d < ndisks; ++d) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(batch_fail(Bt, RF_ERR_DEVICE, "stream creation failed"));
+        }
+        Bt->streams.push_back(s);
+        rf_plan *P = nullptr;
+        st = plan_create_impl(A, B, &opts[d], s, &P, Bt->owner, off, nullptr);
+        if (P) Bt->disks.push_back(P);
+        if (st != RF_OK) {
+            return fail(batch_fail(Bt, st, "disk " + std::to_string(d) + ": " +
+                                               (P ? P->last_error : std::string(rf_status_str(st)))));
+        }
+        off += opts[d].p;
+    }
+    *out = Bt;
+    return RF_OK;
+}
+
+rf_status rf_batch_factor(rf_batch_t Bt) {
+    if (!Bt || !Bt->owner || Bt->disks.empty()) return RF_ERR_ARG;
+    for (rf_plan *d : Bt->disks) d->F.ready = false;
+    rf_status st = rf_factor_shifts(Bt->owner);
+    if (st != RF_OK) {
+        std::string msg = Bt->owner->last_error;
+        if (st == RF_ERR_SINGULAR) {
+            // name the disk of the first singular pole
+            std::vector<int32_t> info(Bt->owner->opts.p);
+            if (hipMemcpy(info.data(), Bt->owner->F.info, sizeof(int32_t) * info.size(),
+                          hipMemcpyDeviceToHost) == hipSuccess) {
+                int off = 0;
+                for (size_t d = 0; d < Bt->disks.size(); ++d) {
+                    bool bad = false;
+                    for (int i = 0; i < Bt->disks[d]->opts.p; ++i) bad |= info[off + i] != 0;
+                    if (bad) { msg = "disk " + std::to_string(d) + ": " + msg; break; }
+                    off += Bt->disks[d]->opts.p;
+                }
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        return batch_fail(Bt, st, msg);
+    }
+    // rf_factor_shifts has drained the owner stream: the factors are complete
+    for (rf_plan *d : Bt->disks) d->F.ready = true;
+    return RF_OK;
+}
+
+rf_plan_t rf_batch_plan(rf_batch_t Bt, int32_t d) {
+    if (!Bt || d < 0 || d >= int32_t(Bt->disks.size())) return nullptr;
+    return Bt->disks[d];
+}
+
+int32_t rf_batch_size(rf_batch_t Bt) { return Bt ? int32_t(Bt->disks.size()) : -1; }
+
+rf_status rf_batch_solve(rf_batch_t Bt, const void *const *Y0, const int64_t *ldy, rf_result *res,
+                         rf_status *status, int32_t threads) {
+    if (!Bt || !res || !status || Bt->disks.empty()) return RF_ERR_ARG;
+    const int nd = int(Bt->disks.size());
+    for (rf_plan *d : Bt->disks)
+        if (!d->F.ready) return batch_fail(Bt, RF_ERR_STATE, "rf_batch_factor has not succeeded");
+    const int nt = std::max(1, std::min(threads <= 0 ? nd : int(threads), nd));
+    const int dev = Bt->owner->device;
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        if (hipSetDevice(dev) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int d; (d = next.fetch_add(1)) < nd;) status[d] = RF_ERR_DEVICE;
+            return;
+        }
+        for (int d; (d = next.fetch_add(1)) < nd;)
+            status[d] = rf_solve_region(Bt->disks[d], Y0 ? Y0[d] : nullptr, ldy ? ldy[d] : 0, &res[d]);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &t : pool) t.join();
+    for (int d = 0; d < nd; ++d)
+        if (status[d] != RF_OK)
+            return batch_fail(Bt, status[d], "disk " + std::to_string(d) + ": " +
+                                                 Bt->disks[d]->last_error);
+    return RF_OK;
+}
+
+const char *rf_batch_last_error(rf_batch_t Bt) { return Bt ? Bt->last_error.c_str() : ""; }
+
+int64_t rf_batch_device_bytes(rf_batch_t Bt) {
+    if (!Bt) return -1;
+    int64_t t = Bt->owner ? Bt->owner->device_bytes : 0;
+    for (rf_plan *d : Bt->disks) t += d->device_bytes;
+    return t;
+}
+
+void rf_batch_destroy(rf_batch_t Bt) {
+    if (Bt) batch_free(Bt);
 }
 
 }  // extern "C"

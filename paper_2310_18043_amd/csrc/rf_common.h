@@ -143,6 +143,7 @@ struct rf_plan {
     std::vector<void *> allocations;
     std::string last_error;
     bool broken = false;
+    bool shared_factors = false;  // F.tiles/perm/info belong to a batch's factor owner
 };
 
 // error helpers --------------------------------------------------------------

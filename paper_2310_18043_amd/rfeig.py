@@ -98,6 +98,25 @@ _lib.rf_status_str.argtypes = [ctypes.c_int]
 _lib.rf_status_str.restype = ctypes.c_char_p
 _lib.rf_last_error.argtypes = [_P]
 _lib.rf_last_error.restype = ctypes.c_char_p
+_lib.rf_batch_create.argtypes = [ctypes.POINTER(RfCsr), ctypes.POINTER(RfCsr),
+                                 ctypes.POINTER(RfOpts), ctypes.c_int32, _P, ctypes.POINTER(_P)]
+_lib.rf_batch_create.restype = ctypes.c_int
+_lib.rf_batch_factor.argtypes = [_P]
+_lib.rf_batch_factor.restype = ctypes.c_int
+_lib.rf_batch_plan.argtypes = [_P, ctypes.c_int32]
+_lib.rf_batch_plan.restype = _P
+_lib.rf_batch_size.argtypes = [_P]
+_lib.rf_batch_size.restype = ctypes.c_int32
+_lib.rf_batch_solve.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(RfResult), ctypes.POINTER(ctypes.c_int),
+                                ctypes.c_int32]
+_lib.rf_batch_solve.restype = ctypes.c_int
+_lib.rf_batch_device_bytes.argtypes = [_P]
+_lib.rf_batch_device_bytes.restype = ctypes.c_int64
+_lib.rf_batch_last_error.argtypes = [_P]
+_lib.rf_batch_last_error.restype = ctypes.c_char_p
+_lib.rf_batch_destroy.argtypes = [_P]
+_lib.rf_batch_destroy.restype = None
 
 
 def library_path() -> str:
@@ -160,24 +179,31 @@ class _HostCsr:
                        self.val.ctypes.data)
 
 
+def make_opts(c: complex, r: float, p: int = 4, q: int = 8, w: int = 32, **opts) -> RfOpts:
+    """rf_opts for disk (c, r): defaults of rf_default_opts, then the given fields."""
+    o = RfOpts()
+    _lib.rf_default_opts(ctypes.byref(o))
+    o.c_re, o.c_im, o.r = float(np.real(c)), float(np.imag(c)), float(r)
+    o.p, o.q, o.w = int(p), int(q), int(w)
+    for key, val in opts.items():
+        if key == "sigma":
+            o.sigma_re, o.sigma_im = float(np.real(val)), float(np.imag(val))
+        elif hasattr(o, key):
+            setattr(o, key, val)
+        else:
+            raise TypeError(f"unknown option {key}")
+    return o
+
+
 class Plan:
     """rf_plan_create: pencil (A, B) as scipy sparse matrices, disk (c, r), rules p, q, width w."""
 
     def __init__(self, A, B, c: complex, r: float, p: int = 4, q: int = 8, w: int = 32,
                  stream=None, **opts):
         torch = _torch()
-        o = RfOpts()
-        _lib.rf_default_opts(ctypes.byref(o))
-        o.c_re, o.c_im, o.r = float(np.real(c)), float(np.imag(c)), float(r)
-        o.p, o.q, o.w = int(p), int(q), int(w)
-        for key, val in opts.items():
-            if key == "sigma":
-                o.sigma_re, o.sigma_im = float(np.real(val)), float(np.imag(val))
-            elif hasattr(o, key):
-                setattr(o, key, val)
-            else:
-                raise TypeError(f"unknown option {key}")
+        o = make_opts(c, r, p, q, w, **opts)
         self.opts = o
+        self._owned = True
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -206,7 +232,8 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
-            _lib.rf_plan_destroy(self._h)
+            if self._owned:
+                _lib.rf_plan_destroy(self._h)
             self._h = _P()
 
     def __del__(self):
@@ -255,28 +282,142 @@ class Plan:
         to the plan's q_max on one shared Krylov basis."""
         return self._region(_lib.rf_solve_region_adaptive, Y0, allow_noconv)
 
-    def _region(self, fn, Y0, allow_noconv):
+    def _result(self):
+        """An rf_result whose arrays live in the returned holder."""
         w = self.w
-        lam = np.zeros(2 * w)
-        err = np.zeros(w)
-        flags = np.zeros(w, dtype=np.int32)
-        X = block(self.n, w)
+        h = {"lam": np.zeros(2 * w), "err": np.zeros(w), "flags": np.zeros(w, dtype=np.int32),
+             "X": block(self.n, w)}
         res = RfResult()
-        res.lambda_ = lam.ctypes.data
-        res.X = X.data_ptr()
+        res.lambda_ = h["lam"].ctypes.data
+        res.X = h["X"].data_ptr()
         res.ldx = self.n
-        res.err = err.ctypes.data
-        res.flags = flags.ctypes.data
+        res.err = h["err"].ctypes.data
+        res.flags = h["flags"].ctypes.data
+        return res, h
+
+    @staticmethod
+    def _unpack(res, h):
+        lam, err, X = h["lam"], h["err"], h["X"]
+        lamc = lam[0::2] + 1j * lam[1::2]
+        k = res.count
+        return {"lam": lamc[:k], "X": X[:, :k], "err": err[:k], "count": k,
+                "all_lam": lamc, "all_err": err, "flags": h["flags"], "all_X": X,
+                "sweeps": res.sweeps, "converged": bool(res.converged),
+                "krylov_steps": list(res.krylov_steps[:min(res.sweeps, 16)]),
+                "ms_filter": res.ms_filter, "ms_hsrr": res.ms_hsrr}
+
+    def _region(self, fn, Y0, allow_noconv):
+        res, h = self._result()
         if Y0 is not None:
             Y0 = as_colmajor(Y0)
             st = fn(self._h, _P(Y0.data_ptr()), _ld(Y0), ctypes.byref(res))
         else:
             st = fn(self._h, None, 0, ctypes.byref(res))
         self._check(st, allow=(RF_ERR_NOCONV,) if allow_noconv else ())
-        lamc = lam[0::2] + 1j * lam[1::2]
-        k = res.count
-        return {"lam": lamc[:k], "X": X[:, :k], "err": err[:k], "count": k,
-                "all_lam": lamc, "all_err": err, "flags": flags, "all_X": X,
-                "sweeps": res.sweeps, "converged": bool(res.converged),
-                "krylov_steps": list(res.krylov_steps[:min(res.sweeps, 16)]),
-                "ms_filter": res.ms_filter, "ms_hsrr": res.ms_hsrr}
+        return self._unpack(res, h)
+
+
+class _DiskPlan(Plan):
+    """Plan of one disk of a Batch (handle owned by the batch)."""
+
+    def __init__(self, batch, d: int, opts: RfOpts):
+        self._batch = batch          # keeps the batch (and the handle) alive
+        self._owned = False
+        self.opts = opts
+        self._h = _P(_lib.rf_batch_plan(batch._h, d))
+        if not self._h.value:
+            raise RfError(RF_ERR_ARG, f"no disk {d}")
+        self.n = int(_lib.rf_plan_n(self._h))
+        self.w = int(opts.w)
+
+
+class Batch:
+    """rf_batch_create: one pencil, many disks.  ``disks`` is a list of dicts with the
+    keys c, r and optionally p, q, w and any rf_opts field."""
+
+    def __init__(self, A, B, disks, stream=None, **common):
+        torch = _torch()
+        n = len(disks)
+        arr = (RfOpts * n)()
+        for d, spec in enumerate(disks):
+            kw = dict(common)
+            kw.update(spec)
+            arr[d] = make_opts(**kw)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        ha, hb = _HostCsr(A), _HostCsr(B)
+        handle = _P()
+        st = _lib.rf_batch_create(ctypes.byref(ha.s), ctypes.byref(hb.s), arr, n,
+                                  _P(stream.cuda_stream), ctypes.byref(handle))
+        if st != RF_OK:
+            msg = _lib.rf_batch_last_error(handle).decode() if handle.value else ""
+            if handle.value:
+                _lib.rf_batch_destroy(handle)
+            raise RfError(st, msg or "rf_batch_create failed")
+        self._h = handle
+        self.opts = arr
+        self.plans = [_DiskPlan(self, d, arr[d]) for d in range(n)]
+
+    def __len__(self):
+        return len(self.plans)
+
+    def _check(self, st, allow=()):
+        if st != RF_OK and st not in allow:
+            raise RfError(st, _lib.rf_batch_last_error(self._h).decode())
+        return st
+
+    @property
+    def device_bytes(self) -> int:
+        return int(_lib.rf_batch_device_bytes(self._h))
+
+    def factor(self):
+        self._check(_lib.rf_batch_factor(self._h))
+
+    def solve(self, Y0s=None, threads: int = 0, allow_noconv=False):
+        """rf_batch_solve: every disk's Alg. composite; one result dict per disk."""
+        torch = _torch()
+        n = len(self.plans)
+        ys = (_P * n)()
+        lds = (ctypes.c_int64 * n)()
+        keep = []
+        if Y0s is not None:
+            for d, Y in enumerate(Y0s):
+                if Y is None:
+                    continue
+                Y = as_colmajor(Y)
+                keep.append(Y)
+                ys[d] = Y.data_ptr()
+                lds[d] = _ld(Y)
+        torch.cuda.synchronize()     # start blocks complete before the disk streams read them
+        results = (RfResult * n)()
+        holders = []
+        for d, P in enumerate(self.plans):
+            res, h = P._result()
+            results[d] = res
+            holders.append(h)
+        status = (ctypes.c_int * n)()
+        st = _lib.rf_batch_solve(self._h, ys, lds, results, status, int(threads))
+        allow = (RF_ERR_NOCONV,) if allow_noconv else ()
+        for d in range(n):
+            if status[d] != RF_OK and status[d] not in allow:
+                raise RfError(status[d], _lib.rf_last_error(self.plans[d]._h).decode())
+        out = []
+        for d in range(n):
+            r = Plan._unpack(results[d], holders[d])
+            r["status"] = int(status[d])
+            out.append(r)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            for P in getattr(self, "plans", []):
+                P._h = _P()
+            _lib.rf_batch_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

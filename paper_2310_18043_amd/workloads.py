@@ -166,6 +166,77 @@ def toeplitz_eigs(n: int, a: complex, b: complex, c: complex) -> np.ndarray:
     return complex(a) + 2.0 * np.sqrt(complex(b) * complex(c)) * np.cos(k * np.pi / (n + 1))
 
 
+def convdiff_const_eigs(n: int, diffusion: float = 1.0, velocity=(20.0, 10.0),
+                        shift: complex = 0.05j) -> np.ndarray:
+    """Closed-form eigenvalues of ``convdiff_pencil`` with constant velocity and B = I.
+
+    A is then the Kronecker sum I (x) T_x + T_y (x) I of two tridiagonal Toeplitz
+    matrices plus ``shift``; T_x has diagonal 2d + |v_x|/h and off-diagonals whose
+    product is d (d + |v_x|/h), d = D/h^2 (the upwind side carries the |v_x|/h), so
+    its eigenvalues follow the tridiagonal Toeplitz formula and those of A are all
+    sums lambda_x(j) + lambda_y(k) + shift.  Returned sorted by real part."""
+    h = 1.0 / (n + 1)
+    d = diffusion / (h * h)
+
+    def axis(v):
+        u = abs(float(v)) / h
+        return toeplitz_eigs(n, 2.0 * d + u, -d, -(d + u))
+
+    lam = (axis(velocity[0])[:, None] + axis(velocity[1])[None, :]).ravel() + shift
+    return lam[np.argsort(lam.real, kind="stable")]
+
+
+def tile_disks(lam: np.ndarray, counts, start: int = 0, slack: int = 3):
+    """Disks covering consecutive runs of eigenvalues lying on one horizontal line.
+
+    ``lam`` sorted by real part, all with the same imaginary part.  Disk d takes
+    about counts[d] eigenvalues following the previous disk's run: the run length is
+    chosen within +-slack of the request to maximise the smaller of the two
+    relative gaps at its ends, the disk's edges sit in the middle of those gaps.
+    Returns a list of (c, r, count)."""
+    x = np.real(lam)
+    y = float(np.mean(np.imag(lam)))
+    out = []
+    i0 = start
+    for want in counts:
+        best = None
+        for s in range(max(1, want - slack), want + slack + 1):
+            if i0 + s >= len(x) or i0 + s - 1 < 0:
+                continue
+            lo = x[i0 - 1] if i0 > 0 else x[i0] - (x[i0 + 1] - x[i0])
+            left = 0.5 * (lo + x[i0])
+            right = 0.5 * (x[i0 + s - 1] + x[i0 + s])
+            r = 0.5 * (right - left)
+            gap = min(x[i0] - left, x[i0 + s] - right, right - x[i0 + s - 1]) / r
+            if best is None or gap > best[0]:
+                best = (gap, s, 0.5 * (left + right), r)
+        _, s, cx, r = best
+        out.append((complex(cx, y), float(r), int(s)))
+        i0 += s
+    return out
+
+
+def disk_batch(n: int = 128, ndisks: int = 16, lo: int = 12, hi: int = 48,
+               seed: int = 0, velocity=(20.0, 10.0)):
+    """Several adjacent disks at the low-|lambda| end of the constant-velocity
+    convection-diffusion pencil with B = I (closed-form spectrum).
+
+    Requested counts are log-uniform over [lo, hi] (PCG64, ``seed``); each disk's
+    block width is the smallest power of two >= 1.25 x its count.  Returns
+    (A, B, disks, exact_eigs) with disks a list of dicts c, r, w, count."""
+    A, B = convdiff_pencil(n, 1.0, velocity, 0.05j, None, seed)
+    lam = convdiff_const_eigs(n, 1.0, velocity, 0.05j)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    want = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size=ndisks))).astype(int)
+    disks = []
+    for c, r, s in tile_disks(lam, want):
+        w = 16
+        while w < 1.25 * s:
+            w *= 2
+        disks.append({"c": c, "r": r, "w": w, "count": s})
+    return A, B, disks, lam
+
+
 # --------------------------------------------------------------------------
 # named workloads (shapes of the paper's experiments; sizes as in the
 # composite-rule benchmark definitions)

@@ -1,0 +1,119 @@
+"""GPU parity of the batched form: many disks of one pencil (Sec. 1: regions in
+parallel), all disks' poles factorized together, the disks solved concurrently.
+
+Each disk of a batch runs exactly the arithmetic of a stand-alone plan with the
+same options (its poles' factors are computed independently of the other
+disks'), so its results must match that plan's to roundoff; and on the
+constant-velocity convection-diffusion pencil with B = I every disk's converged
+eigenvalues must be the closed-form ones inside it.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2310_18043_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def rf(torch_cuda):
+    from paper_2310_18043_amd import rfeig
+    return rfeig
+
+
+def _match_closed_form(res, disk, exact, tol=1e-10):
+    inside = exact[np.abs(exact - disk["c"]) < disk["r"]]
+    assert res["count"] == len(inside), (res["count"], len(inside))
+    d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
+    assert np.all(d <= tol * np.abs(res["lam"])), d.max()
+    assert res["err"].max() <= 1e-10
+
+
+def test_batch_small_mixed_rules_vs_single_plans_and_oracle(rf, torch_cuda):
+    from oracle import solver
+    A, B, disks, exact = W.disk_batch(n=24, ndisks=3, lo=6, hi=12, seed=2)
+    # different inner rules per disk: the factor owner's pole offsets are uneven
+    rules = [(4, 4), (8, 4), (2, 8)]
+    specs = []
+    for dk, (p, q) in zip(disks, rules):
+        specs.append({"c": dk["c"], "r": dk["r"], "w": dk["w"], "p": p, "q": q,
+                      "expected_count": dk["count"]})
+    N = A.shape[0]
+    Y0 = [W.start_block(N, s["w"], 10 + d) for d, s in enumerate(specs)]
+    _say(f"batch convdiff24_I disks={[(s['p'], s['q'], s['w']) for s in specs]}")
+    batch = rf.Batch(A, B, specs)
+    batch.factor()
+    out = batch.solve([torch_cuda.from_numpy(y).cuda() for y in Y0])
+    for d, (s, res) in enumerate(zip(specs, out)):
+        _say(f"  disk {d}: count {res['count']} sweeps {res['sweeps']}")
+        assert res["converged"] and res["status"] == 0
+        _match_closed_form(res, s, exact)
+        one = rf.Plan(A, B, s["c"], s["r"], p=s["p"], q=s["q"], w=s["w"],
+                      expected_count=s["expected_count"])
+        ref = one.solve_region(torch_cuda.from_numpy(Y0[d]).cuda())
+        assert ref["count"] == res["count"] and ref["sweeps"] == res["sweeps"]
+        np.testing.assert_allclose(res["all_lam"], ref["all_lam"], rtol=1e-12, atol=0)
+        one.close()
+    # the oracle on one disk
+    s = specs[1]
+    ref = solver.solve_region(A, B, s["c"], s["r"], s["p"], s["q"], Y0[1],
+                              s_expected=s["expected_count"])
+    assert len(ref.lam) == out[1]["count"]
+    d = np.abs(out[1]["lam"][:, None] - ref.lam[None, :]).min(axis=1)
+    assert np.all(d <= 1e-10 * np.abs(out[1]["lam"])), d.max()
+    batch.close()
+
+
+def test_batch_disk_plans_refuse_their_own_factorization(rf, torch_cuda):
+    A, B, disks, _ = W.disk_batch(n=16, ndisks=2, lo=5, hi=8, seed=1)
+    specs = [{"c": d["c"], "r": d["r"], "w": d["w"]} for d in disks]
+    batch = rf.Batch(A, B, specs, p=4, q=4)
+    _say("batch state checks")
+    with pytest.raises(rf.RfError) as e:
+        batch.solve()
+    assert e.value.status == rf.RF_ERR_STATE
+    with pytest.raises(rf.RfError) as e:
+        batch.plans[0].factor_shifts()
+    assert e.value.status == rf.RF_ERR_STATE
+    batch.factor()
+    # a disk plan is an ordinary plan once the batch is factorized
+    Y = W.start_block(A.shape[0], specs[1]["w"], 3)
+    Yd = torch_cuda.from_numpy(Y).cuda()
+    Z = batch.plans[1].apply_inner(Yd)
+    one = rf.Plan(A, B, specs[1]["c"], specs[1]["r"], p=4, q=4, w=specs[1]["w"])
+    one.factor_shifts()
+    Z1 = one.apply_inner(Yd)
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(Z, Z1)
+    one.close()
+    batch.close()
+
+
+def test_batch_closed_form_128(rf, torch_cuda):
+    # the batched benchmark pencil (128 x 128 grid, B = I), four disks of the set
+    A, B, disks, exact = W.disk_batch(n=128, ndisks=4)
+    specs = [{"c": d["c"], "r": d["r"], "w": d["w"], "expected_count": d["count"]}
+             for d in disks]
+    _say(f"batch convdiff128_I widths={[s['w'] for s in specs]}")
+    batch = rf.Batch(A, B, specs, p=4, q=8, max_krylov_blocks=60)
+    batch.factor()
+    out = batch.solve(threads=4)
+    for s, res in zip(specs, out):
+        assert res["converged"]
+        _match_closed_form(res, s, exact)
+    batch.close()

@@ -93,6 +93,35 @@ def test_plan_create_rejects_bad_arguments_before_device_work(lib):
     assert out.value is None
 
 
+def test_batch_create_rejects_bad_arguments_before_device_work(lib):
+    from paper_2310_18043_amd import rfeig
+    import numpy as np
+    rowptr = np.array([0, 1, 2], dtype=np.int32)
+    col = np.array([0, 1], dtype=np.int32)
+    val = np.array([1.0, 0.0, 2.0, 0.0])
+    A = rfeig.RfCsr(2, 2, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data)
+    opts = (rfeig.RfOpts * 2)()
+    for d in range(2):
+        lib.rf_default_opts(ctypes.byref(opts[d]))
+        opts[d].w = 1
+    out = ctypes.c_void_p()
+    f = lib.rf_batch_create
+    f.restype = ctypes.c_int
+    # no disks
+    assert f(ctypes.byref(A), ctypes.byref(A), opts, 0, None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
+    # disks that ask for different tiles cannot share one factor storage
+    opts[1].tile = 32
+    assert f(ctypes.byref(A), ctypes.byref(A), opts, 2, None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
+    opts[1].tile = 0
+    opts[0].p = 0
+    assert f(ctypes.byref(A), ctypes.byref(A), opts, 2, None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
+    assert out.value is None
+    lib.rf_batch_size.restype = ctypes.c_int32
+    assert lib.rf_batch_size(None) == -1
+    lib.rf_batch_plan.restype = ctypes.c_void_p
+    assert lib.rf_batch_plan(None, 0) is None
+
+
 def _dense_eig(lib, A, B):
     import numpy as np
     f = lib.rf_dense_eig

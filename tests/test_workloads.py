@@ -1,0 +1,39 @@
+"""Pins of the input builders: the closed-form spectra used by the batched-disk
+cases against dense eigenvalue solves, and the disk tiling's counts."""
+import numpy as np
+import pytest
+
+from paper_2310_18043_amd import workloads as W
+
+
+@pytest.mark.parametrize("v", [(20.0, 10.0), (-7.0, 3.0), (0.0, -15.0)])
+def test_convdiff_const_eigs_against_dense_eig(v):
+    n = 9
+    A, B = W.convdiff_pencil(n, 1.0, v, 0.05j, None, 0)
+    ev = np.sort_complex(np.linalg.eigvals(A.toarray()))
+    cf = np.sort_complex(W.convdiff_const_eigs(n, 1.0, v, 0.05j))
+    assert np.max(np.abs(ev - cf)) <= 1e-12 * np.max(np.abs(cf))
+
+
+def test_toeplitz_eigs_against_dense_eig():
+    A, _ = W.toeplitz_pencil(40, 0.3, 1.0, W.TOEPLITZ_C, balanced=False)
+    ev = np.sort_complex(np.linalg.eigvals(A.toarray()))
+    cf = np.sort_complex(W.toeplitz_eigs(40, 0.3, 1.0, W.TOEPLITZ_C))
+    assert np.max(np.abs(ev - cf)) <= 1e-10
+
+
+def test_disk_batch_counts_and_adjacency():
+    A, B, disks, lam = W.disk_batch(n=128, ndisks=16)
+    assert A.shape == (16384, 16384)
+    prev_right = None
+    for d in disks:
+        inside = np.abs(lam - d["c"]) < d["r"]
+        assert inside.sum() == d["count"]
+        assert d["w"] >= 1.25 * d["count"] and d["w"] & (d["w"] - 1) == 0
+        left, right = d["c"].real - d["r"], d["c"].real + d["r"]
+        if prev_right is not None:
+            assert abs(left - prev_right) <= 1e-9 * right
+        prev_right = right
+        # no eigenvalue within 2% of the radius of the rim
+        dist = np.abs(np.abs(lam - d["c"]) / d["r"] - 1.0)
+        assert dist.min() > 0.02
