@@ -110,6 +110,7 @@ def batched_form(ndisks, reps):
     from paper_2310_18043_amd import rfeig
     from paper_2310_18043_amd import workloads as W
     A, B, disks, exact = W.disk_batch(n=128, ndisks=ndisks)
+    _, kappa = W.convdiff_const_cond(128)
     specs = [{"c": d["c"], "r": d["r"], "w": d["w"], "expected_count": d["count"]}
              for d in disks]
     common = dict(p=4, q=8, max_krylov_blocks=60)
@@ -117,12 +118,16 @@ def batched_form(ndisks, reps):
           for d, s in enumerate(specs)]
 
     def good(res, s):
-        inside = exact[np.abs(exact - s["c"]) < s["r"]]
-        lam = res["lam"][res["err"] <= 1e-10]
+        # converged pairs whose eigenvalue is the closed-form one within the
+        # first-order bound kappa * residual norm (the pencil is non-normal)
+        inside = np.abs(exact - s["c"]) < s["r"]
+        ok = res["err"] <= 1e-10
+        lam, e = res["lam"][ok], res["err"][ok]
         if len(lam) == 0:
             return 0
-        dist = np.abs(lam[:, None] - inside[None, :]).min(axis=1)
-        return int(np.sum(dist <= 1e-10 * np.abs(lam)))
+        j = np.abs(lam[:, None] - exact[inside][None, :]).argmin(axis=1)
+        bound = 4.0 * kappa[inside][j] * e * (abs(s["c"]) + s["r"]) + 1e-13 * np.abs(lam)
+        return int(np.sum(np.abs(lam - exact[inside][j]) <= bound))
 
     batch = rfeig.Batch(A, B, specs, **common)
 

@@ -1263,6 +1263,7 @@ rf_status rf_batch_solve(rf_batch_t Bt, const void *const *Y0, const int64_t *ld
                          rf_status *status, int32_t threads) {
     if (!Bt || !res || !status || Bt->disks.empty()) return RF_ERR_ARG;
     const int nd = int(Bt->disks.size());
+    for (int d = 0; d < nd; ++d) status[d] = RF_ERR_STATE;
     for (rf_plan *d : Bt->disks)
         if (!d->F.ready) return batch_fail(Bt, RF_ERR_STATE, "rf_batch_factor has not succeeded");
     const int nt = std::max(1, std::min(threads <= 0 ? nd : int(threads), nd));

@@ -401,7 +401,9 @@ class Batch:
         allow = (RF_ERR_NOCONV,) if allow_noconv else ()
         for d in range(n):
             if status[d] != RF_OK and status[d] not in allow:
-                raise RfError(status[d], _lib.rf_last_error(self.plans[d]._h).decode())
+                raise RfError(status[d], _lib.rf_batch_last_error(self._h).decode())
+        if st != RF_OK and st not in allow:
+            self._check(st)
         out = []
         for d in range(n):
             r = Plan._unpack(results[d], holders[d])

@@ -186,6 +186,38 @@ def convdiff_const_eigs(n: int, diffusion: float = 1.0, velocity=(20.0, 10.0),
     return lam[np.argsort(lam.real, kind="stable")]
 
 
+def convdiff_const_cond(n: int, diffusion: float = 1.0, velocity=(20.0, 10.0),
+                        shift: complex = 0.05j):
+    """Eigenvalues (as ``convdiff_const_eigs``) and their condition numbers
+    kappa = ||x|| ||y|| / |y^H x| for the same pencil.
+
+    A tridiagonal Toeplitz matrix with off-diagonals sup, sub has right eigenvectors
+    x_k = rho^k sin(k j pi/(n+1)) and left ones y_k = rho^-k sin(k j pi/(n+1)),
+    rho = sqrt(sub/sup); for the Kronecker sum both factor as Kronecker products, so
+    kappa is the product of the two axes' values.  A first-order bound on the error of
+    a computed eigenvalue is kappa times the residual norm of its unit vector."""
+    h = 1.0 / (n + 1)
+    d = diffusion / (h * h)
+    k = np.arange(1, n + 1)
+
+    def axis(v):
+        u = abs(float(v)) / h
+        lam = toeplitz_eigs(n, 2.0 * d + u, -d, -(d + u))
+        rho = np.sqrt((d + u) / d)
+        S = np.sin(np.outer(k, k) * np.pi / (n + 1))        # S[k, j]
+        # rho^k overflows nowhere for the grids used here (rho^n < 1e30)
+        xr = np.linalg.norm(S * rho ** k[:, None], axis=0)
+        yl = np.linalg.norm(S / rho ** k[:, None], axis=0)
+        return lam, xr * yl / np.abs(np.sum(S * S, axis=0))
+
+    lx, kx = axis(velocity[0])
+    ly, ky = axis(velocity[1])
+    lam = (lx[:, None] + ly[None, :]).ravel() + shift
+    kap = (kx[:, None] * ky[None, :]).ravel()
+    o = np.argsort(lam.real, kind="stable")
+    return lam[o], kap[o]
+
+
 def tile_disks(lam: np.ndarray, counts, start: int = 0, slack: int = 3):
     """Disks covering consecutive runs of eigenvalues lying on one horizontal line.
 

@@ -37,3 +37,18 @@ def test_disk_batch_counts_and_adjacency():
         # no eigenvalue within 2% of the radius of the rim
         dist = np.abs(np.abs(lam - d["c"]) / d["r"] - 1.0)
         assert dist.min() > 0.02
+
+
+@pytest.mark.parametrize("v", [(20.0, 10.0), (-7.0, 3.0)])
+def test_convdiff_const_cond_against_dense_left_right_vectors(v):
+    import scipy.linalg as sl
+    n = 9
+    A, _ = W.convdiff_pencil(n, 1.0, v, 0.05j, None, 0)
+    lam, vl, vr = sl.eig(A.toarray(), left=True, right=True)
+    kap = (np.linalg.norm(vl, axis=0) * np.linalg.norm(vr, axis=0)
+           / np.abs(np.sum(vl.conj() * vr, axis=0)))
+    cf_lam, cf_kap = W.convdiff_const_cond(n, 1.0, v, 0.05j)
+    assert np.allclose(np.sort_complex(cf_lam), np.sort_complex(W.convdiff_const_eigs(n, 1.0, v)))
+    for i in range(len(lam)):
+        j = np.argmin(np.abs(cf_lam - lam[i]))
+        assert abs(cf_kap[j] - kap[i]) <= 1e-6 * kap[i]
