@@ -181,6 +181,40 @@ int rf_dense_eig(int32_t n, const double *A, const double *B, double *alpha, dou
                  double *vr);
 
 /* ---------------------------------------------------------------------------
+ * Differentiation form.  For a simple eigenvalue lambda of A x = lambda B x with
+ * right vector x and left vector y (y^H A = lambda y^H B), first-order
+ * perturbation theory (textbook; the paper does not treat it) gives
+ *     d lambda = y^H (dA - lambda dB) x / (y^H B x).
+ * The left vectors are the right eigenvectors of the adjoint pencil (A^H, B^H) at
+ * conj(lambda), which the same solver finds over the mirrored disk D(conj c, r).
+ * ------------------------------------------------------------------------- */
+
+/* A new plan for the adjoint pencil (A^H, B^H) with the options of `plan` and the
+ * disk centre (and an explicit HSRR shift) conjugated; its trapezoidal poles are the
+ * conjugates of the plan's (eq. pwtp, the node angles are symmetric).  It factorizes
+ * its own shifted pencils (rf_factor_shifts) and is destroyed with rf_plan_destroy.
+ * Errors as rf_plan_create. */
+rf_status rf_plan_create_adjoint(rf_plan_t plan, void *hip_stream, rf_plan_t *out);
+
+/* Vector-Jacobian product of eigenvalues with respect to the stored entries of A
+ * and B (in the CSR order given at plan creation):
+ *     gA[e] = sum_i g_i * d lambda_i / d A[row(e), col(e)]
+ *           = sum_i g_i conj(y_i[row]) x_i[col] / (y_i^H B x_i),
+ *     gB[e] = -sum_i g_i lambda_i conj(y_i[row]) x_i[col] / (y_i^H B x_i).
+ * s (0..w of the plan) right pairs: lambda (host, 2s doubles), X (device n x s, ldx);
+ * s_left adjoint pairs from the adjoint plan: mu (host, 2 s_left doubles), Yl (device
+ * n x s_left, ldyl).  Each lambda_i is paired with the mu_j whose conjugate is nearest;
+ * RF_ERR_ARG if that distance exceeds 1e-6 (|c| + r) or two lambdas pick the same mu,
+ * or if y^H B x = 0.  g: host 2s doubles.  gA: device nnz(A) complex128 (written);
+ * gB: device nnz(B) complex128 or NULL.  denom (host 2s doubles, optional) gets
+ * y_i^H B x_i and pair (host s ints, optional) the chosen j.  Vector scaling is free:
+ * the quotient does not depend on the norms of x_i, y_i.  Runs on the plan stream and
+ * uses the plan's work buffers. */
+rf_status rf_eig_vjp(rf_plan_t plan, int32_t s, const double *lambda, const void *X, int64_t ldx,
+                     int32_t s_left, const double *mu, const void *Yl, int64_t ldyl,
+                     const double *g, void *gA, void *gB, double *denom, int32_t *pair);
+
+/* ---------------------------------------------------------------------------
  * Batched form: many disks D_d = { |z - c_d| < r_d } of ONE pencil, solved
  * independently (Sec. 1: the solver covers several regions in parallel to build
  * up a partial or full eigen-decomposition).  All disks' poles are factorized

@@ -201,6 +201,14 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
         return RF_ERR_DEVICE;
     }
     P->device = dev;
+    for (int k = 0; k < 2; ++k) {
+        const rf_csr *M = k ? B : A;
+        HostCsr &H = k ? P->hB : P->hA;
+        H.n = M->n;
+        H.rowptr.assign(M->rowptr, M->rowptr + M->n + 1);
+        H.colind.assign(M->colind, M->colind + M->nnz);
+        H.val.assign(M->val, M->val + 2 * M->nnz);
+    }
     {
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
@@ -1300,6 +1308,126 @@ int64_t rf_batch_device_bytes(rf_batch_t Bt) {
 
 void rf_batch_destroy(rf_batch_t Bt) {
     if (Bt) batch_free(Bt);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Differentiation form.  For a simple eigenvalue lambda with right vector x and
+// left vector y (y^H A = lambda y^H B) the first-order perturbation is
+//   d lambda = y^H (dA - lambda dB) x / (y^H B x)
+// (textbook perturbation theory, not part of the paper).  The left vectors are the
+// right eigenvectors of the adjoint pencil (A^H, B^H) at conj(lambda), found by the
+// same filter over the mirrored disk D(conj c, r): its trapezoidal poles are the
+// conjugates of the original ones (eq. pwtp: the angle set is symmetric).
+// ---------------------------------------------------------------------------
+namespace {
+
+void conj_transpose(const HostCsr &M, std::vector<int32_t> &rp, std::vector<int32_t> &ci,
+                    std::vector<double> &v) {
+    const int32_t n = M.n;
+    const int64_t nnz = int64_t(M.colind.size());
+    rp.assign(size_t(n) + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) ++rp[size_t(M.colind[e]) + 1];
+    for (int32_t i = 0; i < n; ++i) rp[i + 1] += rp[i];
+    ci.assign(size_t(nnz), 0);
+    v.assign(size_t(2 * nnz), 0.0);
+    std::vector<int64_t> next(rp.begin(), rp.end() - 1);
+    for (int32_t r = 0; r < n; ++r)       // rows in order: columns of the result stay sorted
+        for (int64_t e = M.rowptr[r]; e < M.rowptr[r + 1]; ++e) {
+            const int64_t t = next[M.colind[e]]++;
+            ci[t] = r;
+            v[2 * t] = M.val[2 * e];
+            v[2 * t + 1] = -M.val[2 * e + 1];
+        }
+}
+
+}  // namespace
+
+extern "C" {
+
+rf_status rf_plan_create_adjoint(rf_plan_t P, void *hip_stream, rf_plan_t *out) {
+    if (!P || !out) return RF_ERR_ARG;
+    *out = nullptr;
+    std::vector<int32_t> arp, aci, brp, bci;
+    std::vector<double> av, bv;
+    conj_transpose(P->hA, arp, aci, av);
+    conj_transpose(P->hB, brp, bci, bv);
+    rf_csr Ah{P->hA.n, int64_t(aci.size()), arp.data(), aci.data(), av.data()};
+    rf_csr Bh{P->hB.n, int64_t(bci.size()), brp.data(), bci.data(), bv.data()};
+    rf_opts o = P->opts;
+    o.c_im = -o.c_im;
+    if (!std::isnan(o.sigma_re)) o.sigma_im = -o.sigma_im;
+    return plan_create_impl(&Ah, &Bh, &o, hip_stream, out, nullptr, 0, nullptr);
+}
+
+rf_status rf_eig_vjp(rf_plan_t P, int32_t s, const double *lambda, const void *X, int64_t ldx,
+                     int32_t s_left, const double *mu, const void *Yl, int64_t ldyl,
+                     const double *g, void *gA, void *gB, double *denom, int32_t *pair_out) {
+    if (!P) return RF_ERR_ARG;
+    if (P->broken) return rf_fail(P, RF_ERR_STATE, "plan is unusable after a device error");
+    if (s < 0 || s > P->opts.w || s_left < 0 || (s > 0 && (!lambda || !X || !mu || !Yl || !g || !gA)) ||
+        (s > 0 && (ldx < P->n || ldyl < P->n)))
+        return rf_fail(P, RF_ERR_ARG, "bad arguments to rf_eig_vjp");
+    const int64_t n = P->n;
+    hipStream_t st = P->stream;
+    if (s == 0) {
+        if (P->A.nnz > 0) RF_HIP(P, hipMemsetAsync(gA, 0, sizeof(zd) * P->A.nnz, st));
+        if (gB && P->B.nnz > 0) RF_HIP(P, hipMemsetAsync(gB, 0, sizeof(zd) * P->B.nnz, st));
+        RF_HIP(P, hipStreamSynchronize(st));
+        return RF_OK;
+    }
+    // pair every right eigenvalue with the adjoint eigenvalue whose conjugate is nearest
+    const double scale = std::hypot(P->opts.c_re, P->opts.c_im) + P->opts.r;
+    const double tol = 1e-6 * scale;
+    std::vector<int> pair(s);
+    std::vector<char> used(size_t(std::max(s_left, 1)), 0);
+    for (int i = 0; i < s; ++i) {
+        int best = -1;
+        double bd = 0.0;
+        for (int j = 0; j < s_left; ++j) {
+            const double d = std::hypot(lambda[2 * i] - mu[2 * j], lambda[2 * i + 1] + mu[2 * j + 1]);
+            if (best < 0 || d < bd) { best = j; bd = d; }
+        }
+        if (best < 0 || bd > tol || used[best])
+            return rf_fail(P, RF_ERR_ARG, "eigenvalue " + std::to_string(i) +
+                                              " has no unambiguous left partner in the adjoint results");
+        used[best] = 1;
+        pair[i] = best;
+    }
+    const zd *Xd = static_cast<const zd *>(X);
+    const zd *Yd = static_cast<const zd *>(Yl);
+    zd *dd = P->small;                 // s denominators
+    zd *coef = P->small + s;           // s coefficients
+    RF_HIP(P, hipMemcpyAsync(P->d_active, pair.data(), sizeof(int) * s, hipMemcpyHostToDevice, st));
+    RF_HIP(P, launch_spmm(P->B, s, Xd, ldx, P->tmp, n, st));
+    RF_HIP(P, launch_paired_dots(n, s, Yd, ldyl, P->d_active, P->tmp, n, dd, st));
+    std::vector<zd> d(s), ca(s), cb(s);
+    RF_HIP(P, hipMemcpyAsync(d.data(), dd, sizeof(zd) * s, hipMemcpyDeviceToHost, st));
+    RF_HIP(P, hipStreamSynchronize(st));
+    for (int i = 0; i < s; ++i) {
+        const std::complex<double> di(d[i].x, d[i].y), gi(g[2 * i], g[2 * i + 1]),
+            li(lambda[2 * i], lambda[2 * i + 1]);
+        if (std::abs(di) == 0.0)
+            return rf_fail(P, RF_ERR_ARG, "y^H B x = 0 for eigenvalue " + std::to_string(i) +
+                                              " (not a simple eigenvalue)");
+        const std::complex<double> a = gi / di, b = -gi * li / di;
+        ca[i] = Z(a.real(), a.imag());
+        cb[i] = Z(b.real(), b.imag());
+        if (denom) { denom[2 * i] = d[i].x; denom[2 * i + 1] = d[i].y; }
+        if (pair_out) pair_out[i] = pair[i];
+    }
+    RF_HIP(P, hipMemcpyAsync(coef, ca.data(), sizeof(zd) * s, hipMemcpyHostToDevice, st));
+    RF_HIP(P, launch_sampled_outer(P->A, s, coef, Yd, ldyl, P->d_active, Xd, ldx,
+                                   static_cast<zd *>(gA), st));
+    RF_HIP(P, hipStreamSynchronize(st));
+    if (gB) {
+        RF_HIP(P, hipMemcpyAsync(coef, cb.data(), sizeof(zd) * s, hipMemcpyHostToDevice, st));
+        RF_HIP(P, launch_sampled_outer(P->B, s, coef, Yd, ldyl, P->d_active, Xd, ldx,
+                                       static_cast<zd *>(gB), st));
+        RF_HIP(P, hipStreamSynchronize(st));
+    }
+    return RF_OK;
 }
 
 }  // extern "C"

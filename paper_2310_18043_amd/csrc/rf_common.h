@@ -59,6 +59,12 @@ struct DevCsr {
     zd *dval = nullptr;        // n entries when diagonal
 };
 
+struct HostCsr {               // host copy of a pencil matrix as given (for the adjoint pencil)
+    int32_t n = 0;
+    std::vector<int32_t> rowptr, colind;
+    std::vector<double> val;   // 2 * nnz (interleaved complex)
+};
+
 struct BandFactors {
     int nb = 0;                // tile size (>= kl, ku)
     int nblk = 0;              // number of row/column blocks
@@ -96,6 +102,7 @@ struct rf_plan {
     int device = 0;
     int max_lds = 65536;      // dynamic LDS bytes a workgroup may use
     DevCsr A, B;
+    HostCsr hA, hB;
     std::vector<zd> poles, weights;       // inner rule (p)
     std::vector<zd> shifts, oweights;     // outer rule (finite shifts)
     double oextra = 0.0;                  // (1/q) term for odd q
@@ -200,6 +207,14 @@ hipError_t launch_copy_block(int64_t n, int ncols, const zd *src, int64_t lds, i
                              const int *map = nullptr, int flags = 0);
 hipError_t launch_copy_cols(int64_t n, int ncols, const zd *src, int64_t lds, zd *dst,
                             int64_t ldd, hipStream_t s);
+// d[i] = sum_r conj(Y[r, pair[i]]) * BX[r, i], i < s   (one workgroup per i)
+hipError_t launch_paired_dots(int64_t n, int s, const zd *Y, int64_t ldy, const int *pair,
+                              const zd *BX, int64_t ldb, zd *d, hipStream_t st);
+// out[e] = sum_i coef[i] * conj(Y[row(e), pair[i]]) * X[col(e), i] over the stored entries e
+// of M (CSR order)
+hipError_t launch_sampled_outer(const DevCsr &M, int s, const zd *coef, const zd *Y, int64_t ldy,
+                                const int *pair, const zd *X, int64_t ldx, zd *out,
+                                hipStream_t st);
 hipError_t launch_spmm(const DevCsr &M, int ncols, const zd *X, int64_t ldx, zd *Y,
                        int64_t ldy, hipStream_t s);
 // Y = A X - sigma * B X   (all n x ncols)

@@ -838,6 +838,61 @@ hipError_t launch_copy_cols(int64_t n, int ncols, const zd *src, int64_t lds, zd
     return hipGetLastError();
 }
 
+// d[i] = y_{pair[i]}^H (B x_i): the denominators of the first-order eigenvalue perturbation
+__global__ __launch_bounds__(GT) void paired_dot_kernel(int64_t n, const zd *Y, int64_t ldy,
+                                                        const int *pair, const zd *BX,
+                                                        int64_t ldb, zd *d) {
+    const int i = blockIdx.x;
+    const zd *y = Y + int64_t(pair[i]) * ldy;
+    const zd *bx = BX + int64_t(i) * ldb;
+    zd acc = zmake(0, 0);
+    for (int64_t r = threadIdx.x; r < n; r += GT) zfma_c(acc, y[r], bx[r]);
+    __shared__ zd red[GT / 64];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        zd t = red[0];
+        for (int k = 1; k < GT / 64; ++k) t = zadd(t, red[k]);
+        d[i] = t;
+    }
+}
+
+// One thread per row of M: for each stored entry (row, col) of the row,
+// out = sum_i coef[i] conj(Y[row, pair[i]]) X[col, i].  Consecutive threads read
+// consecutive rows of Y and nearby rows of X, so every i is a coalesced sweep.
+__global__ void sampled_outer_kernel(int32_t n, const int32_t *rp, const int32_t *ci, int s,
+                                     const zd *coef, const zd *Y, int64_t ldy, const int *pair,
+                                     const zd *X, int64_t ldx, zd *out) {
+    const int32_t r = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+        const int64_t col = ci[e];
+        zd acc = zmake(0, 0);
+        for (int i = 0; i < s; ++i) {
+            zd yc = zmul(coef[i], zconj(Y[r + int64_t(pair[i]) * ldy]));
+            zfma(acc, yc, X[col + int64_t(i) * ldx]);
+        }
+        out[e] = acc;
+    }
+}
+
+hipError_t launch_paired_dots(int64_t n, int s, const zd *Y, int64_t ldy, const int *pair,
+                              const zd *BX, int64_t ldb, zd *d, hipStream_t st) {
+    if (s <= 0) return hipSuccess;
+    hipLaunchKernelGGL(paired_dot_kernel, dim3(s), dim3(GT), 0, st, n, Y, ldy, pair, BX, ldb, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_sampled_outer(const DevCsr &M, int s, const zd *coef, const zd *Y, int64_t ldy,
+                                const int *pair, const zd *X, int64_t ldx, zd *out,
+                                hipStream_t st) {
+    if (M.n == 0 || M.nnz == 0) return hipSuccess;
+    hipLaunchKernelGGL(sampled_outer_kernel, dim3((M.n + 255) / 256), dim3(256), 0, st, M.n,
+                       M.rowptr, M.colind, s, coef, Y, ldy, pair, X, ldx, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_spmm(const DevCsr &M, int ncols, const zd *X, int64_t ldx, zd *Y, int64_t ldy,
                        hipStream_t s) {
     int64_t tot = int64_t(M.n) * ncols;

@@ -98,6 +98,11 @@ _lib.rf_status_str.argtypes = [ctypes.c_int]
 _lib.rf_status_str.restype = ctypes.c_char_p
 _lib.rf_last_error.argtypes = [_P]
 _lib.rf_last_error.restype = ctypes.c_char_p
+_lib.rf_plan_create_adjoint.argtypes = [_P, _P, ctypes.POINTER(_P)]
+_lib.rf_plan_create_adjoint.restype = ctypes.c_int
+_lib.rf_eig_vjp.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
+                            ctypes.c_int64, _P, _P, _P, _P, _P]
+_lib.rf_eig_vjp.restype = ctypes.c_int
 _lib.rf_batch_create.argtypes = [ctypes.POINTER(RfCsr), ctypes.POINTER(RfCsr),
                                  ctypes.POINTER(RfOpts), ctypes.c_int32, _P, ctypes.POINTER(_P)]
 _lib.rf_batch_create.restype = ctypes.c_int
@@ -273,6 +278,51 @@ class Plan:
                    "max_residual": info.max_residual, "inner_columns": info.inner_columns,
                    "ms": info.ms_total}
 
+    def adjoint(self, stream=None):
+        """rf_plan_create_adjoint: plan of (A^H, B^H) over D(conj c, r)."""
+        torch = _torch()
+        stream = self.stream if stream is None else stream
+        handle = _P()
+        st = _lib.rf_plan_create_adjoint(self._h, _P(stream.cuda_stream), ctypes.byref(handle))
+        if st != RF_OK:
+            msg = _lib.rf_last_error(handle).decode() if handle.value else ""
+            if handle.value:
+                _lib.rf_plan_destroy(handle)
+            raise RfError(st, msg or "rf_plan_create_adjoint failed")
+        P = Plan.__new__(Plan)
+        P._h = handle
+        P._owned = True
+        P.opts = self.opts
+        P.stream = stream
+        P.n = self.n
+        P.w = self.w
+        return P
+
+    def eig_vjp(self, lam, X, mu, Yl, g, nnz_a, nnz_b=None):
+        """rf_eig_vjp: (gA, gB, denom, pair) with gA[e] = sum_i g_i d lambda_i / d A_e
+        over the stored entries of A (CSR order), likewise gB (None if nnz_b is None)."""
+        torch = _torch()
+        lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128))
+        mu = np.ascontiguousarray(np.asarray(mu, dtype=np.complex128))
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.complex128))
+        s, sl = len(lam), len(mu)
+        if X.dim() == 1:
+            X = X[:, None]
+        if Yl.dim() == 1:
+            Yl = Yl[:, None]
+        X = as_colmajor(X)
+        Yl = as_colmajor(Yl)
+        gA = torch.empty(int(nnz_a), dtype=torch.complex128, device="cuda")
+        gB = None if nnz_b is None else torch.empty(int(nnz_b), dtype=torch.complex128,
+                                                    device="cuda")
+        denom = np.zeros(s, dtype=np.complex128)
+        pair = np.zeros(max(s, 1), dtype=np.int32)
+        self._check(_lib.rf_eig_vjp(self._h, s, lam.ctypes.data, _P(X.data_ptr()), _ld(X), sl,
+                                    mu.ctypes.data, _P(Yl.data_ptr()), _ld(Yl), g.ctypes.data,
+                                    _P(gA.data_ptr()), _P(gB.data_ptr() if gB is not None else None),
+                                    denom.ctypes.data, pair.ctypes.data))
+        return gA, gB, denom, pair[:s]
+
     def solve_region(self, Y0=None, allow_noconv=False):
         """Alg. composite: subspace iteration with the composite filter."""
         return self._region(_lib.rf_solve_region, Y0, allow_noconv)
@@ -423,3 +473,70 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# differentiation form: eigenvalues inside a disk as a differentiable function of
+# the stored entries of A and B
+# ---------------------------------------------------------------------------
+
+def _csr_with_values(pattern, vals):
+    import scipy.sparse as sp
+    M = sp.csr_matrix((np.asarray(vals, dtype=np.complex128), pattern.indices, pattern.indptr),
+                      shape=pattern.shape)
+    return M
+
+
+def disk_eigenvalues(a_vals, b_vals, A_pattern, B_pattern, c, r, Y0=None, Y0_adj=None,
+                     **plan_opts):
+    """Converged eigenvalues inside D(c, r) of the pencil whose stored entries (CSR
+    order of the sorted patterns) are the complex128 tensors a_vals, b_vals, as a
+    torch function with a backward pass: the gradient comes from rf_eig_vjp with the
+    left vectors of the adjoint pencil, solved by the same filter.
+
+    Returns a complex128 CPU tensor of the converged eigenvalues in the order the
+    solver returns them; the gradients come back on the devices of a_vals, b_vals."""
+    torch = _torch()
+    return _DiskEig.apply(a_vals, b_vals, A_pattern, B_pattern, complex(c), float(r), Y0,
+                          Y0_adj, plan_opts)
+
+
+def _disk_eig_class():
+    torch = _torch()
+
+    class DiskEig(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, a_vals, b_vals, A_pattern, B_pattern, c, r, Y0, Y0_adj, plan_opts):
+            A = _csr_with_values(A_pattern, a_vals.detach().cpu().numpy())
+            B = _csr_with_values(B_pattern, b_vals.detach().cpu().numpy())
+            opts = dict(plan_opts)
+            P = Plan(A, B, c, r, **opts)
+            res = P.solve_region(Y0)
+            Pa = P.adjoint()
+            resa = Pa.solve_region(Y0_adj)
+            ctx.state = (P, Pa, res, resa, A.nnz, B.nnz, a_vals.device, b_vals.device)
+            return torch.from_numpy(np.array(res["lam"], dtype=np.complex128))
+
+        @staticmethod
+        def backward(ctx, grad_lam):
+            P, Pa, res, resa, nnz_a, nnz_b, dev_a, dev_b = ctx.state
+            # torch's convention for complex: grad_in = sum_i grad_i * conj(d lambda_i / d z)
+            g = np.conj(grad_lam.detach().cpu().numpy().astype(np.complex128))
+            gA, gB, _, _ = P.eig_vjp(res["lam"], res["X"], resa["lam"], resa["X"], g,
+                                     nnz_a, nnz_b)
+            return (gA.conj().to(dev_a), gB.conj().to(dev_b), None, None, None, None, None, None,
+                    None)
+
+    return DiskEig
+
+
+class _LazyFn:
+    _cls = None
+
+    def apply(self, *args):
+        if _LazyFn._cls is None:
+            _LazyFn._cls = _disk_eig_class()
+        return _LazyFn._cls.apply(*args)
+
+
+_DiskEig = _LazyFn()

@@ -284,6 +284,15 @@ TOEPLITZ_C = 0.5 * np.exp(1j * np.pi / 3)
 # largest; radius halfway between the 100th and 101st distances.
 CONVDIFF128_DISK = (2525.0 + 0.0494j, 661.5612524628755, 100)
 
+# Disk for the 128 x 128 pencil with a per-cell velocity field v ~ U[-20, 20]^2
+# (random_vfield seed 5), D = 1, +0.05i, B = diag U[0.5, 1.5] (seed 0).  Recipe: the
+# 200 eigenvalues of B^{-1}A nearest 2000 (ARPACK shift-invert, all within 1335 of
+# 2000); centres on Im = 0.0495 scanned in steps of 2 over [1500, 2500) with counts
+# 46..54 and the disk kept inside 0.9 x that range; kept the centre and count with
+# the largest ratio of the (count+1)-th to the count-th distance (1.13); radius
+# halfway between the two.
+RANDOMV128_DISK = (1564.0 + 0.0495j, 350.8144063398522, 52)
+
 _DISKS = {
     (128, (20.0, 10.0), 0, (0.5, 1.5)): CONVDIFF128_DISK,
 }
@@ -312,3 +321,21 @@ def convdiff_workload(n: int = 128, w: int = 128, p: int = 4, q: int = 8,
     c, r, count = disk
     return Workload(f"convdiff{n}", A, B, complex(c), float(r), p, q, w,
                     count, seed)
+
+
+def random_velocity_workload(n: int = 128, w: int = 64, p: int = 4, q: int = 8,
+                             vseed: int = 5, vmax: float = 20.0,
+                             disk: Optional[tuple] = None) -> Workload:
+    """Convection-diffusion pencil with a per-cell velocity field U[-vmax, vmax]^2
+    (seed ``vseed``) and B = diag U[0.5, 1.5] (seed 0): the differentiation-form
+    workload (gradients of eigenvalues with respect to the field)."""
+    v = random_vfield(n, vmax, vseed)
+    A, B = convdiff_pencil(n, 1.0, vfield=v, shift=0.05j, mass=(0.5, 1.5), seed=0)
+    if disk is None:
+        if (n, vseed, vmax) != (128, 5, 20.0):
+            raise KeyError("no stored disk for this pencil; pass disk=(c, r, count)")
+        disk = RANDOMV128_DISK
+    c, r, count = disk
+    wl = Workload(f"convdiff{n}_randv{vseed}", A, B, complex(c), float(r), p, q, w, count, 0)
+    wl.vfield = v
+    return wl

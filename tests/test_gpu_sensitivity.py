@@ -1,0 +1,214 @@
+"""GPU parity of the differentiation form: eigenvalue gradients from the right
+vectors of the pencil and the left vectors of the adjoint pencil (both found by
+the composite-rule solver), contracted on the device by rf_eig_vjp.
+
+* Small pencils: against the oracle's gradient built from a dense LAPACK
+  left/right eigen-decomposition (relative 1e-8: both sides are first-order
+  formulas in vectors accurate to about cond * 1e-10).
+* Through the velocity field (torch autograd over the test-side assembly of A):
+  against the oracle's gradient pushed through the same assembly, and against
+  central differences of re-solved eigenvalues at several steps h (truncation
+  error O(h^2), rounding O(1e-10 / h): the best h of a sweep must agree to 1e-5).
+* Full size (128 x 128 grid, random field, 52 eigenvalues inside): central
+  differences through the GPU solver on sampled cells with |v| > 10 h.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2310_18043_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def rf(torch_cuda):
+    from paper_2310_18043_amd import rfeig
+    return rfeig
+
+
+def _small_case(n=16, vseed=3, count=10):
+    import scipy.linalg as sl
+    v = W.random_vfield(n, 20.0, vseed)
+    A, B = W.convdiff_pencil(n, 1.0, vfield=v, mass=(0.5, 1.5), seed=1)
+    lam = sl.eigvals(A.toarray(), B.toarray())
+    order = np.argsort(lam.real)
+    best = None
+    for k in range(40, 120, 2):
+        c = complex(lam[order[k]].real, 0.05)
+        d = np.sort(np.abs(lam - c))
+        ratio = d[count] / d[count - 1]
+        if best is None or ratio > best[0]:
+            best = (ratio, c, 0.5 * (d[count - 1] + d[count]))
+    _, c, r = best
+    return v, A, B, c, r
+
+
+def _gpu_left_right(rf, torch_cuda, A, B, c, r, w, count, seed=0):
+    plan = rf.Plan(A, B, c, r, p=4, q=8, w=w, expected_count=count)
+    N = A.shape[0]
+    res = plan.solve_region(torch_cuda.from_numpy(W.start_block(N, w, seed)).cuda())
+    adj = plan.adjoint()
+    resa = adj.solve_region(torch_cuda.from_numpy(W.start_block(N, w, seed + 1)).cuda())
+    return plan, adj, res, resa
+
+
+def test_vjp_small_vs_dense_oracle(rf, torch_cuda):
+    from oracle import sensitivity as S
+    v, A, B, c, r = _small_case()
+    _say(f"eig_vjp convdiff16 random field c={c:.3f} r={r:.3f}")
+    plan, adj, res, resa = _gpu_left_right(rf, torch_cuda, A, B, c, r, 16, 10)
+    assert res["converged"] and resa["converged"]
+    assert res["count"] == resa["count"] == 10
+    # the adjoint eigenvalues are the conjugates
+    d = np.abs(res["lam"][:, None] - np.conj(resa["lam"])[None, :]).min(axis=1)
+    assert np.all(d <= 1e-9 * np.abs(res["lam"]))
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal(10) + 1j * rng.standard_normal(10)
+    gA, gB, denom, pair = plan.eig_vjp(res["lam"], res["X"], resa["lam"], resa["X"], g,
+                                       A.nnz, B.nnz)
+    lam_d, X_d, Y_d = S.dense_left_right(A, B)
+    lam_d, X_d, Y_d = S.select(lam_d, X_d, Y_d, res["lam"])
+    refA, refB = S.pencil_vjp(A, B, lam_d, X_d, Y_d, g)
+    gA = gA.cpu().numpy()
+    gB = gB.cpu().numpy()
+    assert np.linalg.norm(gA - refA) <= 1e-8 * np.linalg.norm(refA)
+    assert np.linalg.norm(gB - refB) <= 1e-8 * np.linalg.norm(refB)
+    assert sorted(pair.tolist()) == list(range(10))
+    plan.close()
+    adj.close()
+
+
+def test_vjp_rejects_unpaired_eigenvalues(rf, torch_cuda):
+    v, A, B, c, r = _small_case()
+    _say("eig_vjp pairing errors")
+    plan, adj, res, resa = _gpu_left_right(rf, torch_cuda, A, B, c, r, 16, 10)
+    g = np.ones(10, np.complex128)
+    bad_mu = resa["lam"] + 1.0           # no conjugate within tolerance
+    with pytest.raises(rf.RfError) as e:
+        plan.eig_vjp(res["lam"], res["X"], bad_mu, resa["X"], g, A.nnz, B.nnz)
+    assert e.value.status == rf.RF_ERR_ARG
+    dup_mu = np.repeat(resa["lam"][:1], 10)   # every lambda would pick the same partner
+    with pytest.raises(rf.RfError):
+        plan.eig_vjp(res["lam"], res["X"], dup_mu, resa["X"][:, :1].repeat(1, 10), g,
+                     A.nnz, B.nnz)
+    plan.close()
+    adj.close()
+
+
+def test_velocity_gradient_small(rf, torch_cuda):
+    import torch
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from convdiff_torch import ConvDiffAssembly
+    from oracle import sensitivity as S
+    v, A, B, c, r = _small_case()
+    n = 16
+    asm = ConvDiffAssembly(n)
+    N = n * n
+    Y0 = torch.from_numpy(W.start_block(N, 16, 0)).cuda()
+    Y0a = torch.from_numpy(W.start_block(N, 16, 1)).cuda()
+    b_vals = torch.from_numpy(B.data.copy())
+    rng = np.random.default_rng(9)
+
+    vt = torch.from_numpy(v.copy()).requires_grad_(True)
+    a_vals = asm.values(vt)
+    _say("velocity gradient convdiff16")
+    lam = rf.disk_eigenvalues(a_vals, b_vals, A, B, c, r, Y0, Y0a, p=4, q=8, w=16,
+                              expected_count=10)
+    wts = torch.from_numpy(rng.standard_normal(len(lam)) + 1j * rng.standard_normal(len(lam)))
+    # loss: sum_i Re(conj(w_i) lambda_i)
+    loss = torch.sum((wts.conj() * lam).real)
+    loss.backward()
+    grad = vt.grad.numpy().copy()
+
+    # oracle: dense left/right vectors, same contraction, same assembly
+    lam_d, X_d, Y_d = S.dense_left_right(A, B)
+    lam_np = lam.detach().numpy()
+    lam_d, X_d, Y_d = S.select(lam_d, X_d, Y_d, lam_np)
+    gA, _ = S.pencil_vjp(A, B, lam_d, X_d, Y_d, np.conj(wts.numpy()))
+    vt2 = torch.from_numpy(v.copy()).requires_grad_(True)
+    (ga,) = torch.autograd.grad(asm.values(vt2), vt2, grad_outputs=torch.from_numpy(np.conj(gA)))
+    ref = ga.numpy()
+    assert np.linalg.norm(grad - ref) <= 1e-8 * np.linalg.norm(ref)
+
+    # central differences through the GPU solver on a few cells
+    def L(vv):
+        Av = W.convdiff_pencil(n, 1.0, vfield=vv, mass=(0.5, 1.5), seed=1)[0]
+        P = rf.Plan(Av, B, c, r, p=4, q=8, w=16, expected_count=10)
+        res = P.solve_region(Y0)
+        P.close()
+        # match eigenvalues to the base ones (same order as wts)
+        j = np.abs(lam_np[:, None] - res["lam"][None, :]).argmin(axis=1)
+        return float(np.sum((np.conj(wts.numpy()) * res["lam"][j]).real))
+
+    cells = [(0, 3, 5), (1, 8, 2), (0, 12, 11), (1, 5, 14)]
+    for comp, iy, ix in cells:
+        errs = []
+        for h in (1e-2, 1e-3, 1e-4):
+            vp = v.copy(); vp[comp, iy, ix] += h
+            vm = v.copy(); vm[comp, iy, ix] -= h
+            fd = (L(vp) - L(vm)) / (2 * h)
+            errs.append(abs(fd - grad[comp, iy, ix]) / max(abs(grad[comp, iy, ix]), 1e-8))
+        _say(f"  cell {(comp, iy, ix)} grad {grad[comp, iy, ix]:.6e} fd rel errs {errs}")
+        assert min(errs) <= 1e-5
+
+
+def test_full_size_velocity_gradient_fd(rf, torch_cuda):
+    import torch
+    wl = W.random_velocity_workload()
+    n = 128
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from convdiff_torch import ConvDiffAssembly
+    asm = ConvDiffAssembly(n)
+    N = n * n
+    Y0 = torch.from_numpy(W.start_block(N, wl.w, 0)).cuda()
+    Y0a = torch.from_numpy(W.start_block(N, wl.w, 1)).cuda()
+    b_vals = torch.from_numpy(wl.B.data.copy())
+    v = wl.vfield
+    vt = torch.from_numpy(v.copy()).requires_grad_(True)
+    _say("velocity gradient convdiff128 random field (52 inside)")
+    lam = rf.disk_eigenvalues(asm.values(vt), b_vals, wl.A, wl.B, wl.c, wl.r, Y0, Y0a,
+                              p=wl.p, q=wl.q, w=wl.w, expected_count=wl.s_expected,
+                              max_krylov_blocks=60)
+    assert len(lam) == wl.s_expected
+    # loss: the real part of the eigenvalue sum (the trace of the projected pencil)
+    loss = torch.sum(lam.real)
+    loss.backward()
+    grad = vt.grad.numpy()
+
+    def L(vv):
+        Av = W.convdiff_pencil(n, 1.0, vfield=vv, mass=(0.5, 1.5), seed=0)[0]
+        P = rf.Plan(Av, wl.B, wl.c, wl.r, p=wl.p, q=wl.q, w=wl.w,
+                    expected_count=wl.s_expected, max_krylov_blocks=60)
+        res = P.solve_region(Y0)
+        P.close()
+        assert res["count"] == wl.s_expected
+        return float(np.sum(res["lam"].real))
+
+    rng = np.random.default_rng(11)
+    h = 1e-3
+    # cells where the gradient is not negligible and |v| > 10 h (away from the upwind switch)
+    mag = np.abs(grad)
+    cand = np.argwhere((mag > 1e-3 * mag.max()) & (np.abs(v) > 10 * h))
+    picks = cand[rng.choice(len(cand), size=3, replace=False)]
+    for comp, iy, ix in picks:
+        vp = v.copy(); vp[comp, iy, ix] += h
+        vm = v.copy(); vm[comp, iy, ix] -= h
+        fd = (L(vp) - L(vm)) / (2 * h)
+        rel = abs(fd - grad[comp, iy, ix]) / abs(grad[comp, iy, ix])
+        _say(f"  cell {(int(comp), int(iy), int(ix))} grad {grad[comp, iy, ix]:.6e} fd {fd:.6e} rel {rel:.2e}")
+        assert rel <= 1e-4
