@@ -177,6 +177,52 @@ def batched_form(ndisks, reps):
                            "value": round(found_s / (ms_s / 1000.0), 3)}}
 
 
+def gradient_form(reps):
+    """Eigenvalue gradients on the 128 x 128 random-velocity pencil (52 eigenvalues in
+    the disk): right eigenpairs (factor + Alg. composite), left eigenpairs from the
+    adjoint pencil (factor + Alg. composite), and the device contraction of
+    d lambda_i / d A over the stored entries of A and B for one weight vector."""
+    import torch
+    from paper_2310_18043_amd import rfeig
+    from paper_2310_18043_amd import workloads as W
+    wl = W.random_velocity_workload()
+    opts = dict(p=wl.p, q=wl.q, w=wl.w, expected_count=wl.s_expected, max_krylov_blocks=60)
+    P = rfeig.Plan(wl.A, wl.B, wl.c, wl.r, **opts)
+    Pa = P.adjoint()
+    Y0 = torch.from_numpy(W.start_block(wl.n, wl.w, 0)).cuda()
+    Y0a = torch.from_numpy(W.start_block(wl.n, wl.w, 1)).cuda()
+
+    def step():
+        t0 = time.perf_counter()
+        P.factor_shifts()
+        res = P.solve_region(Y0, allow_noconv=True)
+        t1 = time.perf_counter()
+        Pa.factor_shifts()
+        resa = Pa.solve_region(Y0a, allow_noconv=True)
+        t2 = time.perf_counter()
+        g = np.ones(res["count"], np.complex128)
+        P.eig_vjp(res["lam"], res["X"], resa["lam"], resa["X"], g, wl.A.nnz, wl.B.nnz)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return res, resa, (t1 - t0, t2 - t1, t3 - t2)
+
+    step()
+    tot = np.zeros(3)
+    for _ in range(reps):
+        res, resa, t = step()
+        tot += np.array(t)
+    ms = tot * 1000.0 / reps
+    n_ok = int(np.sum(res["err"] <= 1e-10))
+    out = {"workload": "convdiff128_randv_p4_q8_w64", "expected_count": wl.s_expected,
+           "count": res["count"], "count_adjoint": resa["count"],
+           "ms_right": round(ms[0], 3), "ms_left": round(ms[1], 3), "ms_vjp": round(ms[2], 3),
+           "ms_per_step": round(ms.sum(), 3),
+           "value": round(n_ok / (ms.sum() / 1000.0), 3), "unit": "eigenvalue gradients/s"}
+    P.close()
+    Pa.close()
+    return out
+
+
 def W_start_block(wl):
     from paper_2310_18043_amd import workloads as W
     return W.start_block(wl.n, wl.w, wl.seed)
@@ -194,6 +240,8 @@ def main():
                     help="also time Alg. composite2 up to this outer node count (0: skip)")
     ap.add_argument("--batch-disks", type=int, default=16,
                     help="also time the batched form on this many disks (0: skip)")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="skip the differentiation-form measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -348,6 +396,11 @@ def main():
         bt = batched_form(args.batch_disks, min(args.steps, 2))
         log(f"batched: {bt}")
 
+    grad = None
+    if not args.no_gradient:
+        grad = gradient_form(min(args.steps, 2))
+        log(f"gradient: {grad}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -374,6 +427,7 @@ def main():
         "filter_apply": fa,
         "composite2": c2,
         "batched": bt,
+        "gradient": grad,
         "phases_ms": {"factor": round(stats["factor_ms"] / max(args.steps, 1), 3),
                       "filter": round(res["ms_filter"], 3), "hsrr": round(res["ms_hsrr"], 3)},
     }
