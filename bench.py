@@ -33,6 +33,7 @@ import numpy as np  # noqa: E402
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (complex64 band solves)
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "band_solve_convdiff128_traffic.json")
 
 
@@ -240,6 +241,8 @@ def main():
                     help="also time Alg. composite2 up to this outer node count (0: skip)")
     ap.add_argument("--batch-disks", type=int, default=16,
                     help="also time the batched form on this many disks (0: skip)")
+    ap.add_argument("--no-c64", action="store_true",
+                    help="skip the precision-form (complex64 band solves) measurement")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the differentiation-form measurement")
     ap.add_argument("--calib-copy", action="store_true",
@@ -391,6 +394,43 @@ def main():
         log(f"composite2: {c2}")
         del plan2
 
+    # precision form on the same workload and start block: complex64 band solves,
+    # complex128 outer solves, projections and residuals
+    pc = None
+    if not args.no_c64:
+        plan3 = rfeig.Plan(wl.A, wl.B, wl.c, wl.r, p=wl.p, q=wl.q, w=wl.w,
+                           expected_count=wl.s_expected, subblock=args.subblock, precision=1)
+
+        def step3():
+            plan3.factor_shifts()
+            return plan3.solve_region(Y0, allow_noconv=True)
+
+        step3()
+        torch.cuda.synchronize()
+        plan3.profile_enable(True)
+        tc0 = time.perf_counter()
+        reps3 = max(1, min(args.steps, 2))
+        for _ in range(reps3):
+            r3 = step3()
+        torch.cuda.synchronize()
+        ms3 = (time.perf_counter() - tc0) * 1000.0 / reps3
+        st3 = plan3.profile_read()
+        plan3.profile_enable(False)
+        good3 = (np.abs(r3["lam"] - wl.c) < wl.r) & (r3["err"] <= 1e-10)
+        cols3 = st3["solve_columns"] / max(st3["solve_launches"], 1)
+        t3 = fl_col * st3["solve_columns"] / (st3["solve_ms"] * 1e-3) / 1e12
+        pc = {"ms_per_step": round(ms3, 3), "value": round(int(good3.sum()) / (ms3 / 1000.0), 3),
+              "unit": "eigenpairs/s", "converged_count": int(good3.sum()), "sweeps": r3["sweeps"],
+              "krylov_steps": r3["krylov_steps"], "ms_filter": round(r3["ms_filter"], 3),
+              "ms_hsrr": round(r3["ms_hsrr"], 3),
+              "factor_ms": round(st3["factor_ms"] / reps3, 3),
+              "band_solve_c64": {"avg_launch_ms": round(st3["solve_ms"] / max(st3["solve_launches"], 1), 4),
+                                 "avg_columns_per_launch": round(cols3, 2),
+                                 "achieved": round(t3, 3), "peak": PEAK_FP32_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": round(t3 / PEAK_FP32_TFLOPS, 4)}}
+        log(f"precision form (c64 solves): {pc}")
+        del plan3
+
     bt = None
     if args.batch_disks > 0:
         bt = batched_form(args.batch_disks, min(args.steps, 2))
@@ -426,6 +466,7 @@ def main():
         "cpu_baseline": cpu,
         "filter_apply": fa,
         "composite2": c2,
+        "precision_c64": pc,
         "batched": bt,
         "gradient": grad,
         "phases_ms": {"factor": round(stats["factor_ms"] / max(args.steps, 1), 3),

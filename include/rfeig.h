@@ -73,6 +73,10 @@ typedef struct {
     int32_t trsm_cols;       /* right-hand sides per band-solve workgroup: 1, 2 or 4 (0 = automatic, 3 and 5..8 act as 4) */
     uint64_t seed;           /* seed of the start block when none is given */
     int32_t q_max;           /* largest outer node count of rf_solve_region_adaptive (0 = q) */
+    int32_t precision;       /* 0: complex128 band solves; 1: precision form -- complex64 copies of the
+                                (complex128) factors for every band solve, the outer GMRES to
+                                max(gmres_tol, 1e-6), and from the second sweep of rf_solve_region on
+                                the filter applied through the complex128 residual of the Ritz pairs */
 } rf_opts;
 
 /* Per-call statistics of a filter application. */

@@ -6,6 +6,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <numeric>
@@ -189,6 +191,7 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
         return RF_ERR_ARG;
     if (o.trsm_cols < 0 || o.trsm_cols > 8) return RF_ERR_ARG;
     if (o.q_max < 0 || o.q_max > 256) return RF_ERR_ARG;
+    if (o.precision < 0 || o.precision > 1) return RF_ERR_ARG;
 
     rf_plan *P = new rf_plan();
     P->opts = o;
@@ -307,6 +310,13 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
         P->F.tiles = owner->F.tiles + int64_t(pole_offset) * P->F.nblk * 5 * te;
         P->F.perm = owner->F.perm + int64_t(pole_offset) * P->F.nblk * 2 * nb;
         P->F.info = owner->F.info + pole_offset;
+        if (o.precision == 1) {
+            if (!owner->F.tiles32) {
+                rf_fail(P, RF_ERR_ARG, "the shared factor storage has no complex64 copy");
+                return fail(RF_ERR_ARG);
+            }
+            P->F.tiles32 = owner->F.tiles32 + int64_t(pole_offset) * P->F.nblk * 5 * te;
+        }
     } else {
         ALLOC(P->F.tiles, int64_t(o.p) * P->F.nblk * 5 * te);
         ALLOC(P->F.perm, int64_t(o.p) * P->F.nblk * 2 * nb);
@@ -314,7 +324,11 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
         ALLOC(P->F.info, o.p);
         ALLOC(P->F.rows, int64_t(o.p) * P->F.nblk * te * 3);
         ALLOC(P->F.subperm, int64_t(o.p) * 2 * nb);
+        if (o.precision == 1) ALLOC(P->F.tiles32, int64_t(o.p) * P->F.nblk * 5 * te);
     }
+    ALLOC(P->d_colcoef, int64_t(std::max(nq_alloc, 1)) * o.w);
+    ALLOC(P->d_colw, int64_t(o.p) * o.w);
+    ALLOC(P->d_lam, o.w);
     const int64_t n = P->n, w = o.w;
     ALLOC(P->rhs, npad * w);
     ALLOC(P->ypart, int64_t(o.p) * npad * w);
@@ -400,6 +414,10 @@ rf_status rf_factor_shifts(rf_plan_t P) {
                            "zero pivot in the factorization of pole " + std::to_string(i) +
                                " at column " + std::to_string(info[i] - 1));
         }
+    if (P->F.tiles32) {
+        RF_HIP(P, launch_tiles_to_c64(*P, P->stream));
+        RF_HIP(P, hipStreamSynchronize(P->stream));
+    }
     P->F.ready = true;
     return RF_OK;
 }
@@ -547,17 +565,40 @@ struct KrylovState {
     bool converged = true;
 };
 
+// RFEIG_TRACE=1 in the environment: one line per sweep on stderr.
+bool trace_on() {
+    static const bool on = [] {
+        const char *v = std::getenv("RFEIG_TRACE");
+        return v && *v && *v != '0';
+    }();
+    return on;
+}
+
+// Outer-solve tolerance: the plan's, or at least 1e-6 when the band solves run in
+// complex64 (their rounding bounds how far the outer residual can usefully go).
+double outer_tol(const rf_plan *P) {
+    return P->opts.precision == 1 ? std::max(P->opts.gmres_tol, 1e-6) : P->opts.gmres_tol;
+}
+
+rf_status krylov_start_rhs(rf_plan *P, KrylovState &K);
+
 rf_status krylov_start(rf_plan *P, const zd *Y, int64_t ldy, KrylovState &K) {
+    K = KrylovState();
+    // Ytilde = G(Y)
+    RF_HIP(P, launch_inner_apply(*P, Y, ldy, P->opts.w, P->ytil, P->n, P->stream));
+    K.inner_cols += P->opts.w;
+    return krylov_start_rhs(P, K);
+}
+
+// The right-hand side block of the outer solves is in P->ytil: unit columns and the
+// first basis block of every sub-block.
+rf_status krylov_start_rhs(rf_plan *P, KrylovState &K) {
     hipStream_t s = P->stream;
     const int64_t n = P->n;
     const int w = P->opts.w, b = P->b, nsub = P->nsub, mmax = P->mmax;
     const int64_t ldc = int64_t(mmax + 1) * b;
     const int64_t vstride = n * ldc;
-    K = KrylovState();
     K.msteps.assign(nsub, 0);
-    // Ytilde = G(Y)
-    RF_HIP(P, launch_inner_apply(*P, Y, ldy, w, P->ytil, n, s));
-    K.inner_cols += w;
     // The outer solves are column-wise linear in Ytilde: solve for unit-norm
     // columns (so every column meets the relative tolerance on its own scale,
     // whatever the spread of |R_p(lambda)| across the block) and scale back.
@@ -629,7 +670,7 @@ rf_status krylov_rule(rf_plan *P, KrylovState &K, std::vector<int> &open) {
         RF_HIP(P, hipStreamSynchronize(s));
     }
     for (int sb = 0; sb < nsub; ++sb)
-        if (K.msteps[sb] == 0 || !(krylov_worst(P, resid, sb) <= P->opts.gmres_tol)) open.push_back(sb);
+        if (K.msteps[sb] == 0 || !(krylov_worst(P, resid, sb) <= outer_tol(P))) open.push_back(sb);
     return RF_OK;
 }
 
@@ -707,14 +748,14 @@ rf_status krylov_advance(rf_plan *P, KrylovState &K, std::vector<int> active, bo
         bool any_open = false;
         for (int sb : active) {
             K.msteps[sb] = j + 1;
-            if (!(krylov_worst(P, resid, sb) <= P->opts.gmres_tol)) any_open = true;
+            if (!(krylov_worst(P, resid, sb) <= outer_tol(P))) any_open = true;
         }
         for (int sb : active) {
             const double worst = krylov_worst(P, resid, sb);
-            const bool open = uniform ? any_open : !(worst <= P->opts.gmres_tol);
+            const bool open = uniform ? any_open : !(worst <= outer_tol(P));
             if (open && j + 1 < mmax) still.push_back(sb);
             else {
-                if (!(worst <= P->opts.gmres_tol)) K.converged = false;
+                if (!(worst <= outer_tol(P))) K.converged = false;
                 K.worst = std::max(K.worst, worst);
             }
         }
@@ -767,6 +808,102 @@ rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
     RF_TRY(krylov_rule(P, K, open));
     RF_TRY(krylov_advance(P, K, open, false));
     RF_TRY(krylov_combine(P, K, U, ldu));
+    if (info) {
+        info->krylov_steps = K.steps;
+        info->converged = K.converged ? 1 : 0;
+        info->max_residual = K.worst;
+        info->inner_columns = K.inner_cols;
+        info->ms_total = now_ms() - t0;
+    }
+    return K.converged ? RF_OK : RF_ERR_NOCONV;
+}
+
+// The composite filter applied to a block X with shifts lam (one per column) through
+// the residual R = A X - B X diag(lam), for the precision form.  For any column x
+// with shift l (exact algebra, no approximation):
+//   K_i^{-1} B x = x / (p_i - l) + K_i^{-1} r / (p_i - l)            (K_i = p_i B - A)
+//   G x = g x + rho,  g = sum_i w_i / (p_i - l),  rho = sum_i w_i K_i^{-1} r / (p_i - l)
+//   (G - s_j)^{-1} G x = g / (g - s_j) x - s_j / (g - s_j) (G - s_j)^{-1} rho,
+// so U = sum_j c'_j (G - s_j)^{-1} G X (+ (1/q) G X, odd q; Thm. Rcrm, eq. linearsolve2)
+//      = X diag(f(g)) - sum_j c'_j s_j Z_j diag(1 / (g - s_j)) (+ (1/q) rho),
+//   f(g) = sum_j c'_j g / (g - s_j) (+ g / q),   Z_j = (G - s_j)^{-1} rho.
+// Only rho and the outer solves with right-hand side rho use the band solves, so
+// their complex64 rounding is relative to the residual, which shrinks as the Ritz
+// pairs converge, instead of to X.
+rf_status filter_core_residual(rf_plan *P, const zd *X, int64_t ldx,
+                               const std::vector<std::complex<double>> &lam_in, zd *U,
+                               int64_t ldu, rf_filter_info *info) {
+    const double t0 = now_ms();
+    hipStream_t s = P->stream;
+    const int64_t n = P->n;
+    const int w = P->opts.w, p = P->opts.p;
+    const int nq = int(P->shifts.size());
+    const std::complex<double> c(P->opts.c_re, P->opts.c_im);
+    // shifts: the Ritz values, unless one is not finite or sits (numerically) on a pole
+    // of G or of the outer rule; then the centre (any shift keeps the identity exact)
+    std::vector<std::complex<double>> lam(w), gt(w);
+    auto gval = [&](std::complex<double> l) {
+        std::complex<double> g = 0.0;
+        for (int i = 0; i < p; ++i)
+            g += std::complex<double>(P->weights[i].x, P->weights[i].y) /
+                 (std::complex<double>(P->poles[i].x, P->poles[i].y) - l);
+        return g;
+    };
+    for (int k = 0; k < w; ++k) {
+        std::complex<double> l = k < int(lam_in.size()) ? lam_in[k] : c;
+        bool ok = std::isfinite(l.real()) && std::isfinite(l.imag());
+        for (int i = 0; ok && i < p; ++i)
+            ok = std::abs(std::complex<double>(P->poles[i].x, P->poles[i].y) - l) > 1e-3 * P->opts.r;
+        std::complex<double> g = ok ? gval(l) : 0.0;
+        for (int j = 0; ok && j < nq; ++j)
+            ok = std::abs(g - std::complex<double>(P->shifts[j].x, P->shifts[j].y)) > 1e-6;
+        if (!ok) { l = c; g = gval(c); }
+        lam[k] = l;
+        gt[k] = g;
+    }
+    std::vector<zd> hl(w), colw(size_t(p) * w), coef(size_t(std::max(nq, 1)) * w), alpha(w);
+    for (int k = 0; k < w; ++k) {
+        hl[k] = Z(lam[k].real(), lam[k].imag());
+        for (int i = 0; i < p; ++i) {
+            std::complex<double> v = std::complex<double>(P->weights[i].x, P->weights[i].y) /
+                                     (std::complex<double>(P->poles[i].x, P->poles[i].y) - lam[k]);
+            colw[size_t(i) * w + k] = Z(v.real(), v.imag());
+        }
+        std::complex<double> f = P->oextra * gt[k];
+        for (int j = 0; j < nq; ++j) {
+            const std::complex<double> sj(P->shifts[j].x, P->shifts[j].y),
+                cj(P->oweights[j].x, P->oweights[j].y);
+            f += cj * gt[k] / (gt[k] - sj);
+            const std::complex<double> cc = -cj * sj / (gt[k] - sj);
+            coef[size_t(j) * w + k] = Z(cc.real(), cc.imag());
+        }
+        alpha[k] = Z(f.real(), f.imag());
+    }
+    RF_HIP(P, hipMemcpyAsync(P->d_lam, hl.data(), sizeof(zd) * w, hipMemcpyHostToDevice, s));
+    RF_HIP(P, hipMemcpyAsync(P->d_colw, colw.data(), sizeof(zd) * p * w, hipMemcpyHostToDevice, s));
+    if (nq > 0)
+        RF_HIP(P, hipMemcpyAsync(P->d_colcoef, coef.data(), sizeof(zd) * nq * w, hipMemcpyHostToDevice, s));
+    // R = A X - B X diag(lam)  (complex128), then rho = sum_i K_i^{-1} R diag(w_i / (p_i - lam))
+    RF_HIP(P, launch_spmm(P->A, w, X, ldx, P->tmp, n, s));
+    RF_HIP(P, launch_spmm(P->B, w, X, ldx, P->Wk, n, s));
+    RF_HIP(P, launch_sub_diag(n, w, P->tmp, n, P->Wk, n, P->d_lam, P->tmp, n, s));
+    RF_HIP(P, launch_inner_apply(*P, P->tmp, n, w, P->ytil, n, s, false, P->d_colw));
+    // the host vectors above are pageable: finish their copies before they go away
+    RF_HIP(P, hipStreamSynchronize(s));
+    KrylovState K;
+    K.inner_cols = w;
+    RF_TRY(krylov_start_rhs(P, K));
+    std::vector<int> open;
+    RF_TRY(krylov_rule(P, K, open));
+    RF_TRY(krylov_advance(P, K, open, false));
+    P->colcoef_on = true;
+    rf_status cs = krylov_combine(P, K, U, ldu);
+    P->colcoef_on = false;
+    RF_TRY(cs);
+    // U += X diag(f(g))
+    RF_HIP(P, hipMemcpyAsync(P->d_lam, alpha.data(), sizeof(zd) * w, hipMemcpyHostToDevice, s));
+    RF_HIP(P, launch_add_diag(n, w, X, ldx, P->d_lam, U, ldu, s));
+    RF_HIP(P, hipStreamSynchronize(s));
     if (info) {
         info->krylov_steps = K.steps;
         info->converged = K.converged ? 1 : 0;
@@ -953,7 +1090,9 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
         rf_filter_info fi;
         double t1 = now_ms();
         // U lands in P->Wk? no: Wk is Krylov scratch; use hW as the output block
-        rf_status fs = filter_core(P, Y, n, P->hW, n, &fi);
+        rf_status fs = (P->opts.precision == 1 && t > 1)
+                           ? filter_core_residual(P, Y, n, lam, P->hW, n, &fi)
+                           : filter_core(P, Y, n, P->hW, n, &fi);
         if (fs != RF_OK && fs != RF_ERR_NOCONV) return fs;
         // copy U out of hW before HSRR reuses it
         RF_HIP(P, launch_copy_cols(n, w, P->hW, n, P->ytil, n, s));
@@ -969,6 +1108,14 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
             bool filt = inside && err[i] < P->opts.tau_g;
             flags[i] = (inside ? 1 : 0) | (filt ? 2 : 0) | (err[i] <= P->opts.tau ? 4 : 0);
             if (filt) { ++count; if (!(err[i] <= P->opts.tau)) all_small = false; }
+        }
+        if (trace_on()) {
+            double emax = 0.0;
+            for (int i = 0; i < w; ++i)
+                if (flags[i] & 2) emax = std::max(emax, err[i]);
+            std::fprintf(stderr, "[rfeig] sweep %d: filtered %d, max filtered e %.3e, krylov steps %d, "
+                                 "outer residual %.2e, filter %.1f ms, hsrr %.1f ms\n",
+                         t, count, emax, fi.krylov_steps, fi.max_residual, t2 - t1, now_ms() - t2);
         }
         if (all_small && (count == prev || (t == 1 && P->opts.expected_count >= 0 &&
                                             count == P->opts.expected_count))) {
@@ -995,6 +1142,8 @@ rf_status rf_solve_region_adaptive(rf_plan_t P, const void *Y0, int64_t ldy, rf_
     if (Y0 && ldy < P->n) return rf_fail(P, RF_ERR_ARG, "bad start block");
     if (P->opts.q_max < P->opts.q)
         return rf_fail(P, RF_ERR_ARG, "q_max of the plan must be at least q");
+    if (P->opts.precision != 0)
+        return rf_fail(P, RF_ERR_ARG, "the precision form needs the subspace iteration (rf_solve_region)");
     if (!P->F.ready) RF_TRY(rf_factor_shifts(P));
     hipStream_t s = P->stream;
     const int64_t n = P->n;
@@ -1178,7 +1327,8 @@ rf_status rf_batch_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     if (!opts || ndisks < 1 || !csr_ok(A) || !csr_ok(B) || A->n != B->n) return RF_ERR_ARG;
     int64_t ptot = 0;
     for (int d = 0; d < ndisks; ++d) {
-        if (opts[d].p < 1 || opts[d].tile != opts[0].tile) return RF_ERR_ARG;
+        if (opts[d].p < 1 || opts[d].tile != opts[0].tile || opts[d].precision != opts[0].precision)
+            return RF_ERR_ARG;
         ptot += opts[d].p;
     }
     if (ptot > (int64_t(1) << 20)) return RF_ERR_ARG;

@@ -604,13 +604,28 @@ struct SolveArgs {
     int ncols;               // total right-hand sides
     const zd *X; int64_t ldx;        // right-hand sides (before B)
     const zd *bdiag;                 // diagonal of B, or null (then X already holds B X)
-    const zd *tiles;
+    const void *tiles;               // factor tiles, complex128 or complex64
     const int32_t *perm;
-    const zd *weights;
-    zd *ypart;               // [pole][npad x ncols]  forward results
-    zd *xpart;               // [pole][npad x ncols]  w_i * K_i^{-1} B X
+    const zd *weights;               // w_i per pole
+    const zd *colw;                  // or null: weight per pole and column, [pole][ncols]
+    void *ypart;             // [pole][npad x ncols]  forward results (tile precision)
+    zd *xpart;               // [pole][npad x ncols]  weight * K_i^{-1} B X
     int64_t npad;
 };
+
+// complex64 helpers for the single-precision tiles
+__device__ inline zf fmake(float re, float im) { zf r; r.x = re; r.y = im; return r; }
+__device__ inline void zfma(zf &acc, zf a, zf b) {
+    acc.x = fmaf(a.x, b.x, acc.x); acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y); acc.y = fmaf(a.y, b.x, acc.y);
+}
+__device__ inline zf zsub(zf a, zf b) { return fmake(a.x - b.x, a.y - b.y); }
+template <typename CT> __device__ inline CT czero() { CT z; z.x = 0; z.y = 0; return z; }
+template <typename CT> __device__ inline CT from_zd(zd v);
+template <> __device__ inline zd from_zd<zd>(zd v) { return v; }
+template <> __device__ inline zf from_zd<zf>(zd v) { return fmake(float(v.x), float(v.y)); }
+__device__ inline zd to_zd(zd v) { return v; }
+__device__ inline zd to_zd(zf v) { return zmake(double(v.x), double(v.y)); }
 
 // Solve kernel.  One workgroup of kSolveThreads threads owns one pole and a slice
 // of CW right-hand sides and runs the whole forward and backward sweep as nb x nb
@@ -663,9 +678,9 @@ __device__ constexpr bool piece_zero(int q, int j) {
 
 // Load batch b of this thread's piece of tile T (thread corner tp = T + slot + g NB;
 // the element offsets are compile-time constants).
-template <int NB, int SHAPE>
-__device__ __attribute__((always_inline)) inline void issue_batch(const zd *tp, int b,
-                                                                  zd (&t)[SolveShape<NB>::S]) {
+template <int NB, int SHAPE, typename CT>
+__device__ __attribute__((always_inline)) inline void issue_batch(const CT *tp, int b,
+                                                                  CT (&t)[SolveShape<NB>::S]) {
     using SH = SolveShape<NB>;
 #pragma unroll
     for (int e = 0; e < SH::S; ++e) {
@@ -675,17 +690,17 @@ __device__ __attribute__((always_inline)) inline void issue_batch(const zd *tp, 
 }
 
 // acc[q][c] += sum over batch b of a tile of T[row_q, k] v[k, c]
-template <int CW, int NB, int SHAPE>
+template <int CW, int NB, int SHAPE, typename CT>
 __device__ __attribute__((always_inline)) inline void consume(int g, int b,
-                                                              const zd (&t)[SolveShape<NB>::S],
-                                                              const zd *v,
-                                                              zd (&acc)[SolveShape<NB>::R][CW]) {
+                                                              const CT (&t)[SolveShape<NB>::S],
+                                                              const CT *v,
+                                                              CT (&acc)[SolveShape<NB>::R][CW]) {
     using SH = SolveShape<NB>;
 #pragma unroll
     for (int e = 0; e < SH::S; ++e) {
         const int E = b * SH::S + e, j = E / SH::R, q = E % SH::R;
         if (piece_zero<NB, SHAPE>(q, j)) continue;
-        const zd *vr = v + (j * SH::G + g) * CW;
+        const CT *vr = v + (j * SH::G + g) * CW;
 #pragma unroll
         for (int c = 0; c < CW; ++c) zfma(acc[q][c], t[e], vr[c]);
     }
@@ -695,24 +710,24 @@ __device__ __attribute__((always_inline)) inline void consume(int g, int b,
 // (even / odd batches) and request, batch by batch, the rest of it and then the
 // first batches of the next tile, read as shape SN.  A consumer never uses an
 // element its producer skipped: SN is the next tile's shape or kFull.
-template <int CW, int NB, int SC, int SN>
+template <int CW, int NB, int SC, int SN, typename CT>
 __device__ __attribute__((always_inline)) inline void run_phase(
-        int g, zd (&bufA)[SolveShape<NB>::S], zd (&bufB)[SolveShape<NB>::S],
-        zd (&acc)[SolveShape<NB>::R][CW], const zd *v, const zd *tcur, const zd *tnext) {
+        int g, CT (&bufA)[SolveShape<NB>::S], CT (&bufB)[SolveShape<NB>::S],
+        CT (&acc)[SolveShape<NB>::R][CW], const CT *v, const CT *tcur, const CT *tnext) {
     using SH = SolveShape<NB>;
 #pragma unroll
     for (int bp = 0; bp < SH::NBAT; bp += 2) {
-        consume<CW, NB, SC>(g, bp, bufA, v, acc);
-        if (bp + 2 < SH::NBAT) issue_batch<NB, SC>(tcur, bp + 2, bufA);
-        else issue_batch<NB, SN>(tnext, bp + 2 - SH::NBAT, bufA);
-        consume<CW, NB, SC>(g, bp + 1, bufB, v, acc);
-        if (bp + 3 < SH::NBAT) issue_batch<NB, SC>(tcur, bp + 3, bufB);
-        else issue_batch<NB, SN>(tnext, bp + 3 - SH::NBAT, bufB);
+        consume<CW, NB, SC, CT>(g, bp, bufA, v, acc);
+        if (bp + 2 < SH::NBAT) issue_batch<NB, SC, CT>(tcur, bp + 2, bufA);
+        else issue_batch<NB, SN, CT>(tnext, bp + 2 - SH::NBAT, bufA);
+        consume<CW, NB, SC, CT>(g, bp + 1, bufB, v, acc);
+        if (bp + 3 < SH::NBAT) issue_batch<NB, SC, CT>(tcur, bp + 3, bufB);
+        else issue_batch<NB, SN, CT>(tnext, bp + 3 - SH::NBAT, bufB);
     }
 }
 
-template <int CW, int NB>
-__device__ inline void reduce_rows(zd (&acc)[SolveShape<NB>::R][CW]) {
+template <int CW, int NB, typename CT>
+__device__ inline void reduce_rows(CT (&acc)[SolveShape<NB>::R][CW]) {
     using SH = SolveShape<NB>;
 #pragma unroll
     for (int off = SH::G / 2; off > 0; off >>= 1) {
@@ -726,7 +741,7 @@ __device__ inline void reduce_rows(zd (&acc)[SolveShape<NB>::R][CW]) {
     }
 }
 
-template <int CW, int NB>
+template <int CW, int NB, typename CT>
 __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) {
     using SH = SolveShape<NB>;
     constexpr int NT = kSolveThreads;
@@ -749,14 +764,14 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
     const bool writer = active && g == 0;
 
     extern __shared__ unsigned char smem_raw[];
-    zd *win = reinterpret_cast<zd *>(smem_raw);   // [2NB][CW]
-    zd *win2 = win + 2 * NB * CW;                 // [2NB][CW]
-    zd *ybuf = win2 + 2 * NB * CW;                // [NB][CW]
-    zd *ring = ybuf + NB * CW;                    // [3][NB][CW]
+    CT *win = reinterpret_cast<CT *>(smem_raw);   // [2NB][CW]
+    CT *win2 = win + 2 * NB * CW;                 // [2NB][CW]
+    CT *ybuf = win2 + 2 * NB * CW;                // [NB][CW]
+    CT *ring = ybuf + NB * CW;                    // [3][NB][CW]
 
-    zd *yp = a.ypart + int64_t(pole) * a.npad * a.ncols;
+    CT *yp = static_cast<CT *>(a.ypart) + int64_t(pole) * a.npad * a.ncols;
     zd *xp = a.xpart + int64_t(pole) * a.npad * a.ncols;
-    const zd *tiles = a.tiles + int64_t(pole) * nblk * 5 * te;
+    const CT *tiles = static_cast<const CT *>(a.tiles) + int64_t(pole) * nblk * 5 * te;
     const int32_t *perm = a.perm + int64_t(pole) * nblk * 2 * NB;
 
     // tile of block k, slot t (0 Linv, 1 L21, 2 Uinv, 3 U1, 4 U2), at this thread's corner
@@ -773,17 +788,18 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
     const int prank = slice / spread;
     const int pcount = (nslices + spread - 1) / spread;
     double sink = 0.0;
-    auto touch = [&](const zd *base, int64_t elems) __attribute__((always_inline)) {
-        const int64_t lines = (elems + 7) / 8;              // 8 complex per 128-byte line
+    auto touch = [&](const CT *base, int64_t elems) __attribute__((always_inline)) {
+        constexpr int64_t kLine = 128 / sizeof(CT);         // elements per 128-byte line
+        const int64_t lines = (elems + kLine - 1) / kLine;
         const int64_t per = (lines + pcount - 1) / pcount;
         const int64_t ln = int64_t(prank) * per + tid;
         const bool ok = tid < per && ln < lines;
-        sink += base[ok ? ln * 8 : 0].x;
+        sink += double(base[ok ? ln * kLine : 0].x);
     };
 
     // right-hand sides: rows of block blk, element e of the [NB][CW] block
     constexpr int RPT = (NB * CW + NT - 1) / NT;
-    zd pre[RPT];
+    CT pre[RPT];
     auto prefetch_rhs = [&](int blk) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
@@ -793,10 +809,10 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
             const bool ok = blk < nblk && e < NB * CW && row < a.n && c < ncw;
             zd x = a.X[ok ? row + int64_t(c0 + c) * a.ldx : 0];
             if (a.bdiag) x = zmul(a.bdiag[ok ? row : 0], x);
-            pre[q] = ok ? x : zmake(0, 0);
+            pre[q] = ok ? from_zd<CT>(x) : czero<CT>();
         }
     };
-    auto store_rhs = [&](zd *dst) __attribute__((always_inline)) {
+    auto store_rhs = [&](CT *dst) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             int e = tid + q * NT;
@@ -807,15 +823,15 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
     // the pipelined tile stream: bufA / bufB hold the even / odd batches of the tile
     // being consumed; each consumed batch is replaced by the one two places further
     // down the sequence (the same tile, or the next one)
-    zd bufA[SH::S], bufB[SH::S];
-    issue_batch<NB, kFull>(tile_at(0, 0), 0, bufA);
-    issue_batch<NB, kFull>(tile_at(0, 0), 1, bufB);
-    zd acc[R][CW];
+    CT bufA[SH::S], bufB[SH::S];
+    issue_batch<NB, kFull, CT>(tile_at(0, 0), 0, bufA);
+    issue_batch<NB, kFull, CT>(tile_at(0, 0), 1, bufB);
+    CT acc[R][CW];
     auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < R; ++q)
 #pragma unroll
-            for (int c = 0; c < CW; ++c) acc[q][c] = zmake(0, 0);
+            for (int c = 0; c < CW; ++c) acc[q][c] = czero<CT>();
     };
 
     // ---------------- forward sweep
@@ -841,9 +857,9 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         }
         __syncthreads();
         zero_acc();
-        run_phase<CW, NB, kLower, kFull>(g, bufA, bufB, acc, win2, tile_at(k, 0),
+        run_phase<CW, NB, kLower, kFull, CT>(g, bufA, bufB, acc, win2, tile_at(k, 0),
                                          tile_at(k, 1));          // y_k = Linv w_top
-        reduce_rows<CW, NB>(acc);
+        reduce_rows<CW, NB, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -858,9 +874,9 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         __syncthreads();
         zero_acc();
         // next: Linv_{k+1}, or U1 of the last block to start the backward sweep
-        run_phase<CW, NB, kFull, kFull>(g, bufA, bufB, acc, ybuf, tile_at(k, 1),
+        run_phase<CW, NB, kFull, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 1),
                                         last ? tile_at(k, 3) : tile_at(k + 1, 0));   // t_{k+1} = w_bot - L21 y_k
-        reduce_rows<CW, NB>(acc);
+        reduce_rows<CW, NB, CT>(acc);
         if (writer && !last) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -872,26 +888,26 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         __syncthreads();
     }
     // ---------------- backward sweep
-    for (int e = tid; e < 3 * NB * CW; e += NT) ring[e] = zmake(0, 0);
+    for (int e = tid; e < 3 * NB * CW; e += NT) ring[e] = czero<CT>();
     touch(tiles + int64_t(nblk - 1) * 5 * te + 2 * te, 3 * te);
-    zd ynext[R][CW];
-    auto load_y = [&](int k, zd (&dst)[R][CW]) {
+    CT ynext[R][CW];
+    auto load_y = [&](int k, CT (&dst)[R][CW]) {
 #pragma unroll
         for (int q = 0; q < R; ++q)
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
                 const bool ok = writer && k >= 0 && c < ncw;
-                const zd x = yp[ok ? int64_t(k) * NB + slot + SH::SLOTS * q + int64_t(c0 + c) * a.npad : 0];
-                dst[q][c] = ok ? x : zmake(0, 0);
+                const CT x = yp[ok ? int64_t(k) * NB + slot + SH::SLOTS * q + int64_t(c0 + c) * a.npad : 0];
+                dst[q][c] = ok ? x : czero<CT>();
             }
     };
     load_y(nblk - 1, ynext);
     __syncthreads();
     for (int k = nblk - 1; k >= 0; --k) {
-        zd *xk = ring + (k % 3) * NB * CW;
-        const zd *xk1 = ring + ((k + 1) % 3) * NB * CW;
-        const zd *xk2 = ring + ((k + 2) % 3) * NB * CW;
-        zd y[R][CW];
+        CT *xk = ring + (k % 3) * NB * CW;
+        const CT *xk1 = ring + ((k + 1) % 3) * NB * CW;
+        const CT *xk2 = ring + ((k + 2) % 3) * NB * CW;
+        CT y[R][CW];
 #pragma unroll
         for (int q = 0; q < R; ++q)
 #pragma unroll
@@ -900,9 +916,9 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         touch(tiles + int64_t(max(k - 1, 0)) * 5 * te + 2 * te, 3 * te);   // Uinv, U1, U2 of k-1
         // v = y_k - U1 x_{k+1} - U2 x_{k+2}
         zero_acc();
-        run_phase<CW, NB, kFull, kLower>(g, bufA, bufB, acc, xk1, tile_at(k, 3), tile_at(k, 4));
-        run_phase<CW, NB, kLower, kUpper>(g, bufA, bufB, acc, xk2, tile_at(k, 4), tile_at(k, 2));
-        reduce_rows<CW, NB>(acc);
+        run_phase<CW, NB, kFull, kLower, CT>(g, bufA, bufB, acc, xk1, tile_at(k, 3), tile_at(k, 4));
+        run_phase<CW, NB, kLower, kUpper, CT>(g, bufA, bufB, acc, xk2, tile_at(k, 4), tile_at(k, 2));
+        reduce_rows<CW, NB, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -913,9 +929,9 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         }
         __syncthreads();
         zero_acc();
-        run_phase<CW, NB, kUpper, kFull>(g, bufA, bufB, acc, ybuf, tile_at(k, 2),
+        run_phase<CW, NB, kUpper, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 2),
                                          tile_at(max(k - 1, 0), 3));   // x_k = Uinv v
-        reduce_rows<CW, NB>(acc);
+        reduce_rows<CW, NB, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -923,14 +939,17 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
 #pragma unroll
                 for (int c = 0; c < CW; ++c) {
                     xk[row * CW + c] = acc[q][c];
-                    if (c < ncw) xp[int64_t(k) * NB + row + int64_t(c0 + c) * a.npad] = zmul(wgt, acc[q][c]);
+                    if (c < ncw) {
+                        const zd wc = a.colw ? a.colw[int64_t(pole) * a.ncols + c0 + c] : wgt;
+                        xp[int64_t(k) * NB + row + int64_t(c0 + c) * a.npad] = zmul(wc, to_zd(acc[q][c]));
+                    }
                 }
             }
         }
         __syncthreads();
     }
     // keep the prefetch loads alive without storing anything real (n is never negative)
-    if (a.n < 0) ybuf[0] = zmake(sink, 0.0);
+    if (a.n < 0) ybuf[0] = from_zd<CT>(zmake(sink, 0.0));
 }
 
 // Z[:, c] = sum_pole xpart[pole][:, c]   (fixed order: deterministic)
@@ -1005,40 +1024,62 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
     return hipGetLastError();
 }
 
-static size_t solve_lds(int nb, int cw) {
+static size_t solve_lds(int nb, int cw, size_t elem) {
     // win + win2 (2nb each) + ybuf (nb) + ring (3nb), all x cw
-    return size_t(2 * nb * cw * 2 + nb * cw + 3 * nb * cw) * sizeof(zd);
+    return size_t(2 * nb * cw * 2 + nb * cw + 3 * nb * cw) * elem;
 }
 
-template <int CW, int NB>
+template <int CW, int NB, typename CT>
 static hipError_t launch_solve_nb(const SolveArgs &a, hipStream_t s) {
     const int slices = (a.ncols + CW - 1) / CW;
-    hipLaunchKernelGGL((band_solve_kernel<CW, NB>), dim3(slices * a.p), dim3(kSolveThreads),
-                       solve_lds(NB, CW), s, a);
+    hipLaunchKernelGGL((band_solve_kernel<CW, NB, CT>), dim3(slices * a.p), dim3(kSolveThreads),
+                       solve_lds(NB, CW, sizeof(CT)), s, a);
     return hipGetLastError();
 }
 
-template <int CW>
+template <int CW, typename CT>
 static hipError_t launch_solve_cw(const SolveArgs &a, hipStream_t s) {
     switch (a.nb) {
-        case 16: return launch_solve_nb<CW, 16>(a, s);
-        case 32: return launch_solve_nb<CW, 32>(a, s);
-        case 64: return launch_solve_nb<CW, 64>(a, s);
-        case 128: return launch_solve_nb<CW, 128>(a, s);
-        case 256: return launch_solve_nb<CW, 256>(a, s);
+        case 16: return launch_solve_nb<CW, 16, CT>(a, s);
+        case 32: return launch_solve_nb<CW, 32, CT>(a, s);
+        case 64: return launch_solve_nb<CW, 64, CT>(a, s);
+        case 128: return launch_solve_nb<CW, 128, CT>(a, s);
+        case 256: return launch_solve_nb<CW, 256, CT>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
+namespace {
+__global__ void to_c64_kernel(const zd *src, zf *dst, int64_t count) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const zd v = src[e];
+    dst[e] = fmake(float(v.x), float(v.y));
+}
+}  // namespace
+
+hipError_t launch_tiles_to_c64(const rf_plan &P, hipStream_t s) {
+    if (!P.F.tiles32) return hipErrorInvalidValue;
+    const int64_t count = int64_t(P.opts.p) * P.F.nblk * 5 * P.F.tile_elems;
+    hipLaunchKernelGGL(to_c64_kernel, dim3((count + 255) / 256), dim3(256), 0, s, P.F.tiles,
+                       P.F.tiles32, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int ncols, zd *Z,
-                              int64_t ldz, hipStream_t s) {
+                              int64_t ldz, hipStream_t s, bool apply_b, const zd *colw) {
     SolveArgs a;
     a.n = int(P.n); a.nb = P.F.nb; a.nblk = P.F.nblk; a.p = P.opts.p;
     a.ncols = ncols;
-    a.tiles = P.F.tiles; a.perm = P.F.perm; a.weights = P.d_weights;
+    const bool c64 = P.opts.precision == 1;
+    if (c64 && !P.F.tiles32) return hipErrorInvalidValue;
+    a.tiles = c64 ? static_cast<const void *>(P.F.tiles32) : static_cast<const void *>(P.F.tiles);
+    a.perm = P.F.perm; a.weights = P.d_weights; a.colw = colw;
     a.ypart = P.ypart; a.xpart = P.xpart;
     a.npad = int64_t(P.F.nblk) * P.F.nb;
-    if (P.B.diagonal) {
+    if (!apply_b) {
+        a.X = X; a.ldx = ldx; a.bdiag = nullptr;
+    } else if (P.B.diagonal) {
         a.X = X; a.ldx = ldx; a.bdiag = P.B.dval;
     } else {
         hipError_t e = launch_spmm(P.B, ncols, X, ldx, P.rhs, a.npad, s);
@@ -1052,14 +1093,23 @@ hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int nc
         while (cw > 1 && (int64_t(ncols + cw - 1) / cw) * a.p < 256) cw /= 2;
     }
     if (cw > 2) cw = 4;
-    while (cw > 1 && solve_lds(a.nb, cw) > size_t(P.max_lds)) cw /= 2;
+    const size_t elem = c64 ? sizeof(zf) : sizeof(zd);
+    while (cw > 1 && solve_lds(a.nb, cw, elem) > size_t(P.max_lds)) cw /= 2;
     hipError_t e;
     hipEvent_t ev0 = nullptr;
     P.prof.record_begin(s, ev0);
-    switch (cw) {
-        case 1: e = launch_solve_cw<1>(a, s); break;
-        case 2: e = launch_solve_cw<2>(a, s); break;
-        default: e = launch_solve_cw<4>(a, s); break;
+    if (c64) {
+        switch (cw) {
+            case 1: e = launch_solve_cw<1, zf>(a, s); break;
+            case 2: e = launch_solve_cw<2, zf>(a, s); break;
+            default: e = launch_solve_cw<4, zf>(a, s); break;
+        }
+    } else {
+        switch (cw) {
+            case 1: e = launch_solve_cw<1, zd>(a, s); break;
+            case 2: e = launch_solve_cw<2, zd>(a, s); break;
+            default: e = launch_solve_cw<4, zd>(a, s); break;
+        }
     }
     if (e != hipSuccess) return e;
     P.prof.record_end(s, ev0, ncols, 0);

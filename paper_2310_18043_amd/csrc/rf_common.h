@@ -12,6 +12,7 @@
 // complex FP64 helpers (interleaved re/im in a double2)
 // ---------------------------------------------------------------------------
 typedef double2 zd;
+typedef float2 zf;   // complex64 (single-precision factor tiles)
 
 __host__ __device__ inline zd zmake(double re, double im) { zd r; r.x = re; r.y = im; return r; }
 __host__ __device__ inline zd zadd(zd a, zd b) { return zmake(a.x + b.x, a.y + b.y); }
@@ -76,6 +77,7 @@ struct BandFactors {
     zd *rows = nullptr;        // p * nblk * (nb x 3nb): row blocks of p_i B - A, dense
     int32_t *subperm = nullptr; // p * 2nb: row order of the current sub-panel
     int32_t *info = nullptr;   // p ints: 0 or (1 + first zero-pivot column)
+    zf *tiles32 = nullptr;     // complex64 copy of tiles (precision form), or null
     bool ready = false;
 };
 
@@ -151,6 +153,12 @@ struct rf_plan {
     std::string last_error;
     bool broken = false;
     bool shared_factors = false;  // F.tiles/perm/info belong to a batch's factor owner
+    // precision form: per-(shift, column) combine coefficients and per-(pole, column)
+    // inner weights of the residual form
+    zd *d_colcoef = nullptr;  // nq x w
+    zd *d_colw = nullptr;     // p x w
+    zd *d_lam = nullptr;      // w shifts of the residual
+    bool colcoef_on = false;
 };
 
 // error helpers --------------------------------------------------------------
@@ -172,8 +180,14 @@ rf_status rf_fail(rf_plan *plan, rf_status s, const std::string &msg);
 // band factorization / solves (rf_band.hip)
 hipError_t launch_band_factor(const rf_plan &P, hipStream_t s);
 // Z = sum_i w_i K_i^{-1} (B X): X n x ncols (ldx), Z n x ncols (ldz)
+// apply_b = false: X already holds the right-hand sides (no B product); colw (device,
+// [pole][ncols]) replaces w_i by a weight per pole and column.  The plan's precision
+// selects the complex128 or complex64 factor tiles.
 hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int ncols,
-                              zd *Z, int64_t ldz, hipStream_t s);
+                              zd *Z, int64_t ldz, hipStream_t s, bool apply_b = true,
+                              const zd *colw = nullptr);
+// complex64 copy of the factor tiles (after the complex128 factorization)
+hipError_t launch_tiles_to_c64(const rf_plan &P, hipStream_t s);
 
 // dense kernels (rf_dense.hip)
 // Batched operands: entry t of operand X is at X + (flags & kMapX ? map[t] : t) * sX.
@@ -217,6 +231,12 @@ hipError_t launch_sampled_outer(const DevCsr &M, int s, const zd *coef, const zd
                                 hipStream_t st);
 hipError_t launch_spmm(const DevCsr &M, int ncols, const zd *X, int64_t ldx, zd *Y,
                        int64_t ldy, hipStream_t s);
+// Z[:, c] = X[:, c] - lam[c] Y[:, c]
+hipError_t launch_sub_diag(int64_t n, int ncols, const zd *X, int64_t ldx, const zd *Y,
+                           int64_t ldy, const zd *lam, zd *Z, int64_t ldz, hipStream_t s);
+// Z[:, c] += alpha[c] X[:, c]
+hipError_t launch_add_diag(int64_t n, int ncols, const zd *X, int64_t ldx, const zd *alpha, zd *Z,
+                           int64_t ldz, hipStream_t s);
 // Y = A X - sigma * B X   (all n x ncols)
 hipError_t launch_axpby_cols(int64_t n, int ncols, zd alpha, const zd *X, int64_t ldx,
                              zd beta, const zd *Y, int64_t ldy, zd *Z, int64_t ldz,

@@ -737,8 +737,11 @@ __global__ __launch_bounds__(GT) void ls_solve_kernel(LsSolveArgs a) {
     }
 }
 
+// Ycomb_sb = sum_l c_l Y_{l,sb}; with colcoef (device [nq][w]) the coefficient of
+// column c of sub-block sb is colcoef[l][sb b + c] instead of cw[l].
 __global__ void ls_combine_kernel(int b, int mmax, int m, int nq, int nsub, const zd *Y,
-                                  const zd *cw, const int *active, int nact, zd *Ycomb) {
+                                  const zd *cw, const zd *colcoef, int w, const int *active,
+                                  int nact, zd *Ycomb) {
     int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int mb = m * b, ldr = mmax * b;
     if (e >= int64_t(mb) * b * nact) return;
@@ -749,7 +752,8 @@ __global__ void ls_combine_kernel(int b, int mmax, int m, int nq, int nsub, cons
     zd s = zmake(0, 0);
     for (int l = 0; l < nq; ++l) {
         const zd *Yl = Y + ls_off(l, sb, nsub, int64_t(mmax) * b * b);
-        zfma(s, cw[l], Yl[r + int64_t(c) * ldr]);
+        const zd cl = colcoef ? colcoef[int64_t(l) * w + sb * b + c] : cw[l];
+        zfma(s, cl, Yl[r + int64_t(c) * ldr]);
     }
     Ycomb[int64_t(sb) * ldr * b + r + int64_t(c) * ldr] = s;
 }
@@ -902,6 +906,42 @@ hipError_t launch_spmm(const DevCsr &M, int ncols, const zd *X, int64_t ldx, zd 
     return hipGetLastError();
 }
 
+__global__ void sub_diag_kernel(int64_t n, int ncols, const zd *X, int64_t ldx, const zd *Y,
+                                int64_t ldy, const zd *lam, zd *Z, int64_t ldz) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n * ncols) return;
+    int64_t r = e % n, c = e / n;
+    zd v = X[r + c * ldx];
+    zfms(v, lam[c], Y[r + c * ldy]);
+    Z[r + c * ldz] = v;
+}
+
+__global__ void add_diag_kernel(int64_t n, int ncols, const zd *X, int64_t ldx, const zd *alpha,
+                                zd *Z, int64_t ldz) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n * ncols) return;
+    int64_t r = e % n, c = e / n;
+    zfma(Z[r + c * ldz], alpha[c], X[r + c * ldx]);
+}
+
+hipError_t launch_sub_diag(int64_t n, int ncols, const zd *X, int64_t ldx, const zd *Y,
+                           int64_t ldy, const zd *lam, zd *Z, int64_t ldz, hipStream_t s) {
+    int64_t tot = n * ncols;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(sub_diag_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, n, ncols, X, ldx,
+                       Y, ldy, lam, Z, ldz);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_diag(int64_t n, int ncols, const zd *X, int64_t ldx, const zd *alpha, zd *Z,
+                           int64_t ldz, hipStream_t s) {
+    int64_t tot = n * ncols;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(add_diag_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, n, ncols, X, ldx,
+                       alpha, Z, ldz);
+    return hipGetLastError();
+}
+
 hipError_t launch_axpby_cols(int64_t n, int ncols, zd alpha, const zd *X, int64_t ldx, zd beta,
                              const zd *Y, int64_t ldy, zd *Z, int64_t ldz, hipStream_t s) {
     int64_t tot = n * ncols;
@@ -969,6 +1009,7 @@ hipError_t launch_ls_solve(const rf_plan &P, int m, const int *active, int nact,
     if (e != hipSuccess) return e;
     int64_t tot = int64_t(m) * P.b * P.b * nact;
     hipLaunchKernelGGL(ls_combine_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, P.b, P.mmax, m,
-                       a.nq, P.nsub, P.lsY, P.d_oweights, active, nact, P.ycomb);
+                       a.nq, P.nsub, P.lsY, P.d_oweights, P.colcoef_on ? P.d_colcoef : nullptr,
+                       P.opts.w, active, nact, P.ycomb);
     return hipGetLastError();
 }

@@ -44,7 +44,8 @@ class RfOpts(ctypes.Structure):
                 ("max_subspace_it", ctypes.c_int32), ("max_krylov_blocks", ctypes.c_int32),
                 ("subblock", ctypes.c_int32), ("expected_count", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("trsm_cols", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("q_max", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("q_max", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
 
 
 class RfFilterInfo(ctypes.Structure):

@@ -90,6 +90,12 @@ def test_plan_create_rejects_bad_arguments_before_device_work(lib):
         assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None,
                                   ctypes.byref(out)) == rfeig.RF_ERR_ARG
     o.tile = 0
+    # precision other than 0 (complex128) and 1 (complex64 band solves)
+    for bad in (-1, 2):
+        o.precision = bad
+        assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None,
+                                  ctypes.byref(out)) == rfeig.RF_ERR_ARG
+    o.precision = 0
     assert out.value is None
 
 

@@ -108,3 +108,20 @@ def test_unconjugated_left_vectors_are_caught():
     fd = (lp[np.argmin(np.abs(lp - lam[0]))] - lm[np.argmin(np.abs(lm - lam[0]))]) / (2 * h)
     assert abs(fd - gA_good[e]) <= 1e-6 * max(1, abs(fd))
     assert abs(fd - gA_bad[e]) > 1e-3 * max(1, abs(fd))
+
+
+def test_sparse_condition_numbers_against_dense():
+    import scipy.sparse as sp
+    from paper_2310_18043_amd import workloads as W
+    v = W.random_vfield(8, 20.0, 2)
+    A, B = W.convdiff_pencil(8, 1.0, vfield=v, mass=(0.5, 1.5), seed=3)
+    lam, X, Y = S.dense_left_right(A, B)
+    kap_dense = (np.linalg.norm(X, axis=0) * np.linalg.norm(Y, axis=0)
+                 / np.abs(np.sum(Y.conj() * (B @ X), axis=0)))
+    pick = np.argsort(lam.real)[[3, 20, 40]]
+    kap, Xs, Ys = S.eig_condition_sparse(A, B, lam[pick])
+    assert np.allclose(kap, kap_dense[pick], rtol=1e-6)
+    # the vectors are eigenvectors
+    for k, i in enumerate(pick):
+        r = A @ Xs[:, k] - lam[i] * (B @ Xs[:, k])
+        assert np.linalg.norm(r) <= 1e-8 * np.abs(lam[i])
