@@ -27,41 +27,48 @@ __device__ inline int64_t bidx(const int *map, int flags, int bit, int t) {
 // C_part[chunk] = A[rows of chunk]^H B[rows of chunk]   (tile 64 x 64 per WG)
 // grid: (ceil(m/64), ceil(k/64), batch * nchunks)
 // ---------------------------------------------------------------------------
+// TNV: output columns per thread (tile width 16 TNV): 4 for wide right operands, 2
+// when k <= 32 (the Krylov sub-block width), so that no multiply-add is spent on padding.
+template <int TNV>
 __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
     int64_t n, int m, int k, const zd *__restrict__ A, int64_t lda, int64_t sA,
     const zd *__restrict__ B, int64_t ldb, int64_t sB, zd *__restrict__ part, int nchunks,
     int64_t chunk, const int *map, int flags) {
+    constexpr int TNT = 16 * TNV;
     const int bt = blockIdx.z / nchunks, ch = blockIdx.z % nchunks;
-    const int m0 = blockIdx.x * TM, k0 = blockIdx.y * TN;
+    const int m0 = blockIdx.x * TM, k0 = blockIdx.y * TNT;
     A += bidx(map, flags, kMapA, bt) * sA;
     B += bidx(map, flags, kMapB, bt) * sB;
     const int64_t r0 = int64_t(ch) * chunk;
     const int64_t r1 = min(n, r0 + chunk);
     __shared__ zd As[TK][TM + 1];
-    __shared__ zd Bs[TK][TN + 1];
+    __shared__ zd Bs[TK][TNT + 1];
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    zd acc[4][4];
+    zd acc[4][TNV];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = zmake(0, 0);
+        for (int j = 0; j < TNV; ++j) acc[i][j] = zmake(0, 0);
     for (int64_t rr = r0; rr < r1; rr += TK) {
         for (int e = tid; e < TK * TM; e += GT) {
             int i = e % TK, c = e / TK;
             int64_t row = rr + i;
             As[i][c] = (row < r1 && m0 + c < m) ? A[row + int64_t(m0 + c) * lda] : zmake(0, 0);
-            Bs[i][c] = (row < r1 && k0 + c < k) ? B[row + int64_t(k0 + c) * ldb] : zmake(0, 0);
+            if (c < TNT)
+                Bs[i][c] = (row < r1 && k0 + c < k) ? B[row + int64_t(k0 + c) * ldb] : zmake(0, 0);
         }
         __syncthreads();
 #pragma unroll 4
         for (int i = 0; i < TK; ++i) {
-            zd av[4], bv[4];
+            zd av[4], bv[TNV];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) { av[u] = As[i][ty + 16 * u]; bv[u] = Bs[i][tx + 16 * u]; }
+            for (int u = 0; u < 4; ++u) av[u] = As[i][ty + 16 * u];
+#pragma unroll
+            for (int v = 0; v < TNV; ++v) bv[v] = Bs[i][tx + 16 * v];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) zfma_c(acc[u][v], av[u], bv[v]);
+                for (int v = 0; v < TNV; ++v) zfma_c(acc[u][v], av[u], bv[v]);
         }
         __syncthreads();
     }
@@ -69,7 +76,7 @@ __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < TNV; ++v) {
             int mi = m0 + ty + 16 * u, kj = k0 + tx + 16 * v;
             if (mi < m && kj < k) P[mi + int64_t(kj) * m] = acc[u][v];
         }
@@ -97,44 +104,49 @@ __global__ void gemm_cn_reduce_kernel(int m, int k, const zd *part, int nchunks,
 // ---------------------------------------------------------------------------
 // C (n x k) = alpha * A (n x m) B (m x k) + beta * C     grid: (ceil(n/64), ceil(k/64), batch)
 // ---------------------------------------------------------------------------
+template <int TNV>
 __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd alpha,
                                                      const zd *__restrict__ A, int64_t lda,
                                                      int64_t sA, const zd *__restrict__ B,
                                                      int64_t ldb, int64_t sB, zd beta, zd *C,
                                                      int64_t ldc, int64_t sC, const int *map,
                                                      int flags) {
+    constexpr int TNT = 16 * TNV;
     const int bt = blockIdx.z;
     const int64_t n0 = int64_t(blockIdx.x) * TM;
-    const int k0 = blockIdx.y * TN;
+    const int k0 = blockIdx.y * TNT;
     A += bidx(map, flags, kMapA, bt) * sA;
     B += bidx(map, flags, kMapB, bt) * sB;
     C += bidx(map, flags, kMapC, bt) * sC;
     __shared__ zd As[TK][TM + 1];
-    __shared__ zd Bs[TK][TN + 1];
+    __shared__ zd Bs[TK][TNT + 1];
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    zd acc[4][4];
+    zd acc[4][TNV];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = zmake(0, 0);
+        for (int j = 0; j < TNV; ++j) acc[i][j] = zmake(0, 0);
     for (int kk = 0; kk < m; kk += TK) {
         for (int e = tid; e < TK * TM; e += GT) {
             int r = e % TM, i = e / TM;          // A tile: rows n0.., cols kk..
             int64_t row = n0 + r;
             As[i][r] = (row < n && kk + i < m) ? A[row + int64_t(kk + i) * lda] : zmake(0, 0);
             int i2 = e % TK, c = e / TK;         // B tile: rows kk.., cols k0..
-            Bs[i2][c] = (kk + i2 < m && k0 + c < k) ? B[(kk + i2) + int64_t(k0 + c) * ldb] : zmake(0, 0);
+            if (c < TNT)
+                Bs[i2][c] = (kk + i2 < m && k0 + c < k) ? B[(kk + i2) + int64_t(k0 + c) * ldb] : zmake(0, 0);
         }
         __syncthreads();
 #pragma unroll 4
         for (int i = 0; i < TK; ++i) {
-            zd av[4], bv[4];
+            zd av[4], bv[TNV];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) { av[u] = As[i][ty + 16 * u]; bv[u] = Bs[i][tx + 16 * u]; }
+            for (int u = 0; u < 4; ++u) av[u] = As[i][ty + 16 * u];
+#pragma unroll
+            for (int v = 0; v < TNV; ++v) bv[v] = Bs[i][tx + 16 * v];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) zfma(acc[u][v], av[u], bv[v]);
+                for (int v = 0; v < TNV; ++v) zfma(acc[u][v], av[u], bv[v]);
         }
         __syncthreads();
     }
@@ -142,7 +154,7 @@ __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < TNV; ++v) {
             int64_t row = n0 + ty + 16 * u;
             int col = k0 + tx + 16 * v;
             if (row < n && col < k) {
@@ -176,6 +188,10 @@ __global__ __launch_bounds__(GT) void chol_inv_lds_kernel(int k, const zd *S, in
     __shared__ int bad;
     __shared__ double shift;
     const int tid = threadIdx.x;
+    // column ownership: thread group g (tpc consecutive lanes) owns column g
+    int tpc = 64;
+    while (tpc > 1 && tpc * k > GT) tpc >>= 1;
+    const int g = tid / tpc, part = tid % tpc;
     for (int e = tid; e < k * k; e += GT) L[e] = Sg[e];
     if (tid == 0) bad = 0;
     __syncthreads();
@@ -185,41 +201,44 @@ __global__ __launch_bounds__(GT) void chol_inv_lds_kernel(int k, const zd *S, in
         shift = shift_rel * mx;
     }
     __syncthreads();
+    // right-looking: the owner of column j finishes it (its own updates are done),
+    // one barrier, then every later column takes its rank-one update
     for (int j = 0; j < k; ++j) {
-        if (tid == 0) {
+        if (g == j) {
             double d = L[j + j * k].x + shift;
-            if (!(d > 0.0)) { if (!bad) bad = j + 1; d = 1.0; }
-            L[j + j * k] = zmake(sqrt(d), 0.0);
+            if (!(d > 0.0)) { if (part == 0 && !bad) bad = j + 1; d = 1.0; }
+            const double sq = sqrt(d), inv = 1.0 / sq;
+            for (int i = j + 1 + part; i < k; i += tpc) L[i + j * k] = zscale(L[i + j * k], inv);
+            if (part == 0) L[j + j * k] = zmake(sq, 0.0);
         }
         __syncthreads();
-        const double inv = 1.0 / L[j + j * k].x;
-        for (int i = j + 1 + tid; i < k; i += GT) L[i + j * k] = zscale(L[i + j * k], inv);
-        __syncthreads();
-        const int rem = k - j - 1;
-        for (int e = tid; e < rem * rem; e += GT) {
-            int i = j + 1 + e % rem, l = j + 1 + e / rem;
-            if (l > i) continue;
-            zd v = L[i + l * k];
-            zd lij = L[i + j * k], llj = L[l + j * k];
-            v.x -= lij.x * llj.x + lij.y * llj.y;
-            v.y -= lij.y * llj.x - lij.x * llj.y;
-            if (i == l) v.y = 0.0;
-            L[i + l * k] = v;
+        if (g > j && g < k) {
+            const zd lgj = zconj(L[g + j * k]);
+            for (int i = g + part; i < k; i += tpc) {
+                zd v = L[i + g * k];
+                zfms(v, L[i + j * k], lgj);
+                if (i == g) v.y = 0.0;
+                L[i + g * k] = v;
+            }
         }
-        __syncthreads();
     }
-    // X = L^{-1} (lower), column c by thread group; forward substitution row by row
-    for (int e = tid; e < k * k; e += GT) X[e] = zmake(0, 0);
     __syncthreads();
-    for (int r = 0; r < k; ++r) {
-        // X[r][c] = (delta_rc - sum_{q<r} L[r][q] X[q][c]) / L[r][r], c <= r
-        for (int c = tid; c <= r; c += GT) {
-            zd v = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
-            for (int q = c; q < r; ++q) zfms(v, L[r + q * k], X[q + c * k]);
-            X[r + c * k] = zscale(v, 1.0 / L[r + r * k].x);
+    // X = L^{-1}: column g by its group, forward substitution; each lane keeps the
+    // entries x_q, q = part mod tpc, that its own partial sums use
+    if (g < k) {
+        for (int r = g; r < k; ++r) {
+            zd d = zmake(0, 0);
+            for (int q = g + part; q < r; q += tpc) zfma(d, L[r + q * k], X[q + g * k]);
+            for (int off = tpc / 2; off > 0; off >>= 1) {
+                d.x += __shfl_xor(d.x, off, 64);
+                d.y += __shfl_xor(d.y, off, 64);
+            }
+            const zd rhs = (r == g) ? zsub(zmake(1.0, 0.0), d) : zmake(-d.x, -d.y);
+            const zd xr = zscale(rhs, 1.0 / L[r + r * k].x);
+            if ((r - g) % tpc == part) X[r + g * k] = xr;
         }
-        __syncthreads();
     }
+    __syncthreads();
     // R = L^H (upper), Rinv = X^H
     for (int e = tid; e < k * k; e += GT) {
         int i = e % k, j = e / k;
@@ -570,18 +589,16 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
         }
         __syncthreads();
     }
-    // 3. Householder QR of the bottom 2b x b block (in LDS), accumulating Q_j in LDS.
-    //    Per column: wave 0 forms the reflector v (one wave reduction); the dot
-    //    products v^H slab(:, cc) and Q_j v are plain loops, one thread each (the
-    //    column loop starts at a different row per thread, so the reads of a wave fall
-    //    in distinct banks); then both rank-one updates run over all threads.
-    for (int e = tid; e < m2 * m2; e += GT) {
-        int r = e % m2, c = e / m2;
-        Ql[r + c * ldq] = (r == c) ? zmake(1.0, 0.0) : zmake(0, 0);
-    }
-    __shared__ double s_beta;
-    __shared__ zd s_dcol[32], s_dq[64];
-    __syncthreads();
+    // 3. Householder QR of the bottom 2b x b block (in LDS).  Per column c: wave 0
+    //    forms the reflector H_c = I - tau_c v_c v_c^H (v_c kept in slab2), then for
+    //    every later column a group of threads takes the dot v_c^H slab(:, cc) (partial
+    //    sums combined by lane shuffles) and applies the rank-one update to the same
+    //    column, so one barrier separates the columns.  Q_j = H_0 H_1 ... H_{b-1} is then
+    //    formed column by column, each column by its own thread group with no barrier.
+    __shared__ double s_tau[32];
+    zd *Vh = slab2;                                       // [2b][b] reflectors
+    const int tpd = min(64, GT / b);                      // threads per trailing column
+    const int dcol = tid / tpd, dpart = tid % tpd;
     for (int c = 0; c < b; ++c) {
         if (wave == 0) {
             zd x = (lane >= c && lane < m2) ? slab[lane + c * m2] : zmake(0, 0);
@@ -591,51 +608,50 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
             double nrm = sqrt(nrm2);
             zd ph = (ax0 > 0.0) ? zscale(x0, 1.0 / ax0) : zmake(1.0, 0.0);
             zd alpha = zscale(ph, -nrm);                  // alpha = -phase(x0) ||x||
-            if (lane < m2) vv[lane] = (lane == c) ? zsub(x, alpha) : x;
-            if (lane == 0) s_beta = (nrm > 0.0) ? 2.0 * nrm * (nrm + ax0) : 0.0;   // v^H v
+            if (lane < m2) {
+                Vh[lane + c * m2] = (lane == c) ? zsub(x, alpha) : x;     // zero above c
+                // column c itself becomes (alpha, 0, ..., 0) below row c
+                if (lane == c) slab[lane + c * m2] = alpha;
+                else if (lane > c) slab[lane + c * m2] = zmake(0, 0);
+            }
+            if (lane == 0) s_tau[c] = (nrm > 0.0) ? 1.0 / (nrm * (nrm + ax0)) : 0.0;  // 2 / v^H v
         }
         __syncthreads();
-        const double inv2 = (s_beta > 0.0) ? 2.0 / s_beta : 0.0;
-        if (tid < m2) {
-            // (Q_j v)[row]
+        const int cc = c + 1 + dcol;
+        if (cc < b && dcol < GT / tpd) {
+            const zd *vc = Vh + c * m2;
+            zd *col = slab + cc * m2;
             zd d = zmake(0, 0);
-            for (int t = 0; t < m2; ++t) zfma(d, Ql[tid + t * ldq], vv[t]);
-            s_dq[tid] = zscale(d, inv2);
-        } else if (tid >= 64 && tid < 64 + b) {
-            // (v^H slab)[cc] for cc > c
-            const int cc = tid - 64;
-            zd d = zmake(0, 0);
-            if (cc > c) {
-                for (int k = 0; k < m2; ++k) {
-                    int r = k + cc;
-                    if (r >= m2) r -= m2;
-                    zfma_c(d, vv[r], slab[r + cc * m2]);
-                }
+            for (int r = c + dpart; r < m2; r += tpd) zfma_c(d, vc[r], col[r]);
+            for (int off = tpd / 2; off > 0; off >>= 1) {
+                d.x += __shfl_xor(d.x, off, 64);
+                d.y += __shfl_xor(d.y, off, 64);
             }
-            s_dcol[cc] = zscale(d, inv2);
-        }
-        __syncthreads();
-        for (int e = tid; e < m2 * (b - c - 1); e += GT) {
-            const int r = e % m2, cc = c + 1 + e / m2;
-            zfms(slab[r + cc * m2], vv[r], s_dcol[cc]);
-        }
-        if (tid < m2) {
-            // column c itself becomes (alpha, 0, ..., 0)
-            zd y = slab[tid + c * m2];
-            if (tid == c) {
-                const zd vc = vv[c];
-                y = zsub(y, vc);                          // x_c - v_c = alpha
-            } else if (tid > c) {
-                y = zmake(0, 0);
-            }
-            slab[tid + c * m2] = y;
-        }
-        for (int e = tid; e < m2 * m2; e += GT) {
-            const int row = e % m2, t = e / m2;
-            zfms(Ql[row + t * ldq], s_dq[row], zconj(vv[t]));
+            d = zscale(d, s_tau[c]);
+            for (int r = c + dpart; r < m2; r += tpd) zfms(col[r], vc[r], d);
         }
         __syncthreads();
     }
+    {
+        const int tpq = min(64, GT / m2);                 // threads per column of Q_j
+        const int qcol = tid / tpq, qpart = tid % tpq;
+        if (qcol < m2) {
+            zd *Qc = Ql + qcol * ldq;
+            for (int r = qpart; r < m2; r += tpq) Qc[r] = (r == qcol) ? zmake(1.0, 0.0) : zmake(0, 0);
+            for (int c = b - 1; c >= 0; --c) {            // Q <- H_c Q
+                const zd *vc = Vh + c * m2;
+                zd d = zmake(0, 0);
+                for (int r = c + qpart; r < m2; r += tpq) zfma_c(d, vc[r], Qc[r]);
+                for (int off = tpq / 2; off > 0; off >>= 1) {
+                    d.x += __shfl_xor(d.x, off, 64);
+                    d.y += __shfl_xor(d.y, off, 64);
+                }
+                d = zscale(d, s_tau[c]);
+                for (int r = c + qpart; r < m2; r += tpq) zfms(Qc[r], vc[r], d);
+            }
+        }
+    }
+    __syncthreads();
     zd *Qj = Qs + int64_t(j) * qsz;
     for (int e = tid; e < m2 * m2; e += GT) Qj[e] = Ql[(e % m2) + (e / m2) * ldq];
     // 4. diagonal block R_jj (upper triangle of the reduced window)
@@ -768,7 +784,8 @@ hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_
                           int64_t ldc, int64_t sC, int batch, zd *work, int64_t work_elems,
                           hipStream_t s, const int *map, int flags) {
     if (n <= 0 || m <= 0 || k <= 0 || batch <= 0) return hipSuccess;
-    const int tiles = ((m + TM - 1) / TM) * ((k + TN - 1) / TN) * batch;
+    const int tn = k <= 32 ? 32 : TN;                        // tile width
+    const int tiles = ((m + TM - 1) / TM) * ((k + tn - 1) / tn) * batch;
     int nchunks = int((1024 + tiles - 1) / tiles);          // aim for ~1024 workgroups
     int64_t maxch = (n + 255) / 256;
     if (nchunks > maxch) nchunks = int(maxch);
@@ -778,9 +795,13 @@ hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_
     int64_t chunk = (n + nchunks - 1) / nchunks;
     chunk = ((chunk + TK - 1) / TK) * TK;
     nchunks = int((n + chunk - 1) / chunk);
-    dim3 grid((m + TM - 1) / TM, (k + TN - 1) / TN, batch * nchunks);
-    hipLaunchKernelGGL(gemm_cn_partial_kernel, grid, dim3(GT), 0, s, n, m, k, A, lda, sA, B, ldb,
-                       sB, work, nchunks, chunk, map, flags);
+    dim3 grid((m + TM - 1) / TM, (k + tn - 1) / tn, batch * nchunks);
+    if (tn == 32)
+        hipLaunchKernelGGL(gemm_cn_partial_kernel<2>, grid, dim3(GT), 0, s, n, m, k, A, lda, sA, B,
+                           ldb, sB, work, nchunks, chunk, map, flags);
+    else
+        hipLaunchKernelGGL(gemm_cn_partial_kernel<4>, grid, dim3(GT), 0, s, n, m, k, A, lda, sA, B,
+                           ldb, sB, work, nchunks, chunk, map, flags);
     int64_t tot = int64_t(m) * k * batch;
     hipLaunchKernelGGL(gemm_cn_reduce_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, m, k,
                        work, nchunks, alpha, beta, C, ldc, sC, batch, map, flags);
@@ -792,9 +813,14 @@ hipError_t launch_gemm_nn(int64_t n, int m, int k, zd alpha, const zd *A, int64_
                           int64_t ldc, int64_t sC, int batch, hipStream_t s, const int *map,
                           int flags) {
     if (n <= 0 || k <= 0 || batch <= 0) return hipSuccess;
-    dim3 grid(unsigned((n + TM - 1) / TM), (k + TN - 1) / TN, batch);
-    hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(GT), 0, s, n, m, k, alpha, A, lda, sA, B, ldb,
-                       sB, beta, C, ldc, sC, map, flags);
+    const int tn = k <= 32 ? 32 : TN;                        // tile width
+    dim3 grid(unsigned((n + TM - 1) / TM), (k + tn - 1) / tn, batch);
+    if (tn == 32)
+        hipLaunchKernelGGL(gemm_nn_kernel<2>, grid, dim3(GT), 0, s, n, m, k, alpha, A, lda, sA, B,
+                           ldb, sB, beta, C, ldc, sC, map, flags);
+    else
+        hipLaunchKernelGGL(gemm_nn_kernel<4>, grid, dim3(GT), 0, s, n, m, k, alpha, A, lda, sA, B,
+                           ldb, sB, beta, C, ldc, sC, map, flags);
     return hipGetLastError();
 }
 

@@ -96,6 +96,24 @@ def test_inner_apply_tile_override_and_column_slices(rf, torch_cuda):
         assert _relerr(Z, ref) <= 1e-12, (tile, cols)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_inner_apply_tile_256(rf, torch_cuda, precision):
+    # the largest tile: 16-column factorization sub-steps (LDS), four rows per solve
+    # thread; N = 1089 gives 5 block steps with a ragged last block
+    from oracle import filters
+    A, B = W.convdiff_pencil(33, mass=(0.5, 1.5), seed=4)           # kl = 33
+    X = W.start_block(A.shape[0], 24, seed=3)
+    ref = filters.InnerOperator(A, B, 3000 + 0.05j, 400.0, 2)(X)
+    for cols in (1, 2, 4):
+        _say(f"inner_apply tile=256 trsm_cols={cols} precision={precision}")
+        plan = rf.Plan(A, B, 3000 + 0.05j, 400.0, p=2, q=4, w=24, tile=256, trsm_cols=cols,
+                       precision=precision)
+        plan.factor_shifts()
+        Z = _to_host(plan.apply_inner(torch_cuda.from_numpy(X).cuda()))
+        assert _relerr(Z, ref) <= (1e-12 if precision == 0 else 1e-5), (cols, _relerr(Z, ref))
+        plan.close()
+
+
 def test_pole_on_eigenvalue_is_reported_singular(rf, torch_cuda):
     # diagonal pencil with an eigenvalue exactly at a trapezoidal pole
     lam = np.linspace(-3, 3, 64) + 0.0j
