@@ -140,21 +140,17 @@ __device__ inline zd lane_get(zd x, int ln) {
 }
 
 // value of row `row` (wave-uniform) of a column spread as v[s] = row lane + 64 s:
-// a uniform branch picks the slot, so only that slot is read out with readlane
-// (and the register array is never indexed dynamically)
+// every slot of lane row % 64 is read out with readlane and the uniform slot index
+// selects among the scalars (no branches, and the register array is never indexed
+// dynamically, which would put it in scratch memory)
 template <int NS>
 __device__ __attribute__((always_inline)) inline zd row_get(const zd (&v)[NS], int row) {
     const int sl = __builtin_amdgcn_readfirstlane(row >> 6), ln = row & 63;
-    zd x;
-    switch (sl) {
-        case 0: x = lane_get(v[0], ln); break;
-        case 1: x = lane_get(v[NS > 1 ? 1 : 0], ln); break;
-        case 2: x = lane_get(v[NS > 2 ? 2 : 0], ln); break;
-        case 3: x = lane_get(v[NS > 3 ? 3 : 0], ln); break;
-        case 4: x = lane_get(v[NS > 4 ? 4 : 0], ln); break;
-        case 5: x = lane_get(v[NS > 5 ? 5 : 0], ln); break;
-        case 6: x = lane_get(v[NS > 6 ? 6 : 0], ln); break;
-        default: x = lane_get(v[NS > 7 ? 7 : 0], ln); break;
+    zd x = lane_get(v[0], ln);
+#pragma unroll
+    for (int s = 1; s < NS; ++s) {
+        const zd t = lane_get(v[s], ln);
+        if (sl == s) x = t;
     }
     return x;
 }
@@ -177,38 +173,39 @@ __device__ __attribute__((always_inline)) inline void step_update(zd (&x)[NS], c
     }
 }
 
-// Wave-wide argmax of (m, i) by largest m, ties to the smallest i (a total order, so
-// the combination order does not matter), with DPP moves: within each row of 16
-// lanes by shifts of 1, 2, 4, 8, then across rows by the row-15 and row-31
-// broadcasts; lane 63 ends with the result.  Lanes whose DPP source does not exist
-// keep their own value.
-__device__ __attribute__((always_inline)) inline void wave_argmax(double &m, int &i) {
-#define RF_ARGMAX_STEP(CTRL, ROWMASK)                                                         \
+// Wave-wide maximum of a 64-bit key with DPP moves: within each row of 16 lanes by
+// shifts of 1, 2, 4, 8, then across rows by the row-15 and row-31 broadcasts; lane
+// 63 ends with the maximum.  Lanes whose DPP source does not exist keep their own
+// value.  A non-negative double's bit pattern orders like the double, so the keys
+// are the bits of |a|^2.
+__device__ __attribute__((always_inline)) inline uint64_t wave_max_u64(uint64_t key) {
+#define RF_MAX_STEP(CTRL, ROWMASK)                                                            \
     {                                                                                         \
-        const int lo = __double2loint(m), hi = __double2hiint(m);                             \
+        const int lo = int(uint32_t(key)), hi = int(uint32_t(key >> 32));                     \
         const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);       \
         const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);       \
-        const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROWMASK, 0xF, false);          \
-        const double om = __hiloint2double(ohi, olo);                                         \
-        if (om > m || (om == m && oi < i)) { m = om; i = oi; }                                \
+        const uint64_t o = (uint64_t(uint32_t(ohi)) << 32) | uint32_t(olo);                   \
+        key = o > key ? o : key;                                                              \
     }
-    RF_ARGMAX_STEP(0x111, 0xF)     // row_shr:1
-    RF_ARGMAX_STEP(0x112, 0xF)     // row_shr:2
-    RF_ARGMAX_STEP(0x114, 0xF)     // row_shr:4
-    RF_ARGMAX_STEP(0x118, 0xF)     // row_shr:8
-    RF_ARGMAX_STEP(0x142, 0xA)     // row_bcast:15 into rows 1 and 3
-    RF_ARGMAX_STEP(0x143, 0xC)     // row_bcast:31 into rows 2 and 3
-#undef RF_ARGMAX_STEP
+    RF_MAX_STEP(0x111, 0xF)     // row_shr:1
+    RF_MAX_STEP(0x112, 0xF)     // row_shr:2
+    RF_MAX_STEP(0x114, 0xF)     // row_shr:4
+    RF_MAX_STEP(0x118, 0xF)     // row_shr:8
+    RF_MAX_STEP(0x142, 0xA)     // row_bcast:15 into rows 1 and 3
+    RF_MAX_STEP(0x143, 0xC)     // row_bcast:31 into rows 2 and 3
+#undef RF_MAX_STEP
+    return key;
 }
 
 // Pivot step on a column held as x[s] = row lane + 64 s (sub-panel column j, panel
-// column gj): partial pivoting by largest |.|^2 (ties: smallest row), swap, scale by
-// 1 / pivot, publish the multipliers in lc and the pivot row in s_piv[j]; lane 0
-// records the interchange in the sub-panel order idxl and the step order pmf.
+// column gj): partial pivoting by largest |.|^2 (ties: the lowest lane, within a lane
+// the smallest row), swap, scale by 1 / pivot, publish the multipliers in lc and the
+// pivot row in s_piv[j].  The interchanges are replayed into the row orders after
+// the sub-panel is done, off this critical path.
 template <int NS>
 __device__ __attribute__((always_inline)) inline void panel_pivot(
-        zd (&x)[NS], int j, int gj, int R, int lane, zd *lc, int *s_piv, int *idxl, int *pmf,
-        int *s_info, int info_base, int *s_flag) {
+        zd (&x)[NS], int j, int gj, int R, int lane, zd *lc, int *s_piv, int *s_info,
+        int info_base, int *s_flag) {
     double best = -1.0;
     int bi = gj;
 #pragma unroll
@@ -217,26 +214,13 @@ __device__ __attribute__((always_inline)) inline void panel_pivot(
         double m = zabs2(x[s]);
         if (r >= gj && r < R && m > best) { best = m; bi = r; }
     }
-    wave_argmax(best, bi);                               // lane 63 holds the result
-    const double bmax = dlane_get(best, 63);
-    const bool sing = !(bmax > 0.0);
-    const int p = sing ? gj : __builtin_amdgcn_readlane(bi, 63);
-#ifdef RF_CHECK_ARGMAX
-    {   // cross-check against a butterfly over all lanes (diagnostic builds only)
-        double b2 = -1.0; int i2 = gj;
-        for (int s = 0; s < NS; ++s) {
-            int r = lane + 64 * s;
-            double m = zabs2(x[s]);
-            if (r >= gj && r < R && m > b2) { b2 = m; i2 = r; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            double ob = __shfl_xor(b2, off, 64);
-            int oi = __shfl_xor(i2, off, 64);
-            if (ob > b2 || (ob == b2 && oi < i2)) { b2 = ob; i2 = oi; }
-        }
-        if (lane == 0 && (b2 > 0.0 ? i2 : gj) != p) *s_info = 1;
-    }
-#endif
+    const uint64_t mine = best > 0.0 ? uint64_t(__double_as_longlong(best)) : 0;
+    const uint64_t top = wave_max_u64(mine);
+    const uint64_t kmax = (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(top >> 32)), 63))) << 32) |
+                          uint32_t(__builtin_amdgcn_readlane(int(uint32_t(top)), 63));
+    const bool sing = kmax == 0;
+    const uint64_t hit = __ballot(mine == kmax);
+    const int p = sing ? gj : __builtin_amdgcn_readlane(bi, int(__builtin_ctzll(hit)));
     const zd ap = row_get<NS>(x, p), a0 = row_get<NS>(x, gj);
     const zd inv = sing ? zmake(0, 0) : zdiv(zmake(1.0, 0.0), ap);
 #pragma unroll
@@ -250,8 +234,6 @@ __device__ __attribute__((always_inline)) inline void panel_pivot(
     }
     if (lane == 0) {
         s_piv[j] = p;
-        int t = idxl[gj]; idxl[gj] = idxl[p]; idxl[p] = t;
-        t = pmf[gj]; pmf[gj] = pmf[p]; pmf[p] = t;
         if (sing && *s_info == 0) *s_info = info_base + gj + 1;
     }
     // publish: the wave's multipliers and lane 0's records reach LDS before the flag
@@ -313,7 +295,7 @@ __global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, i
     // owner of column j+1 applies step j to it first and publishes step j+1, so the
     // other columns' updates stay off the critical path.
     if (wave == 0)
-        panel_pivot<NS>(v[0], 0, c0, R, lane, Lh, s_piv, idxl, pmf, &s_info, k * nb, s_flag);
+        panel_pivot<NS>(v[0], 0, c0, R, lane, Lh, s_piv, &s_info, k * nb, s_flag);
     for (int j = 0; j < SW; ++j) {
         const int gj = c0 + j;
         wait_flag(&s_flag[j], &s_info);
@@ -333,9 +315,9 @@ __global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, i
             // constant register indices in every branch (no dynamically indexed arrays)
 #define RF_OWNER_STEP(I_)                                                                       \
             case I_:                                                                            \
-                step_update<NS>(v[I_], l, p, gj, lane);                                         \
-                panel_pivot<NS>(v[I_], j + 1, gj + 1, R, lane, lnext, s_piv, idxl, pmf,         \
-                                &s_info, k * nb, s_flag);                                       \
+                step_update<NS>(v[I_], l, p, gj, lane);                                    \
+                panel_pivot<NS>(v[I_], j + 1, gj + 1, R, lane, lnext, s_piv, &s_info, k * nb,   \
+                                s_flag);                                                   \
                 break;
             switch (ii) {
                 RF_OWNER_STEP(0)
@@ -345,11 +327,11 @@ __global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, i
                     if (ii == 2) {
                         step_update<NS>(v[CPT > 2 ? 2 : 0], l, p, gj, lane);
                         panel_pivot<NS>(v[CPT > 2 ? 2 : 0], j + 1, gj + 1, R, lane, lnext, s_piv,
-                                        idxl, pmf, &s_info, k * nb, s_flag);
+                                        &s_info, k * nb, s_flag);
                     } else {
                         step_update<NS>(v[CPT > 3 ? 3 : 0], l, p, gj, lane);
                         panel_pivot<NS>(v[CPT > 3 ? 3 : 0], j + 1, gj + 1, R, lane, lnext, s_piv,
-                                        idxl, pmf, &s_info, k * nb, s_flag);
+                                        &s_info, k * nb, s_flag);
                     }
                 }
             }
@@ -382,6 +364,14 @@ __global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, i
             if (r < R) W[r + int64_t(col) * ldw] = v[i][s];
         }
     }
+    // replay the interchanges of the sub-panel into its row order and the step order
+    if (tid == 0)
+        for (int j = 0; j < SW; ++j) {
+            const int gj = c0 + j, p = s_piv[j];
+            int t = idxl[gj]; idxl[gj] = idxl[p]; idxl[p] = t;
+            t = pmf[gj]; pmf[gj] = pmf[p]; pmf[p] = t;
+        }
+    __syncthreads();
     int32_t *sp = a.subperm + int64_t(pole) * 2 * nb;
     for (int r = tid; r < 2 * nb; r += kFacThreads) {
         sp[r] = idxl[r];
