@@ -21,7 +21,13 @@ Everything is complex FP64.  Each function cites the passage of Chen & Li,
                   the Krylov space).
 * ``hsrr``     -- the projection step HSRR (Sec. 2.1, Alg. SIsketch) and the
                   relative eigenpair error (eq. rel-error).
-* ``solver``   -- Alg. composite (Sec. 3.2) around the pieces above.
+* ``solver``   -- Alg. composite (Sec. 3.2) around the pieces above, and
+                  Alg. composite2 (Sec. 3.2) by the composite identity.
+* ``precision``   -- the residual form of the composite filter used by the
+                  precision form (exact algebra; not in the paper).
+* ``sensitivity`` -- first-order eigenvalue perturbation with dense left/right
+                  vectors, and eigenvalue condition numbers by sparse inverse
+                  iteration (textbook; not in the paper).
 
 Readings of passages that are ambiguous or in error in the paper:
 
