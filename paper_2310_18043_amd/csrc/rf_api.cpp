@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <functional>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -373,6 +374,7 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
     ALLOC(P->hBV, n * w);
     ALLOC(P->hW, n * w);
     ALLOC(P->hX, n * w);
+    ALLOC(P->hY, n * w);
     ALLOC(P->hproj, 2 * w * w);
     ALLOC(P->herr, 2 * w);
 #undef ALLOC
@@ -557,6 +559,8 @@ rf_status cholqr2_batched_fixup(rf_plan *P, zd *W, int64_t sW, const zd *backup,
 //                   the tolerance for every shift;
 //   krylov_combine  U = sum_j c'_j (G - s_j I)^{-1} Ytilde (+ (1/q) Ytilde, odd q).
 struct KrylovState {
+    std::function<bool()> poll;  // optional: called after every block step; true stops the process
+    bool stopped = false;        // the poll stopped it (the basis is incomplete)
     std::vector<int> msteps;   // basis depth (blocks) per sub-block
     std::vector<double> scale; // column norms of Ytilde
     int64_t inner_cols = 0;
@@ -583,7 +587,9 @@ double outer_tol(const rf_plan *P) {
 rf_status krylov_start_rhs(rf_plan *P, KrylovState &K);
 
 rf_status krylov_start(rf_plan *P, const zd *Y, int64_t ldy, KrylovState &K) {
+    std::function<bool()> poll = std::move(K.poll);
     K = KrylovState();
+    K.poll = std::move(poll);
     // Ytilde = G(Y)
     RF_HIP(P, launch_inner_apply(*P, Y, ldy, P->opts.w, P->ytil, P->n, P->stream));
     K.inner_cols += P->opts.w;
@@ -760,6 +766,10 @@ rf_status krylov_advance(rf_plan *P, KrylovState &K, std::vector<int> active, bo
             }
         }
         active.swap(still);
+        if (K.poll && !active.empty() && K.poll()) {
+            K.stopped = true;
+            break;
+        }
     }
     return RF_OK;
 }
@@ -800,13 +810,17 @@ rf_status krylov_combine(rf_plan *P, KrylovState &K, zd *U, int64_t ldu) {
 // U = sum_j c'_j (G - s_j I)^{-1} G(Y) (Alg. composite's filter): a fresh basis,
 // every sub-block stopping on its own.
 rf_status filter_core(rf_plan *P, const zd *Y, int64_t ldy, zd *U, int64_t ldu,
-                      rf_filter_info *info) {
+                      rf_filter_info *info, std::function<bool()> poll = nullptr,
+                      bool *stopped = nullptr) {
     const double t0 = now_ms();
     KrylovState K;
+    K.poll = std::move(poll);
     RF_TRY(krylov_start(P, Y, ldy, K));
     std::vector<int> open;
     RF_TRY(krylov_rule(P, K, open));
     RF_TRY(krylov_advance(P, K, open, false));
+    if (stopped) *stopped = K.stopped;
+    if (K.stopped) return RF_OK;
     RF_TRY(krylov_combine(P, K, U, ldu));
     if (info) {
         info->krylov_steps = K.steps;
@@ -957,10 +971,21 @@ rf_status orth_panels(rf_plan *P, zd *U, int64_t n, int w) {
     return RF_OK;
 }
 
-// HSRR(A, B, U, sigma) (Sec. 2.1): Ritz values lam (host), unit-norm Ritz vectors in
-// P->hX, errors e_i (eq. rel-error) in err (host).
-rf_status hsrr(rf_plan *P, zd *U, std::vector<std::complex<double>> &lam,
-               std::vector<double> &err) {
+// HSRR(A, B, U, sigma) (Sec. 2.1) in three parts, so that the host QZ can run while the
+// device does other work:
+//   hsrr_project  V = orth(U) (in P->hV), W = orth(AV - sigma BV), the projected pencil
+//                 (W^* A V, W^* B V) copied to the host (pr.A, pr.B);
+//   pr.run_qz     complex QZ and eigenvectors on the host (no device access);
+//   hsrr_finish   Ritz values, unit-norm Ritz vectors X = V (P_R V_R) in P->hX and the
+//                 errors e_i (eq. rel-error).  Needs P->hV as hsrr_project left it.
+struct Projected {
+    int w = 0;
+    std::vector<zd> A, B, al, be, vr;
+    int qz_status = 0;
+    void run_qz() { qz_status = host_qz_eig(w, A.data(), B.data(), al.data(), be.data(), vr.data()); }
+};
+
+rf_status hsrr_project(rf_plan *P, zd *U, Projected &pr) {
     hipStream_t s = P->stream;
     const int64_t n = P->n;
     const int w = P->opts.w;
@@ -989,22 +1014,35 @@ rf_status hsrr(rf_plan *P, zd *U, std::vector<std::complex<double>> &lam,
                              P->partial_elems, s));
     RF_HIP(P, launch_gemm_cn(n, w, w, Z(1), P->hW, n, 0, P->hBV, n, 0, Z(0), Bh, w, 0, 1, P->partial,
                              P->partial_elems, s));
-    std::vector<zd> hA(size_t(w) * w), hB(size_t(w) * w), al(w), be(w), vr(size_t(w) * w);
-    RF_HIP(P, hipMemcpyAsync(hA.data(), Ah, sizeof(zd) * w * w, hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipMemcpyAsync(hB.data(), Bh, sizeof(zd) * w * w, hipMemcpyDeviceToHost, s));
+    pr.w = w;
+    pr.A.resize(size_t(w) * w);
+    pr.B.resize(size_t(w) * w);
+    pr.al.resize(w);
+    pr.be.resize(w);
+    pr.vr.resize(size_t(w) * w);
+    RF_HIP(P, hipMemcpyAsync(pr.A.data(), Ah, sizeof(zd) * w * w, hipMemcpyDeviceToHost, s));
+    RF_HIP(P, hipMemcpyAsync(pr.B.data(), Bh, sizeof(zd) * w * w, hipMemcpyDeviceToHost, s));
     RF_HIP(P, hipStreamSynchronize(s));
-    if (host_qz_eig(w, hA.data(), hB.data(), al.data(), be.data(), vr.data()) != 0)
-        return rf_fail(P, RF_ERR_NOCONV, "QZ iteration did not converge");
+    return RF_OK;
+}
+
+rf_status hsrr_finish(rf_plan *P, const Projected &pr, std::vector<std::complex<double>> &lam,
+                      std::vector<double> &err) {
+    hipStream_t s = P->stream;
+    const int64_t n = P->n;
+    const int w = P->opts.w;
+    if (pr.qz_status != 0) return rf_fail(P, RF_ERR_NOCONV, "QZ iteration did not converge");
     lam.resize(w);
     std::vector<zd> dlam(w);
     for (int i = 0; i < w; ++i) {
-        std::complex<double> a(al[i].x, al[i].y), bb(be[i].x, be[i].y);
+        std::complex<double> a(pr.al[i].x, pr.al[i].y), bb(pr.be[i].x, pr.be[i].y);
         lam[i] = (std::abs(bb) > 0.0) ? a / bb : std::complex<double>(INFINITY, 0.0);
         dlam[i] = Z(lam[i].real(), lam[i].imag());
     }
     // X = V (P_R V_R), unit columns
+    std::vector<double> cn(w);
     zd *dvr = P->small;
-    RF_HIP(P, hipMemcpyAsync(dvr, vr.data(), sizeof(zd) * w * w, hipMemcpyHostToDevice, s));
+    RF_HIP(P, hipMemcpyAsync(dvr, pr.vr.data(), sizeof(zd) * w * w, hipMemcpyHostToDevice, s));
     RF_HIP(P, launch_gemm_nn(n, w, w, Z(1), P->hV, n, 0, dvr, w, 0, Z(0), P->hX, n, 0, 1, s));
     RF_HIP(P, launch_colnorms(n, w, P->hX, n, nullptr, 0, nullptr, P->colnorm, s));
     RF_HIP(P, hipMemcpyAsync(cn.data(), P->colnorm, sizeof(double) * w, hipMemcpyDeviceToHost, s));
@@ -1029,6 +1067,15 @@ rf_status hsrr(rf_plan *P, zd *U, std::vector<std::complex<double>> &lam,
         err[i] = (den > 0.0 && std::isfinite(lam[i].real())) ? e2[i] / den : INFINITY;
     }
     return RF_OK;
+}
+
+// HSRR in one piece (Ritz values lam, Ritz vectors in P->hX, errors err).
+rf_status hsrr(rf_plan *P, zd *U, std::vector<std::complex<double>> &lam,
+               std::vector<double> &err) {
+    Projected pr;
+    RF_TRY(hsrr_project(P, U, pr));
+    pr.run_qz();
+    return hsrr_finish(P, pr, lam, err);
 }
 
 // Copy the last Ritz pairs into the caller's result, converged pairs inside D first.
@@ -1068,7 +1115,6 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
     if (!res || !res->lambda || !res->X || !res->err || !res->flags || res->ldx < P->n)
         return rf_fail(P, RF_ERR_ARG, "bad result buffers");
     if (Y0 && ldy < P->n) return rf_fail(P, RF_ERR_ARG, "bad start block");
-    const double t_start = now_ms();
     if (!P->F.ready) RF_TRY(rf_factor_shifts(P));
     hipStream_t s = P->stream;
     const int64_t n = P->n;
@@ -1082,25 +1128,13 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
     const double r = P->opts.r;
     std::vector<std::complex<double>> lam;
     std::vector<double> err;
-    int prev = -1, t = 0;
+    int prev = -1, t = 1;
     bool converged = false;
     double ms_filter = 0.0, ms_hsrr = 0.0;
     std::vector<int> flags(w);
-    for (t = 1; t <= P->opts.max_subspace_it; ++t) {
-        rf_filter_info fi;
-        double t1 = now_ms();
-        // U lands in P->Wk? no: Wk is Krylov scratch; use hW as the output block
-        rf_status fs = (P->opts.precision == 1 && t > 1)
-                           ? filter_core_residual(P, Y, n, lam, P->hW, n, &fi)
-                           : filter_core(P, Y, n, P->hW, n, &fi);
-        if (fs != RF_OK && fs != RF_ERR_NOCONV) return fs;
-        // copy U out of hW before HSRR reuses it
-        RF_HIP(P, launch_copy_cols(n, w, P->hW, n, P->ytil, n, s));
-        double t2 = now_ms();
-        ms_filter += t2 - t1;
-        if (t <= 16) res->krylov_steps[t - 1] = fi.krylov_steps;
-        RF_TRY(hsrr(P, P->ytil, lam, err));
-        ms_hsrr += now_ms() - t2;
+    rf_filter_info fi{};
+    // the stopping rule of Alg. composite on sweep t's Ritz pairs
+    auto judge = [&](int sweep, double ms_f) {
         int count = 0;
         bool all_small = true;
         for (int i = 0; i < w; ++i) {
@@ -1114,15 +1148,88 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
             for (int i = 0; i < w; ++i)
                 if (flags[i] & 2) emax = std::max(emax, err[i]);
             std::fprintf(stderr, "[rfeig] sweep %d: filtered %d, max filtered e %.3e, krylov steps %d, "
-                                 "outer residual %.2e, filter %.1f ms, hsrr %.1f ms\n",
-                         t, count, emax, fi.krylov_steps, fi.max_residual, t2 - t1, now_ms() - t2);
+                                 "outer residual %.2e, filter %.1f ms\n",
+                         sweep, count, emax, fi.krylov_steps, fi.max_residual, ms_f);
         }
-        if (all_small && (count == prev || (t == 1 && P->opts.expected_count >= 0 &&
-                                            count == P->opts.expected_count))) {
-            converged = true;
-            break;
-        }
+        const bool stop = all_small && (count == prev || (sweep == 1 && P->opts.expected_count >= 0 &&
+                                                          count == P->opts.expected_count));
         prev = count;
+        return stop;
+    };
+    auto filter_into_ytil = [&](const zd *Yin, int sweep, std::function<bool()> poll,
+                                bool *stopped) -> rf_status {
+        const double t1 = now_ms();
+        rf_status fs = (P->opts.precision == 1 && sweep > 1)
+                           ? filter_core_residual(P, Yin, n, lam, P->hW, n, &fi)
+                           : filter_core(P, Yin, n, P->hW, n, &fi, std::move(poll), stopped);
+        if (fs != RF_OK && fs != RF_ERR_NOCONV) return fs;
+        if (!(stopped && *stopped)) {
+            // U out of hW (HSRR reuses it) into ytil
+            RF_HIP(P, launch_copy_cols(n, w, P->hW, n, P->ytil, n, s));
+            if (sweep <= 16) res->krylov_steps[sweep - 1] = fi.krylov_steps;
+        }
+        ms_filter += now_ms() - t1;
+        return RF_OK;
+    };
+    if (P->opts.precision == 1) {
+        // precision form: the residual form needs the Ritz pairs of the previous sweep
+        for (t = 1; t <= P->opts.max_subspace_it; ++t) {
+            RF_TRY(filter_into_ytil(Y, t, nullptr, nullptr));
+            const double t2 = now_ms();
+            RF_TRY(hsrr(P, P->ytil, lam, err));
+            ms_hsrr += now_ms() - t2;
+            if (judge(t, 0.0)) { converged = true; break; }
+        }
+    } else {
+        // Sweep t + 1 filters the orthonormal basis V_t of sweep t's HSRR (P->hV) instead of
+        // its Ritz vectors X_t = V_t (P_R V_R): the filter is linear, so span(filter(X_t)) =
+        // span(filter(V_t)), and HSRR depends on that span only.  This lets the host QZ of
+        // sweep t run while the device already filters for sweep t + 1; sweep t's Ritz
+        // pairs are finished between two block-Arnoldi steps as soon as the QZ is done,
+        // and if they meet the stopping rule the speculative filter is abandoned.
+        RF_TRY(filter_into_ytil(Y, 1, nullptr, nullptr));
+        Projected pr;
+        for (t = 1;; ++t) {
+            double t2 = now_ms();
+            RF_TRY(hsrr_project(P, P->ytil, pr));
+            ms_hsrr += now_ms() - t2;
+            std::atomic<bool> qz_done{false};
+            std::thread qz;
+            try {
+                qz = std::thread([&] { pr.run_qz(); qz_done.store(true, std::memory_order_release); });
+            } catch (...) {                    // no thread: run the QZ here
+                pr.run_qz();
+                qz_done.store(true);
+            }
+            bool decided = false;
+            rf_status fin = RF_OK;
+            auto finish = [&]() {
+                const double t3 = now_ms();
+                if (qz.joinable()) qz.join();
+                fin = hsrr_finish(P, pr, lam, err);
+                decided = true;
+                ms_hsrr += now_ms() - t3;
+                if (fin == RF_OK) converged = judge(t, 0.0);
+                return fin == RF_OK && converged;
+            };
+            if (t < P->opts.max_subspace_it) {
+                RF_HIP(P, launch_copy_cols(n, w, P->hV, n, P->hY, n, s));
+                bool stopped = false;
+                auto poll = [&]() {
+                    if (decided || !qz_done.load(std::memory_order_acquire)) return false;
+                    return finish();
+                };
+                rf_status fs = filter_into_ytil(P->hY, t + 1, poll, &stopped);
+                if (!decided) finish();
+                if (fs != RF_OK) return fs;
+                RF_TRY(fin);
+                if (converged) break;
+            } else {
+                finish();
+                RF_TRY(fin);
+                break;
+            }
+        }
     }
     if (t > P->opts.max_subspace_it) t = P->opts.max_subspace_it;
     RF_TRY(fill_result(P, lam, err, flags, res));
@@ -1130,7 +1237,6 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
     res->converged = converged ? 1 : 0;
     res->ms_filter = ms_filter;
     res->ms_hsrr = ms_hsrr;
-    (void)t_start;
     return converged ? RF_OK : RF_ERR_NOCONV;
 }
 

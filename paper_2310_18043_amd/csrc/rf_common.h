@@ -146,6 +146,7 @@ struct rf_plan {
     int *h_pinned_int = nullptr; // pinned host mirror of d_active
     // HSRR
     zd *hV = nullptr, *hAV = nullptr, *hBV = nullptr, *hW = nullptr, *hX = nullptr;
+    zd *hY = nullptr;         // n x w: block being filtered while the host QZ runs
     zd *hproj = nullptr;      // 2 * w * w
     double *herr = nullptr;   // w
     int64_t device_bytes = 0;
