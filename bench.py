@@ -178,6 +178,35 @@ def batched_form(ndisks, reps):
                            "value": round(found_s / (ms_s / 1000.0), 3)}}
 
 
+def circuit_form(reps):
+    """The paper's circuit pencil (App. B) at n_x = 10 (N = 1220), its solver shape
+    (k1 = k2 = 8, n_col = 24) and a disk with 17 eigenvalues: Alg. composite."""
+    import torch
+    from paper_2310_18043_amd import rfeig
+    from paper_2310_18043_amd import workloads as W
+    wl = W.circuit_workload()
+    P = rfeig.Plan(wl.A, wl.B, wl.c, wl.r, p=wl.p, q=wl.q, w=wl.w, expected_count=wl.s_expected)
+    Y0 = torch.from_numpy(W.start_block(wl.n, wl.w, 0)).cuda()
+
+    def step():
+        P.factor_shifts()
+        return P.solve_region(Y0, allow_noconv=True)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / reps
+    good = int(np.sum((np.abs(res["lam"] - wl.c) < wl.r) & (res["err"] <= 1e-10)))
+    P.close()
+    return {"workload": "circuit_nx10_p8_q8_w24", "n": wl.n, "expected_count": wl.s_expected,
+            "converged_count": good, "sweeps": res["sweeps"], "krylov_steps": res["krylov_steps"],
+            "ms_per_step": round(ms, 3), "value": round(good / (ms / 1000.0), 3),
+            "unit": "eigenpairs/s"}
+
+
 def gradient_form(reps):
     """Eigenvalue gradients on the 128 x 128 random-velocity pencil (52 eigenvalues in
     the disk): right eigenpairs (factor + Alg. composite), left eigenpairs from the
@@ -241,6 +270,8 @@ def main():
                     help="also time Alg. composite2 up to this outer node count (0: skip)")
     ap.add_argument("--batch-disks", type=int, default=16,
                     help="also time the batched form on this many disks (0: skip)")
+    ap.add_argument("--no-circuit", action="store_true",
+                    help="skip the circuit-pencil measurement")
     ap.add_argument("--no-c64", action="store_true",
                     help="skip the precision-form (complex64 band solves) measurement")
     ap.add_argument("--no-gradient", action="store_true",
@@ -436,6 +467,11 @@ def main():
         bt = batched_form(args.batch_disks, min(args.steps, 2))
         log(f"batched: {bt}")
 
+    circ = None
+    if not args.no_circuit:
+        circ = circuit_form(min(args.steps, 2))
+        log(f"circuit: {circ}")
+
     grad = None
     if not args.no_gradient:
         grad = gradient_form(min(args.steps, 2))
@@ -469,6 +505,7 @@ def main():
         "precision_c64": pc,
         "batched": bt,
         "gradient": grad,
+        "circuit": circ,
         "phases_ms": {"factor": round(stats["factor_ms"] / max(args.steps, 1), 3),
                       "filter": round(res["ms_filter"], 3), "hsrr": round(res["ms_hsrr"], 3)},
     }

@@ -339,3 +339,103 @@ def random_velocity_workload(n: int = 128, w: int = 64, p: int = 4, q: int = 8,
     wl = Workload(f"convdiff{n}_randv{vseed}", A, B, complex(c), float(r), p, q, w, count, 0)
     wl.vfield = v
     return wl
+
+
+# --------------------------------------------------------------------------
+# the paper's circuit pencil (App. B, construction of the matrix)
+# --------------------------------------------------------------------------
+
+def _weighted_laplacian_1d(n: int):
+    """(n / 100) tridiag(-1, 2, -1) with 1 in both corners (App. B)."""
+    d = np.full(n, 2.0)
+    d[0] = d[-1] = 1.0
+    return (n / 100.0) * sp.diags([-np.ones(n - 1), d, -np.ones(n - 1)], [-1, 0, 1])
+
+
+def circuit_pencil(nx: int, seed: int = 0, layers: int = 10):
+    """Power-grid pencil of App. B on an nx x nx x 10 grid, as (A, B) = (-G, C).
+
+    G = [[G11, G12], [-G12^T, 0]], C = diag(C_c, L):
+      G11 = L_nx (x) I_nx (x) I_10 + I_nx (x) L_nx (x) I_10 + (1/10) I (x) I (x) L_10;
+      G12: 20 input-port columns with a +1 at their node -- 10 ports spread along the
+           edge (i, 1, 1) and 10 along (i, nx, 10) (all nodes of each edge when nx = 10) --
+           and 2 nx^2 inductor columns, each joining a randomly picked interior node of a
+           layer to a random one of its four neighbours on that layer (+1, -1);
+      C_c = diag U[0.5, 1.5] 1e-3 (grounded capacitors), L = diag(0 (ports),
+           U[0.5, 1.5] nx 1e-4 (inductances)).
+    All draws from PCG64(seed) in that order: inductor nodes (without replacement),
+    directions, capacitances, inductances.  For nx = 10 this gives the size (1220) and
+    nonzero count of G + C (7440) the paper lists.
+
+    The eigenvalue problem is taken as -G x = lambda C x (the circuit's poles, in the left
+    half plane, where the paper's target regions lie).  Unknowns are ordered node by node,
+    each port current right after its node and each inductor current after the node
+    midway between its two nodes, so the pencil stays banded (bandwidth about 1.2 x 10 nx,
+    128 for nx = 10).  Returns (A, B) as complex128 CSR."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nl = layers
+    eye = lambda n: sp.identity(n)
+    G11 = (sp.kron(sp.kron(_weighted_laplacian_1d(nx), eye(nx)), eye(nl))
+           + sp.kron(sp.kron(eye(nx), _weighted_laplacian_1d(nx)), eye(nl))
+           + 0.1 * sp.kron(sp.kron(eye(nx), eye(nx)), _weighted_laplacian_1d(nl)))
+    nn = nx * nx * nl
+
+    def node(i, j, l):
+        return (i * nx + j) * nl + l
+
+    extra = []                                    # (first node, rows, values)
+    edge = np.unique(np.rint(np.linspace(0, nx - 1, 10)).astype(int))
+    for i in edge:
+        extra.append((node(i, 0, 0), [node(i, 0, 0)], [1.0]))
+    for i in edge:
+        extra.append((node(i, nx - 1, nl - 1), [node(i, nx - 1, nl - 1)], [1.0]))
+    nports = len(extra)
+    interior = [(i, j, l) for i in range(1, nx - 1) for j in range(1, nx - 1) for l in range(nl)]
+    pick = rng.choice(len(interior), size=2 * nx * nx, replace=False)
+    dirs = rng.integers(0, 4, size=len(pick))
+    steps = [(1, 0), (-1, 0), (0, 1), (0, -1)]
+    for t, dsel in zip(pick, dirs):
+        i, j, l = interior[t]
+        di, dj = steps[dsel]
+        a, b = node(i, j, l), node(i + di, j + dj, l)
+        extra.append(((a + b) // 2, [a, b], [1.0, -1.0]))
+    m = len(extra)
+    cap = rng.uniform(0.5, 1.5, nn) * 1e-3
+    ind = rng.uniform(0.5, 1.5, m - nports) * nx * 1e-4
+    rows, cols, vals = [], [], []
+    for k, (_, rr, vv) in enumerate(extra):
+        rows += rr
+        cols += [k] * len(rr)
+        vals += vv
+    G12 = sp.csr_matrix((vals, (rows, cols)), shape=(nn, m))
+    G = sp.bmat([[G11, G12], [-G12.T, None]]).tocsr()
+    C = sp.diags(np.concatenate([cap, np.zeros(nports), ind])).tocsr()
+    # ordering: node k, then the extra unknowns placed at node k
+    first = np.array([e[0] for e in extra])
+    key = np.concatenate([np.arange(nn) * 2.0, first * 2.0 + 1.0])
+    order = np.argsort(key, kind="stable")
+    A = (-G)[order][:, order].astype(np.complex128).tocsr()
+    B = C[order][:, order].astype(np.complex128).tocsr()
+    A.sort_indices()
+    B.sort_indices()
+    return A, B
+
+
+# Disk for circuit_pencil(10, seed 0): centre of the paper's n_x = 10 region,
+# -200 + 1000i; of the dense eigenvalues of (-G, C), the counts 16..26 nearest the
+# centre were scanned and 17 kept, whose 18th/17th distance ratio (1.13) is the
+# largest near the paper's 20; radius halfway between the 17th and 18th distances.
+CIRCUIT10_DISK = (-200.0 + 1000.0j, 71.3035740717, 17)
+
+
+def circuit_workload(nx: int = 10, w: int = 24, p: int = 8, q: int = 8, seed: int = 0,
+                     disk: Optional[tuple] = None) -> Workload:
+    """The paper's circuit pencil (App. B) with the solver shape of its experiments
+    (k1 = k2 = 8, n_col = 24)."""
+    A, B = circuit_pencil(nx, seed)
+    if disk is None:
+        if (nx, seed) != (10, 0):
+            raise KeyError("no stored disk for this circuit pencil; pass disk=(c, r, count)")
+        disk = CIRCUIT10_DISK
+    c, r, count = disk
+    return Workload(f"circuit{nx}", A, B, complex(c), float(r), p, q, w, count, seed)

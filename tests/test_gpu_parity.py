@@ -334,3 +334,38 @@ def test_solve_region_adaptive_toeplitz_closed_form(rf, torch_cuda):
     d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
     assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
     assert res["err"].max() <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# the paper's circuit workload (App. B), n_x = 10: k1 = k2 = 8, n_col = 24
+# ---------------------------------------------------------------------------
+def test_solve_region_circuit10_vs_dense(rf, torch_cuda):
+    import scipy.linalg as sl
+    from oracle import hsrr
+    wl = W.circuit_workload()
+    _say("solve_region circuit10 (p = q = 8, w = 24)")
+    plan = rf.Plan(wl.A, wl.B, wl.c, wl.r, p=wl.p, q=wl.q, w=wl.w, expected_count=wl.s_expected)
+    res = plan.solve_region(torch_cuda.from_numpy(W.start_block(wl.n, wl.w, 0)).cuda())
+    w = sl.eigvals(wl.A.toarray(), wl.B.toarray())
+    w = w[np.isfinite(w)]
+    inside = w[np.abs(w - wl.c) < wl.r]
+    assert res["converged"] and res["count"] == len(inside) == wl.s_expected
+    d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
+    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+    e = hsrr.rel_errors(wl.A, wl.B, res["lam"], _to_host(res["X"]), wl.c, wl.r)
+    assert e.max() <= 1e-10
+
+
+def test_solve_region_adaptive_circuit10_vs_dense(rf, torch_cuda):
+    import scipy.linalg as sl
+    wl = W.circuit_workload()
+    _say("solve_region_adaptive circuit10 (p = 8, q = 2 .. 16)")
+    plan = rf.Plan(wl.A, wl.B, wl.c, wl.r, p=wl.p, q=2, w=wl.w, expected_count=wl.s_expected,
+                   q_max=16)
+    res = plan.solve_region_adaptive(torch_cuda.from_numpy(W.start_block(wl.n, wl.w, 0)).cuda())
+    w = sl.eigvals(wl.A.toarray(), wl.B.toarray())
+    w = w[np.isfinite(w)]
+    inside = w[np.abs(w - wl.c) < wl.r]
+    assert res["converged"] and res["count"] == len(inside)
+    d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
+    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
