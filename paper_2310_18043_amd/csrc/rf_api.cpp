@@ -375,6 +375,11 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
     ALLOC(P->hW, n * w);
     ALLOC(P->hX, n * w);
     ALLOC(P->hY, n * w);
+    if (o.q_max > o.q) {
+        ALLOC(P->hV2, n * w);
+        ALLOC(P->hAV2, n * w);
+        ALLOC(P->hBV2, n * w);
+    }
     ALLOC(P->hproj, 2 * w * w);
     ALLOC(P->herr, 2 * w);
 #undef ALLOC
@@ -980,13 +985,20 @@ rf_status orth_panels(rf_plan *P, zd *U, int64_t n, int w) {
 //                 errors e_i (eq. rel-error).  Needs P->hV as hsrr_project left it.
 struct Projected {
     int w = 0;
+    zd *V = nullptr, *AV = nullptr, *BV = nullptr;   // the basis and its products (device)
     std::vector<zd> A, B, al, be, vr;
     int qz_status = 0;
     void run_qz() { qz_status = host_qz_eig(w, A.data(), B.data(), al.data(), be.data(), vr.data()); }
 };
 
-rf_status hsrr_project(rf_plan *P, zd *U, Projected &pr) {
+// buf selects one of the plan's two sets of basis buffers (the adaptive solver keeps
+// two levels in flight).
+rf_status hsrr_project(rf_plan *P, zd *U, Projected &pr, int buf = 0) {
     hipStream_t s = P->stream;
+    if (buf == 1 && !P->hV2) return rf_fail(P, RF_ERR_STATE, "second basis buffer not allocated");
+    pr.V = buf ? P->hV2 : P->hV;
+    pr.AV = buf ? P->hAV2 : P->hAV;
+    pr.BV = buf ? P->hBV2 : P->hBV;
     const int64_t n = P->n;
     const int w = P->opts.w;
     const std::complex<double> sigma =
@@ -999,20 +1011,20 @@ rf_status hsrr_project(rf_plan *P, zd *U, Projected &pr) {
     RF_HIP(P, hipStreamSynchronize(s));
     for (auto &v : cn) v = v > 0.0 ? 1.0 / v : 1.0;
     RF_HIP(P, hipMemcpyAsync(P->colnorm, cn.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
-    RF_HIP(P, launch_copy_cols(n, w, U, n, P->hV, n, s));
-    RF_HIP(P, launch_scale_cols(n, w, P->hV, n, P->colnorm, s));
-    RF_TRY(orth_panels(P, P->hV, n, w));
+    RF_HIP(P, launch_copy_cols(n, w, U, n, pr.V, n, s));
+    RF_HIP(P, launch_scale_cols(n, w, pr.V, n, P->colnorm, s));
+    RF_TRY(orth_panels(P, pr.V, n, w));
     // AV, BV, W = orth(AV - sigma BV)
-    RF_HIP(P, launch_spmm(P->A, w, P->hV, n, P->hAV, n, s));
-    RF_HIP(P, launch_spmm(P->B, w, P->hV, n, P->hBV, n, s));
-    RF_HIP(P, launch_axpby_cols(n, w, Z(1), P->hAV, n, Z(-sigma.real(), -sigma.imag()), P->hBV, n,
+    RF_HIP(P, launch_spmm(P->A, w, pr.V, n, pr.AV, n, s));
+    RF_HIP(P, launch_spmm(P->B, w, pr.V, n, pr.BV, n, s));
+    RF_HIP(P, launch_axpby_cols(n, w, Z(1), pr.AV, n, Z(-sigma.real(), -sigma.imag()), pr.BV, n,
                                 P->hW, n, s));
     RF_TRY(orth_panels(P, P->hW, n, w));
     // projected pencil
     zd *Ah = P->hproj, *Bh = P->hproj + int64_t(w) * w;
-    RF_HIP(P, launch_gemm_cn(n, w, w, Z(1), P->hW, n, 0, P->hAV, n, 0, Z(0), Ah, w, 0, 1, P->partial,
+    RF_HIP(P, launch_gemm_cn(n, w, w, Z(1), P->hW, n, 0, pr.AV, n, 0, Z(0), Ah, w, 0, 1, P->partial,
                              P->partial_elems, s));
-    RF_HIP(P, launch_gemm_cn(n, w, w, Z(1), P->hW, n, 0, P->hBV, n, 0, Z(0), Bh, w, 0, 1, P->partial,
+    RF_HIP(P, launch_gemm_cn(n, w, w, Z(1), P->hW, n, 0, pr.BV, n, 0, Z(0), Bh, w, 0, 1, P->partial,
                              P->partial_elems, s));
     pr.w = w;
     pr.A.resize(size_t(w) * w);
@@ -1043,7 +1055,7 @@ rf_status hsrr_finish(rf_plan *P, const Projected &pr, std::vector<std::complex<
     std::vector<double> cn(w);
     zd *dvr = P->small;
     RF_HIP(P, hipMemcpyAsync(dvr, pr.vr.data(), sizeof(zd) * w * w, hipMemcpyHostToDevice, s));
-    RF_HIP(P, launch_gemm_nn(n, w, w, Z(1), P->hV, n, 0, dvr, w, 0, Z(0), P->hX, n, 0, 1, s));
+    RF_HIP(P, launch_gemm_nn(n, w, w, Z(1), pr.V, n, 0, dvr, w, 0, Z(0), P->hX, n, 0, 1, s));
     RF_HIP(P, launch_colnorms(n, w, P->hX, n, nullptr, 0, nullptr, P->colnorm, s));
     RF_HIP(P, hipMemcpyAsync(cn.data(), P->colnorm, sizeof(double) * w, hipMemcpyDeviceToHost, s));
     RF_HIP(P, hipStreamSynchronize(s));
@@ -1053,10 +1065,10 @@ rf_status hsrr_finish(rf_plan *P, const Projected &pr, std::vector<std::complex<
     // e_i = ||A x - lam B x|| / ((|c| + r) ||B x||)
     zd *dl = P->small + int64_t(w) * w;
     RF_HIP(P, hipMemcpyAsync(dl, dlam.data(), sizeof(zd) * w, hipMemcpyHostToDevice, s));
-    RF_HIP(P, launch_spmm(P->A, w, P->hX, n, P->hAV, n, s));
-    RF_HIP(P, launch_spmm(P->B, w, P->hX, n, P->hBV, n, s));
-    RF_HIP(P, launch_colnorms(n, w, P->hAV, n, P->hBV, n, dl, P->herr, s));
-    RF_HIP(P, launch_colnorms(n, w, P->hBV, n, nullptr, 0, nullptr, P->herr + w, s));
+    RF_HIP(P, launch_spmm(P->A, w, P->hX, n, pr.AV, n, s));
+    RF_HIP(P, launch_spmm(P->B, w, P->hX, n, pr.BV, n, s));
+    RF_HIP(P, launch_colnorms(n, w, pr.AV, n, pr.BV, n, dl, P->herr, s));
+    RF_HIP(P, launch_colnorms(n, w, pr.BV, n, nullptr, 0, nullptr, P->herr + w, s));
     std::vector<double> e2(2 * w);
     RF_HIP(P, hipMemcpyAsync(e2.data(), P->herr, sizeof(double) * 2 * w, hipMemcpyDeviceToHost, s));
     RF_HIP(P, hipStreamSynchronize(s));
@@ -1272,19 +1284,19 @@ rf_status rf_solve_region_adaptive(rf_plan_t P, const void *Y0, int64_t ldy, rf_
     int prev = -1, t = 0;
     bool converged = false;
     rf_status out = RF_OK;
-    for (int k2 = P->opts.q; k2 <= P->opts.q_max; k2 *= 2, ++t) {
-        t1 = now_ms();
+    // U of level t (k2 = q 2^t) into P->Wk
+    auto level_filter = [&](int level) -> rf_status {
+        const double ta = now_ms();
+        const int k2 = P->opts.q << level;
         outer_rule(k2, P->shifts, P->oweights, P->oextra);
-        out = krylov_rule(P, K, open);
-        if (out == RF_OK && !open.empty()) out = krylov_advance(P, K, all, true);
-        if (out == RF_OK) out = krylov_combine(P, K, P->Wk, n);
-        if (out != RF_OK) break;
-        if (t < 16) res->krylov_steps[t] = K.msteps.empty() ? 0 : K.msteps[0];
-        double t2 = now_ms();
-        ms_filter += t2 - t1;
-        out = hsrr(P, P->Wk, lam, err);
-        ms_hsrr += now_ms() - t2;
-        if (out != RF_OK) break;
+        RF_TRY(krylov_rule(P, K, open));
+        if (!open.empty()) RF_TRY(krylov_advance(P, K, all, true));
+        RF_TRY(krylov_combine(P, K, P->Wk, n));
+        if (level < 16) res->krylov_steps[level] = K.msteps.empty() ? 0 : K.msteps[0];
+        ms_filter += now_ms() - ta;
+        return RF_OK;
+    };
+    auto judge = [&](int level) {
         int count = 0;
         bool all_small = true;
         for (int i = 0; i < w; ++i) {
@@ -1293,14 +1305,72 @@ rf_status rf_solve_region_adaptive(rf_plan_t P, const void *Y0, int64_t ldy, rf_
             flags[i] = (inside ? 1 : 0) | (filt ? 2 : 0) | (err[i] <= P->opts.tau ? 4 : 0);
             if (filt) { ++count; if (!(err[i] <= P->opts.tau)) all_small = false; }
         }
-        if (all_small && (count == prev || (t == 0 && P->opts.expected_count >= 0 &&
-                                            count == P->opts.expected_count))) {
+        const bool stop = all_small && (count == prev || (level == 0 && P->opts.expected_count >= 0 &&
+                                                          count == P->opts.expected_count));
+        prev = count;
+        return stop;
+    };
+    // Levels are pipelined: while the host QZ of level t runs on its own thread, the
+    // device computes level t + 1's filter and projection into the second basis set, and
+    // level t + 1's QZ starts on another thread; level t is then finished and judged, and
+    // a converged level discards the one behind it.
+    const int nlevels = [&] { int m = 0; for (int k2 = P->opts.q; k2 <= P->opts.q_max; k2 *= 2) ++m; return m; }();
+    struct Flight {
+        Projected pr;
+        std::thread th;
+        void start() {
+            try {
+                th = std::thread([this] { pr.run_qz(); });
+            } catch (...) {
+                pr.run_qz();
+            }
+        }
+        void wait() { if (th.joinable()) th.join(); }
+    };
+    Flight fl[2];
+    out = level_filter(0);
+    if (out == RF_OK) {
+        const double ta = now_ms();
+        out = hsrr_project(P, P->Wk, fl[0].pr, 0);
+        ms_hsrr += now_ms() - ta;
+    }
+    if (out == RF_OK) fl[0].start();
+    for (t = 0; out == RF_OK && t < nlevels; ++t) {
+        Flight &cur = fl[t % 2], &nxt = fl[(t + 1) % 2];
+        const bool ahead = (t + 1 < nlevels) && P->hV2 != nullptr;
+        if (ahead) {
+            out = level_filter(t + 1);
+            if (out == RF_OK) {
+                const double ta = now_ms();
+                out = hsrr_project(P, P->Wk, nxt.pr, (t + 1) % 2);
+                ms_hsrr += now_ms() - ta;
+            }
+            if (out == RF_OK) nxt.start();
+        }
+        const double tb = now_ms();
+        cur.wait();
+        rf_status fin = (out == RF_OK) ? hsrr_finish(P, cur.pr, lam, err) : out;
+        ms_hsrr += now_ms() - tb;
+        if (fin != RF_OK) { out = fin; nxt.wait(); break; }
+        if (judge(t)) {
             converged = true;
+            nxt.wait();
             ++t;
             break;
         }
-        prev = count;
+        if (!ahead && t + 1 < nlevels) {
+            // no second basis set: the next level in order
+            out = level_filter(t + 1);
+            if (out == RF_OK) {
+                const double ta = now_ms();
+                out = hsrr_project(P, P->Wk, nxt.pr, 0);
+                ms_hsrr += now_ms() - ta;
+            }
+            if (out == RF_OK) nxt.start();
+        }
     }
+    fl[0].wait();
+    fl[1].wait();
     // the plan's own outer rule (q) for later calls
     outer_rule(P->opts.q, P->shifts, P->oweights, P->oextra);
     if (out != RF_OK) return out;

@@ -147,6 +147,7 @@ struct rf_plan {
     // HSRR
     zd *hV = nullptr, *hAV = nullptr, *hBV = nullptr, *hW = nullptr, *hX = nullptr;
     zd *hY = nullptr;         // n x w: block being filtered while the host QZ runs
+    zd *hV2 = nullptr, *hAV2 = nullptr, *hBV2 = nullptr;  // second basis set (adaptive solver)
     zd *hproj = nullptr;      // 2 * w * w
     double *herr = nullptr;   // w
     int64_t device_bytes = 0;
