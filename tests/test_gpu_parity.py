@@ -369,3 +369,40 @@ def test_solve_region_adaptive_circuit10_vs_dense(rf, torch_cuda):
     assert res["converged"] and res["count"] == len(inside)
     d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
     assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+
+
+def test_solve_region_sweep_cap_returns_noconv_with_results(rf, torch_cuda):
+    # one sweep allowed and no expected count: the stopping rule cannot be met (it needs
+    # two equal counts), so the call reports RF_ERR_NOCONV with the sweep's pairs filled in
+    wl = W.toeplitz_workload(n=2000, w=32, count=20)
+    _say("solve_region toeplitz2000, sweep cap 1")
+    plan = rf.Plan(wl.A, wl.B, wl.c, wl.r, p=4, q=4, w=32, max_subspace_it=1)
+    with pytest.raises(rf.RfError) as e:
+        plan.solve_region(torch_cuda.from_numpy(W.start_block(wl.n, 32, 0)).cuda())
+    assert e.value.status == rf.RF_ERR_NOCONV
+    res = plan.solve_region(torch_cuda.from_numpy(W.start_block(wl.n, 32, 0)).cuda(),
+                            allow_noconv=True)
+    assert res["sweeps"] == 1 and not res["converged"]
+    exact = W.toeplitz_eigs(wl.n, 0, 1, W.TOEPLITZ_C)
+    inside = exact[np.abs(exact - wl.c) < wl.r]
+    # after one sweep the filtered pairs (inside D, e < tau_g) are the 20 eigenvalues, to
+    # the accuracy their residuals allow (the matrix is normal: |dlambda| <= residual)
+    filt = (res["flags"] & 3) == 3
+    assert filt.sum() == len(inside)
+    lam = res["all_lam"][filt]
+    d = np.abs(lam[:, None] - inside[None, :]).min(axis=1)
+    resid = res["all_err"][filt] * (abs(wl.c) + wl.r)
+    assert np.all(d <= 2.0 * resid + 1e-12)
+
+
+def test_solve_region_repeatable_and_independent_of_previous_calls(rf, torch_cuda):
+    # the plan keeps no state between calls except the factors: two calls with the same
+    # start block give the same pairs, bit for bit
+    wl = W.toeplitz_workload(n=2000, w=32, count=20)
+    _say("solve_region toeplitz2000 twice")
+    plan = rf.Plan(wl.A, wl.B, wl.c, wl.r, p=4, q=4, w=32, expected_count=20)
+    Y0 = torch_cuda.from_numpy(W.start_block(wl.n, 32, 0)).cuda()
+    r1 = plan.solve_region(Y0)
+    r2 = plan.solve_region(Y0)
+    assert np.array_equal(r1["all_lam"], r2["all_lam"])
+    assert np.array_equal(r1["all_err"], r2["all_err"])
