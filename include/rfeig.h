@@ -184,6 +184,17 @@ rf_status rf_profile_read(rf_plan_t plan, rf_kernel_stats *out);
 int rf_dense_eig(int32_t n, const double *A, const double *B, double *alpha, double *beta,
                  double *vr);
 
+/* rf_solve_region on `count` distinct plans at once, each on a host thread of its own
+ * and its plan's stream (plans created on different streams run concurrently on the
+ * device; plans sharing a stream still give the right results); factor != 0 runs
+ * rf_factor_shifts first on every plan (concurrently too).  Y0, ldy: host arrays
+ * of start blocks and leading dimensions (NULL or NULL entries: seeded Gaussian); res,
+ * status: host arrays of count results and return codes.  Returns RF_OK if every plan
+ * returned RF_OK, else the first other code in plan order; RF_ERR_ARG if a plan
+ * appears twice.  For independent problems, e.g. a pencil and its adjoint. */
+rf_status rf_solve_regions(int32_t count, rf_plan_t *plans, int32_t factor, const void *const *Y0,
+                           const int64_t *ldy, rf_result *res, rf_status *status);
+
 /* ---------------------------------------------------------------------------
  * Differentiation form.  For a simple eigenvalue lambda of A x = lambda B x with
  * right vector x and left vector y (y^H A = lambda y^H B), first-order

@@ -1593,6 +1593,61 @@ rf_plan_t rf_batch_plan(rf_batch_t Bt, int32_t d) {
 
 int32_t rf_batch_size(rf_batch_t Bt) { return Bt ? int32_t(Bt->disks.size()) : -1; }
 
+}  // extern "C"
+
+namespace {
+
+// rf_solve_region on several plans at once, at most `threads` at a time, each plan on
+// the host thread that takes it (its GPU work goes to the plan's own stream).
+void solve_many(rf_plan *const *plans, int np, const void *const *Y0, const int64_t *ldy,
+                rf_result *res, rf_status *status, int threads, bool factor = false) {
+    const int nt = std::max(1, std::min(threads <= 0 ? np : threads, np));
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        for (int d; (d = next.fetch_add(1)) < np;) {
+            if (hipSetDevice(plans[d]->device) != hipSuccess) {
+                (void)hipGetLastError();
+                status[d] = RF_ERR_DEVICE;
+                continue;
+            }
+            if (factor) {
+                status[d] = rf_factor_shifts(plans[d]);
+                if (status[d] != RF_OK) continue;
+            }
+            status[d] = rf_solve_region(plans[d], Y0 ? Y0[d] : nullptr, ldy ? ldy[d] : 0, &res[d]);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) {
+        try {
+            pool.emplace_back(worker);
+        } catch (...) {
+            break;                               // fewer threads: the others take more plans
+        }
+    }
+    worker();
+    for (auto &t : pool) t.join();
+}
+
+}  // namespace
+
+extern "C" {
+
+rf_status rf_solve_regions(int32_t count, rf_plan_t *plans, int32_t factor, const void *const *Y0,
+                           const int64_t *ldy, rf_result *res, rf_status *status) {
+    if (count < 0 || (count > 0 && (!plans || !res || !status))) return RF_ERR_ARG;
+    for (int d = 0; d < count; ++d) status[d] = RF_ERR_ARG;
+    for (int d = 0; d < count; ++d) {
+        if (!plans[d]) return RF_ERR_ARG;
+        for (int e = 0; e < d; ++e)
+            if (plans[e] == plans[d]) return RF_ERR_ARG;   // one plan, one thread at a time
+    }
+    solve_many(plans, count, Y0, ldy, res, status, count, factor != 0);
+    for (int d = 0; d < count; ++d)
+        if (status[d] != RF_OK) return status[d];
+    return RF_OK;
+}
+
 rf_status rf_batch_solve(rf_batch_t Bt, const void *const *Y0, const int64_t *ldy, rf_result *res,
                          rf_status *status, int32_t threads) {
     if (!Bt || !res || !status || Bt->disks.empty()) return RF_ERR_ARG;
@@ -1600,22 +1655,7 @@ rf_status rf_batch_solve(rf_batch_t Bt, const void *const *Y0, const int64_t *ld
     for (int d = 0; d < nd; ++d) status[d] = RF_ERR_STATE;
     for (rf_plan *d : Bt->disks)
         if (!d->F.ready) return batch_fail(Bt, RF_ERR_STATE, "rf_batch_factor has not succeeded");
-    const int nt = std::max(1, std::min(threads <= 0 ? nd : int(threads), nd));
-    const int dev = Bt->owner->device;
-    std::atomic<int> next{0};
-    auto worker = [&]() {
-        if (hipSetDevice(dev) != hipSuccess) {
-            (void)hipGetLastError();
-            for (int d; (d = next.fetch_add(1)) < nd;) status[d] = RF_ERR_DEVICE;
-            return;
-        }
-        for (int d; (d = next.fetch_add(1)) < nd;)
-            status[d] = rf_solve_region(Bt->disks[d], Y0 ? Y0[d] : nullptr, ldy ? ldy[d] : 0, &res[d]);
-    };
-    std::vector<std::thread> pool;
-    for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
-    worker();
-    for (auto &t : pool) t.join();
+    solve_many(Bt->disks.data(), nd, Y0, ldy, res, status, threads);
     for (int d = 0; d < nd; ++d)
         if (status[d] != RF_OK)
             return batch_fail(Bt, status[d], "disk " + std::to_string(d) + ": " +

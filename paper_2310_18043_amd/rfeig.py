@@ -99,6 +99,10 @@ _lib.rf_status_str.argtypes = [ctypes.c_int]
 _lib.rf_status_str.restype = ctypes.c_char_p
 _lib.rf_last_error.argtypes = [_P]
 _lib.rf_last_error.restype = ctypes.c_char_p
+_lib.rf_solve_regions.argtypes = [ctypes.c_int32, ctypes.POINTER(_P), ctypes.c_int32,
+                                  ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64), _P,
+                                  ctypes.POINTER(ctypes.c_int)]
+_lib.rf_solve_regions.restype = ctypes.c_int
 _lib.rf_plan_create_adjoint.argtypes = [_P, _P, ctypes.POINTER(_P)]
 _lib.rf_plan_create_adjoint.restype = ctypes.c_int
 _lib.rf_eig_vjp.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P,
@@ -476,6 +480,47 @@ class Batch:
             pass
 
 
+def solve_regions(plans, Y0s=None, factor=False, allow_noconv=False):
+    """rf_solve_regions: Alg. composite on several independent plans at once (each on
+    its own host thread and the plan's stream); factor=True refactorizes first."""
+    torch = _torch()
+    n = len(plans)
+    hs = (_P * n)(*[P._h for P in plans])
+    ys = (_P * n)()
+    lds = (ctypes.c_int64 * n)()
+    keep = []
+    if Y0s is not None:
+        for d, Y in enumerate(Y0s):
+            if Y is None:
+                continue
+            Y = as_colmajor(Y)
+            keep.append(Y)
+            ys[d] = Y.data_ptr()
+            lds[d] = _ld(Y)
+    torch.cuda.synchronize()         # start blocks complete before the plans' streams read them
+    results = (RfResult * n)()
+    holders = []
+    for d, P in enumerate(plans):
+        res, h = P._result()
+        results[d] = res
+        holders.append(h)
+    status = (ctypes.c_int * n)()
+    st = _lib.rf_solve_regions(n, hs, 1 if factor else 0, ys, lds,
+                               ctypes.cast(results, _P), status)
+    allow = (RF_ERR_NOCONV,) if allow_noconv else ()
+    for d in range(n):
+        if status[d] != RF_OK and status[d] not in allow:
+            raise RfError(status[d], _lib.rf_last_error(plans[d]._h).decode())
+    if st != RF_OK and st not in allow:
+        raise RfError(st, "rf_solve_regions failed")
+    out = []
+    for d in range(n):
+        r = Plan._unpack(results[d], holders[d])
+        r["status"] = int(status[d])
+        out.append(r)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # differentiation form: eigenvalues inside a disk as a differentiable function of
 # the stored entries of A and B
@@ -512,9 +557,9 @@ def _disk_eig_class():
             B = _csr_with_values(B_pattern, b_vals.detach().cpu().numpy())
             opts = dict(plan_opts)
             P = Plan(A, B, c, r, **opts)
-            res = P.solve_region(Y0)
-            Pa = P.adjoint()
-            resa = Pa.solve_region(Y0_adj)
+            # the adjoint on a stream of its own: both problems are solved concurrently
+            Pa = P.adjoint(stream=torch.cuda.Stream())
+            res, resa = solve_regions([P, Pa], [Y0, Y0_adj])
             ctx.state = (P, Pa, res, resa, A.nnz, B.nnz, a_vals.device, b_vals.device)
             return torch.from_numpy(np.array(res["lam"], dtype=np.complex128))
 

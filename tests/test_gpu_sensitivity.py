@@ -93,6 +93,33 @@ def test_vjp_small_vs_dense_oracle(rf, torch_cuda):
     adj.close()
 
 
+def test_concurrent_solves_match_separate_solves(rf, torch_cuda):
+    # rf_solve_regions drives the pencil and its adjoint from two host threads on two
+    # streams; every kernel and the host QZ are deterministic, so the results are the
+    # separate solves' bit for bit, with factorization inside the call too
+    v, A, B, c, r = _small_case()
+    _say("rf_solve_regions pencil + adjoint, two streams")
+    plan, adj, res, resa = _gpu_left_right(rf, torch_cuda, A, B, c, r, 16, 10)
+    N = A.shape[0]
+    adj2 = plan.adjoint(stream=torch_cuda.cuda.Stream())
+    Y = [torch_cuda.from_numpy(W.start_block(N, 16, s)).cuda() for s in (0, 1)]
+    for factor in (False, True):
+        if not factor:
+            adj2.factor_shifts()
+        out, outa = rf.solve_regions([plan, adj2], Y, factor=factor)
+        for a, b in ((out, res), (outa, resa)):
+            assert a["status"] == rf.RF_OK and a["converged"]
+            assert a["count"] == b["count"] and a["sweeps"] == b["sweeps"]
+            assert np.array_equal(a["lam"], b["lam"])
+            assert torch_cuda.equal(a["X"], b["X"])
+    with pytest.raises(rf.RfError) as e:
+        rf.solve_regions([plan, plan], Y)
+    assert e.value.status == rf.RF_ERR_ARG
+    plan.close()
+    adj.close()
+    adj2.close()
+
+
 def test_vjp_rejects_unpaired_eigenvalues(rf, torch_cuda):
     v, A, B, c, r = _small_case()
     _say("eig_vjp pairing errors")

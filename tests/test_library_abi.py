@@ -128,6 +128,24 @@ def test_batch_create_rejects_bad_arguments_before_device_work(lib):
     assert lib.rf_batch_plan(None, 0) is None
 
 
+def test_solve_regions_rejects_bad_arguments_before_device_work(lib):
+    from paper_2310_18043_amd import rfeig
+    f = lib.rf_solve_regions
+    f.restype = ctypes.c_int
+    res = (rfeig.RfResult * 2)()
+    status = (ctypes.c_int * 2)(123, 123)
+    assert f(-1, None, 0, None, None, res, status) == rfeig.RF_ERR_ARG
+    assert f(2, None, 0, None, None, res, status) == rfeig.RF_ERR_ARG
+    # a plan handed in twice would be driven by two threads at once: refused before
+    # any handle is touched (these handles are never dereferenced)
+    plans = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    assert f(2, plans, 0, None, None, res, status) == rfeig.RF_ERR_ARG
+    assert list(status) == [rfeig.RF_ERR_ARG] * 2
+    plans = (ctypes.c_void_p * 2)(0x1000, None)
+    assert f(2, plans, 1, None, None, res, status) == rfeig.RF_ERR_ARG
+    assert f(0, None, 0, None, None, None, None) == rfeig.RF_OK
+
+
 def _dense_eig(lib, A, B):
     import numpy as np
     f = lib.rf_dense_eig
