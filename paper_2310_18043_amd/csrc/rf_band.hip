@@ -113,11 +113,9 @@ __global__ __launch_bounds__(256) void band_window_init_kernel(FactorArgs a) {
 // The factorization of block step k runs as nb/SW sub-steps of SW columns
 // (right-looking, blocked), each one pair of launches for all p poles:
 //   band_panel_kernel (one workgroup per pole): LU with partial pivoting of the
-//       R x SW sub-panel (window columns c0..c0+SW-1) held in registers, column c
-//       owned by wave c % 8, rows spread over the lanes (NS per lane).  The owner
-//       of column j+1 applies pivot step j to it first and finds the next pivot at
-//       once, so each column costs one barrier.  Writes the sub-panel back, its
-//       row permutation (subperm) and the running permutation of the block step.
+//       R x SW sub-panel (window columns c0..c0+SW-1) held in registers, one
+//       window row per thread, one barrier per column.  Writes the sub-panel back,
+//       its row permutation (subperm) and the running permutation of the block step.
 //   band_trail_kernel (one wave per window column, many workgroups per pole):
 //       columns right of the sub-panel: gather in the sub-panel's row order, solve
 //       with its unit lower SW x SW block, subtract L * U from the rows below;
@@ -127,51 +125,6 @@ __global__ __launch_bounds__(256) void band_window_init_kernel(FactorArgs a) {
 // Kernel boundaries order the sub-steps, so no workgroup ever waits on another.
 constexpr int kFacThreads = 512;
 constexpr int kFacWaves = kFacThreads / 64;
-
-// lane ln's value of x (ln wave-uniform); readlane moves 32 bits at a time
-__device__ inline double dlane_get(double x, int ln) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), ln);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), ln);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ inline zd lane_get(zd x, int ln) {
-    return zmake(dlane_get(x.x, ln), dlane_get(x.y, ln));
-}
-
-// value of row `row` (wave-uniform) of a column spread as v[s] = row lane + 64 s:
-// every slot of lane row % 64 is read out with readlane and the uniform slot index
-// selects among the scalars (no branches, and the register array is never indexed
-// dynamically, which would put it in scratch memory)
-template <int NS>
-__device__ __attribute__((always_inline)) inline zd row_get(const zd (&v)[NS], int row) {
-    const int sl = __builtin_amdgcn_readfirstlane(row >> 6), ln = row & 63;
-    zd x = lane_get(v[0], ln);
-#pragma unroll
-    for (int s = 1; s < NS; ++s) {
-        const zd t = lane_get(v[s], ln);
-        if (sl == s) x = t;
-    }
-    return x;
-}
-
-// Pivot step (pivot row p, column gj, multipliers l) applied to a column right of it.
-template <int NS>
-__device__ __attribute__((always_inline)) inline void step_update(zd (&x)[NS], const zd (&l)[NS],
-                                                                  int p, int gj, int lane) {
-    const zd u = row_get<NS>(x, p), t = row_get<NS>(x, gj);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        int r = lane + 64 * s;
-        zd y = x[s];
-        if (r == gj) y = u;
-        else if (r > gj) {
-            if (r == p) y = t;
-            zfms(y, l[s], u);
-        }
-        x[s] = y;
-    }
-}
 
 // Wave-wide maximum of a 64-bit key with DPP moves: within each row of 16 lanes by
 // shifts of 1, 2, 4, 8, then across rows by the row-15 and row-31 broadcasts; lane
@@ -197,187 +150,114 @@ __device__ __attribute__((always_inline)) inline uint64_t wave_max_u64(uint64_t 
     return key;
 }
 
-// Pivot step on a column held as x[s] = row lane + 64 s (sub-panel column j, panel
-// column gj): partial pivoting by largest |.|^2 (ties: the lowest lane, within a lane
-// the smallest row), swap, scale by 1 / pivot, publish the multipliers in lc and the
-// pivot row in s_piv[j].  The interchanges are replayed into the row orders after
-// the sub-panel is done, off this critical path.
-template <int NS>
-__device__ __attribute__((always_inline)) inline void panel_pivot(
-        zd (&x)[NS], int j, int gj, int R, int lane, zd *lc, int *s_piv, int *s_info,
-        int info_base, int *s_flag) {
-    double best = -1.0;
-    int bi = gj;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        int r = lane + 64 * s;
-        double m = zabs2(x[s]);
-        if (r >= gj && r < R && m > best) { best = m; bi = r; }
-    }
-    const uint64_t mine = best > 0.0 ? uint64_t(__double_as_longlong(best)) : 0;
-    const uint64_t top = wave_max_u64(mine);
-    const uint64_t kmax = (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(top >> 32)), 63))) << 32) |
-                          uint32_t(__builtin_amdgcn_readlane(int(uint32_t(top)), 63));
-    const bool sing = kmax == 0;
-    const uint64_t hit = __ballot(mine == kmax);
-    const int p = sing ? gj : __builtin_amdgcn_readlane(bi, int(__builtin_ctzll(hit)));
-    const zd ap = row_get<NS>(x, p), a0 = row_get<NS>(x, gj);
-    const zd inv = sing ? zmake(0, 0) : zdiv(zmake(1.0, 0.0), ap);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        int r = lane + 64 * s;
-        zd y = x[s];
-        if (r == gj) y = ap;
-        else if (r > gj) y = zmul((r == p) ? a0 : y, inv);
-        x[s] = y;
-        if (r < R) lc[r] = y;
-    }
-    if (lane == 0) {
-        s_piv[j] = p;
-        if (sing && *s_info == 0) *s_info = info_base + gj + 1;
-    }
-    // publish: the wave's multipliers and lane 0's records reach LDS before the flag
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    if (lane == 0) __hip_atomic_store(&s_flag[j], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
+struct PivotCand {
+    uint64_t key;       // bits of |a|^2 (0: no candidate or exact zero)
+    int tid;            // thread holding the row
+    int pos;            // its current position in the window
+};
 
-// Wait until pivot step j has been published.  The wait is bounded: past the bound
-// the step is taken as failed (s_info = -1) and the wave goes on, so no wave can
-// hang; the host reports the failure.
-__device__ __attribute__((always_inline)) inline void wait_flag(int *flag, int *s_info) {
-    int it = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
-        if (++it > (1 << 20)) {
-            if (__lane_id() == 0) *s_info = -1;
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-template <int NS, int SW>
-__global__ __launch_bounds__(kFacThreads) void band_panel_kernel(FactorArgs a, int k, int buf,
-                                                                int c0) {
-    constexpr int CPT = SW / kFacWaves;                  // columns per wave
+// One workgroup per pole, one thread per window row (row `tid` of the window at the
+// start of the sub-step, R live rows), the row's SW sub-panel entries in registers.
+// Partial pivoting by largest |.|^2 over the rows at positions >= the current
+// column (ties: lowest thread).  Interchanges are not carried out: every thread keeps
+// the position of its row, and the pivot row and the row at the pivot position trade
+// positions, so row interchanges of the whole sub-panel (the multipliers of earlier
+// columns included) come for free.  Per column: the candidate of each wave (DPP max,
+// ballot) writes its key and its row from the pivot column on to LDS, one barrier,
+// every thread picks the winner among the waves' candidates and updates its own row.
+// Candidates and pivot rows are double-buffered by column parity, so one barrier per
+// column suffices.  The rows are written back at their new positions, with the
+// sub-panel's row order (subperm) and the running permutation of the block step.
+template <int SW, int NT>
+__global__ __launch_bounds__(NT) void band_panel_kernel(FactorArgs a, int k, int buf, int c0) {
+    constexpr int NWMAX = NT / 64;
     const int pole = blockIdx.x;
     const int nb = a.nb, nblk = a.nblk, ldw = 2 * nb;
     zd *W = pole_window(a.window, pole, buf, nb);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nw = int(blockDim.x) >> 6;
     const int R = (k + 1 < nblk) ? 2 * nb : nb;
-    // multipliers of every pivot step of the sub-panel (kept, so that no wave waits
-    // for another to finish reading them)
-    extern __shared__ unsigned char smem_raw[];
-    zd *Lh = reinterpret_cast<zd *>(smem_raw);            // [SW][2nb]
-    const int ldl = 2 * nb;
-    __shared__ int idxl[2 * 256], pmf[2 * 256], s_piv[SW], s_flag[SW];
-    __shared__ int s_info;
+    const bool live = tid < R;
+    __shared__ PivotCand cand[2][NWMAX];
+    __shared__ zd urow[2][NWMAX][SW];
+    __shared__ int s_pm[NT];
     int32_t *pm = a.perm + (int64_t(pole) * nblk + k) * (2 * nb);
-    for (int r = tid; r < 2 * nb; r += kFacThreads) {
-        idxl[r] = r;
-        pmf[r] = (c0 == 0) ? r : pm[r];
-    }
-    if (tid < SW) s_flag[tid] = 0;
-    if (tid == 0) s_info = 0;
-    zd v[CPT][NS];
+    // the running permutation is read before the first barrier and written after the
+    // last one (through LDS, so that every read has landed before any thread writes)
+    if (tid < 2 * nb) s_pm[tid] = (c0 == 0) ? tid : pm[tid];
+    zd x[SW];
 #pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        const int col = c0 + wave + kFacWaves * i;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            int r = lane + 64 * s;
-            v[i][s] = (r < R) ? W[r + int64_t(col) * ldw] : zmake(0, 0);
-        }
+    for (int j = 0; j < SW; ++j) x[j] = live ? W[tid + int64_t(c0 + j) * ldw] : zmake(0, 0);
+    // the pivot-row buffers start finite (a singular column reads one, times zero)
+    for (int e = tid; e < 2 * NWMAX * SW; e += int(blockDim.x)) (&urow[0][0][0])[e] = zmake(0, 0);
+    // waves that do not exist never offer a candidate
+    if (tid < 2 * NWMAX && (tid % NWMAX) >= nw) {
+        cand[tid / NWMAX][tid % NWMAX].key = 0;
+        cand[tid / NWMAX][tid % NWMAX].tid = -1;
+        cand[tid / NWMAX][tid % NWMAX].pos = -1;
     }
-    __syncthreads();
-    // Pivot steps without workgroup barriers: step j is published by the owner of
-    // column j (flag, pivot row, multipliers); every wave waits only for that.  The
-    // owner of column j+1 applies step j to it first and publishes step j+1, so the
-    // other columns' updates stay off the critical path.
-    if (wave == 0)
-        panel_pivot<NS>(v[0], 0, c0, R, lane, Lh, s_piv, &s_info, k * nb, s_flag);
+    int pos = tid;
+    int info = 0;
+#pragma unroll
     for (int j = 0; j < SW; ++j) {
-        const int gj = c0 + j;
-        wait_flag(&s_flag[j], &s_info);
-        const int p = __builtin_amdgcn_readfirstlane(s_piv[j]);
-        const zd *lc = Lh + j * ldl;
-        zd l[NS];
+        const int gj = c0 + j, par = j & 1;
+        const bool is_cand = live && pos >= gj;
+        const double m = zabs2(x[j]);
+        const uint64_t mine = (is_cand && m > 0.0) ? uint64_t(__double_as_longlong(m)) : 0;
+        const uint64_t top = wave_max_u64(mine);
+        const uint64_t wmax =
+            (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(top >> 32)), 63))) << 32) |
+            uint32_t(__builtin_amdgcn_readlane(int(uint32_t(top)), 63));
+        const uint64_t hit = __ballot(is_cand && mine == wmax);
+        if (hit != 0 && lane == int(__builtin_ctzll(hit))) {
+            PivotCand c;
+            c.key = wmax; c.tid = tid; c.pos = pos;
+            cand[par][wave] = c;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            int r = lane + 64 * s;
-            l[s] = (r < R) ? lc[r] : zmake(0, 0);
+            for (int q = j; q < SW; ++q) urow[par][wave][q] = x[q];
+        } else if (hit == 0 && lane == 0) {
+            PivotCand c;
+            c.key = 0; c.tid = -1; c.pos = -1;
+            cand[par][wave] = c;
         }
-        // the owner of column j+1 updates it first and finds the next pivot
-        const bool owner = (j + 1 < SW) && wave == ((j + 1) % kFacWaves);
-        const int ii = (j + 1) / kFacWaves;
-        zd *lnext = Lh + (j + 1) * ldl;
-        if (owner) {
-            // constant register indices in every branch (no dynamically indexed arrays)
-#define RF_OWNER_STEP(I_)                                                                       \
-            case I_:                                                                            \
-                step_update<NS>(v[I_], l, p, gj, lane);                                    \
-                panel_pivot<NS>(v[I_], j + 1, gj + 1, R, lane, lnext, s_piv, &s_info, k * nb,   \
-                                s_flag);                                                   \
-                break;
-            switch (ii) {
-                RF_OWNER_STEP(0)
-                RF_OWNER_STEP(1)
-                default:
-                if constexpr (CPT > 2) {
-                    if (ii == 2) {
-                        step_update<NS>(v[CPT > 2 ? 2 : 0], l, p, gj, lane);
-                        panel_pivot<NS>(v[CPT > 2 ? 2 : 0], j + 1, gj + 1, R, lane, lnext, s_piv,
-                                        &s_info, k * nb, s_flag);
-                    } else {
-                        step_update<NS>(v[CPT > 3 ? 3 : 0], l, p, gj, lane);
-                        panel_pivot<NS>(v[CPT > 3 ? 3 : 0], j + 1, gj + 1, R, lane, lnext, s_piv,
-                                        &s_info, k * nb, s_flag);
-                    }
-                }
-            }
-#undef RF_OWNER_STEP
-        }
+        __syncthreads();
+        // winner: largest nonzero key, ties to the lowest wave (so the lowest thread);
+        // none: singular column (no interchange, zero multipliers)
+        PivotCand cw[NWMAX];
 #pragma unroll
-        for (int i = 0; i < CPT; ++i) {
-            const int c = wave + kFacWaves * i;
-            if (owner && i == ii) continue;
-            if (c > j) {
-                step_update<NS>(v[i], l, p, gj, lane);
-            } else if (c < j && p != gj) {
-                const zd u = row_get<NS>(v[i], p), t = row_get<NS>(v[i], gj);
+        for (int w = 0; w < NWMAX; ++w) cw[w] = cand[par][w];
+        uint64_t bk = 0;
+        int tw = -1, pw = gj, bw = 0;
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    int r = lane + 64 * s;
-                    if (r == gj) v[i][s] = u;
-                    else if (r == p) v[i][s] = t;
-                }
-            }
-        }
+        for (int w = 0; w < NWMAX; ++w)
+            if (cw[w].key > bk) { bk = cw[w].key; tw = cw[w].tid; pw = cw[w].pos; bw = w; }
+        tw = __builtin_amdgcn_readfirstlane(tw);
+        pw = __builtin_amdgcn_readfirstlane(pw);
+        bw = __builtin_amdgcn_readfirstlane(bw);
+        const bool sing = tw < 0;
+        if (sing && info == 0) info = k * nb + gj + 1;
+        const zd *ur = urow[par][bw];
+        const zd uj = ur[j];
+        // 1 / u_j = conj(u_j) / |u_j|^2 (the pivot is the column's largest entry)
+        const double sc = 1.0 / zabs2(uj);
+        pos = (tid == tw) ? gj : (pos == gj ? pw : pos);
+        const bool upd = live && pos > gj;
+        const zd xl = zmake(x[j].x * uj.x + x[j].y * uj.y, x[j].y * uj.x - x[j].x * uj.y);
+        const zd l = (upd && !sing) ? zmake(xl.x * sc, xl.y * sc) : zmake(0, 0);
+        if (upd) x[j] = l;
+#pragma unroll
+        for (int q = j + 1; q < SW; ++q) zfms(x[q], l, ur[q]);
     }
-    __syncthreads();
+    if (live && pos >= c0) {
 #pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        const int col = c0 + wave + kFacWaves * i;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            int r = lane + 64 * s;
-            if (r < R) W[r + int64_t(col) * ldw] = v[i][s];
-        }
+        for (int j = 0; j < SW; ++j) W[pos + int64_t(c0 + j) * ldw] = x[j];
     }
-    // replay the interchanges of the sub-panel into its row order and the step order
-    if (tid == 0)
-        for (int j = 0; j < SW; ++j) {
-            const int gj = c0 + j, p = s_piv[j];
-            int t = idxl[gj]; idxl[gj] = idxl[p]; idxl[p] = t;
-            t = pmf[gj]; pmf[gj] = pmf[p]; pmf[p] = t;
-        }
-    __syncthreads();
     int32_t *sp = a.subperm + int64_t(pole) * 2 * nb;
-    for (int r = tid; r < 2 * nb; r += kFacThreads) {
-        sp[r] = idxl[r];
-        pm[r] = pmf[r];
+    if (tid < 2 * nb) {
+        sp[pos] = tid;
+        pm[pos] = s_pm[tid];
     }
-    if (tid == 0 && s_info != 0 && a.info[pole] == 0) a.info[pole] = s_info;
+    if (tid == 0 && info != 0 && a.info[pole] == 0) a.info[pole] = info;
 }
 
 // grid: (ceil(columns / 8), p); one window column per wave.
@@ -973,6 +853,9 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
     if (trail_lds(sw) > size_t(P.max_lds) || nb > 256) return hipErrorInvalidValue;
     a.rows = P.F.rows;
     a.subperm = P.F.subperm;
+    // one thread per window row; 32-column sub-steps only for nb <= 128 (trail LDS)
+    const int panel_threads = 2 * nb < 64 ? 64 : 2 * nb;
+    if (sw == 32 && panel_threads > 256) return hipErrorInvalidValue;
     hipLaunchKernelGGL(rowblock_prep_kernel, dim3(a.nblk, p), dim3(256), 0, s, a);
     hipLaunchKernelGGL(band_window_init_kernel, dim3(p), dim3(256), 0, s, a);
     int buf = 0;
@@ -983,8 +866,8 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
             const dim3 tg((total + kFacWaves - 1) / kFacWaves, p);
             const size_t tl = trail_lds(sw);
 #define RF_FAC_LAUNCH(NS_, SW_)                                                                   \
-            hipLaunchKernelGGL((band_panel_kernel<NS_, SW_>), dim3(p), dim3(kFacThreads),          \
-                               size_t(SW_) * 2 * nb * sizeof(zd), s, a, \
+            hipLaunchKernelGGL((band_panel_kernel<SW_, SW_ == 32 ? 256 : 512>), dim3(p),          \
+                               dim3(panel_threads), 0, s, a,                                     \
                                k, buf, c0);                                                      \
             hipLaunchKernelGGL((band_trail_kernel<NS_, SW_>), tg, dim3(kFacThreads), tl, s, a, k,  \
                                buf, c0)
