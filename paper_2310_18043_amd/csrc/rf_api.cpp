@@ -220,6 +220,12 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
             P->max_lds = lds;
         else
             (void)hipGetLastError();
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            P->num_cu = cus;
+        else
+            (void)hipGetLastError();
     }
     auto fail = [&](rf_status s) {
         *out = P;  // keep the plan so the caller can read rf_last_error, then destroy

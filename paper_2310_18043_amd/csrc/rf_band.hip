@@ -961,9 +961,10 @@ hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int nc
     }
     int cw = P.opts.trsm_cols;
     if (cw <= 0) {
-        // enough workgroups to cover the chip, at most 8 columns each
-        cw = 4;
-        while (cw > 1 && (int64_t(ncols + cw - 1) / cw) * a.p < 256) cw /= 2;
+        // the narrowest slices whose workgroups all run at once, one per compute unit
+        // (a second workgroup on a unit only queues behind the first's tile stream)
+        cw = 1;
+        while (cw < 4 && (int64_t(ncols + cw - 1) / cw) * a.p > P.num_cu) cw *= 2;
     }
     if (cw > 2) cw = 4;
     const size_t elem = c64 ? sizeof(zf) : sizeof(zd);

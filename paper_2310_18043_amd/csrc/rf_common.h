@@ -103,6 +103,7 @@ struct rf_plan {
     hipStream_t stream = nullptr;
     int device = 0;
     int max_lds = 65536;      // dynamic LDS bytes a workgroup may use
+    int num_cu = 256;         // compute units of the device
     DevCsr A, B;
     HostCsr hA, hB;
     std::vector<zd> poles, weights;       // inner rule (p)
