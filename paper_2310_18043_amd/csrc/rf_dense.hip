@@ -24,49 +24,76 @@ __device__ inline int64_t bidx(const int *map, int flags, int bit, int t) {
 }
 
 // ---------------------------------------------------------------------------
-// C_part[chunk] = A[rows of chunk]^H B[rows of chunk]   (tile 64 x 64 per WG)
-// grid: (ceil(m/64), ceil(k/64), batch * nchunks)
+// C_part[chunk] = A[rows of chunk]^H B[rows of chunk]   (tile 16 TMV x 16 TNV per WG)
+// grid: (ceil(m / 16 TMV), ceil(k / 16 TNV), batch * nchunks)
 // ---------------------------------------------------------------------------
-// TNV: output columns per thread (tile width 16 TNV): 4 for wide right operands, 2
-// when k <= 32 (the Krylov sub-block width), so that no multiply-add is spent on padding.
-template <int TNV>
+// Slabs of TKS rows go through LDS; the next slab is read into registers while the
+// current one is multiplied, so the global-memory latency is paid once per chunk.
+// TMV / TNV: output rows / columns per thread (tile 16 TMV x 16 TNV): 2 when the
+// operand is at most 32 wide (the Krylov sub-block width), so that no multiply-add
+// is spent on padding, else 4.
+constexpr int TKS = 32;
+
+template <int TMV, int TNV>
 __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
     int64_t n, int m, int k, const zd *__restrict__ A, int64_t lda, int64_t sA,
     const zd *__restrict__ B, int64_t ldb, int64_t sB, zd *__restrict__ part, int nchunks,
     int64_t chunk, const int *map, int flags) {
-    constexpr int TNT = 16 * TNV;
+    constexpr int TMT = 16 * TMV, TNT = 16 * TNV;
+    constexpr int LA = TKS * TMT / GT, LB = TKS * TNT / GT;     // slab elements per thread
     const int bt = blockIdx.z / nchunks, ch = blockIdx.z % nchunks;
-    const int m0 = blockIdx.x * TM, k0 = blockIdx.y * TNT;
+    const int m0 = blockIdx.x * TMT, k0 = blockIdx.y * TNT;
     A += bidx(map, flags, kMapA, bt) * sA;
     B += bidx(map, flags, kMapB, bt) * sB;
     const int64_t r0 = int64_t(ch) * chunk;
     const int64_t r1 = min(n, r0 + chunk);
-    __shared__ zd As[TK][TM + 1];
-    __shared__ zd Bs[TK][TNT + 1];
+    __shared__ zd As[TKS][TMT + 1];
+    __shared__ zd Bs[TKS][TNT + 1];
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    zd acc[4][TNV];
+    zd ra[LA], rb[LB];
+    // rows are the fastest index of a slab element: coalesced column runs
+    auto fetch = [&](int64_t rr) __attribute__((always_inline)) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int q = 0; q < LA; ++q) {
+            const int e = tid + q * GT, i = e % TKS, c = e / TKS;
+            const int64_t row = rr + i;
+            ra[q] = (row < r1 && m0 + c < m) ? A[row + int64_t(m0 + c) * lda] : zmake(0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = tid + q * GT, i = e % TKS, c = e / TKS;
+            const int64_t row = rr + i;
+            rb[q] = (row < r1 && k0 + c < k) ? B[row + int64_t(k0 + c) * ldb] : zmake(0, 0);
+        }
+    };
+    zd acc[TMV][TNV];
+#pragma unroll
+    for (int i = 0; i < TMV; ++i)
 #pragma unroll
         for (int j = 0; j < TNV; ++j) acc[i][j] = zmake(0, 0);
-    for (int64_t rr = r0; rr < r1; rr += TK) {
-        for (int e = tid; e < TK * TM; e += GT) {
-            int i = e % TK, c = e / TK;
-            int64_t row = rr + i;
-            As[i][c] = (row < r1 && m0 + c < m) ? A[row + int64_t(m0 + c) * lda] : zmake(0, 0);
-            if (c < TNT)
-                Bs[i][c] = (row < r1 && k0 + c < k) ? B[row + int64_t(k0 + c) * ldb] : zmake(0, 0);
+    if (r0 < r1) fetch(r0);
+    for (int64_t rr = r0; rr < r1; rr += TKS) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+            const int e = tid + q * GT;
+            As[e % TKS][e / TKS] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = tid + q * GT;
+            Bs[e % TKS][e / TKS] = rb[q];
         }
         __syncthreads();
+        if (rr + TKS < r1) fetch(rr + TKS);
 #pragma unroll 4
-        for (int i = 0; i < TK; ++i) {
-            zd av[4], bv[TNV];
+        for (int i = 0; i < TKS; ++i) {
+            zd av[TMV], bv[TNV];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) av[u] = As[i][ty + 16 * u];
+            for (int u = 0; u < TMV; ++u) av[u] = As[i][ty + 16 * u];
 #pragma unroll
             for (int v = 0; v < TNV; ++v) bv[v] = Bs[i][tx + 16 * v];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < TMV; ++u)
 #pragma unroll
                 for (int v = 0; v < TNV; ++v) zfma_c(acc[u][v], av[u], bv[v]);
         }
@@ -74,7 +101,7 @@ __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
     }
     zd *P = part + (int64_t(bt) * nchunks + ch) * int64_t(m) * k;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < TMV; ++u)
 #pragma unroll
         for (int v = 0; v < TNV; ++v) {
             int mi = m0 + ty + 16 * u, kj = k0 + tx + 16 * v;
@@ -102,8 +129,10 @@ __global__ void gemm_cn_reduce_kernel(int m, int k, const zd *part, int nchunks,
 }
 
 // ---------------------------------------------------------------------------
-// C (n x k) = alpha * A (n x m) B (m x k) + beta * C     grid: (ceil(n/64), ceil(k/64), batch)
+// C (n x k) = alpha * A (n x m) B (m x k) + beta * C     grid: (ceil(n/64), ceil(k/16 TNV), batch)
 // ---------------------------------------------------------------------------
+// Slabs of TKS columns of A (and rows of B) through LDS, the next slab read into
+// registers while the current one is multiplied.
 template <int TNV>
 __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd alpha,
                                                      const zd *__restrict__ A, int64_t lda,
@@ -112,32 +141,51 @@ __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd
                                                      int64_t ldc, int64_t sC, const int *map,
                                                      int flags) {
     constexpr int TNT = 16 * TNV;
+    constexpr int LA = TKS * TM / GT, LB = TKS * TNT / GT;
     const int bt = blockIdx.z;
     const int64_t n0 = int64_t(blockIdx.x) * TM;
     const int k0 = blockIdx.y * TNT;
     A += bidx(map, flags, kMapA, bt) * sA;
     B += bidx(map, flags, kMapB, bt) * sB;
     C += bidx(map, flags, kMapC, bt) * sC;
-    __shared__ zd As[TK][TM + 1];
-    __shared__ zd Bs[TK][TNT + 1];
+    __shared__ zd As[TKS][TM + 1];
+    __shared__ zd Bs[TKS][TNT + 1];
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    zd ra[LA], rb[LB];
+    auto fetch = [&](int kk) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+            const int e = tid + q * GT, r = e % TM, i = e / TM;   // rows of A fastest
+            const int64_t row = n0 + r;
+            ra[q] = (row < n && kk + i < m) ? A[row + int64_t(kk + i) * lda] : zmake(0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = tid + q * GT, i = e % TKS, c = e / TKS;  // rows of B fastest
+            rb[q] = (kk + i < m && k0 + c < k) ? B[(kk + i) + int64_t(k0 + c) * ldb] : zmake(0, 0);
+        }
+    };
     zd acc[4][TNV];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < TNV; ++j) acc[i][j] = zmake(0, 0);
-    for (int kk = 0; kk < m; kk += TK) {
-        for (int e = tid; e < TK * TM; e += GT) {
-            int r = e % TM, i = e / TM;          // A tile: rows n0.., cols kk..
-            int64_t row = n0 + r;
-            As[i][r] = (row < n && kk + i < m) ? A[row + int64_t(kk + i) * lda] : zmake(0, 0);
-            int i2 = e % TK, c = e / TK;         // B tile: rows kk.., cols k0..
-            if (c < TNT)
-                Bs[i2][c] = (kk + i2 < m && k0 + c < k) ? B[(kk + i2) + int64_t(k0 + c) * ldb] : zmake(0, 0);
+    if (m > 0) fetch(0);
+    for (int kk = 0; kk < m; kk += TKS) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+            const int e = tid + q * GT;
+            As[e / TM][e % TM] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = tid + q * GT;
+            Bs[e % TKS][e / TKS] = rb[q];
         }
         __syncthreads();
+        if (kk + TKS < m) fetch(kk + TKS);
 #pragma unroll 4
-        for (int i = 0; i < TK; ++i) {
+        for (int i = 0; i < TKS; ++i) {
             zd av[4], bv[TNV];
 #pragma unroll
             for (int u = 0; u < 4; ++u) av[u] = As[i][ty + 16 * u];
@@ -785,7 +833,8 @@ hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_
                           hipStream_t s, const int *map, int flags) {
     if (n <= 0 || m <= 0 || k <= 0 || batch <= 0) return hipSuccess;
     const int tn = k <= 32 ? 32 : TN;                        // tile width
-    const int tiles = ((m + TM - 1) / TM) * ((k + tn - 1) / tn) * batch;
+    const int tm = m <= 32 ? 32 : TM;                        // tile height
+    const int tiles = ((m + tm - 1) / tm) * ((k + tn - 1) / tn) * batch;
     int nchunks = int((1024 + tiles - 1) / tiles);          // aim for ~1024 workgroups
     int64_t maxch = (n + 255) / 256;
     if (nchunks > maxch) nchunks = int(maxch);
@@ -795,13 +844,18 @@ hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_
     int64_t chunk = (n + nchunks - 1) / nchunks;
     chunk = ((chunk + TK - 1) / TK) * TK;
     nchunks = int((n + chunk - 1) / chunk);
-    dim3 grid((m + TM - 1) / TM, (k + tn - 1) / tn, batch * nchunks);
-    if (tn == 32)
-        hipLaunchKernelGGL(gemm_cn_partial_kernel<2>, grid, dim3(GT), 0, s, n, m, k, A, lda, sA, B,
-                           ldb, sB, work, nchunks, chunk, map, flags);
-    else
-        hipLaunchKernelGGL(gemm_cn_partial_kernel<4>, grid, dim3(GT), 0, s, n, m, k, A, lda, sA, B,
-                           ldb, sB, work, nchunks, chunk, map, flags);
+    dim3 grid((m + tm - 1) / tm, (k + tn - 1) / tn, batch * nchunks);
+#define RF_CN_LAUNCH(TMV_, TNV_)                                                                \
+    hipLaunchKernelGGL((gemm_cn_partial_kernel<TMV_, TNV_>), grid, dim3(GT), 0, s, n, m, k, A, lda, \
+                       sA, B, ldb, sB, work, nchunks, chunk, map, flags)
+    if (tm == 32) {
+        if (tn == 32) RF_CN_LAUNCH(2, 2);
+        else RF_CN_LAUNCH(2, 4);
+    } else {
+        if (tn == 32) RF_CN_LAUNCH(4, 2);
+        else RF_CN_LAUNCH(4, 4);
+    }
+#undef RF_CN_LAUNCH
     int64_t tot = int64_t(m) * k * batch;
     hipLaunchKernelGGL(gemm_cn_reduce_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, m, k,
                        work, nchunks, alpha, beta, C, ldc, sC, batch, map, flags);
