@@ -219,84 +219,142 @@ __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd
 // dimension k), then Rinv = R^{-1}.  The diagonal is raised by shift_rel * max_i S_ii
 // before factoring (shifted CholeskyQR).  status[t] = 1 + the first column whose
 // pivot is not positive; dratio[t] = min_i R_ii / max_i R_ii (condition estimate).
-// LDS version (k <= 64): the whole matrix, its factor and its inverse stay in LDS.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(GT) void chol_inv_lds_kernel(int k, const zd *S, int64_t sS,
+// Register version for k <= K (K = 32 or 64): thread (i = tid % K, g = tid / K) holds
+// row i, columns g CPT .. g CPT + CPT - 1 of the matrix being reduced.
+//   Cholesky, right-looking: before step j every thread reads column j (published in
+//   LDS by its owners at the end of step j - 1), scales its element of column j by
+//   1 / sqrt(d_j) and takes the rank-one update of its elements right of column j;
+//   the owners of column j + 1 then publish it.  Column buffers alternate by step
+//   parity, so one barrier per column suffices.
+//   X = L^{-1}, right-looking forward substitution on the identity: the owners of row
+//   r scale it by 1 / L_rr and publish it, every row below subtracts L_ir times it.
+// Rows and columns past k are the identity and take no part.
+template <int K, int NT>
+__global__ __launch_bounds__(NT) void chol_inv_reg_kernel(int k, const zd *S, int64_t sS,
                                                           zd *Rout, int64_t sR, zd *Rinv,
                                                           int64_t sRi, int *status,
                                                           double *dratio, double shift_rel,
                                                           const int *map, int flags) {
+    constexpr int NCG = NT / K, CPT = K / NCG;
     const int bt = blockIdx.x;
     const zd *Sg = S + bidx(map, flags, kMapA, bt) * sS;
     zd *Rg = Rout + bidx(map, flags, kMapB, bt) * sR;
     zd *Rig = Rinv + bidx(map, flags, kMapC, bt) * sRi;
-    extern __shared__ unsigned char smem_raw[];
-    zd *L = reinterpret_cast<zd *>(smem_raw);      // [k][k] column-major lower factor
-    zd *X = L + k * k;                             // [k][k] inverse of L (lower)
-    __shared__ int bad;
-    __shared__ double shift;
-    const int tid = threadIdx.x;
-    // column ownership: thread group g (tpc consecutive lanes) owns column g
-    int tpc = 64;
-    while (tpc > 1 && tpc * k > GT) tpc >>= 1;
-    const int g = tid / tpc, part = tid % tpc;
-    for (int e = tid; e < k * k; e += GT) L[e] = Sg[e];
-    if (tid == 0) bad = 0;
+    const int tid = threadIdx.x, i = tid % K, g = tid / K, c0 = g * CPT;
+    __shared__ zd colb[2][K];
+    __shared__ zd Ls[K][K + 1];              // Ls[c][r] = L[r][c]
+    __shared__ double rdiag[K], sdiag[K];    // 1 / L_jj, L_jj
+    __shared__ double s_shift;
+    __shared__ int s_bad;
+    zd a[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int l = c0 + q;
+        a[q] = (i < k && l < k) ? Sg[i + int64_t(l) * k] : zmake(i == l ? 1.0 : 0.0, 0.0);
+    }
+    // the diagonal for the shift (one element per thread, read in parallel)
+    if (tid < K) sdiag[tid] = (tid < k) ? Sg[tid + int64_t(tid) * k].x : 0.0;
+    // column 0 published by its owners
+    if (g == 0) colb[0][i] = a[0];
     __syncthreads();
     if (tid == 0) {
         double mx = 0.0;
-        for (int i = 0; i < k; ++i) mx = fmax(mx, L[i + i * k].x);
-        shift = shift_rel * mx;
+        for (int r = 0; r < k; ++r) mx = fmax(mx, sdiag[r]);
+        s_shift = shift_rel * mx;
+        s_bad = 0;
     }
     __syncthreads();
-    // right-looking: the owner of column j finishes it (its own updates are done),
-    // one barrier, then every later column takes its rank-one update
-    for (int j = 0; j < k; ++j) {
-        if (g == j) {
-            double d = L[j + j * k].x + shift;
-            if (!(d > 0.0)) { if (part == 0 && !bad) bad = j + 1; d = 1.0; }
-            const double sq = sqrt(d), inv = 1.0 / sq;
-            for (int i = j + 1 + part; i < k; i += tpc) L[i + j * k] = zscale(L[i + j * k], inv);
-            if (part == 0) L[j + j * k] = zmake(sq, 0.0);
-        }
-        __syncthreads();
-        if (g > j && g < k) {
-            const zd lgj = zconj(L[g + j * k]);
-            for (int i = g + part; i < k; i += tpc) {
-                zd v = L[i + g * k];
-                zfms(v, L[i + j * k], lgj);
-                if (i == g) v.y = 0.0;
-                L[i + g * k] = v;
+    const double shift = s_shift;
+    // column j = jb CPT + jj: the group index jb is a loop variable and jj a constant
+    // of the unrolled inner loop, so every register index below is a constant
+#pragma unroll 1
+    for (int jb = 0; jb < NCG; ++jb) {
+#pragma unroll
+        for (int jj = 0; jj < CPT; ++jj) {
+            const int j = jb * CPT + jj, par = jj & 1;     // CPT is even: parity of j
+            const zd *cj = colb[par];
+            double d = cj[j].x + (j < k ? shift : 0.0);
+            if (!(d > 0.0)) {
+                if (tid == 0 && s_bad == 0) s_bad = j + 1;
+                d = 1.0;
             }
-        }
-    }
-    __syncthreads();
-    // X = L^{-1}: column g by its group, forward substitution; each lane keeps the
-    // entries x_q, q = part mod tpc, that its own partial sums use
-    if (g < k) {
-        for (int r = g; r < k; ++r) {
-            zd d = zmake(0, 0);
-            for (int q = g + part; q < r; q += tpc) zfma(d, L[r + q * k], X[q + g * k]);
-            for (int off = tpc / 2; off > 0; off >>= 1) {
-                d.x += __shfl_xor(d.x, off, 64);
-                d.y += __shfl_xor(d.y, off, 64);
+            const double sq = sqrt(d), rs = 1.0 / sq, rd = 1.0 / d;
+            if (tid == 0) { rdiag[j] = rs; sdiag[j] = sq; }
+            const zd ci = cj[i];
+            zd cl[CPT];                                // all reads issued before any use
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) cl[q] = cj[c0 + q];
+            const zd cir = zmake(ci.x * rd, ci.y * rd);
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                const int l = c0 + q;
+                // A_il -= A_ij conj(A_lj) / d right of column j (lower triangle only)
+                const bool right = (g > jb) || (g == jb && q > jj);
+                if (right && l <= i) {
+                    a[q].x -= cir.x * cl[q].x + cir.y * cl[q].y;
+                    a[q].y -= cir.y * cl[q].x - cir.x * cl[q].y;
+                }
             }
-            const zd rhs = (r == g) ? zsub(zmake(1.0, 0.0), d) : zmake(-d.x, -d.y);
-            const zd xr = zscale(rhs, 1.0 / L[r + r * k].x);
-            if ((r - g) % tpc == part) X[r + g * k] = xr;
+            if (g == jb)
+                a[jj] = (i == j) ? zmake(sq, 0.0) : (i > j ? zmake(ci.x * rs, ci.y * rs) : zmake(0, 0));
+            // publish column j + 1
+            if (jj + 1 < CPT) {
+                if (g == jb) colb[par ^ 1][i] = a[jj + 1 < CPT ? jj + 1 : 0];
+            } else if (g == jb + 1) {
+                colb[par ^ 1][i] = a[0];
+            }
+            __syncthreads();
         }
     }
+    // L to LDS (lower triangle, zeros above); the identity starts X
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int l = c0 + q;
+        Ls[l][i] = (l <= i) ? a[q] : zmake(0, 0);
+        a[q] = zmake(l == i ? 1.0 : 0.0, 0.0);
+    }
     __syncthreads();
+    // X = L^{-1}: step r fixes row r and removes it from the rows below
+#pragma unroll 1
+    for (int rb = 0; rb < NCG; ++rb) {
+#pragma unroll
+        for (int rr = 0; rr < CPT; ++rr) {
+            const int r = rb * CPT + rr, par = rr & 1;
+            if (i == r) {
+                const double rq = rdiag[r];
+#pragma unroll
+                for (int q = 0; q < CPT; ++q) {
+                    a[q] = zmake(a[q].x * rq, a[q].y * rq);
+                    colb[par][c0 + q] = a[q];
+                }
+            }
+            __syncthreads();
+            // rows below r: subtract L_ir x_r (x_r is zero right of column r, so the
+            // update is taken everywhere; rows at or above r take it times zero)
+            const zd lir = (i > r) ? Ls[r][i] : zmake(0, 0);
+            zd xr[CPT];
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) xr[q] = colb[par][c0 + q];
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) zfms(a[q], lir, xr[q]);
+        }
+    }
     // R = L^H (upper), Rinv = X^H
-    for (int e = tid; e < k * k; e += GT) {
-        int i = e % k, j = e / k;
-        Rg[e] = (i <= j) ? zconj(L[j + i * k]) : zmake(0, 0);
-        Rig[e] = (i <= j) ? zconj(X[j + i * k]) : zmake(0, 0);
+    if (i < k) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int l = c0 + q;
+            if (l < k) {
+                Rg[l + int64_t(i) * k] = (l <= i) ? zconj(Ls[l][i]) : zmake(0, 0);
+                Rig[l + int64_t(i) * k] = (l <= i) ? zconj(a[q]) : zmake(0, 0);
+            }
+        }
     }
     if (tid == 0) {
         double mn = 1e300, mx = 0.0;
-        for (int i = 0; i < k; ++i) { mn = fmin(mn, L[i + i * k].x); mx = fmax(mx, L[i + i * k].x); }
-        if (status) status[bt] = bad;
+        for (int r = 0; r < k; ++r) { mn = fmin(mn, sdiag[r]); mx = fmax(mx, sdiag[r]); }
+        if (status) status[bt] = s_bad;
         if (dratio) dratio[bt] = (mx > 0.0) ? mn / mx : 0.0;
     }
 }
@@ -882,9 +940,12 @@ hipError_t launch_chol_inv(int k, zd *S, int64_t sS, zd *Rout, int64_t sR, zd *R
                            int64_t sRi, int batch, int *status, double *dratio, double shift_rel,
                            hipStream_t s, const int *map, int flags) {
     if (batch <= 0) return hipSuccess;
-    if (k <= 64) {
-        hipLaunchKernelGGL(chol_inv_lds_kernel, dim3(batch), dim3(GT), size_t(2) * k * k * sizeof(zd),
-                           s, k, S, sS, Rout, sR, Rinv, sRi, status, dratio, shift_rel, map, flags);
+    if (k <= 32) {
+        hipLaunchKernelGGL((chol_inv_reg_kernel<32, 256>), dim3(batch), dim3(256), 0, s, k, S, sS, Rout, sR,
+                           Rinv, sRi, status, dratio, shift_rel, map, flags);
+    } else if (k <= 64) {
+        hipLaunchKernelGGL((chol_inv_reg_kernel<64, 512>), dim3(batch), dim3(512), 0, s, k, S, sS, Rout, sR,
+                           Rinv, sRi, status, dratio, shift_rel, map, flags);
     } else {
         if (map) return hipErrorInvalidValue;
         hipLaunchKernelGGL(chol_inv_kernel, dim3(batch), dim3(GT), 0, s, k, S, sS, Rout, sR, Rinv,
