@@ -113,6 +113,39 @@ rf_status upload_csr(rf_plan *P, const rf_csr *M, DevCsr &D) {
 
 }  // namespace
 
+// Device-to-host reads through the plan's pinned staging buffer: read() enqueues an
+// asynchronous copy on the stream, sync() waits for the stream once and copies every
+// pending read out.  (A copy into pageable memory would wait for the stream by
+// itself, once per array.)  Use in straight-line code: nothing that syncs another
+// Readback of the same plan may run between read() and sync().
+struct Readback {
+    rf_plan *P;
+    hipStream_t s;
+    size_t off = 0;
+    struct Item { void *dst; size_t off, bytes; };
+    std::vector<Item> items;
+    Readback(rf_plan *p, hipStream_t st) : P(p), s(st) {}
+    hipError_t read(void *dst, const void *src, size_t bytes) {
+        const size_t o = (off + 63) & ~size_t(63);
+        if (!P->h_stage || o + bytes > P->stage_bytes)
+            return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+        hipError_t e = hipMemcpyAsync(P->h_stage + o, src, bytes, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) {
+            items.push_back({dst, o, bytes});
+            off = o + bytes;
+        }
+        return e;
+    }
+    hipError_t sync() {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e == hipSuccess)
+            for (const Item &it : items) std::memcpy(it.dst, P->h_stage + it.off, it.bytes);
+        items.clear();
+        off = 0;
+        return e;
+    }
+};
+
 rf_status rf_fail(rf_plan *plan, rf_status s, const std::string &msg) {
     if (plan) plan->last_error = msg;
     return s;
@@ -163,6 +196,7 @@ void rf_plan_destroy(rf_plan_t plan) {
     plan->prof.release();
     for (void *p : plan->allocations) (void)hipFree(p);
     if (plan->h_pinned_int) (void)hipHostFree(plan->h_pinned_int);
+    if (plan->h_stage) (void)hipHostFree(plan->h_stage);
     delete plan;
 }
 
@@ -375,6 +409,18 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
         rf_fail(P, RF_ERR_NOMEM, "pinned host allocation failed");
         return fail(RF_ERR_NOMEM);
     }
+    {
+        // status flags, residuals, column norms and the projected pencil
+        const int64_t nqm = std::max<int64_t>(std::max(o.q, o.q_max), 1);
+        P->stage_bytes = size_t(2 * w * w) * sizeof(zd) + size_t(nqm * w + 8 * w) * sizeof(double) +
+                         (size_t(1) << 16);
+        if (hipHostMalloc(reinterpret_cast<void **>(&P->h_stage), P->stage_bytes, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            P->h_stage = nullptr;
+            rf_fail(P, RF_ERR_NOMEM, "pinned host allocation failed");
+            return fail(RF_ERR_NOMEM);
+        }
+    }
     ALLOC(P->hV, n * w);
     ALLOC(P->hAV, n * w);
     ALLOC(P->hBV, n * w);
@@ -412,9 +458,11 @@ rf_status rf_factor_shifts(rf_plan_t P) {
     RF_HIP(P, launch_band_factor(*P, P->stream));
     P->prof.record_end(P->stream, ev0, 0, 1);
     std::vector<int32_t> info(P->opts.p);
-    RF_HIP(P, hipMemcpyAsync(info.data(), P->F.info, sizeof(int32_t) * P->opts.p,
-                             hipMemcpyDeviceToHost, P->stream));
-    RF_HIP(P, hipStreamSynchronize(P->stream));
+    {
+        Readback rb(P, P->stream);
+        RF_HIP(P, rb.read(info.data(), P->F.info, sizeof(int32_t) * P->opts.p));
+        RF_HIP(P, rb.sync());
+    }
     for (int i = 0; i < P->opts.p; ++i)
         if (info[i] < 0) {
             P->F.ready = false;
@@ -475,9 +523,10 @@ rf_status cholqr(rf_plan *P, zd *Wb, int64_t n, int k, zd *Rout, zd *tmp) {
         RF_HIP(P, launch_chol_inv(k, S, 0, R1, 0, R1i, 0, 1, status, dratio, shift, s));
         int hstat = 0;
         double dr = 0.0;
-        RF_HIP(P, hipMemcpyAsync(&hstat, status, sizeof(int), hipMemcpyDeviceToHost, s));
-        RF_HIP(P, hipMemcpyAsync(&dr, dratio, sizeof(double), hipMemcpyDeviceToHost, s));
-        RF_HIP(P, hipStreamSynchronize(s));
+        Readback rb(P, s);
+        RF_HIP(P, rb.read(&hstat, status, sizeof(int)));
+        RF_HIP(P, rb.read(&dr, dratio, sizeof(double)));
+        RF_HIP(P, rb.sync());
         if (hstat == 0) { passes = (attempt == 0 && dr > 1e-5) ? 1 : 2; break; }
         if (attempt == 1) return rf_fail(P, RF_ERR_NOCONV, "CholeskyQR breakdown (rank-deficient block)");
     }
@@ -496,8 +545,11 @@ rf_status cholqr(rf_plan *P, zd *Wb, int64_t n, int k, zd *Rout, zd *tmp) {
     if (src != Wb) RF_HIP(P, hipMemcpyAsync(Wb, src, sizeof(zd) * n * k, hipMemcpyDeviceToDevice, s));
     if (Rout) RF_HIP(P, hipMemcpyAsync(Rout, Racc, sizeof(zd) * k * k, hipMemcpyDeviceToDevice, s));
     int hstat = 0;
-    RF_HIP(P, hipMemcpyAsync(&hstat, status, sizeof(int), hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipStreamSynchronize(s));
+    {
+        Readback rb(P, s);
+        RF_HIP(P, rb.read(&hstat, status, sizeof(int)));
+        RF_HIP(P, rb.sync());
+    }
     if (hstat != 0) return rf_fail(P, RF_ERR_NOCONV, "CholeskyQR breakdown in the second pass");
     return RF_OK;
 }
@@ -622,12 +674,11 @@ rf_status krylov_start_rhs(rf_plan *P, KrylovState &K) {
     double *d_scale = P->colnorm;          // w column norms
     double *d_inv = P->colnorm + w;        // w inverse norms
     RF_HIP(P, launch_colnorms(n, w, P->ytil, n, nullptr, 0, nullptr, d_scale, s));
-    std::vector<double> inv(w), ones(w, 1.0);
+    std::vector<double> ones(w, 1.0);
     K.scale.resize(w);
-    RF_HIP(P, hipMemcpyAsync(K.scale.data(), d_scale, sizeof(double) * w, hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipStreamSynchronize(s));
-    for (int c = 0; c < w; ++c) inv[c] = K.scale[c] > 0.0 ? 1.0 / K.scale[c] : 0.0;
-    RF_HIP(P, hipMemcpyAsync(d_inv, inv.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
+    Readback rb(P, s);
+    RF_HIP(P, rb.read(K.scale.data(), d_scale, sizeof(double) * w));     // used after the loop
+    RF_HIP(P, launch_inv_pos(w, d_scale, d_inv, 0.0, s));
     RF_HIP(P, hipMemcpyAsync(P->r0norm, ones.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
     // V_sb[0] R0_sb = Ytilde_sb D_sb^{-1}   (all sub-blocks at once)
     RF_HIP(P, launch_copy_block(n, b, P->ytil, n, n * b, P->V, n, vstride, nsub, s));
@@ -637,9 +688,9 @@ rf_status krylov_start_rhs(rf_plan *P, KrylovState &K) {
     RF_TRY(cholqr2_batched_enqueue(P, P->V, vstride, nsub, n, b, P->R0, P->tmp));
     std::vector<int> st(2 * nsub);
     std::vector<double> dr(2 * nsub);
-    RF_HIP(P, hipMemcpyAsync(st.data(), P->d_status, sizeof(int) * 2 * nsub, hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipMemcpyAsync(dr.data(), P->d_dratio, sizeof(double) * 2 * nsub, hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipStreamSynchronize(s));
+    RF_HIP(P, rb.read(st.data(), P->d_status, sizeof(int) * 2 * nsub));
+    RF_HIP(P, rb.read(dr.data(), P->d_dratio, sizeof(double) * 2 * nsub));
+    RF_HIP(P, rb.sync());
     RF_TRY(cholqr2_batched_fixup(P, P->V, vstride, P->Gin, n * b, nsub, n, b, P->R0, P->tmp, st, dr));
     return RF_OK;
 }
@@ -682,9 +733,9 @@ rf_status krylov_rule(rf_plan *P, KrylovState &K, std::vector<int> &open) {
     }
     std::vector<double> resid(size_t(nq) * nsub * b);
     if (depth > 0) {
-        RF_HIP(P, hipMemcpyAsync(resid.data(), P->resid, sizeof(double) * nq * nsub * b,
-                                 hipMemcpyDeviceToHost, s));
-        RF_HIP(P, hipStreamSynchronize(s));
+        Readback rb(P, s);
+        RF_HIP(P, rb.read(resid.data(), P->resid, sizeof(double) * nq * nsub * b));
+        RF_HIP(P, rb.sync());
     }
     for (int sb = 0; sb < nsub; ++sb)
         if (K.msteps[sb] == 0 || !(krylov_worst(P, resid, sb) <= outer_tol(P))) open.push_back(sb);
@@ -742,9 +793,12 @@ rf_status krylov_advance(rf_plan *P, KrylovState &K, std::vector<int> active, bo
         RF_HIP(P, launch_copy_cols(n, nact * b, P->Wk, n, P->Gin, n, s));
         RF_TRY(cholqr2_batched_enqueue(P, P->Wk, n * b, nact, n, b, Rn, P->tmp));
         // the fallback check needs the flags before V and H are written
-        RF_HIP(P, hipMemcpyAsync(st.data(), P->d_status, sizeof(int) * 2 * nact, hipMemcpyDeviceToHost, s));
-        RF_HIP(P, hipMemcpyAsync(dr.data(), P->d_dratio, sizeof(double) * 2 * nact, hipMemcpyDeviceToHost, s));
-        RF_HIP(P, hipStreamSynchronize(s));
+        {
+            Readback rb(P, s);
+            RF_HIP(P, rb.read(st.data(), P->d_status, sizeof(int) * 2 * nact));
+            RF_HIP(P, rb.read(dr.data(), P->d_dratio, sizeof(double) * 2 * nact));
+            RF_HIP(P, rb.sync());
+        }
         {
             std::vector<const zd *> basis(nact);
             for (int a = 0; a < nact; ++a) basis[a] = P->V + active[a] * vstride;
@@ -757,9 +811,11 @@ rf_status krylov_advance(rf_plan *P, KrylovState &K, std::vector<int> active, bo
                                     d_active, kMapC));
         // per-shift least squares update and residuals
         RF_HIP(P, launch_ls_update(*P, j, d_active, nact, s));
-        RF_HIP(P, hipMemcpyAsync(resid.data(), P->resid, sizeof(double) * nq * nsub * b,
-                                 hipMemcpyDeviceToHost, s));
-        RF_HIP(P, hipStreamSynchronize(s));
+        {
+            Readback rb(P, s);
+            RF_HIP(P, rb.read(resid.data(), P->resid, sizeof(double) * nq * nsub * b));
+            RF_HIP(P, rb.sync());
+        }
         K.steps = std::max(K.steps, j + 1);
         std::vector<int> still;
         bool any_open = false;
@@ -974,9 +1030,12 @@ rf_status orth_panels(rf_plan *P, zd *U, int64_t n, int w) {
         }
         RF_HIP(P, launch_copy_cols(n, k, Ut, n, P->Gin, n, s));
         RF_TRY(cholqr2_batched_enqueue(P, Ut, n * k, 1, n, k, R, P->tmp));
-        RF_HIP(P, hipMemcpyAsync(st.data(), P->d_status, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
-        RF_HIP(P, hipMemcpyAsync(dr.data(), P->d_dratio, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
-        RF_HIP(P, hipStreamSynchronize(s));
+        {
+            Readback rb(P, s);
+            RF_HIP(P, rb.read(st.data(), P->d_status, sizeof(int) * 2));
+            RF_HIP(P, rb.read(dr.data(), P->d_dratio, sizeof(double) * 2));
+            RF_HIP(P, rb.sync());
+        }
         RF_TRY(cholqr2_batched_fixup(P, Ut, n * k, P->Gin, n * k, 1, n, k, R, P->tmp, st, dr));
     }
     return RF_OK;
@@ -1011,12 +1070,8 @@ rf_status hsrr_project(rf_plan *P, zd *U, Projected &pr, int buf = 0) {
         std::isnan(P->opts.sigma_re) ? std::complex<double>(P->opts.c_re, P->opts.c_im)
                                      : std::complex<double>(P->opts.sigma_re, P->opts.sigma_im);
     // V = orth(U): normalise columns first (span unchanged), then CholeskyQR
-    RF_HIP(P, launch_colnorms(n, w, U, n, nullptr, 0, nullptr, P->colnorm, s));
-    std::vector<double> cn(w);
-    RF_HIP(P, hipMemcpyAsync(cn.data(), P->colnorm, sizeof(double) * w, hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipStreamSynchronize(s));
-    for (auto &v : cn) v = v > 0.0 ? 1.0 / v : 1.0;
-    RF_HIP(P, hipMemcpyAsync(P->colnorm, cn.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
+    RF_HIP(P, launch_colnorms(n, w, U, n, nullptr, 0, nullptr, P->colnorm + w, s));
+    RF_HIP(P, launch_inv_pos(w, P->colnorm + w, P->colnorm, 1.0, s));
     RF_HIP(P, launch_copy_cols(n, w, U, n, pr.V, n, s));
     RF_HIP(P, launch_scale_cols(n, w, pr.V, n, P->colnorm, s));
     RF_TRY(orth_panels(P, pr.V, n, w));
@@ -1038,9 +1093,10 @@ rf_status hsrr_project(rf_plan *P, zd *U, Projected &pr, int buf = 0) {
     pr.al.resize(w);
     pr.be.resize(w);
     pr.vr.resize(size_t(w) * w);
-    RF_HIP(P, hipMemcpyAsync(pr.A.data(), Ah, sizeof(zd) * w * w, hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipMemcpyAsync(pr.B.data(), Bh, sizeof(zd) * w * w, hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipStreamSynchronize(s));
+    Readback rb(P, s);
+    RF_HIP(P, rb.read(pr.A.data(), Ah, sizeof(zd) * w * w));
+    RF_HIP(P, rb.read(pr.B.data(), Bh, sizeof(zd) * w * w));
+    RF_HIP(P, rb.sync());
     return RF_OK;
 }
 
@@ -1058,15 +1114,11 @@ rf_status hsrr_finish(rf_plan *P, const Projected &pr, std::vector<std::complex<
         dlam[i] = Z(lam[i].real(), lam[i].imag());
     }
     // X = V (P_R V_R), unit columns
-    std::vector<double> cn(w);
     zd *dvr = P->small;
     RF_HIP(P, hipMemcpyAsync(dvr, pr.vr.data(), sizeof(zd) * w * w, hipMemcpyHostToDevice, s));
     RF_HIP(P, launch_gemm_nn(n, w, w, Z(1), pr.V, n, 0, dvr, w, 0, Z(0), P->hX, n, 0, 1, s));
-    RF_HIP(P, launch_colnorms(n, w, P->hX, n, nullptr, 0, nullptr, P->colnorm, s));
-    RF_HIP(P, hipMemcpyAsync(cn.data(), P->colnorm, sizeof(double) * w, hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipStreamSynchronize(s));
-    for (auto &v : cn) v = v > 0.0 ? 1.0 / v : 1.0;
-    RF_HIP(P, hipMemcpyAsync(P->colnorm, cn.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
+    RF_HIP(P, launch_colnorms(n, w, P->hX, n, nullptr, 0, nullptr, P->colnorm + w, s));
+    RF_HIP(P, launch_inv_pos(w, P->colnorm + w, P->colnorm, 1.0, s));
     RF_HIP(P, launch_scale_cols(n, w, P->hX, n, P->colnorm, s));
     // e_i = ||A x - lam B x|| / ((|c| + r) ||B x||)
     zd *dl = P->small + int64_t(w) * w;
@@ -1076,8 +1128,11 @@ rf_status hsrr_finish(rf_plan *P, const Projected &pr, std::vector<std::complex<
     RF_HIP(P, launch_colnorms(n, w, pr.AV, n, pr.BV, n, dl, P->herr, s));
     RF_HIP(P, launch_colnorms(n, w, pr.BV, n, nullptr, 0, nullptr, P->herr + w, s));
     std::vector<double> e2(2 * w);
-    RF_HIP(P, hipMemcpyAsync(e2.data(), P->herr, sizeof(double) * 2 * w, hipMemcpyDeviceToHost, s));
-    RF_HIP(P, hipStreamSynchronize(s));
+    {
+        Readback rb(P, s);
+        RF_HIP(P, rb.read(e2.data(), P->herr, sizeof(double) * 2 * w));
+        RF_HIP(P, rb.sync());
+    }
     const double scale = std::abs(std::complex<double>(P->opts.c_re, P->opts.c_im)) + P->opts.r;
     err.resize(w);
     for (int i = 0; i < w; ++i) {

@@ -145,6 +145,8 @@ struct rf_plan {
     double *d_dratio = nullptr; // 2w Cholesky diagonal ratios
     int *d_active = nullptr;  // w active sub-block indices
     int *h_pinned_int = nullptr; // pinned host mirror of d_active
+    char *h_stage = nullptr;     // pinned staging for device-to-host reads
+    size_t stage_bytes = 0;
     // HSRR
     zd *hV = nullptr, *hAV = nullptr, *hBV = nullptr, *hW = nullptr, *hX = nullptr;
     zd *hY = nullptr;         // n x w: block being filtered while the host QZ runs
@@ -247,6 +249,7 @@ hipError_t launch_axpby_cols(int64_t n, int ncols, zd alpha, const zd *X, int64_
 // column 2-norms of (X - Y diag(lam)) (Y may be null) -> out[c]
 hipError_t launch_colnorms(int64_t n, int ncols, const zd *X, int64_t ldx, const zd *Y,
                            int64_t ldy, const zd *lam, double *out, hipStream_t s);
+hipError_t launch_inv_pos(int m, const double *src, double *dst, double other, hipStream_t s);
 hipError_t launch_scale_cols(int64_t n, int ncols, zd *X, int64_t ldx, const double *inv,
                              hipStream_t s);
 hipError_t launch_gaussian(int64_t n, int ncols, zd *X, int64_t ldx, uint64_t seed,

@@ -515,6 +515,13 @@ __global__ void scale_cols_kernel(int64_t n, int ncols, zd *X, int64_t ldx, cons
     X[r + c * ldx] = zscale(X[r + c * ldx], inv[c]);
 }
 
+// dst[c] = 1 / src[c] for positive entries, else `other` (column scalings computed
+// on the device, so that no host round trip sits between the norms and their use)
+__global__ void inv_pos_kernel(int m, const double *src, double *dst, double other) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < m) dst[c] = src[c] > 0.0 ? 1.0 / src[c] : other;
+}
+
 // splitmix64-based counter generator: element (r, c) draws from counter r + c*n
 __device__ inline uint64_t splitmix64(uint64_t x) {
     x += 0x9E3779B97F4A7C15ull;
@@ -1096,6 +1103,12 @@ hipError_t launch_colnorms(int64_t n, int ncols, const zd *X, int64_t ldx, const
                            int64_t ldy, const zd *lam, double *out, hipStream_t s) {
     if (ncols == 0) return hipSuccess;
     hipLaunchKernelGGL(colnorm_kernel, dim3(ncols), dim3(GT), 0, s, n, X, ldx, Y, ldy, lam, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_inv_pos(int m, const double *src, double *dst, double other, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(inv_pos_kernel, dim3((m + 255) / 256), dim3(256), 0, s, m, src, dst, other);
     return hipGetLastError();
 }
 
