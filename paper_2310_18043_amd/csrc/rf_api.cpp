@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
+#include <tuple>
 #include <limits>
 #include <numeric>
 #include <string>
@@ -133,6 +135,26 @@ struct Readback {
         if (e == hipSuccess) {
             items.push_back({dst, o, bytes});
             off = o + bytes;
+        }
+        return e;
+    }
+    // one copy of a device block, handed out in parts (destination, byte offset in the
+    // block, bytes)
+    hipError_t read_parts(const void *src, size_t total,
+                          std::initializer_list<std::tuple<void *, size_t, size_t>> parts) {
+        const size_t o = (off + 63) & ~size_t(63);
+        if (!P->h_stage || o + total > P->stage_bytes) {
+            for (const auto &pt : parts) {
+                hipError_t e = hipMemcpyAsync(std::get<0>(pt), static_cast<const char *>(src) + std::get<1>(pt),
+                                              std::get<2>(pt), hipMemcpyDeviceToHost, s);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        }
+        hipError_t e = hipMemcpyAsync(P->h_stage + o, src, total, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) {
+            for (const auto &pt : parts) items.push_back({std::get<0>(pt), o + std::get<1>(pt), std::get<2>(pt)});
+            off = o + total;
         }
         return e;
     }
@@ -400,8 +422,9 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
     P->partial_elems = std::max<int64_t>(int64_t(1) << 22, 16 * w * w);
     ALLOC(P->partial, P->partial_elems);
     ALLOC(P->flag, 64 + w);
-    ALLOC(P->d_status, 2 * w);
-    ALLOC(P->d_dratio, 2 * w);
+    // Cholesky flags and diagonal ratios side by side: one read fetches both
+    ALLOC(P->d_dratio, 2 * w + (2 * w * int64_t(sizeof(int)) + 7) / 8);
+    P->d_status = reinterpret_cast<int *>(P->d_dratio + 2 * w);
     ALLOC(P->d_active, w);
     if (hipHostMalloc(reinterpret_cast<void **>(&P->h_pinned_int), sizeof(int) * w, 0) != hipSuccess) {
         (void)hipGetLastError();
@@ -500,6 +523,15 @@ rf_status rf_apply_inner(rf_plan_t P, const void *X, int64_t ldx, int32_t ncols,
 namespace {
 
 const double kUnit = 1.1102230246251565e-16;
+
+// Breakdown flags (2 cnt ints) and diagonal ratios (2 cnt doubles) of the batched
+// Cholesky passes, from their joint device block in one copy.
+hipError_t read_chol_flags(Readback &rb, rf_plan *P, int *st, double *dr, int cnt) {
+    const size_t w = size_t(P->opts.w);
+    const size_t total = 2 * w * sizeof(double) + 2 * w * sizeof(int);
+    return rb.read_parts(P->d_dratio, total,
+                         {{dr, 0, sizeof(double) * 2 * cnt}, {st, 2 * w * sizeof(double), sizeof(int) * 2 * cnt}});
+}
 
 // Orthonormalise one n x k block Wb (ld n) in place by CholeskyQR2, with a shifted
 // first pass (CholeskyQR3) when the Gram matrix is numerically indefinite.  Rout
@@ -688,8 +720,7 @@ rf_status krylov_start_rhs(rf_plan *P, KrylovState &K) {
     RF_TRY(cholqr2_batched_enqueue(P, P->V, vstride, nsub, n, b, P->R0, P->tmp));
     std::vector<int> st(2 * nsub);
     std::vector<double> dr(2 * nsub);
-    RF_HIP(P, rb.read(st.data(), P->d_status, sizeof(int) * 2 * nsub));
-    RF_HIP(P, rb.read(dr.data(), P->d_dratio, sizeof(double) * 2 * nsub));
+    RF_HIP(P, read_chol_flags(rb, P, st.data(), dr.data(), nsub));
     RF_HIP(P, rb.sync());
     RF_TRY(cholqr2_batched_fixup(P, P->V, vstride, P->Gin, n * b, nsub, n, b, P->R0, P->tmp, st, dr));
     return RF_OK;
@@ -765,11 +796,15 @@ rf_status krylov_advance(rf_plan *P, KrylovState &K, std::vector<int> active, bo
     zd *h2 = P->hbuf + int64_t(nsub) * ldc * b;
     zd *Rn = P->rnew;                    // nsub x (b x b)
     int j0 = active.empty() ? 0 : K.msteps[active[0]];
+    std::vector<int> uploaded;           // the list last copied to d_active
     for (int j = j0; j < mmax && !active.empty(); ++j) {
         const int nact = int(active.size());
         const int kb = (j + 1) * b;
-        for (int a = 0; a < nact; ++a) h_active[a] = active[a];
-        RF_HIP(P, hipMemcpyAsync(d_active, h_active, sizeof(int) * nact, hipMemcpyHostToDevice, s));
+        if (active != uploaded) {         // the device list changes only when a sub-block stops
+            for (int a = 0; a < nact; ++a) h_active[a] = active[a];
+            RF_HIP(P, hipMemcpyAsync(d_active, h_active, sizeof(int) * nact, hipMemcpyHostToDevice, s));
+            uploaded = active;
+        }
         // gather the newest basis block of every active sub-block, apply G
         RF_HIP(P, launch_copy_block(n, b, P->V + int64_t(j) * b * n, n, vstride, P->Gin, n, n * b,
                                     nact, s, d_active, kMapA));
@@ -795,8 +830,7 @@ rf_status krylov_advance(rf_plan *P, KrylovState &K, std::vector<int> active, bo
         // the fallback check needs the flags before V and H are written
         {
             Readback rb(P, s);
-            RF_HIP(P, rb.read(st.data(), P->d_status, sizeof(int) * 2 * nact));
-            RF_HIP(P, rb.read(dr.data(), P->d_dratio, sizeof(double) * 2 * nact));
+            RF_HIP(P, read_chol_flags(rb, P, st.data(), dr.data(), nact));
             RF_HIP(P, rb.sync());
         }
         {
@@ -1032,8 +1066,7 @@ rf_status orth_panels(rf_plan *P, zd *U, int64_t n, int w) {
         RF_TRY(cholqr2_batched_enqueue(P, Ut, n * k, 1, n, k, R, P->tmp));
         {
             Readback rb(P, s);
-            RF_HIP(P, rb.read(st.data(), P->d_status, sizeof(int) * 2));
-            RF_HIP(P, rb.read(dr.data(), P->d_dratio, sizeof(double) * 2));
+            RF_HIP(P, read_chol_flags(rb, P, st.data(), dr.data(), 1));
             RF_HIP(P, rb.sync());
         }
         RF_TRY(cholqr2_batched_fixup(P, Ut, n * k, P->Gin, n * k, 1, n, k, R, P->tmp, st, dr));

@@ -260,6 +260,15 @@ __global__ __launch_bounds__(NT) void band_panel_kernel(FactorArgs a, int k, int
     if (tid == 0 && info != 0 && a.info[pole] == 0) a.info[pole] = info;
 }
 
+// value of x in lane ln (ln wave-uniform): four readlanes, no LDS round trip
+__device__ __attribute__((always_inline)) inline zd lane_bcast(zd x, int ln) {
+    const int a = __builtin_amdgcn_readlane(__double2loint(x.x), ln);
+    const int b = __builtin_amdgcn_readlane(__double2hiint(x.x), ln);
+    const int c = __builtin_amdgcn_readlane(__double2loint(x.y), ln);
+    const int d = __builtin_amdgcn_readlane(__double2hiint(x.y), ln);
+    return zmake(__hiloint2double(b, a), __hiloint2double(d, c));
+}
+
 // grid: (ceil(columns / 8), p); one window column per wave.
 template <int NS, int SW>
 __global__ __launch_bounds__(kFacThreads) void band_trail_kernel(FactorArgs a, int k, int buf,
@@ -339,13 +348,13 @@ __global__ __launch_bounds__(kFacThreads) void band_trail_kernel(FactorArgs a, i
 #pragma unroll
             for (int s = 1; s < NS; ++s) if (s == sl) vt = v[s];
             for (int q = 0; q < SW; ++q) {
-                zd u = zmake(__shfl(vt.x, base + q, 64), __shfl(vt.y, base + q, 64));
+                const zd u = lane_bcast(vt, base + q);
                 if (lane > base + q && lane < base + SW) zfms(vt, Ls[q * ldw + sl * 64 + lane], u);
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) if (s == sl) v[s] = vt;
             for (int q = 0; q < SW; ++q) {
-                zd u = zmake(__shfl(vt.x, base + q, 64), __shfl(vt.y, base + q, 64));
+                const zd u = lane_bcast(vt, base + q);
                 const zd *lq = Ls + q * ldw;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
