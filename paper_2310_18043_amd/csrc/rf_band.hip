@@ -196,6 +196,8 @@ __global__ __launch_bounds__(NT) void band_panel_kernel(FactorArgs a, int k, int
         cand[tid / NWMAX][tid % NWMAX].tid = -1;
         cand[tid / NWMAX][tid % NWMAX].pos = -1;
     }
+    // the initialisation above must land before the first candidates are written
+    __syncthreads();
     int pos = tid;
     int info = 0;
 #pragma unroll

@@ -127,3 +127,29 @@ def test_batch_closed_form_128(rf, torch_cuda):
         assert res["converged"]
         _match_closed_form(res, s, exact, kappa)
     batch.close()
+
+
+def test_batch_repeated_factorizations_are_identical(rf, torch_cuda):
+    # regression: many panel workgroups at once (64 disks x 4 poles = 256 pencils)
+    # once exposed an LDS initialisation race in the band LU panel that surfaced as
+    # spurious zero pivots in some factorizations; every factorization of the same
+    # pencils must succeed and give bit-identical factors
+    A, B, disks, _ = W.disk_batch(n=128, ndisks=64)
+    specs = [{"c": d["c"], "r": d["r"], "w": d["w"], "expected_count": d["count"]}
+             for d in disks]
+    _say("batch convdiff128_I 64 disks, repeated factorizations")
+    batch = rf.Batch(A, B, specs, p=4, q=8, max_krylov_blocks=60)
+    X = torch_cuda.from_numpy(W.start_block(A.shape[0], 8, 5)).cuda()
+    probe = (0, 21, 34, 63)
+    ref = None
+    for it in range(6):
+        batch.factor()
+        Z = [batch.plans[d].apply_inner(X) for d in probe]
+        torch_cuda.cuda.synchronize()
+        if ref is None:
+            ref = [z.clone() for z in Z]
+            assert all(bool(torch_cuda.isfinite(z).all()) for z in Z)
+        else:
+            for d, z, z0 in zip(probe, Z, ref):
+                assert torch_cuda.equal(z, z0), (it, d)
+    batch.close()
