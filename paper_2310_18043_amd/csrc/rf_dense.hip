@@ -620,6 +620,123 @@ __device__ inline zd wave_sum(zd v) {
     return v;
 }
 
+// Sums over aligned groups of 8 (or 4) lanes with DPP lane moves (no LDS round trip);
+// every lane of a group ends with the same value.
+__device__ __attribute__((always_inline)) inline double dpp_move(double v, int ctrl_sel) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int olo, ohi;
+    switch (ctrl_sel) {
+        case 0:  // quad_perm [1,0,3,2]: lane xor 1
+            olo = __builtin_amdgcn_update_dpp(lo, lo, 0xB1, 0xF, 0xF, false);
+            ohi = __builtin_amdgcn_update_dpp(hi, hi, 0xB1, 0xF, 0xF, false);
+            break;
+        case 1:  // quad_perm [2,3,0,1]: lane xor 2
+            olo = __builtin_amdgcn_update_dpp(lo, lo, 0x4E, 0xF, 0xF, false);
+            ohi = __builtin_amdgcn_update_dpp(hi, hi, 0x4E, 0xF, 0xF, false);
+            break;
+        default:  // row_half_mirror: lane 7 - i within each group of 8
+            olo = __builtin_amdgcn_update_dpp(lo, lo, 0x141, 0xF, 0xF, false);
+            ohi = __builtin_amdgcn_update_dpp(hi, hi, 0x141, 0xF, 0xF, false);
+            break;
+    }
+    return __hiloint2double(ohi, olo);
+}
+__device__ __attribute__((always_inline)) inline double group4_sum(double v) {
+    v += dpp_move(v, 0);
+    v += dpp_move(v, 1);
+    return v;
+}
+__device__ __attribute__((always_inline)) inline double group8_sum(double v) {
+    v = group4_sum(v);
+    v += dpp_move(v, 2);      // the other quad of the group holds the other half
+    return v;
+}
+
+// Householder QR of the 2b x b window (b = 32, 256 threads) in registers: thread
+// (column tid / 8, part tid % 8) holds rows part, part + 8, ... of its column.  Per
+// column c the eight threads of column c form the reflector (norm and pivot entry by
+// group sums) and publish it to Vh (rows above c zero) and tau to s_tau; after one
+// barrier every later column takes its update.  Then Q_j = H_0 H_1 ... H_{b-1}: thread
+// (column tid / 4, part tid % 4) holds rows part, part + 4, ... of a column of Q_j and
+// applies the reflectors last to first, with no barrier.  On return slab holds the
+// reduced window (R above, zeros below), Vh the reflectors, Ql (ld ldq) Q_j.
+__device__ void ls_qr32(zd *slab, zd *Vh, double *s_tau, zd *Ql, int ldq) {
+    constexpr int B = 32, M2 = 64;
+    const int tid = threadIdx.x;
+    {
+        const int col = tid >> 3, part = tid & 7;
+        zd x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = slab[(part + 8 * i) + col * M2];
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            if (col == c) {
+                double n2 = 0.0, p0x = 0.0, p0y = 0.0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int r = part + 8 * i;
+                    if (r >= c) n2 += zabs2(x[i]);
+                    if (i == c / 8 && part == c % 8) { p0x = x[i].x; p0y = x[i].y; }
+                }
+                const double nrm2 = group8_sum(n2);
+                const zd x0 = zmake(group8_sum(p0x), group8_sum(p0y));
+                const double ax0 = sqrt(zabs2(x0)), nrm = sqrt(nrm2);
+                const zd ph = (ax0 > 0.0) ? zscale(x0, 1.0 / ax0) : zmake(1.0, 0.0);
+                const zd alpha = zscale(ph, -nrm);          // alpha = -phase(x0) ||x||
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int r = part + 8 * i;
+                    const zd v = (r > c) ? x[i] : (r == c ? zsub(x[i], alpha) : zmake(0, 0));
+                    Vh[r + c * M2] = v;
+                    x[i] = (r == c) ? alpha : (r > c ? zmake(0, 0) : x[i]);
+                }
+                if (part == 0) s_tau[c] = (nrm > 0.0) ? 1.0 / (nrm * (nrm + ax0)) : 0.0;
+            }
+            __syncthreads();
+            if (col > c) {
+                zd v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = Vh[(part + 8 * i) + c * M2];
+                zd d0 = zmake(0, 0), d1 = zmake(0, 0);
+#pragma unroll
+                for (int i = 0; i < 8; i += 2) {
+                    zfma_c(d0, v[i], x[i]);
+                    zfma_c(d1, v[i + 1], x[i + 1]);
+                }
+                const double tau = s_tau[c];
+                const zd d = zscale(zmake(group8_sum(d0.x + d1.x), group8_sum(d0.y + d1.y)), tau);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) zfms(x[i], v[i], d);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) slab[(part + 8 * i) + col * M2] = x[i];
+    }
+    __syncthreads();
+    {
+        const int qcol = tid >> 2, part = tid & 3;
+        zd q[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) q[i] = zmake((part + 4 * i) == qcol ? 1.0 : 0.0, 0.0);
+        for (int c = B - 1; c >= 0; --c) {                  // Q <- H_c Q
+            zd v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = Vh[(part + 4 * i) + c * M2];
+            zd d0 = zmake(0, 0), d1 = zmake(0, 0);
+#pragma unroll
+            for (int i = 0; i < 16; i += 2) {
+                zfma_c(d0, v[i], q[i]);
+                zfma_c(d1, v[i + 1], q[i + 1]);
+            }
+            const zd d = zscale(zmake(group4_sum(d0.x + d1.x), group4_sum(d0.y + d1.y)), s_tau[c]);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) zfms(q[i], v[i], d);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Ql[(part + 4 * i) + qcol * ldq] = q[i];
+    }
+}
+
 constexpr int kQPer = (64 * 64 + GT - 1) / GT;   // Q elements per thread (2b <= 64)
 
 __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
@@ -712,6 +829,10 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
     zd *Vh = slab2;                                       // [2b][b] reflectors
     const int tpd = min(64, GT / b);                      // threads per trailing column
     const int dcol = tid / tpd, dpart = tid % tpd;
+    if (b == 32) {
+        __syncthreads();
+        ls_qr32(slab, Vh, s_tau, Ql, ldq);
+    } else {
     for (int c = 0; c < b; ++c) {
         if (wave == 0) {
             zd x = (lane >= c && lane < m2) ? slab[lane + c * m2] : zmake(0, 0);
@@ -763,6 +884,7 @@ __global__ __launch_bounds__(GT) void ls_update_kernel(LsArgs a) {
                 for (int r = c + qpart; r < m2; r += tpq) zfms(Qc[r], vc[r], d);
             }
         }
+    }
     }
     __syncthreads();
     zd *Qj = Qs + int64_t(j) * qsz;
