@@ -944,6 +944,7 @@ __global__ __launch_bounds__(GT) void ls_solve_kernel(LsSolveArgs a) {
     zd *yb = acc + cpw * mb;                               // [cpw][b] solved block
     zd *D = yb + cpw * b;                                  // [b][b+1] diagonal block of R
     const int ldd = b + 1;
+    __shared__ zd dinv[64];                                // 1 / D_kk
     for (int e = tid; e < mb * cpw; e += GT) {
         int r = e % mb, c = e / mb;
         acc[r + c * mb] = G[r + int64_t(c0 + c) * ldc];
@@ -954,13 +955,24 @@ __global__ __launch_bounds__(GT) void ls_solve_kernel(LsSolveArgs a) {
             int r = e % b, c = e / b;
             D[r + c * ldd] = R[r0 + r + int64_t(r0 + c) * ldr];
         }
+        if (tid < b) {
+            // 1 / d = conj(d) / |d|^2, all diagonal entries at once
+            const zd d = R[r0 + tid + int64_t(r0 + tid) * ldr];
+            const double s2 = 1.0 / zabs2(d);
+            dinv[tid] = zmake(d.x * s2, -d.y * s2);
+        }
         __syncthreads();
-        // diagonal block: one wave per column, lane = row (b <= 64)
+        // diagonal block: one wave per column, lane = row (b <= 64); the pivot entry of
+        // step k is read out of lane k (wave-uniform) with readlane
         for (int c = wave; c < cpw; c += nwaves) {
             zd v = (lane < b) ? acc[r0 + lane + c * mb] : zmake(0, 0);
             for (int k = b - 1; k >= 0; --k) {
-                zd vk = zmake(__shfl(v.x, k, 64), __shfl(v.y, k, 64));
-                zd yk = zdiv(vk, D[k + k * ldd]);
+                const zd vk = zmake(
+                    __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v.x), k),
+                                     __builtin_amdgcn_readlane(__double2loint(v.x), k)),
+                    __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v.y), k),
+                                     __builtin_amdgcn_readlane(__double2loint(v.y), k)));
+                const zd yk = zmul(vk, dinv[k]);
                 if (lane == k) v = yk;
                 else if (lane < k) zfms(v, D[lane + k * ldd], yk);
             }
@@ -974,11 +986,19 @@ __global__ __launch_bounds__(GT) void ls_solve_kernel(LsSolveArgs a) {
         for (int row = tid; row < r0; row += GT) {
             zd s[8];
             for (int c = 0; c < 8; ++c) s[c] = zmake(0, 0);
-            for (int k = 0; k < b; ++k) {
-                const zd rv = R[row + int64_t(r0 + k) * ldr];
+            // R entries in batches of 8, all loads of a batch issued before its use
+            for (int k0 = 0; k0 < b; k0 += 8) {
+                zd rv[8];
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (c < cpw) zfma(s[c], rv, yb[k + c * b]);
+                for (int u = 0; u < 8; ++u)
+                    rv[u] = (k0 + u < b) ? R[row + int64_t(r0 + k0 + u) * ldr] : zmake(0, 0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (k0 + u >= b) break;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (c < cpw) zfma(s[c], rv[u], yb[k0 + u + c * b]);
+                }
             }
 #pragma unroll
             for (int c = 0; c < 8; ++c)
