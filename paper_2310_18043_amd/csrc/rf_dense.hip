@@ -23,6 +23,39 @@ __device__ inline int64_t bidx(const int *map, int flags, int bit, int t) {
     return (map && (flags & bit)) ? map[t] : t;
 }
 
+// Sums over aligned groups of 8 (or 4) lanes with DPP lane moves (no LDS round trip);
+// every lane of a group ends with the same value.
+__device__ __attribute__((always_inline)) inline double dpp_move(double v, int ctrl_sel) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int olo, ohi;
+    switch (ctrl_sel) {
+        case 0:  // quad_perm [1,0,3,2]: lane xor 1
+            olo = __builtin_amdgcn_update_dpp(lo, lo, 0xB1, 0xF, 0xF, false);
+            ohi = __builtin_amdgcn_update_dpp(hi, hi, 0xB1, 0xF, 0xF, false);
+            break;
+        case 1:  // quad_perm [2,3,0,1]: lane xor 2
+            olo = __builtin_amdgcn_update_dpp(lo, lo, 0x4E, 0xF, 0xF, false);
+            ohi = __builtin_amdgcn_update_dpp(hi, hi, 0x4E, 0xF, 0xF, false);
+            break;
+        default:  // row_half_mirror: lane 7 - i within each group of 8
+            olo = __builtin_amdgcn_update_dpp(lo, lo, 0x141, 0xF, 0xF, false);
+            ohi = __builtin_amdgcn_update_dpp(hi, hi, 0x141, 0xF, 0xF, false);
+            break;
+    }
+    return __hiloint2double(ohi, olo);
+}
+__device__ __attribute__((always_inline)) inline double group4_sum(double v) {
+    v += dpp_move(v, 0);
+    v += dpp_move(v, 1);
+    return v;
+}
+__device__ __attribute__((always_inline)) inline double group8_sum(double v) {
+    v = group4_sum(v);
+    v += dpp_move(v, 2);      // the other quad of the group holds the other half
+    return v;
+}
+
+
 // ---------------------------------------------------------------------------
 // C_part[chunk] = A[rows of chunk]^H B[rows of chunk]   (tile 16 TMV x 16 TNV per WG)
 // grid: (ceil(m / 16 TMV), ceil(k / 16 TNV), batch * nchunks)
@@ -109,23 +142,41 @@ __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
         }
 }
 
-// C = alpha * sum_chunks part + beta * C   (fixed summation order)
+// C = alpha * sum_chunks part + beta * C   (fixed summation order).  Four lanes per
+// output: lane q sums chunks [q P, (q+1) P) in order with all of its reads in flight
+// at once, then the four sums are added in a fixed tree by DPP (the partials were
+// written from every XCD, so each read is a far round trip).
 __global__ void gemm_cn_reduce_kernel(int m, int k, const zd *part, int nchunks, zd alpha,
                                       zd beta, zd *C, int64_t ldc, int64_t sC, int batch,
                                       const int *map, int flags) {
-    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t mk = int64_t(m) * k;
-    if (e >= mk * batch) return;
-    int bt = int(e / mk);
-    int64_t r = e % mk;
-    int mi = int(r % m), kj = int(r / m);
+    const int64_t gt = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t e = gt >> 2;
+    const int q = int(gt & 3);
+    const int64_t mk = int64_t(m) * k;
+    const bool ok = e < mk * batch;          // the same for the four lanes of an output
+    const int64_t ee = ok ? e : 0;
+    const int bt = int(ee / mk);
+    const int64_t r = ee % mk;
+    const int mi = int(r % m), kj = int(r / m);
     const zd *P = part + int64_t(bt) * nchunks * mk + r;
-    zd s = P[0];
-    for (int c = 1; c < nchunks; ++c) s = zadd(s, P[int64_t(c) * mk]);
-    zd *cp = C + bidx(map, flags, kMapC, bt) * sC + mi + int64_t(kj) * ldc;
-    zd out = zmul(alpha, s);
-    if (beta.x != 0.0 || beta.y != 0.0) zfma(out, beta, *cp);
-    *cp = out;
+    const int per = (nchunks + 3) / 4;
+    const int c0 = q * per, c1 = min(nchunks, c0 + per);
+    zd s = zmake(0, 0);
+    for (int c = c0; c < c1; c += 16) {
+        zd t[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) t[u] = (c + u < c1) ? P[int64_t(c + u) * mk] : zmake(0, 0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s = zadd(s, t[u]);
+    }
+    s.x = group4_sum(s.x);
+    s.y = group4_sum(s.y);
+    if (ok && q == 0) {
+        zd *cp = C + bidx(map, flags, kMapC, bt) * sC + mi + int64_t(kj) * ldc;
+        zd out = zmul(alpha, s);
+        if (beta.x != 0.0 || beta.y != 0.0) zfma(out, beta, *cp);
+        *cp = out;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -620,38 +671,6 @@ __device__ inline zd wave_sum(zd v) {
     return v;
 }
 
-// Sums over aligned groups of 8 (or 4) lanes with DPP lane moves (no LDS round trip);
-// every lane of a group ends with the same value.
-__device__ __attribute__((always_inline)) inline double dpp_move(double v, int ctrl_sel) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    int olo, ohi;
-    switch (ctrl_sel) {
-        case 0:  // quad_perm [1,0,3,2]: lane xor 1
-            olo = __builtin_amdgcn_update_dpp(lo, lo, 0xB1, 0xF, 0xF, false);
-            ohi = __builtin_amdgcn_update_dpp(hi, hi, 0xB1, 0xF, 0xF, false);
-            break;
-        case 1:  // quad_perm [2,3,0,1]: lane xor 2
-            olo = __builtin_amdgcn_update_dpp(lo, lo, 0x4E, 0xF, 0xF, false);
-            ohi = __builtin_amdgcn_update_dpp(hi, hi, 0x4E, 0xF, 0xF, false);
-            break;
-        default:  // row_half_mirror: lane 7 - i within each group of 8
-            olo = __builtin_amdgcn_update_dpp(lo, lo, 0x141, 0xF, 0xF, false);
-            ohi = __builtin_amdgcn_update_dpp(hi, hi, 0x141, 0xF, 0xF, false);
-            break;
-    }
-    return __hiloint2double(ohi, olo);
-}
-__device__ __attribute__((always_inline)) inline double group4_sum(double v) {
-    v += dpp_move(v, 0);
-    v += dpp_move(v, 1);
-    return v;
-}
-__device__ __attribute__((always_inline)) inline double group8_sum(double v) {
-    v = group4_sum(v);
-    v += dpp_move(v, 2);      // the other quad of the group holds the other half
-    return v;
-}
-
 // Householder QR of the 2b x b window (b = 32, 256 threads) in registers: thread
 // (column tid / 8, part tid % 8) holds rows part, part + 8, ... of its column.  Per
 // column c the eight threads of column c form the reflector (norm and pivot entry by
@@ -1063,7 +1082,7 @@ hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_
         else RF_CN_LAUNCH(4, 4);
     }
 #undef RF_CN_LAUNCH
-    int64_t tot = int64_t(m) * k * batch;
+    int64_t tot = 4 * int64_t(m) * k * batch;                 // four lanes per output
     hipLaunchKernelGGL(gemm_cn_reduce_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, m, k,
                        work, nchunks, alpha, beta, C, ldc, sC, batch, map, flags);
     return hipGetLastError();
