@@ -1,6 +1,6 @@
 // Dense and sparse block kernels of the composite-rule filter (gfx950):
 //   * tall-skinny complex products V^H W (split over rows, fixed-order reduction)
-//     and W - V H, used by block Gram-Schmidt in the block-Arnoldi process
+//     and W - V H on the FP64 matrix cores, used by block Gram-Schmidt in the block-Arnoldi process
 //     (Sec. 3.2, multi-shift GMRES) and by the projections of HSRR (Sec. 2.1);
 //   * Cholesky of small Gram matrices (CholeskyQR orthonormalisation, the
 //     "orth" of Alg. SIsketch);
@@ -57,23 +57,35 @@ __device__ __attribute__((always_inline)) inline double group8_sum(double v) {
 
 
 // ---------------------------------------------------------------------------
-// C_part[chunk] = A[rows of chunk]^H B[rows of chunk]   (tile 16 TMV x 16 TNV per WG)
-// grid: (ceil(m / 16 TMV), ceil(k / 16 TNV), batch * nchunks)
+// Tall-skinny products on the FP64 matrix cores.
+//   C_part[chunk] = A[rows of chunk]^H B[rows of chunk]     (split over rows, then a
+//   fixed-order reduction; grid (ceil(m / 16 TMB), ceil(k / 16 TNB), batch * nchunks))
+//   C = alpha A B + beta C                                    (64-row tiles)
+// v_mfma_f64_16x16x4f64 takes a 16 x 4 block of A with element (i, k) in lane i + 16 k,
+// a 4 x 16 block of B with element (k, j) in lane j + 16 k, and accumulates the 16 x 16
+// product with element (4 r + l / 16, l % 16) in slot r of lane l.  A complex block
+// product is four real ones, real and imaginary parts accumulated separately; each
+// wave owns 16 x 16 output blocks.  Slabs of TKS rows (columns) go through LDS, the
+// next slab read into registers while the current one is multiplied, so global
+// latency is paid once per chunk.  Output tiles are 32 wide when an operand is one
+// Krylov sub-block (b = 32), so no multiply-add is spent on padding.
 // ---------------------------------------------------------------------------
-// Slabs of TKS rows go through LDS; the next slab is read into registers while the
-// current one is multiplied, so the global-memory latency is paid once per chunk.
-// TMV / TNV: output rows / columns per thread (tile 16 TMV x 16 TNV): 2 when the
-// operand is at most 32 wide (the Krylov sub-block width), so that no multiply-add
-// is spent on padding, else 4.
 constexpr int TKS = 32;
+typedef double dv4 __attribute__((ext_vector_type(4)));
 
-template <int TMV, int TNV>
-__global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
+__device__ __attribute__((always_inline)) inline dv4 mfma_f64(double a, double b, dv4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int TMB, int TNB>
+__global__ __launch_bounds__(GT) void gemm_cn_mfma_kernel(
     int64_t n, int m, int k, const zd *__restrict__ A, int64_t lda, int64_t sA,
     const zd *__restrict__ B, int64_t ldb, int64_t sB, zd *__restrict__ part, int nchunks,
     int64_t chunk, const int *map, int flags) {
-    constexpr int TMT = 16 * TMV, TNT = 16 * TNV;
-    constexpr int LA = TKS * TMT / GT, LB = TKS * TNT / GT;     // slab elements per thread
+    constexpr int TMT = 16 * TMB, TNT = 16 * TNB;
+    constexpr int BPW = TMB * TNB / 4;                          // output blocks per wave
+    constexpr int LA = TKS * TMT / GT, LB = TKS * TNT / GT;
+    static_assert(TMB * TNB % 4 == 0, "four waves share the output blocks");
     const int bt = blockIdx.z / nchunks, ch = blockIdx.z % nchunks;
     const int m0 = blockIdx.x * TMT, k0 = blockIdx.y * TNT;
     A += bidx(map, flags, kMapA, bt) * sA;
@@ -82,7 +94,8 @@ __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
     const int64_t r1 = min(n, r0 + chunk);
     __shared__ zd As[TKS][TMT + 1];
     __shared__ zd Bs[TKS][TNT + 1];
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
     zd ra[LA], rb[LB];
     // rows are the fastest index of a slab element: coalesced column runs
     auto fetch = [&](int64_t rr) __attribute__((always_inline)) {
@@ -99,11 +112,9 @@ __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
             rb[q] = (row < r1 && k0 + c < k) ? B[row + int64_t(k0 + c) * ldb] : zmake(0, 0);
         }
     };
-    zd acc[TMV][TNV];
+    dv4 accR[BPW], accI[BPW];
 #pragma unroll
-    for (int i = 0; i < TMV; ++i)
-#pragma unroll
-        for (int j = 0; j < TNV; ++j) acc[i][j] = zmake(0, 0);
+    for (int t = 0; t < BPW; ++t) { accR[t] = dv4{0, 0, 0, 0}; accI[t] = dv4{0, 0, 0, 0}; }
     if (r0 < r1) fetch(r0);
     for (int64_t rr = r0; rr < r1; rr += TKS) {
 #pragma unroll
@@ -118,28 +129,33 @@ __global__ __launch_bounds__(GT) void gemm_cn_partial_kernel(
         }
         __syncthreads();
         if (rr + TKS < r1) fetch(rr + TKS);
-#pragma unroll 4
-        for (int i = 0; i < TKS; ++i) {
-            zd av[TMV], bv[TNV];
 #pragma unroll
-            for (int u = 0; u < TMV; ++u) av[u] = As[i][ty + 16 * u];
+        for (int ks = 0; ks < TKS / 4; ++ks) {
+            const int row = ks * 4 + lk;
 #pragma unroll
-            for (int v = 0; v < TNV; ++v) bv[v] = Bs[i][tx + 16 * v];
-#pragma unroll
-            for (int u = 0; u < TMV; ++u)
-#pragma unroll
-                for (int v = 0; v < TNV; ++v) zfma_c(acc[u][v], av[u], bv[v]);
+            for (int t = 0; t < BPW; ++t) {
+                const int blk = wave * BPW + t, bi = blk / TNB, bj = blk % TNB;
+                const zd a = As[row][bi * 16 + li];       // conj(A)^T: (i, k) = conj(A[k][i])
+                const zd b = Bs[row][bj * 16 + li];
+                accR[t] = mfma_f64(a.x, b.x, accR[t]);
+                accR[t] = mfma_f64(a.y, b.y, accR[t]);
+                accI[t] = mfma_f64(a.x, b.y, accI[t]);
+                accI[t] = mfma_f64(-a.y, b.x, accI[t]);
+            }
         }
         __syncthreads();
     }
     zd *P = part + (int64_t(bt) * nchunks + ch) * int64_t(m) * k;
 #pragma unroll
-    for (int u = 0; u < TMV; ++u)
+    for (int t = 0; t < BPW; ++t) {
+        const int blk = wave * BPW + t, bi = blk / TNB, bj = blk % TNB;
+        const int kj = k0 + bj * 16 + li;
 #pragma unroll
-        for (int v = 0; v < TNV; ++v) {
-            int mi = m0 + ty + 16 * u, kj = k0 + tx + 16 * v;
-            if (mi < m && kj < k) P[mi + int64_t(kj) * m] = acc[u][v];
+        for (int r = 0; r < 4; ++r) {
+            const int mi = m0 + bi * 16 + 4 * r + lk;
+            if (mi < m && kj < k) P[mi + int64_t(kj) * m] = zmake(accR[t][r], accI[t][r]);
         }
+    }
 }
 
 // C = alpha * sum_chunks part + beta * C   (fixed summation order).  Four lanes per
@@ -179,19 +195,16 @@ __global__ void gemm_cn_reduce_kernel(int m, int k, const zd *part, int nchunks,
     }
 }
 
-// ---------------------------------------------------------------------------
-// C (n x k) = alpha * A (n x m) B (m x k) + beta * C     grid: (ceil(n/64), ceil(k/16 TNV), batch)
-// ---------------------------------------------------------------------------
-// Slabs of TKS columns of A (and rows of B) through LDS, the next slab read into
-// registers while the current one is multiplied.
-template <int TNV>
-__global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd alpha,
-                                                     const zd *__restrict__ A, int64_t lda,
-                                                     int64_t sA, const zd *__restrict__ B,
-                                                     int64_t ldb, int64_t sB, zd beta, zd *C,
-                                                     int64_t ldc, int64_t sC, const int *map,
-                                                     int flags) {
-    constexpr int TNT = 16 * TNV;
+// C (n x k) = alpha A (n x m) B (m x k) + beta C, grid (ceil(n / 64), ceil(k / 16 TNB),
+// batch): wave w owns rows 16 w .. 16 w + 15 of the 64-row tile and all TNB column blocks.
+template <int TNB>
+__global__ __launch_bounds__(GT) void gemm_nn_mfma_kernel(int64_t n, int m, int k, zd alpha,
+                                                          const zd *__restrict__ A, int64_t lda,
+                                                          int64_t sA, const zd *__restrict__ B,
+                                                          int64_t ldb, int64_t sB, zd beta, zd *C,
+                                                          int64_t ldc, int64_t sC, const int *map,
+                                                          int flags) {
+    constexpr int TNT = 16 * TNB;
     constexpr int LA = TKS * TM / GT, LB = TKS * TNT / GT;
     const int bt = blockIdx.z;
     const int64_t n0 = int64_t(blockIdx.x) * TM;
@@ -201,7 +214,8 @@ __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd
     C += bidx(map, flags, kMapC, bt) * sC;
     __shared__ zd As[TKS][TM + 1];
     __shared__ zd Bs[TKS][TNT + 1];
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
     zd ra[LA], rb[LB];
     auto fetch = [&](int kk) __attribute__((always_inline)) {
 #pragma unroll
@@ -216,11 +230,9 @@ __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd
             rb[q] = (kk + i < m && k0 + c < k) ? B[(kk + i) + int64_t(k0 + c) * ldb] : zmake(0, 0);
         }
     };
-    zd acc[4][TNV];
+    dv4 accR[TNB], accI[TNB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < TNV; ++j) acc[i][j] = zmake(0, 0);
+    for (int t = 0; t < TNB; ++t) { accR[t] = dv4{0, 0, 0, 0}; accI[t] = dv4{0, 0, 0, 0}; }
     if (m > 0) fetch(0);
     for (int kk = 0; kk < m; kk += TKS) {
 #pragma unroll
@@ -235,34 +247,36 @@ __global__ __launch_bounds__(GT) void gemm_nn_kernel(int64_t n, int m, int k, zd
         }
         __syncthreads();
         if (kk + TKS < m) fetch(kk + TKS);
-#pragma unroll 4
-        for (int i = 0; i < TKS; ++i) {
-            zd av[4], bv[TNV];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) av[u] = As[i][ty + 16 * u];
+        for (int ks = 0; ks < TKS / 4; ++ks) {
+            const int i = ks * 4 + lk;
+            const zd a = As[i][wave * 16 + li];               // A block (row li, column lk)
 #pragma unroll
-            for (int v = 0; v < TNV; ++v) bv[v] = Bs[i][tx + 16 * v];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < TNV; ++v) zfma(acc[u][v], av[u], bv[v]);
+            for (int t = 0; t < TNB; ++t) {
+                const zd b = Bs[i][t * 16 + li];               // B block (row lk, column li)
+                accR[t] = mfma_f64(a.x, b.x, accR[t]);
+                accR[t] = mfma_f64(-a.y, b.y, accR[t]);
+                accI[t] = mfma_f64(a.x, b.y, accI[t]);
+                accI[t] = mfma_f64(a.y, b.x, accI[t]);
+            }
         }
         __syncthreads();
     }
     const bool use_beta = (beta.x != 0.0 || beta.y != 0.0);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int t = 0; t < TNB; ++t) {
+        const int col = k0 + t * 16 + li;
 #pragma unroll
-        for (int v = 0; v < TNV; ++v) {
-            int64_t row = n0 + ty + 16 * u;
-            int col = k0 + tx + 16 * v;
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = n0 + wave * 16 + 4 * r + lk;
             if (row < n && col < k) {
                 zd *cp = C + row + int64_t(col) * ldc;
-                zd out = zmul(alpha, acc[u][v]);
+                zd out = zmul(alpha, zmake(accR[t][r], accI[t][r]));
                 if (use_beta) zfma(out, beta, *cp);
                 *cp = out;
             }
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1071,8 +1085,8 @@ hipError_t launch_gemm_cn(int64_t n, int m, int k, zd alpha, const zd *A, int64_
     chunk = ((chunk + TK - 1) / TK) * TK;
     nchunks = int((n + chunk - 1) / chunk);
     dim3 grid((m + tm - 1) / tm, (k + tn - 1) / tn, batch * nchunks);
-#define RF_CN_LAUNCH(TMV_, TNV_)                                                                \
-    hipLaunchKernelGGL((gemm_cn_partial_kernel<TMV_, TNV_>), grid, dim3(GT), 0, s, n, m, k, A, lda, \
+#define RF_CN_LAUNCH(TMB_, TNB_)                                                                \
+    hipLaunchKernelGGL((gemm_cn_mfma_kernel<TMB_, TNB_>), grid, dim3(GT), 0, s, n, m, k, A, lda,   \
                        sA, B, ldb, sB, work, nchunks, chunk, map, flags)
     if (tm == 32) {
         if (tn == 32) RF_CN_LAUNCH(2, 2);
@@ -1096,11 +1110,11 @@ hipError_t launch_gemm_nn(int64_t n, int m, int k, zd alpha, const zd *A, int64_
     const int tn = k <= 32 ? 32 : TN;                        // tile width
     dim3 grid(unsigned((n + TM - 1) / TM), (k + tn - 1) / tn, batch);
     if (tn == 32)
-        hipLaunchKernelGGL(gemm_nn_kernel<2>, grid, dim3(GT), 0, s, n, m, k, alpha, A, lda, sA, B,
-                           ldb, sB, beta, C, ldc, sC, map, flags);
+        hipLaunchKernelGGL(gemm_nn_mfma_kernel<2>, grid, dim3(GT), 0, s, n, m, k, alpha, A, lda, sA,
+                           B, ldb, sB, beta, C, ldc, sC, map, flags);
     else
-        hipLaunchKernelGGL(gemm_nn_kernel<4>, grid, dim3(GT), 0, s, n, m, k, alpha, A, lda, sA, B,
-                           ldb, sB, beta, C, ldc, sC, map, flags);
+        hipLaunchKernelGGL(gemm_nn_mfma_kernel<4>, grid, dim3(GT), 0, s, n, m, k, alpha, A, lda, sA,
+                           B, ldb, sB, beta, C, ldc, sC, map, flags);
     return hipGetLastError();
 }
 
