@@ -477,6 +477,68 @@ __global__ __launch_bounds__(kThreads) void tri_inverse_kernel(zd *tiles, int nb
     }
 }
 
+// Register version for NB = 64 or 128: thread (row i = tid % NB, group g = tid / NB)
+// holds columns g CPT .. g CPT + CPT - 1 of row i of X, which starts as the identity.
+// Right-looking substitution: at step r (lower: r = 0 .. NB-1; upper: r = NB-1 .. 0) the
+// owners of row r finish it (upper: scale by 1 / U_rr) and publish it in LDS (double
+// buffered by step parity: one barrier per step), and every row still to be reached
+// subtracts T_ir times it.  Column r of the triangle is read coalesced, eight steps
+// of it at a time.  Row r of X is zero outside the triangle, so the update is taken
+// by every row (times zero where it does not apply).
+template <int NB>
+__global__ __launch_bounds__(4 * NB) void tri_inverse_reg_kernel(zd *tiles, int nblk) {
+    constexpr int CPT = NB / 4, STEPB = 8;
+    const int k = blockIdx.x, pole = blockIdx.y, upper = blockIdx.z;
+    constexpr int64_t te = int64_t(NB) * NB;
+    zd *T = tiles + tile_index(pole, k, upper ? 2 : 0, nblk, te);
+    const int tid = threadIdx.x, i = tid % NB, g = tid / NB, c0 = g * CPT;
+    __shared__ zd xrow[2][NB];
+    __shared__ zd rdiag[NB];
+    zd a[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) a[q] = zmake(c0 + q == i ? 1.0 : 0.0, 0.0);
+    if (upper && tid < NB) {
+        const zd d = T[tid + int64_t(tid) * NB];
+        const double s2 = zabs2(d);
+        rdiag[tid] = (s2 > 0.0) ? zmake(d.x / s2, -d.y / s2) : zmake(0, 0);
+    }
+    __syncthreads();
+    for (int s0 = 0; s0 < NB; s0 += STEPB) {
+        zd tcol[STEPB];
+#pragma unroll
+        for (int u = 0; u < STEPB; ++u) {
+            const int r = upper ? NB - 1 - (s0 + u) : s0 + u;
+            const bool reach = upper ? (i < r) : (i > r);
+            tcol[u] = reach ? T[i + int64_t(r) * NB] : zmake(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < STEPB; ++u) {
+            const int r = upper ? NB - 1 - (s0 + u) : s0 + u;
+            const int par = u & 1;
+            if (i == r) {
+                if (upper) {
+                    const zd rr = rdiag[r];
+#pragma unroll
+                    for (int q = 0; q < CPT; ++q) a[q] = zmul(a[q], rr);
+                }
+#pragma unroll
+                for (int q = 0; q < CPT; ++q) xrow[par][c0 + q] = a[q];
+            }
+            __syncthreads();
+            // row r of X is zero left of r (upper) or right of r (lower): groups whose
+            // columns all lie there skip the update (a group is whole waves)
+            const bool live = upper ? (c0 + CPT - 1 >= r) : (c0 <= r);
+            if (live) {
+#pragma unroll
+                for (int q = 0; q < CPT; ++q) zfms(a[q], tcol[u], xrow[par][c0 + q]);
+            }
+        }
+    }
+    __syncthreads();                       // every read of the triangle is done
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) T[i + int64_t(c0 + q) * NB] = a[q];
+}
+
 // ---------------------------------------------------------------------------
 // solves
 // ---------------------------------------------------------------------------
@@ -899,7 +961,13 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (size_t(nb) * 32 * sizeof(zd) <= size_t(P.max_lds))
+    if (nb == 128)
+        hipLaunchKernelGGL(tri_inverse_reg_kernel<128>, dim3(a.nblk, p, 2), dim3(512), 0, s,
+                           P.F.tiles, a.nblk);
+    else if (nb == 64)
+        hipLaunchKernelGGL(tri_inverse_reg_kernel<64>, dim3(a.nblk, p, 2), dim3(256), 0, s,
+                           P.F.tiles, a.nblk);
+    else if (size_t(nb) * 32 * sizeof(zd) <= size_t(P.max_lds))
         hipLaunchKernelGGL(tri_inverse_kernel<32>, dim3(a.nblk, p, 2), dim3(kThreads),
                            size_t(nb) * 32 * sizeof(zd), s, P.F.tiles, nb, a.nblk);
     else
