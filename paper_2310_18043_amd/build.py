@@ -31,6 +31,9 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
 # per-source flags: the host QZ uses plain complex multiply/divide (its operands
 # are finite; no Annex-G infinity recovery calls in the inner loops)
 EXTRA = {"rf_qz.cpp": ["-fcx-limited-range"]}
+# sources with host code only are compiled as C++ (no device pass), so that host-only
+# attributes such as run-time CPU dispatch are available to them
+HOST_ONLY = {"rf_qz.cpp"}
 
 
 def _obj(src: str) -> str:
@@ -42,8 +45,12 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     procs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
-        # every source includes HIP headers: compile all of them as HIP for gfx950
-        cmd = [HIPCC] + COMMON + DEVICE + EXTRA.get(src, []) + ["-x", "hip", "-c", path, "-o", _obj(src)]
+        # every source includes HIP headers: compile them as HIP for gfx950, host-only ones as C++
+        if src in HOST_ONLY:
+            cmd = [HIPCC] + COMMON + EXTRA.get(src, []) + ["-x", "c++", "-c", path, "-o", _obj(src)]
+        else:
+            cmd = [HIPCC] + COMMON + DEVICE + EXTRA.get(src, []) + ["-x", "hip", "-c", path,
+                                                                    "-o", _obj(src)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,

@@ -1086,7 +1086,17 @@ struct Projected {
     zd *V = nullptr, *AV = nullptr, *BV = nullptr;   // the basis and its products (device)
     std::vector<zd> A, B, al, be, vr;
     int qz_status = 0;
-    void run_qz() { qz_status = host_qz_eig(w, A.data(), B.data(), al.data(), be.data(), vr.data()); }
+    double qz_ms = 0.0;           // host time of the last QZ (reported by RFEIG_TRACE)
+    QzStats qz_stats{};
+    void run_qz() {
+        const auto t0 = std::chrono::steady_clock::now();
+        qz_status = host_qz_eig(w, reinterpret_cast<const double *>(A.data()),
+                                reinterpret_cast<const double *>(B.data()),
+                                reinterpret_cast<double *>(al.data()), reinterpret_cast<double *>(be.data()),
+                                reinterpret_cast<double *>(vr.data()));
+        qz_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        qz_stats = host_qz_last_stats;
+    }
 };
 
 // buf selects one of the plan's two sets of basis buffers (the adaptive solver keeps
@@ -1313,6 +1323,10 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
                 const double t3 = now_ms();
                 if (qz.joinable()) qz.join();
                 fin = hsrr_finish(P, pr, lam, err);
+                if (trace_on())
+                    std::fprintf(stderr, "[rfeig] sweep %d: host QZ %.1f ms (QR %.1f, HT %.1f, QZ %.1f in %d "
+                                         "sweeps, vectors %.1f)\n", t, pr.qz_ms, pr.qz_stats.qr_ms,
+                                 pr.qz_stats.ht_ms, pr.qz_stats.qz_ms, pr.qz_stats.sweeps, pr.qz_stats.vec_ms);
                 decided = true;
                 ms_hsrr += now_ms() - t3;
                 if (fin == RF_OK) converged = judge(t, 0.0);

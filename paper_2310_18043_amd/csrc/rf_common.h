@@ -262,4 +262,4 @@ hipError_t launch_ls_solve(const rf_plan &P, int m, const int *active, int nact,
 
 // host QZ (rf_qz.cpp): eigenvalues and right eigenvectors of the pencil (A, B),
 // both n x n column-major complex; vr gets eigenvectors (columns, unit 2-norm).
-int host_qz_eig(int n, const zd *A, const zd *B, zd *alpha, zd *beta, zd *vr);
+#include "rf_qz.h"

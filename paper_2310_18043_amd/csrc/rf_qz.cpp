@@ -16,11 +16,16 @@
 //   4. lambda_i = S_ii / T_ii; right eigenvectors of the triangular pencil (S, T)
 //      by back substitution, mapped back with Z (= P_R V_R) and normalised.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
+#include <thread>
 #include <vector>
 
-#include "rf_common.h"
+#include <cstddef>
+#include <cstdint>
+
+#include "rf_qz.h"
 
 namespace {
 
@@ -63,13 +68,22 @@ void rot_cols(Mat &M, int i, int k, double c, cd s, int r0, int r1) {
 
 }  // namespace
 
-int host_qz_eig(int n, const zd *Ain, const zd *Bin, zd *alpha_out, zd *beta_out, zd *vr_out) {
+thread_local QzStats host_qz_last_stats;
+
+int host_qz_eig(int n, const double *Ain, const double *Bin, double *alpha_out, double *beta_out,
+                double *vr_out) {
     if (n <= 0) return 0;
+    using clk = std::chrono::steady_clock;
+    auto ms = [](clk::time_point a, clk::time_point b) {
+        return std::chrono::duration<double, std::milli>(b - a).count();
+    };
+    const clk::time_point t0 = clk::now();
     Mat A(n), B(n), Z(n);
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i) {
-            A(i, j) = cd(Ain[i + size_t(j) * n].x, Ain[i + size_t(j) * n].y);
-            B(i, j) = cd(Bin[i + size_t(j) * n].x, Bin[i + size_t(j) * n].y);
+            const size_t e = 2 * (i + size_t(j) * n);
+            A(i, j) = cd(Ain[e], Ain[e + 1]);
+            B(i, j) = cd(Bin[e], Bin[e + 1]);
             Z(i, j) = (i == j) ? 1.0 : 0.0;
         }
     const double eps = 2.220446049250313e-16;
@@ -100,6 +114,7 @@ int host_qz_eig(int n, const zd *Ain, const zd *Bin, zd *alpha_out, zd *beta_out
         apply(A);
         for (int i = k + 1; i < n; ++i) B(i, k) = 0.0;
     }
+    const clk::time_point t1 = clk::now();
     // 2. Hessenberg-triangular reduction
     for (int j = 0; j < n - 2; ++j) {
         for (int i = n - 1; i >= j + 2; --i) {
@@ -117,6 +132,7 @@ int host_qz_eig(int n, const zd *Ain, const zd *Bin, zd *alpha_out, zd *beta_out
             rot_cols(Z, i, i - 1, c, s, 0, n);
         }
     }
+    const clk::time_point t2 = clk::now();
     // 3. QZ iterations
     double anorm = 0.0, bnorm = 0.0;
     for (int j = 0; j < n; ++j)
@@ -181,42 +197,59 @@ int host_qz_eig(int n, const zd *Ain, const zd *Bin, zd *alpha_out, zd *beta_out
             if (k + 1 < hi) { f = A(k + 1, k); g = A(k + 2, k); }
         }
     }
+    const clk::time_point t3 = clk::now();
     // 4. eigenvalues and right eigenvectors
     for (int i = 0; i < n; ++i) {
-        alpha_out[i] = zmake(A(i, i).real(), A(i, i).imag());
-        beta_out[i] = zmake(B(i, i).real(), B(i, i).imag());
+        alpha_out[2 * i] = A(i, i).real(); alpha_out[2 * i + 1] = A(i, i).imag();
+        beta_out[2 * i] = B(i, i).real(); beta_out[2 * i + 1] = B(i, i).imag();
     }
     const double small = eps * std::max(anorm, bnorm);
-    std::vector<cd> y(n);
-    for (int i = 0; i < n; ++i) {
-        cd al = A(i, i), be = B(i, i);
-        std::fill(y.begin(), y.end(), cd(0.0));
-        y[i] = 1.0;
-        for (int k = i - 1; k >= 0; --k) {
-            cd sum = 0.0;
-            for (int j = k + 1; j <= i; ++j) sum += (be * A(k, j) - al * B(k, j)) * y[j];
-            cd d = be * A(k, k) - al * B(k, k);
-            if (std::abs(d) < small) d = small;
-            y[k] = -sum / d;
+    // the eigenvectors are independent: a few host threads take every nt-th of them
+    auto vectors = [&](int first, int stride) {
+        std::vector<cd> y(n), x(n);
+        for (int i = first; i < n; i += stride) {
+            cd al = A(i, i), be = B(i, i);
+            std::fill(y.begin(), y.end(), cd(0.0));
+            y[i] = 1.0;
+            for (int k = i - 1; k >= 0; --k) {
+                cd sum = 0.0;
+                for (int j = k + 1; j <= i; ++j) sum += (be * A(k, j) - al * B(k, j)) * y[j];
+                cd d = be * A(k, k) - al * B(k, k);
+                if (std::abs(d) < small) d = small;
+                y[k] = -sum / d;
+            }
+            double nrm2 = 0.0;
+            for (int r = 0; r < n; ++r) {
+                cd acc = 0.0;
+                for (int j = 0; j <= i; ++j) acc += Z(r, j) * y[j];
+                x[r] = acc;
+                nrm2 += std::norm(acc);
+            }
+            double inv = nrm2 > 0.0 ? 1.0 / std::sqrt(nrm2) : 0.0;
+            for (int r = 0; r < n; ++r) {
+                vr_out[2 * (r + size_t(i) * n)] = x[r].real() * inv;
+                vr_out[2 * (r + size_t(i) * n) + 1] = x[r].imag() * inv;
+            }
         }
-        double nrm2 = 0.0;
-        std::vector<cd> x(n, 0.0);
-        for (int r = 0; r < n; ++r) {
-            cd acc = 0.0;
-            for (int j = 0; j <= i; ++j) acc += Z(r, j) * y[j];
-            x[r] = acc;
-            nrm2 += std::norm(acc);
+    };
+    const int nt = n >= 64 ? 4 : 1;
+    std::vector<std::thread> helpers;
+    for (int t = 1; t < nt; ++t) {
+        try {
+            helpers.emplace_back(vectors, t, nt);
+        } catch (...) {
+            vectors(t, nt);               // no thread: do its share here
         }
-        double inv = nrm2 > 0.0 ? 1.0 / std::sqrt(nrm2) : 0.0;
-        for (int r = 0; r < n; ++r) vr_out[r + size_t(i) * n] = zmake(x[r].real() * inv, x[r].imag() * inv);
     }
+    vectors(0, nt);
+    for (std::thread &h : helpers) h.join();
+    const clk::time_point t4 = clk::now();
+    host_qz_last_stats = QzStats{ms(t0, t1), ms(t1, t2), ms(t2, t3), ms(t3, t4), total};
     return 0;
 }
 
 extern "C" int rf_dense_eig(int32_t n, const double *A, const double *B, double *alpha, double *beta,
                             double *vr) {
     if (n < 0 || (n > 0 && (!A || !B || !alpha || !beta || !vr))) return -2;
-    return host_qz_eig(n, reinterpret_cast<const zd *>(A), reinterpret_cast<const zd *>(B),
-                       reinterpret_cast<zd *>(alpha), reinterpret_cast<zd *>(beta),
-                       reinterpret_cast<zd *>(vr));
+    return host_qz_eig(n, A, B, alpha, beta, vr);
 }
