@@ -588,8 +588,9 @@ __device__ inline zd to_zd(zf v) { return zmake(double(v.x), double(v.y)); }
 // batches held in two register buffers, and as soon as a batch has been consumed
 // the batch two places further down the sequence is requested, so the next
 // product's loads are in flight across the reductions and barriers of the current
-// one.  The workgroups of a pole also touch the next block's tiles so that they are
-// in L2.
+// one.  Where registers allow, the entries of v that a batch multiplies are read
+// from LDS one batch ahead too, so the multiply-adds do not wait on LDS latency.
+// The workgroups of a pole also touch the next block's tiles so that they are in L2.
 constexpr int kSolveThreads = 512;
 
 template <int NB>
@@ -667,6 +668,75 @@ __device__ __attribute__((always_inline)) inline void run_phase(
         if (bp + 3 < SH::NBAT) issue_batch<NB, SC, CT>(tcur, bp + 3, bufB);
         else issue_batch<NB, SN, CT>(tnext, bp + 3 - SH::NBAT, bufB);
     }
+}
+
+// the entries of v that batch b of a tile piece multiplies: columns j G + g for the
+// batch's S / R values of j
+template <int CW, int NB, typename CT>
+__device__ __attribute__((always_inline)) inline void load_v(
+        int g, int b, const CT *v, CT (&vb)[SolveShape<NB>::S / SolveShape<NB>::R][CW]) {
+    using SH = SolveShape<NB>;
+    constexpr int JB = SH::S / SH::R;
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) {
+        const CT *vr = v + ((b * SH::S) / SH::R + jj) * SH::G * CW + g * CW;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) vb[jj][c] = vr[c];
+    }
+}
+
+// consume with the batch's entries of v already in registers
+template <int CW, int NB, int SHAPE, typename CT>
+__device__ __attribute__((always_inline)) inline void consume_v(
+        int b, const CT (&t)[SolveShape<NB>::S],
+        const CT (&vb)[SolveShape<NB>::S / SolveShape<NB>::R][CW],
+        CT (&acc)[SolveShape<NB>::R][CW]) {
+    using SH = SolveShape<NB>;
+#pragma unroll
+    for (int e = 0; e < SH::S; ++e) {
+        const int E = b * SH::S + e, j = E / SH::R, q = E % SH::R;
+        if (piece_zero<NB, SHAPE>(q, j)) continue;
+        const int jj = j - (b * SH::S) / SH::R;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) zfma(acc[q][c], t[e], vb[jj][c]);
+    }
+}
+
+// run_phase with the entries of v read one batch ahead into two register sets
+template <int CW, int NB, int SC, int SN, typename CT>
+__device__ __attribute__((always_inline)) inline void run_phase_vpre(
+        int g, CT (&bufA)[SolveShape<NB>::S], CT (&bufB)[SolveShape<NB>::S],
+        CT (&acc)[SolveShape<NB>::R][CW], const CT *v, const CT *tcur, const CT *tnext) {
+    using SH = SolveShape<NB>;
+    constexpr int JB = SH::S / SH::R;
+    static_assert(SH::S % SH::R == 0, "batch covers whole columns");
+    CT vA[JB][CW], vB[JB][CW];
+    load_v<CW, NB, CT>(g, 0, v, vA);
+    load_v<CW, NB, CT>(g, 1, v, vB);
+#pragma unroll
+    for (int bp = 0; bp < SH::NBAT; bp += 2) {
+        consume_v<CW, NB, SC, CT>(bp, bufA, vA, acc);
+        if (bp + 2 < SH::NBAT) issue_batch<NB, SC, CT>(tcur, bp + 2, bufA);
+        else issue_batch<NB, SN, CT>(tnext, bp + 2 - SH::NBAT, bufA);
+        if (bp + 2 < SH::NBAT) load_v<CW, NB, CT>(g, bp + 2, v, vA);
+        consume_v<CW, NB, SC, CT>(bp + 1, bufB, vB, acc);
+        if (bp + 3 < SH::NBAT) issue_batch<NB, SC, CT>(tcur, bp + 3, bufB);
+        else issue_batch<NB, SN, CT>(tnext, bp + 3 - SH::NBAT, bufB);
+        if (bp + 3 < SH::NBAT) load_v<CW, NB, CT>(g, bp + 3, v, vB);
+    }
+}
+
+// The tile products of the solve: the v-prefetching form where its two register
+// sets fit beside the accumulators (complex128 up to two columns, complex64 up to
+// four), the plain form otherwise.
+template <int CW, int NB, int SC, int SN, typename CT>
+__device__ __attribute__((always_inline)) inline void tile_product(
+        int g, CT (&bufA)[SolveShape<NB>::S], CT (&bufB)[SolveShape<NB>::S],
+        CT (&acc)[SolveShape<NB>::R][CW], const CT *v, const CT *tcur, const CT *tnext) {
+    if constexpr (CW * sizeof(CT) <= 32)
+        run_phase_vpre<CW, NB, SC, SN, CT>(g, bufA, bufB, acc, v, tcur, tnext);
+    else
+        run_phase<CW, NB, SC, SN, CT>(g, bufA, bufB, acc, v, tcur, tnext);
 }
 
 template <int CW, int NB, typename CT>
@@ -800,8 +870,8 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         }
         __syncthreads();
         zero_acc();
-        run_phase<CW, NB, kLower, kFull, CT>(g, bufA, bufB, acc, win2, tile_at(k, 0),
-                                         tile_at(k, 1));          // y_k = Linv w_top
+        tile_product<CW, NB, kLower, kFull, CT>(g, bufA, bufB, acc, win2, tile_at(k, 0),
+                                                tile_at(k, 1));          // y_k = Linv w_top
         reduce_rows<CW, NB, CT>(acc);
         if (writer) {
 #pragma unroll
@@ -817,8 +887,8 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         __syncthreads();
         zero_acc();
         // next: Linv_{k+1}, or U1 of the last block to start the backward sweep
-        run_phase<CW, NB, kFull, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 1),
-                                        last ? tile_at(k, 3) : tile_at(k + 1, 0));   // t_{k+1} = w_bot - L21 y_k
+        tile_product<CW, NB, kFull, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 1),
+                                               last ? tile_at(k, 3) : tile_at(k + 1, 0));   // t_{k+1} = w_bot - L21 y_k
         reduce_rows<CW, NB, CT>(acc);
         if (writer && !last) {
 #pragma unroll
@@ -859,8 +929,10 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         touch(tiles + int64_t(max(k - 1, 0)) * 5 * te + 2 * te, 3 * te);   // Uinv, U1, U2 of k-1
         // v = y_k - U1 x_{k+1} - U2 x_{k+2}
         zero_acc();
-        run_phase<CW, NB, kFull, kLower, CT>(g, bufA, bufB, acc, xk1, tile_at(k, 3), tile_at(k, 4));
-        run_phase<CW, NB, kLower, kUpper, CT>(g, bufA, bufB, acc, xk2, tile_at(k, 4), tile_at(k, 2));
+        tile_product<CW, NB, kFull, kLower, CT>(g, bufA, bufB, acc, xk1, tile_at(k, 3),
+                                                tile_at(k, 4));
+        tile_product<CW, NB, kLower, kUpper, CT>(g, bufA, bufB, acc, xk2, tile_at(k, 4),
+                                                 tile_at(k, 2));
         reduce_rows<CW, NB, CT>(acc);
         if (writer) {
 #pragma unroll
@@ -872,8 +944,8 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         }
         __syncthreads();
         zero_acc();
-        run_phase<CW, NB, kUpper, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 2),
-                                         tile_at(max(k - 1, 0), 3));   // x_k = Uinv v
+        tile_product<CW, NB, kUpper, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 2),
+                                                tile_at(max(k - 1, 0), 3));   // x_k = Uinv v
         reduce_rows<CW, NB, CT>(acc);
         if (writer) {
 #pragma unroll
