@@ -96,6 +96,27 @@ def test_inner_apply_tile_override_and_column_slices(rf, torch_cuda):
         assert _relerr(Z, ref) <= 1e-12, (tile, cols)
 
 
+@pytest.mark.parametrize("tile", [64, 128])
+def test_inner_apply_slice_width_agreement(rf, torch_cuda, tile):
+    # each right-hand side of a solve workgroup accumulates the same tile elements in
+    # the same order whatever the slice width, so 1, 2 and 4 columns per workgroup
+    # (the v-prefetching products at 1 and 2, the plain ones at 4) agree to rounding
+    # (not bit for bit: the compiler may contract the complex weight and mass products
+    # into fused multiply-adds differently in each instantiation)
+    A, B = W.convdiff_pencil(33, mass=(0.5, 1.5), seed=4)           # N = 1089: ragged last block
+    X = torch_cuda.from_numpy(W.start_block(A.shape[0], 13, seed=5)).cuda()   # ragged slices
+    out = []
+    for cols in (1, 2, 4):
+        _say(f"inner_apply tile={tile} trsm_cols={cols} (agreement across slice widths)")
+        plan = rf.Plan(A, B, 3000 + 0.05j, 400.0, p=3, q=4, w=24, tile=tile, trsm_cols=cols)
+        plan.factor_shifts()
+        out.append(_to_host(plan.apply_inner(X)))
+        plan.close()
+    d = [_relerr(out[i], out[0]) for i in (1, 2)]
+    _say(f"  relative differences vs one column per workgroup: {d[0]:.1e}, {d[1]:.1e}")
+    assert max(d) <= 1e-14, d
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_inner_apply_tile_256(rf, torch_cuda, precision):
     # the largest tile: 16-column factorization sub-steps (LDS), four rows per solve
