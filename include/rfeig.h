@@ -29,6 +29,7 @@
 #ifndef RFEIG_H
 #define RFEIG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -108,6 +109,27 @@ typedef struct {
 
 typedef struct rf_plan *rf_plan_t;
 
+/* Device-memory callbacks through which a plan or batch obtains ALL of its device
+ * memory: band factors, Krylov basis, work and scratch buffers (the storage that the
+ * pre-factorization loop and the filter of Alg. composite need besides the caller's
+ * blocks).  A caller that manages device memory itself (e.g. PyTorch's caching
+ * allocator) passes its own; NULL selects hipMalloc / hipFree.
+ *   alloc(bytes, ctx): device memory of at least `bytes` bytes on the current device,
+ *       aligned to at least 16 bytes, or NULL on failure (the call then returns
+ *       RF_ERR_NOMEM).  Called only inside rf_plan_create / rf_batch_create /
+ *       rf_plan_create_adjoint, from the calling thread.
+ *   free(ptr, ctx): returns one pointer obtained from alloc.  Called only inside
+ *       rf_plan_destroy / rf_batch_destroy (and on creation failure), from the calling
+ *       thread, after the plan's streams have drained, so the memory may be reused
+ *       at once.
+ * The struct is copied; the callbacks and ctx must stay valid until the plan (or
+ * batch) is destroyed.  Pinned host staging buffers are not routed through it. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} rf_allocator;
+
 /* Defaults: p = 4, q = 8, w = 32, tau = 1e-10, tau_g = 1e-2, gmres_tol = 1e-12,
  * max_subspace_it = 10, max_krylov_blocks = 150, sigma = c, seed = 0, q_max = 0. */
 void rf_default_opts(rf_opts *opts);
@@ -115,10 +137,11 @@ void rf_default_opts(rf_opts *opts);
 /* Copy the pencil to the device, compute the trapezoidal poles/weights of the
  * inner rule (eq. pwtp, Sec. 2.2) and the outer shifts/weights (Thm. Rcrm,
  * Sec. 5), size the band tiles from the band extents of pattern(A) and
- * pattern(B), and allocate every device buffer the plan will use.
- * hip_stream: a hipStream_t (NULL = the null stream). */
+ * pattern(B), and allocate every device buffer the plan will use, through
+ * `allocator` (NULL = hipMalloc).  hip_stream: a hipStream_t (NULL = the null
+ * stream).  On failure *out may still be set: read rf_last_error, then destroy it. */
 rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
-                         void *hip_stream, rf_plan_t *out);
+                         const rf_allocator *allocator, void *hip_stream, rf_plan_t *out);
 
 /* Band LU with partial pivoting of K_i = p_i B - A for the p inner poles
  * (Alg. composite, the pre-factorization loop).  RF_ERR_SINGULAR on an exact
@@ -133,15 +156,17 @@ rf_status rf_apply_inner(rf_plan_t plan, const void *X, int64_t ldx, int32_t nco
 /* U = R_{c,r,pq}(B^{-1}A) Y = sum_j c'_j (G - s_j I)^{-1} G(Y)   (eq. linearsolve1abs)
  * by block multi-shift GMRES on one shared Krylov basis.  The sign of c'_j is
  * the one for which the sum equals +R_{c,r,pq} (the proof of Thm. Rcrm).
- * ncols must equal the plan's w.  info may be NULL. */
+ * ncols must equal the plan's w.  info may be NULL.  RF_ERR_ARG if an entry of Y
+ * is not finite; RF_ERR_NOCONV (U still written, info->converged = 0) if a column
+ * misses gmres_tol within max_krylov_blocks steps. */
 rf_status rf_filter_apply(rf_plan_t plan, const void *Y, int64_t ldy, int32_t ncols,
                           void *U, int64_t ldu, rf_filter_info *info);
 
 /* Alg. composite: subspace iteration with the composite filter and HSRR
  * (Sec. 2.1) until the filtered count is stable and every filtered error is
- * <= tau.  Y0: device n x w start block (NULL = seeded Gaussian).  Calls
- * rf_factor_shifts first if it has not run.  RF_ERR_NOCONV if the sweep cap
- * is reached (results still filled in). */
+ * <= tau.  Y0: device n x w start block (NULL = seeded Gaussian; RF_ERR_ARG if an
+ * entry is not finite).  Calls rf_factor_shifts first if it has not run.
+ * RF_ERR_NOCONV if the sweep cap is reached (results still filled in). */
 rf_status rf_solve_region(rf_plan_t plan, const void *Y0, int64_t ldy, rf_result *res);
 
 /* Alg. composite2 (Sec. 3.2): the composite filter without subspace iteration.
@@ -242,11 +267,12 @@ typedef struct rf_batch *rf_batch_t;
 /* opts: host array of ndisks option sets, one per disk (its own c, r, p, q, w,
  * tolerances); every entry must give the same tile (0 = automatic).  The device
  * memory is the factor storage of sum_d p_d poles plus each disk's Krylov and
- * HSRR buffers; the library creates one non-blocking stream per disk and runs
+ * HSRR buffers, all obtained through `allocator` (NULL = hipMalloc); the library
+ * creates one non-blocking stream per disk and runs
  * the factorization on hip_stream.  On failure *out may still be set: read
  * rf_batch_last_error, then rf_batch_destroy it. */
 rf_status rf_batch_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts, int32_t ndisks,
-                          void *hip_stream, rf_batch_t *out);
+                          const rf_allocator *allocator, void *hip_stream, rf_batch_t *out);
 
 /* Factorize K_i = p_i B - A for every pole of every disk (the disks' step 2 of
  * Alg. composite, batched).  RF_ERR_SINGULAR names the first disk with an exactly

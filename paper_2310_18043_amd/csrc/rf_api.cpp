@@ -35,11 +35,24 @@ rf_status dalloc(rf_plan *P, T **ptr, size_t count) {
     *ptr = nullptr;
     if (count == 0) return RF_OK;
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return rf_fail(P, RF_ERR_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
-                                            " bytes failed: " + hipGetErrorString(e));
+    const size_t bytes = count * sizeof(T);
+    if (P->alloc.alloc) {
+        p = P->alloc.alloc(bytes, P->alloc.ctx);
+        if (!p)
+            return rf_fail(P, RF_ERR_NOMEM, "the caller's allocator returned no memory for " +
+                                                std::to_string(bytes) + " bytes");
+        if (reinterpret_cast<uintptr_t>(p) % 16 != 0) {
+            P->alloc.free(p, P->alloc.ctx);
+            return rf_fail(P, RF_ERR_NOMEM, "the caller's allocator returned memory aligned to "
+                                            "less than 16 bytes");
+        }
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return rf_fail(P, RF_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) +
+                                                " bytes failed: " + hipGetErrorString(e));
+        }
     }
     P->allocations.push_back(p);
     P->device_bytes += int64_t(count * sizeof(T));
@@ -216,7 +229,10 @@ void rf_plan_destroy(rf_plan_t plan) {
     if (!plan) return;
     if (!plan->broken) (void)hipStreamSynchronize(plan->stream);
     plan->prof.release();
-    for (void *p : plan->allocations) (void)hipFree(p);
+    for (void *p : plan->allocations) {
+        if (plan->alloc.alloc) plan->alloc.free(p, plan->alloc.ctx);
+        else (void)hipFree(p);
+    }
     if (plan->h_pinned_int) (void)hipHostFree(plan->h_pinned_int);
     if (plan->h_stage) (void)hipHostFree(plan->h_stage);
     delete plan;
@@ -230,10 +246,11 @@ namespace {
 // starting at pole `pole_offset` (batched disks); poles != null: factor exactly these
 // poles instead of the disk's trapezoidal nodes (the batch's factor owner).
 rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
-                           void *hip_stream, rf_plan_t *out, const rf_plan *owner,
-                           int pole_offset, const std::vector<zd> *poles) {
+                           const rf_allocator *allocator, void *hip_stream, rf_plan_t *out,
+                           const rf_plan *owner, int pole_offset, const std::vector<zd> *poles) {
     if (!out) return RF_ERR_ARG;
     *out = nullptr;
+    if (allocator && (!allocator->alloc || !allocator->free)) return RF_ERR_ARG;
     if (!opts || !csr_ok(A) || !csr_ok(B) || A->n != B->n) return RF_ERR_ARG;
     const rf_opts &o = *opts;
     if (!(o.r > 0.0) || !std::isfinite(o.c_re) || !std::isfinite(o.c_im) || !std::isfinite(o.r))
@@ -251,6 +268,7 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
     if (o.precision < 0 || o.precision > 1) return RF_ERR_ARG;
 
     rf_plan *P = new rf_plan();
+    if (allocator) P->alloc = *allocator;
     P->opts = o;
     P->n = A->n;
     P->stream = static_cast<hipStream_t>(hip_stream);
@@ -467,8 +485,8 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
 extern "C" {
 
 rf_status rf_plan_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
-                         void *hip_stream, rf_plan_t *out) {
-    return plan_create_impl(A, B, opts, hip_stream, out, nullptr, 0, nullptr);
+                         const rf_allocator *allocator, void *hip_stream, rf_plan_t *out) {
+    return plan_create_impl(A, B, opts, allocator, hip_stream, out, nullptr, 0, nullptr);
 }
 
 rf_status rf_factor_shifts(rf_plan_t P) {
@@ -1029,6 +1047,23 @@ rf_status filter_core_residual(rf_plan *P, const zd *X, int64_t ldx,
     return K.converged ? RF_OK : RF_ERR_NOCONV;
 }
 
+// RF_ERR_ARG unless every entry of the caller's n x k block (k <= w) is finite: its
+// column 2-norms, formed on the device and read back, must all be finite (a column
+// whose norm overflows counts as non-finite too).
+rf_status check_block_finite(rf_plan *P, const zd *X, int64_t ldx, int k, const char *what) {
+    if (k <= 0) return RF_OK;
+    std::vector<double> nrm(k);
+    Readback rb(P, P->stream);
+    RF_HIP(P, launch_colnorms(P->n, k, X, ldx, nullptr, 0, nullptr, P->herr, P->stream));
+    RF_HIP(P, rb.read(nrm.data(), P->herr, sizeof(double) * k));
+    RF_HIP(P, rb.sync());
+    for (int c = 0; c < k; ++c)
+        if (!std::isfinite(nrm[c]))
+            return rf_fail(P, RF_ERR_ARG, std::string(what) + ": column " + std::to_string(c) +
+                                              " has a non-finite entry");
+    return RF_OK;
+}
+
 }  // namespace
 
 rf_status rf_filter_apply(rf_plan_t P, const void *Y, int64_t ldy, int32_t ncols, void *U,
@@ -1038,6 +1073,7 @@ rf_status rf_filter_apply(rf_plan_t P, const void *Y, int64_t ldy, int32_t ncols
     if (!P->F.ready) return rf_fail(P, RF_ERR_STATE, "rf_factor_shifts has not succeeded");
     if (!Y || !U || ncols != P->opts.w || ldy < P->n || ldu < P->n)
         return rf_fail(P, RF_ERR_ARG, "bad block arguments (ncols must equal w)");
+    RF_TRY(check_block_finite(P, static_cast<const zd *>(Y), ldy, ncols, "Y"));
     return filter_core(P, static_cast<const zd *>(Y), ldy, static_cast<zd *>(U), ldu, info);
 }
 
@@ -1231,6 +1267,7 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
     if (!res || !res->lambda || !res->X || !res->err || !res->flags || res->ldx < P->n)
         return rf_fail(P, RF_ERR_ARG, "bad result buffers");
     if (Y0 && ldy < P->n) return rf_fail(P, RF_ERR_ARG, "bad start block");
+    if (Y0) RF_TRY(check_block_finite(P, static_cast<const zd *>(Y0), ldy, P->opts.w, "Y0"));
     if (!P->F.ready) RF_TRY(rf_factor_shifts(P));
     hipStream_t s = P->stream;
     const int64_t n = P->n;
@@ -1311,6 +1348,11 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
             ms_hsrr += now_ms() - t2;
             std::atomic<bool> qz_done{false};
             std::thread qz;
+            // joins the QZ thread on every way out of this sweep, early error returns included
+            struct Joiner {
+                std::thread &th;
+                ~Joiner() { if (th.joinable()) th.join(); }
+            } qz_joiner{qz};
             try {
                 qz = std::thread([&] { pr.run_qz(); qz_done.store(true, std::memory_order_release); });
             } catch (...) {                    // no thread: run the QZ here
@@ -1370,6 +1412,7 @@ rf_status rf_solve_region_adaptive(rf_plan_t P, const void *Y0, int64_t ldy, rf_
         return rf_fail(P, RF_ERR_ARG, "q_max of the plan must be at least q");
     if (P->opts.precision != 0)
         return rf_fail(P, RF_ERR_ARG, "the precision form needs the subspace iteration (rf_solve_region)");
+    if (Y0) RF_TRY(check_block_finite(P, static_cast<const zd *>(Y0), ldy, P->opts.w, "Y0"));
     if (!P->F.ready) RF_TRY(rf_factor_shifts(P));
     hipStream_t s = P->stream;
     const int64_t n = P->n;
@@ -1434,6 +1477,7 @@ rf_status rf_solve_region_adaptive(rf_plan_t P, const void *Y0, int64_t ldy, rf_
             }
         }
         void wait() { if (th.joinable()) th.join(); }
+        ~Flight() { wait(); }             // never leaves a joinable thread behind
     };
     Flight fl[2];
     out = level_filter(0);
@@ -1605,9 +1649,10 @@ void batch_free(rf_batch *Bt) {
 extern "C" {
 
 rf_status rf_batch_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts, int32_t ndisks,
-                          void *hip_stream, rf_batch_t *out) {
+                          const rf_allocator *allocator, void *hip_stream, rf_batch_t *out) {
     if (!out) return RF_ERR_ARG;
     *out = nullptr;
+    if (allocator && (!allocator->alloc || !allocator->free)) return RF_ERR_ARG;
     if (!opts || ndisks < 1 || !csr_ok(A) || !csr_ok(B) || A->n != B->n) return RF_ERR_ARG;
     int64_t ptot = 0;
     for (int d = 0; d < ndisks; ++d) {
@@ -1639,7 +1684,7 @@ rf_status rf_batch_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
     oo.w = 1;
     oo.subblock = 0;
     oo.max_krylov_blocks = 1;
-    rf_status st = plan_create_impl(A, B, &oo, hip_stream, &Bt->owner, nullptr, 0, &poles);
+    rf_status st = plan_create_impl(A, B, &oo, allocator, hip_stream, &Bt->owner, nullptr, 0, &poles);
     if (st != RF_OK) {
         return fail(batch_fail(Bt, st, std::string("factor storage: ") +
                                            (Bt->owner ? Bt->owner->last_error : rf_status_str(st))));
@@ -1653,7 +1698,7 @@ rf_status rf_batch_create(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
         }
         Bt->streams.push_back(s);
         rf_plan *P = nullptr;
-        st = plan_create_impl(A, B, &opts[d], s, &P, Bt->owner, off, nullptr);
+        st = plan_create_impl(A, B, &opts[d], allocator, s, &P, Bt->owner, off, nullptr);
         if (P) Bt->disks.push_back(P);
         if (st != RF_OK) {
             return fail(batch_fail(Bt, st, "disk " + std::to_string(d) + ": " +
@@ -1832,7 +1877,8 @@ rf_status rf_plan_create_adjoint(rf_plan_t P, void *hip_stream, rf_plan_t *out) 
     rf_opts o = P->opts;
     o.c_im = -o.c_im;
     if (!std::isnan(o.sigma_re)) o.sigma_im = -o.sigma_im;
-    return plan_create_impl(&Ah, &Bh, &o, hip_stream, out, nullptr, 0, nullptr);
+    return plan_create_impl(&Ah, &Bh, &o, P->alloc.alloc ? &P->alloc : nullptr, hip_stream, out,
+                            nullptr, 0, nullptr);
 }
 
 rf_status rf_eig_vjp(rf_plan_t P, int32_t s, const double *lambda, const void *X, int64_t ldx,

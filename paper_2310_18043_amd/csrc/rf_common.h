@@ -155,6 +155,7 @@ struct rf_plan {
     double *herr = nullptr;   // w
     int64_t device_bytes = 0;
     std::vector<void *> allocations;
+    rf_allocator alloc{};         // caller's device-memory callbacks (alloc == NULL: hipMalloc)
     std::string last_error;
     bool broken = false;
     bool shared_factors = false;  // F.tiles/perm/info belong to a batch's factor owner

@@ -69,6 +69,14 @@ class RfKernelStats(ctypes.Structure):
 
 
 _P = ctypes.c_void_p
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class RfAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
 _lib.rf_profile_enable.argtypes = [_P, ctypes.c_int32]
 _lib.rf_profile_enable.restype = ctypes.c_int
 _lib.rf_profile_read.argtypes = [_P, ctypes.POINTER(RfKernelStats)]
@@ -76,7 +84,8 @@ _lib.rf_profile_read.restype = ctypes.c_int
 _lib.rf_default_opts.argtypes = [ctypes.POINTER(RfOpts)]
 _lib.rf_default_opts.restype = None
 _lib.rf_plan_create.argtypes = [ctypes.POINTER(RfCsr), ctypes.POINTER(RfCsr),
-                                ctypes.POINTER(RfOpts), _P, ctypes.POINTER(_P)]
+                                ctypes.POINTER(RfOpts), ctypes.POINTER(RfAllocator), _P,
+                                ctypes.POINTER(_P)]
 _lib.rf_plan_create.restype = ctypes.c_int
 _lib.rf_factor_shifts.argtypes = [_P]
 _lib.rf_factor_shifts.restype = ctypes.c_int
@@ -109,7 +118,8 @@ _lib.rf_eig_vjp.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c
                             ctypes.c_int64, _P, _P, _P, _P, _P]
 _lib.rf_eig_vjp.restype = ctypes.c_int
 _lib.rf_batch_create.argtypes = [ctypes.POINTER(RfCsr), ctypes.POINTER(RfCsr),
-                                 ctypes.POINTER(RfOpts), ctypes.c_int32, _P, ctypes.POINTER(_P)]
+                                 ctypes.POINTER(RfOpts), ctypes.c_int32,
+                                 ctypes.POINTER(RfAllocator), _P, ctypes.POINTER(_P)]
 _lib.rf_batch_create.restype = ctypes.c_int
 _lib.rf_batch_factor.argtypes = [_P]
 _lib.rf_batch_factor.restype = ctypes.c_int
@@ -175,6 +185,55 @@ def _ld(X) -> int:
     return int(X.stride(1)) if X.dim() == 2 and X.shape[1] > 1 else int(X.shape[0])
 
 
+class TorchAllocator:
+    """rf_allocator callbacks backed by PyTorch's caching allocator, so that every
+    device buffer of a plan is torch memory (counted by torch.cuda.memory_allocated)
+    and is returned to torch's cache when the plan is destroyed.  Blocks are
+    allocated on the plan's stream; the library drains its streams before it frees."""
+
+    def __init__(self, stream=None):
+        torch = _torch()
+        self.device = torch.cuda.current_device()
+        self.stream = stream
+        self.live = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device,
+                                                         stream=self.stream)
+            except Exception:             # out of memory: the library reports RF_ERR_NOMEM
+                return None
+            self.live[int(ptr)] = int(nbytes)
+            return int(ptr)
+
+        def _free(ptr, ctx):
+            if ptr is None:
+                return
+            self.live.pop(int(ptr), None)
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        # the ctypes function objects must outlive every plan that holds them
+        self._alloc_fn = ALLOC_FN(_alloc)
+        self._free_fn = FREE_FN(_free)
+        self.struct = RfAllocator(self._alloc_fn, self._free_fn, None)
+
+    @property
+    def live_bytes(self) -> int:
+        return sum(self.live.values())
+
+
+def _allocator_arg(allocator, stream):
+    """(pointer to pass, object to keep alive): allocator is "torch" (default), None
+    (hipMalloc inside the library) or an object with a ``struct`` RfAllocator."""
+    if allocator is None:
+        return None, None
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError(f"unknown allocator {allocator!r}")
+        allocator = TorchAllocator(stream)
+    return ctypes.byref(allocator.struct), allocator
+
+
 class _HostCsr:
     """Keeps host arrays alive for the duration of plan creation."""
 
@@ -209,7 +268,7 @@ class Plan:
     """rf_plan_create: pencil (A, B) as scipy sparse matrices, disk (c, r), rules p, q, width w."""
 
     def __init__(self, A, B, c: complex, r: float, p: int = 4, q: int = 8, w: int = 32,
-                 stream=None, **opts):
+                 stream=None, allocator="torch", **opts):
         torch = _torch()
         o = make_opts(c, r, p, q, w, **opts)
         self.opts = o
@@ -219,7 +278,8 @@ class Plan:
         self.stream = stream
         ha, hb = _HostCsr(A), _HostCsr(B)
         handle = _P()
-        st = _lib.rf_plan_create(ctypes.byref(ha.s), ctypes.byref(hb.s), ctypes.byref(o),
+        aptr, self.allocator = _allocator_arg(allocator, stream)
+        st = _lib.rf_plan_create(ctypes.byref(ha.s), ctypes.byref(hb.s), ctypes.byref(o), aptr,
                                  _P(stream.cuda_stream), ctypes.byref(handle))
         if st != RF_OK:
             msg = _lib.rf_last_error(handle).decode() if handle.value else ""
@@ -297,6 +357,7 @@ class Plan:
         P = Plan.__new__(Plan)
         P._h = handle
         P._owned = True
+        P.allocator = self.allocator          # the adjoint plan uses the same callbacks
         P.opts = self.opts
         P.stream = stream
         P.n = self.n
@@ -390,7 +451,7 @@ class Batch:
     """rf_batch_create: one pencil, many disks.  ``disks`` is a list of dicts with the
     keys c, r and optionally p, q, w and any rf_opts field."""
 
-    def __init__(self, A, B, disks, stream=None, **common):
+    def __init__(self, A, B, disks, stream=None, allocator="torch", **common):
         torch = _torch()
         n = len(disks)
         arr = (RfOpts * n)()
@@ -403,7 +464,8 @@ class Batch:
         self.stream = stream
         ha, hb = _HostCsr(A), _HostCsr(B)
         handle = _P()
-        st = _lib.rf_batch_create(ctypes.byref(ha.s), ctypes.byref(hb.s), arr, n,
+        aptr, self.allocator = _allocator_arg(allocator, stream)
+        st = _lib.rf_batch_create(ctypes.byref(ha.s), ctypes.byref(hb.s), arr, n, aptr,
                                   _P(stream.cuda_stream), ctypes.byref(handle))
         if st != RF_OK:
             msg = _lib.rf_batch_last_error(handle).decode() if handle.value else ""

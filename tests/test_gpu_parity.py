@@ -1,15 +1,24 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
+Every block comparison is per column: max over columns c of
+||u_c - u*_c|| / ||u*_c||.
+
 Tolerances
 ----------
 * G(X) = sum_i w_i K_i^{-1} B X: both sides are backward-stable banded LU
-  solves of the same systems, so they agree to a few units of roundoff times
-  cond(K_i); we require 1e-12 relative (Frobenius) on well-conditioned pencils.
-* filter_apply: the composite method reaches the simple-rule value
-  R_{c,r,pq}(B^{-1}A)Y only up to the outer GMRES tolerance (1e-13 here),
-  amplified by at most the conditioning of the shifted outer systems; we
-  require 1e-11 relative.
-* eigenpairs: |dlambda|/|lambda| <= 1e-10 and e_i <= 1e-10 (eq. rel-error).
+  solves of the same systems; 1e-12 per column.
+* filter_apply on NORMAL pencils (balanced Toeplitz, diagonal): the composite
+  method reaches the simple-rule value R_{c,r,pq}(B^{-1}A)Y (Thm. Rcrm) up to the
+  outer GMRES tolerance (1e-13 here); 1e-12 per column.
+* filter_apply on NON-NORMAL pencils (convection-diffusion): R(B^{-1}A) is a
+  function of a matrix whose eigenvector basis X has condition kappa(X) of 1e4 to
+  1e5, so any floating-point evaluation of it -- the oracle's two direct ones
+  (band LU, dense LAPACK) included -- is only defined to about kappa(X) u ||y_c||.
+  The bar is 16 kappa(X) u ||y_c|| / ||u*_c|| plus the oracle's own spread (band LU
+  vs dense solves) per column, both computed densely in the test, and the measured
+  error is printed beside kappa(X) u and cond(K_i).
+* eigenpairs: |dlambda|/|lambda| <= 1e-10 over a minimum-cost assignment of the
+  eigenvalues, and e_i <= 1e-10 (eq. rel-error) re-evaluated by the oracle.
 """
 import sys
 
@@ -40,8 +49,58 @@ def rf(torch_cuda):
     return rfeig
 
 
+U_ROUND = np.finfo(np.float64).eps / 2          # unit roundoff 1.1e-16
+
+
 def _relerr(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _colerr(a, b):
+    """per-column relative errors ||a_c - b_c|| / ||b_c||"""
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+
+
+def _match_rel(lam, ref):
+    """|lambda_i - ref_pi(i)| / |ref_pi(i)| over the minimum-cost assignment pi of
+    the computed eigenvalues to the reference ones (equal counts)"""
+    from scipy.optimize import linear_sum_assignment
+    lam, ref = np.asarray(lam), np.asarray(ref)
+    assert len(lam) == len(ref), (len(lam), len(ref))
+    cost = np.abs(lam[:, None] - ref[None, :])
+    r, c = linear_sum_assignment(cost)
+    return cost[r, c] / np.abs(ref[c])
+
+
+_DENSE = {}
+
+
+def _dense_bar(name, A, B, c, r, p, q, Y):
+    """For a small non-normal pencil: (oracle block, bar per column, kappa(X) u, max
+    cond(K_i), oracle spread).  The oracle's simple rule with pq poles is evaluated
+    twice, by its band LU and by dense LAPACK solves; their per-column difference is
+    the oracle's own rounding spread.  kappa(X) is the condition number of the
+    eigenvector matrix of B^{-1} A.  A backward-stable evaluation of R(B^{-1}A) y
+    perturbs it by a matrix of norm about kappa(X) u times the size of the filter, so
+    its error scales with ||y||, not with the (possibly strongly damped) ||R y||: the
+    bar on ||u_c - u*_c|| / ||u*_c|| is 16 kappa(X) u ||y_c|| / ||u*_c|| + spread_c."""
+    from oracle import coeffs, filters
+    key = (name, p, q, Y.shape[1])
+    if key not in _DENSE:
+        Ad, Bd = A.toarray(), B.toarray()
+        poles, wts = coeffs.trapezoid_nodes(c, r, p * q)
+        dense = sum(wi * np.linalg.solve(z * Bd - Ad, Bd @ Y) for z, wi in zip(poles, wts))
+        band = filters.simple_filter(A, B, c, r, p * q, Y)
+        _, X = np.linalg.eig(np.linalg.solve(Bd, Ad))
+        kx = np.linalg.cond(X) * U_ROUND
+        ip, _ = coeffs.trapezoid_nodes(c, r, p)
+        ck = max(np.linalg.cond(z * Bd - Ad) for z in ip)
+        spread = _colerr(dense, band)
+        scale = np.linalg.norm(Y, axis=0) / np.linalg.norm(band, axis=0)
+        _DENSE[key] = (band, 16.0 * kx * scale + spread, kx, ck, spread.max())
+    return _DENSE[key]
 
 
 def _to_host(X):
@@ -80,7 +139,8 @@ def test_inner_apply_matches_oracle(rf, torch_cuda, case, ncols):
     X = W.start_block(A.shape[0], ncols, seed=7)
     Z = _to_host(plan.apply_inner(torch_cuda.from_numpy(X).cuda()))
     ref = filters.InnerOperator(A, B, c, r, p)(X)
-    assert _relerr(Z, ref) <= 1e-12, (name, _relerr(Z, ref))
+    e = _colerr(Z, ref)
+    assert e.max() <= 1e-12, (name, e.max())
 
 
 def test_inner_apply_tile_override_and_column_slices(rf, torch_cuda):
@@ -93,7 +153,7 @@ def test_inner_apply_tile_override_and_column_slices(rf, torch_cuda):
         plan = rf.Plan(A, B, 300 + 0.05j, 100.0, p=3, q=4, w=16, tile=tile, trsm_cols=cols)
         plan.factor_shifts()
         Z = _to_host(plan.apply_inner(torch_cuda.from_numpy(X).cuda()))
-        assert _relerr(Z, ref) <= 1e-12, (tile, cols)
+        assert _colerr(Z, ref).max() <= 1e-12, (tile, cols)
 
 
 @pytest.mark.parametrize("tile", [64, 128])
@@ -112,7 +172,7 @@ def test_inner_apply_slice_width_agreement(rf, torch_cuda, tile):
         plan.factor_shifts()
         out.append(_to_host(plan.apply_inner(X)))
         plan.close()
-    d = [_relerr(out[i], out[0]) for i in (1, 2)]
+    d = [_colerr(out[i], out[0]).max() for i in (1, 2)]
     _say(f"  relative differences vs one column per workgroup: {d[0]:.1e}, {d[1]:.1e}")
     assert max(d) <= 1e-14, d
 
@@ -131,7 +191,8 @@ def test_inner_apply_tile_256(rf, torch_cuda, precision):
                        precision=precision)
         plan.factor_shifts()
         Z = _to_host(plan.apply_inner(torch_cuda.from_numpy(X).cuda()))
-        assert _relerr(Z, ref) <= (1e-12 if precision == 0 else 1e-5), (cols, _relerr(Z, ref))
+        e = _colerr(Z, ref).max()
+        assert e <= (1e-12 if precision == 0 else 1e-5), (cols, e)
         plan.close()
 
 
@@ -151,6 +212,8 @@ def test_pole_on_eigenvalue_is_reported_singular(rf, torch_cuda):
 
 @pytest.mark.parametrize("q", [4, 8, 3])
 def test_filter_apply_matches_simple_rule(rf, torch_cuda, q):
+    # balanced Toeplitz (normal): the composite filter equals the simple rule with pq
+    # poles (Thm. Rcrm) to 1e-12 per column
     from oracle import filters
     wl = W.toeplitz_workload(n=2000, w=32, count=20)
     _say(f"filter_apply toeplitz2000 q={q}")
@@ -160,22 +223,63 @@ def test_filter_apply_matches_simple_rule(rf, torch_cuda, q):
     U, info = plan.filter_apply(torch_cuda.from_numpy(Y).cuda())
     ref = filters.simple_filter(wl.A, wl.B, wl.c, wl.r, 4 * q, Y)
     assert info["converged"]
-    assert _relerr(_to_host(U), ref) <= 1e-11, _relerr(_to_host(U), ref)
+    e = _colerr(_to_host(U), ref)
+    print(f"toeplitz2000 q={q}: per-column filter error max {e.max():.2e} median {np.median(e):.2e}")
+    assert e.max() <= 1e-12, e.max()
+
+
+@pytest.mark.parametrize("q", [8, 16])
+def test_filter_apply_diagonal_pencil_closed_form(rf, torch_cuda, q):
+    # diagonal pencil A = diag(a_j), B = diag(b_j) (normal): the filter is
+    # diag(1 / (1 + ((a_j/b_j - c)/r)^(pq))) Y exactly (Lemma compact with eq. pwtp),
+    # written out here; the oracle's simple rule is checked too
+    from oracle import filters
+    rng = np.random.default_rng(5)
+    lam = rng.uniform(-3, 3, 800) + 1j * rng.uniform(-1, 1, 800)
+    bd = rng.uniform(0.5, 1.5, 800)
+    A, B = W.diagonal_pencil(lam, bd)
+    c, r, p = 0.2 + 0.1j, 1.0, 4
+    _say(f"filter_apply diagonal800 q={q}")
+    plan = rf.Plan(A, B, c, r, p=p, q=q, w=32, gmres_tol=1e-13)
+    plan.factor_shifts()
+    Y = W.start_block(800, 32, seed=3)
+    U, info = plan.filter_apply(torch_cuda.from_numpy(Y).cuda())
+    assert info["converged"]
+    closed = (1.0 / (1.0 + ((lam - c) / r) ** (p * q)))[:, None] * Y
+    e = _colerr(_to_host(U), closed)
+    e2 = _colerr(_to_host(U), filters.simple_filter(A, B, c, r, p * q, Y))
+    print(f"diagonal800 q={q}: per-column error vs closed form {e.max():.2e}, vs oracle {e2.max():.2e}")
+    assert e.max() <= 1e-12 and e2.max() <= 1e-12, (e.max(), e2.max())
+
+
+def _nonnormal_filter_case(rf, torch_cuda, name, A, B, c, r, p, q, w, **opts):
+    Y = W.start_block(A.shape[0], w, seed=8)
+    ref, bar, kx, ck, spread = _dense_bar(name, A, B, c, r, p, q, Y)
+    plan = rf.Plan(A, B, c, r, p=p, q=q, w=w, gmres_tol=1e-13, **opts)
+    plan.factor_shifts()
+    U, info = plan.filter_apply(torch_cuda.from_numpy(Y).cuda())
+    assert info["converged"]
+    e = _colerr(_to_host(U), ref)
+    print(f"{name}: per-column filter error max {e.max():.2e} median {np.median(e):.2e}; "
+          f"kappa(X) u {kx:.2e}, oracle spread {spread:.2e}, max cond(K_i) {ck:.2e}")
+    assert np.all(e <= bar), (e / bar).max()
+    return e
 
 
 @pytest.mark.parametrize("subblock", [8, 16, 32])
 def test_filter_apply_convdiff_random_mass(rf, torch_cuda, subblock):
-    from oracle import filters
     A, B = W.convdiff_pencil(24, mass=(0.5, 1.5), seed=4)           # N=576, kl=24
-    c, r = 1500 + 0.05j, 300.0
     _say(f"filter_apply convdiff24 subblock={subblock}")
-    plan = rf.Plan(A, B, c, r, p=4, q=8, w=32, gmres_tol=1e-13, subblock=subblock)
-    plan.factor_shifts()
-    Y = W.start_block(A.shape[0], 32, seed=8)
-    U, info = plan.filter_apply(torch_cuda.from_numpy(Y).cuda())
-    ref = filters.simple_filter(A, B, c, r, 32, Y)
-    assert info["converged"]
-    assert _relerr(_to_host(U), ref) <= 1e-11, _relerr(_to_host(U), ref)
+    _nonnormal_filter_case(rf, torch_cuda, "convdiff24_mass", A, B, 1500 + 0.05j, 300.0, 4, 8, 32,
+                           subblock=subblock)
+
+
+def test_filter_apply_convdiff_identity_mass(rf, torch_cuda):
+    # constant-coefficient convection-diffusion, B = I: similar to a symmetric matrix
+    # through a diagonal scaling, but that scaling has condition 1e5 at n = 33
+    A, B = W.convdiff_pencil(33, mass=None)
+    _say("filter_apply convdiff33 B = I")
+    _nonnormal_filter_case(rf, torch_cuda, "convdiff33_I", A, B, 3000 + 0.05j, 400.0, 4, 8, 32)
 
 
 def test_solve_region_toeplitz_closed_form(rf, torch_cuda):
@@ -187,8 +291,9 @@ def test_solve_region_toeplitz_closed_form(rf, torch_cuda):
     exact = W.toeplitz_eigs(wl.n, 0, 1, W.TOEPLITZ_C)
     inside = exact[np.abs(exact - wl.c) < wl.r]
     assert res["converged"] and res["count"] == len(inside) == 20
-    d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
-    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+    rel = _match_rel(res["lam"], inside)
+    print(f"toeplitz2000: max |dlambda|/|lambda| {rel.max():.2e}")
+    assert rel.max() <= 1e-10, rel.max()
     assert res["err"].max() <= 1e-10
 
 
@@ -206,8 +311,9 @@ def test_solve_region_small_convdiff_vs_oracle(rf, torch_cuda):
     res = plan.solve_region(torch_cuda.from_numpy(Y0).cuda())
     ref = solver.solve_region(A, B, c, r, 4, 8, Y0, s_expected=12)
     assert res["count"] == len(ref.lam) == 12
-    d = np.abs(res["lam"][:, None] - ref.lam[None, :]).min(axis=1)
-    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+    rel = _match_rel(res["lam"], ref.lam)
+    print(f"convdiff20: max |dlambda|/|lambda| {rel.max():.2e}")
+    assert rel.max() <= 1e-10, rel.max()
     # residuals re-evaluated by the oracle's definition on the returned vectors
     e = hsrr.rel_errors(A, B, res["lam"], _to_host(res["X"]), c, r)
     assert e.max() <= 1e-10
@@ -230,11 +336,13 @@ def test_filter_apply_on_converged_ritz_vectors(rf, torch_cuda, subblock):
     res = plan.solve_region(torch_cuda.from_numpy(W.start_block(n * n, 32, 0)).cuda())
     Xr = res["all_X"]
     U, info = plan.filter_apply(Xr, allow_noconv=True)
-    ref = filters.simple_filter(A, B, c, r, 32, _to_host(Xr))
-    print("krylov steps", info["krylov_steps"], "max residual", info["max_residual"],
-          "relerr", _relerr(_to_host(U), ref))
+    ref, bar, kx, ck, spread = _dense_bar(f"ritz{subblock}", A, B, c, r, 4, 8, _to_host(Xr))
+    e = _colerr(_to_host(U), ref)
+    print(f"ritz block subblock={subblock}: krylov steps {info['krylov_steps']}, max residual "
+          f"{info['max_residual']:.1e}, per-column filter error max {e.max():.2e}; kappa(X) u "
+          f"{kx:.2e}, oracle spread {spread:.2e}, max cond(K_i) {ck:.2e}")
     assert info["converged"], info
-    assert _relerr(_to_host(U), ref) <= 1e-10
+    assert np.all(e <= bar), (e / bar).max()
 
 
 # ---------------------------------------------------------------------------
@@ -263,32 +371,48 @@ def convdiff128(rf, torch_cuda):
     return wl, plan
 
 
-def test_full_size_inner_apply_sampled_columns(rf, torch_cuda, convdiff128):
-    # G on all 128 columns in the benchmark's launch shape; the oracle checks 3 of them
+def test_full_size_inner_apply_all_columns(rf, torch_cuda, convdiff128):
+    # G on all 128 columns in the benchmark's launch shape, every column checked
+    # against the oracle's G (four band LUs and solves, about 7 s on one core)
     from oracle import filters
     wl, plan = convdiff128
     _say("convdiff128 apply_inner, 128 columns")
     X = W.start_block(wl.n, wl.w, seed=11)
     Z = _to_host(plan.apply_inner(torch_cuda.from_numpy(X).cuda()))
-    cols = [0, 77, 127]
-    ref = filters.InnerOperator(wl.A, wl.B, wl.c, wl.r, wl.p)(X[:, cols])
-    assert _relerr(Z[:, cols], ref) <= 1e-12, _relerr(Z[:, cols], ref)
+    ref = filters.InnerOperator(wl.A, wl.B, wl.c, wl.r, wl.p)(X)
+    e = _colerr(Z, ref)
+    print(f"convdiff128 G: per-column error max {e.max():.2e} median {np.median(e):.2e}")
+    assert e.max() <= 1e-12, e.max()
 
 
-def test_full_size_filter_apply_sampled_columns(rf, torch_cuda, convdiff128):
-    # one composite filter application on the 128-column start block; the oracle's
-    # simple rule with pq = 32 poles on 2 of the columns
-    from oracle import filters
+def test_full_size_filter_apply_all_columns(rf, torch_cuda, convdiff128):
+    # one composite filter application on the 128-column start block, every column
+    # against the oracle's simple rule with pq = 32 poles, stored as a 128-vector
+    # Gaussian sketch of each column (tests/golden/make_convdiff128_filter.py).  The
+    # pencil is non-normal: the filtered columns lie in the span of the eigenvectors
+    # inside the disk, whose eigenvalue condition numbers kappa_B reach 1.2e4
+    # (tests/golden/convdiff128_cond.txt), so the bar is 16 max(kappa_B) u per column
+    # as on the small non-normal pencils (where kappa(X) is computed densely).
+    import os
     wl, plan = convdiff128
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    g = np.load(os.path.join(here, "convdiff128_filter_sketch.npz"))
+    kappa = np.loadtxt(os.path.join(here, "convdiff128_cond.txt"))[:, 2].max()
+    assert int(g["y_seed"]) == wl.seed and int(g["k"]) == wl.p * wl.q
     _say("convdiff128 filter_apply, 128 columns")
     Y = W.start_block(wl.n, wl.w, wl.seed)
     U, info = plan.filter_apply(torch_cuda.from_numpy(Y).cuda())
     assert info["converged"], info
-    cols = [5, 100]
-    ref = filters.simple_filter(wl.A, wl.B, wl.c, wl.r, wl.p * wl.q, Y[:, cols])
-    e = _relerr(_to_host(U)[:, cols], ref)
-    print("filter relerr", e, "krylov steps", info["krylov_steps"])
-    assert e <= 1e-11, e
+    Uh = _to_host(U)
+    S = W.start_block(wl.n, 128, int(g["sketch_seed"]))
+    sk = S.conj().T @ Uh
+    e = np.linalg.norm(sk - g["sketch"], axis=0) / np.linalg.norm(g["sketch"], axis=0)
+    nrm = np.abs(np.linalg.norm(Uh, axis=0) / g["norms"] - 1.0)
+    bar = 16.0 * kappa * U_ROUND
+    print(f"convdiff128 filter: per-column sketched error max {e.max():.2e} median "
+          f"{np.median(e):.2e}, column-norm deviation max {nrm.max():.1e}, krylov steps "
+          f"{info['krylov_steps']}; 16 max(kappa_B) u = {bar:.2e}")
+    assert e.max() <= bar and nrm.max() <= bar, (e.max(), nrm.max(), bar)
 
 
 def test_full_size_solve_region_matches_oracle(rf, torch_cuda, convdiff128):
@@ -333,15 +457,16 @@ def test_solve_region_adaptive_small_convdiff_vs_oracle(rf, torch_cuda):
     assert res["converged"] and ref.converged
     assert res["count"] == len(ref.lam) == 12
     assert res["sweeps"] == ref.sweeps
-    d = np.abs(res["lam"][:, None] - ref.lam[None, :]).min(axis=1)
-    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+    rel = _match_rel(res["lam"], ref.lam)
+    assert rel.max() <= 1e-10, rel.max()
     e = hsrr.rel_errors(A, B, res["lam"], _to_host(res["X"]), c, r)
     assert e.max() <= 1e-10
     # the plan's own rule is back in place: filter_apply still matches the simple rule
     from oracle import filters
     Y = W.start_block(n * n, 16, seed=3)
     U, info = plan.filter_apply(torch_cuda.from_numpy(Y).cuda())
-    assert _relerr(_to_host(U), filters.simple_filter(A, B, c, r, 16, Y)) <= 1e-11
+    ref, bar, kx, ck, spread = _dense_bar("convdiff20_ad", A, B, c, r, 4, 4, Y)
+    assert np.all(_colerr(_to_host(U), ref) <= bar)
 
 
 def test_solve_region_adaptive_toeplitz_closed_form(rf, torch_cuda):
@@ -352,8 +477,8 @@ def test_solve_region_adaptive_toeplitz_closed_form(rf, torch_cuda):
     exact = W.toeplitz_eigs(wl.n, 0, 1, W.TOEPLITZ_C)
     inside = exact[np.abs(exact - wl.c) < wl.r]
     assert res["converged"] and res["count"] == len(inside) == 20
-    d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
-    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+    rel = _match_rel(res["lam"], inside)
+    assert rel.max() <= 1e-10, rel.max()
     assert res["err"].max() <= 1e-10
 
 
@@ -371,8 +496,8 @@ def test_solve_region_circuit10_vs_dense(rf, torch_cuda):
     w = w[np.isfinite(w)]
     inside = w[np.abs(w - wl.c) < wl.r]
     assert res["converged"] and res["count"] == len(inside) == wl.s_expected
-    d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
-    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+    rel = _match_rel(res["lam"], inside)
+    assert rel.max() <= 1e-10, rel.max()
     e = hsrr.rel_errors(wl.A, wl.B, res["lam"], _to_host(res["X"]), wl.c, wl.r)
     assert e.max() <= 1e-10
 
@@ -388,8 +513,8 @@ def test_solve_region_adaptive_circuit10_vs_dense(rf, torch_cuda):
     w = w[np.isfinite(w)]
     inside = w[np.abs(w - wl.c) < wl.r]
     assert res["converged"] and res["count"] == len(inside)
-    d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
-    assert np.all(d <= 1e-10 * np.abs(res["lam"])), d.max()
+    rel = _match_rel(res["lam"], inside)
+    assert rel.max() <= 1e-10, rel.max()
 
 
 def test_solve_region_sweep_cap_returns_noconv_with_results(rf, torch_cuda):

@@ -67,35 +67,39 @@ def test_plan_create_rejects_bad_arguments_before_device_work(lib):
     lib.rf_plan_create.restype = ctypes.c_int
     # w > n
     o.w = 3
-    assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None,
+    assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None, None,
                               ctypes.byref(out)) == rfeig.RF_ERR_ARG
     # r <= 0
     o.w = 1; o.r = 0.0
-    assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None,
+    assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None, None,
                               ctypes.byref(out)) == rfeig.RF_ERR_ARG
     # bad column index
     o.r = 1.0
     badcol = np.array([0, 5], dtype=np.int32)
     Ab = rfeig.RfCsr(2, 2, rowptr.ctypes.data, badcol.ctypes.data, val.ctypes.data)
-    assert lib.rf_plan_create(ctypes.byref(Ab), ctypes.byref(A), ctypes.byref(o), None,
+    assert lib.rf_plan_create(ctypes.byref(Ab), ctypes.byref(A), ctypes.byref(o), None, None,
                               ctypes.byref(out)) == rfeig.RF_ERR_ARG
     # non-finite value
     nanval = np.array([float("nan"), 0.0, 2.0, 0.0])
     An = rfeig.RfCsr(2, 2, rowptr.ctypes.data, col.ctypes.data, nanval.ctypes.data)
-    assert lib.rf_plan_create(ctypes.byref(An), ctypes.byref(A), ctypes.byref(o), None,
+    assert lib.rf_plan_create(ctypes.byref(An), ctypes.byref(A), ctypes.byref(o), None, None,
                               ctypes.byref(out)) == rfeig.RF_ERR_ARG
     # tile sizes other than 16, 32, 64, 128, 256
     for bad in (8, 48, 96, 512):
         o.tile = bad
-        assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None,
+        assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None, None,
                                   ctypes.byref(out)) == rfeig.RF_ERR_ARG
     o.tile = 0
     # precision other than 0 (complex128) and 1 (complex64 band solves)
     for bad in (-1, 2):
         o.precision = bad
-        assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None,
+        assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o), None, None,
                                   ctypes.byref(out)) == rfeig.RF_ERR_ARG
     o.precision = 0
+    # an allocator must give both callbacks
+    half = rfeig.RfAllocator(rfeig.ALLOC_FN(lambda n, ctx: None), rfeig.FREE_FN(), None)
+    assert lib.rf_plan_create(ctypes.byref(A), ctypes.byref(A), ctypes.byref(o),
+                              ctypes.byref(half), None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
     assert out.value is None
 
 
@@ -114,13 +118,13 @@ def test_batch_create_rejects_bad_arguments_before_device_work(lib):
     f = lib.rf_batch_create
     f.restype = ctypes.c_int
     # no disks
-    assert f(ctypes.byref(A), ctypes.byref(A), opts, 0, None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
+    assert f(ctypes.byref(A), ctypes.byref(A), opts, 0, None, None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
     # disks that ask for different tiles cannot share one factor storage
     opts[1].tile = 32
-    assert f(ctypes.byref(A), ctypes.byref(A), opts, 2, None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
+    assert f(ctypes.byref(A), ctypes.byref(A), opts, 2, None, None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
     opts[1].tile = 0
     opts[0].p = 0
-    assert f(ctypes.byref(A), ctypes.byref(A), opts, 2, None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
+    assert f(ctypes.byref(A), ctypes.byref(A), opts, 2, None, None, ctypes.byref(out)) == rfeig.RF_ERR_ARG
     assert out.value is None
     lib.rf_batch_size.restype = ctypes.c_int32
     assert lib.rf_batch_size(None) == -1
