@@ -13,10 +13,10 @@ Tolerances
 * filter_apply on NON-NORMAL pencils (convection-diffusion): R(B^{-1}A) is a
   function of a matrix whose eigenvector basis X has condition kappa(X) of 1e4 to
   1e5, so any floating-point evaluation of it -- the oracle's two direct ones
-  (band LU, dense LAPACK) included -- is only defined to about kappa(X) u ||y_c||.
-  The bar is 16 kappa(X) u ||y_c|| / ||u*_c|| plus the oracle's own spread (band LU
-  vs dense solves) per column, both computed densely in the test, and the measured
-  error is printed beside kappa(X) u and cond(K_i).
+  (band LU, dense LAPACK) included -- is only defined to about
+  kappa(X) u max(||y_c||, ||u*_c||).  The bar is that times 16, over ||u*_c||, plus
+  the oracle's own spread (band LU vs dense solves) per column, all computed densely
+  in the test, and the measured error is printed beside kappa(X) u and cond(K_i).
 * eigenpairs: |dlambda|/|lambda| <= 1e-10 over a minimum-cost assignment of the
   eigenvalues, and e_i <= 1e-10 (eq. rel-error) re-evaluated by the oracle.
 """
@@ -84,8 +84,10 @@ def _dense_bar(name, A, B, c, r, p, q, Y):
     the oracle's own rounding spread.  kappa(X) is the condition number of the
     eigenvector matrix of B^{-1} A.  A backward-stable evaluation of R(B^{-1}A) y
     perturbs it by a matrix of norm about kappa(X) u times the size of the filter, so
-    its error scales with ||y||, not with the (possibly strongly damped) ||R y||: the
-    bar on ||u_c - u*_c|| / ||u*_c|| is 16 kappa(X) u ||y_c|| / ||u*_c|| + spread_c."""
+    its error scales with the larger of ||y|| and ||R y|| (R damps the columns of a
+    nearly invariant block outside the disk and, the pencil being non-normal, can also
+    amplify a column): the bar on ||u_c - u*_c|| / ||u*_c|| is
+    16 kappa(X) u max(||y_c||, ||u*_c||) / ||u*_c|| + spread_c."""
     from oracle import coeffs, filters
     key = (name, p, q, Y.shape[1])
     if key not in _DENSE:
@@ -98,7 +100,8 @@ def _dense_bar(name, A, B, c, r, p, q, Y):
         ip, _ = coeffs.trapezoid_nodes(c, r, p)
         ck = max(np.linalg.cond(z * Bd - Ad) for z in ip)
         spread = _colerr(dense, band)
-        scale = np.linalg.norm(Y, axis=0) / np.linalg.norm(band, axis=0)
+        ny, nu = np.linalg.norm(Y, axis=0), np.linalg.norm(band, axis=0)
+        scale = np.maximum(ny, nu) / nu
         _DENSE[key] = (band, 16.0 * kx * scale + spread, kx, ck, spread.max())
     return _DENSE[key]
 
