@@ -153,6 +153,20 @@ rf_status rf_factor_shifts(rf_plan_t plan);
 rf_status rf_apply_inner(rf_plan_t plan, const void *X, int64_t ldx, int32_t ncols,
                          void *Z, int64_t ldz);
 
+/* rf_apply_inner for callers that cannot allocate device memory or synchronize
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, but the work blocks (per-pole forward results and
+ * solutions, the B X staging) live in one file-scope device array of the library,
+ * 64 MiB per device, held from the first call on a device until the process ends;
+ * the call allocates nothing and only enqueues its work on the plan stream (no stream
+ * synchronization: Z is ready when the stream reaches that point).  Columns are
+ * processed in chunks that fit the array; ncols may exceed w.  RF_ERR_ARG if a single
+ * column does not fit (n_pad (p (16 or 8) + 16 + 16) bytes, n_pad = n rounded up to
+ * the tile).  All calls on one device share the array: calls that can overlap on one
+ * device (different streams, different plans, different threads) race; order them. */
+rf_status rf_apply_inner_noalloc(rf_plan_t plan, const void *X, int64_t ldx, int32_t ncols,
+                                 void *Z, int64_t ldz);
+
 /* U = R_{c,r,pq}(B^{-1}A) Y = sum_j c'_j (G - s_j I)^{-1} G(Y)   (eq. linearsolve1abs)
  * by block multi-shift GMRES on one shared Krylov basis.  The sign of c'_j is
  * the one for which the sum equals +R_{c,r,pq} (the proof of Thm. Rcrm).

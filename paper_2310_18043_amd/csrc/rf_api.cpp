@@ -538,6 +538,24 @@ rf_status rf_apply_inner(rf_plan_t P, const void *X, int64_t ldx, int32_t ncols,
     return RF_OK;
 }
 
+rf_status rf_apply_inner_noalloc(rf_plan_t P, const void *X, int64_t ldx, int32_t ncols, void *Zp,
+                                 int64_t ldz) {
+    if (!P) return RF_ERR_ARG;
+    if (P->broken) return rf_fail(P, RF_ERR_STATE, "plan is unusable after a device error");
+    if (!X || !Zp || ncols < 0 || ldx < P->n || ldz < P->n)
+        return rf_fail(P, RF_ERR_ARG, "bad block arguments");
+    const size_t per = inner_scratch_per_column(*P) + 3 * 256;
+    if (per > inner_scratch_capacity())
+        return rf_fail(P, RF_ERR_ARG, "one column needs " + std::to_string(per) +
+                                          " bytes of work space; the library's static array holds " +
+                                          std::to_string(inner_scratch_capacity()));
+    if (!P->F.ready) return rf_fail(P, RF_ERR_STATE, "rf_factor_shifts has not succeeded");
+    if (ncols == 0) return RF_OK;
+    RF_HIP(P, launch_inner_apply_static(*P, static_cast<const zd *>(X), ldx, ncols,
+                                        static_cast<zd *>(Zp), ldz, P->stream));
+    return RF_OK;
+}
+
 namespace {
 
 const double kUnit = 1.1102230246251565e-16;

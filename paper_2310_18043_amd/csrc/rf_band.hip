@@ -20,6 +20,8 @@
 // at factorization time turns the triangular solves into the same products.
 //
 // Rows beyond n are padded with the identity so that every block is full.
+#include <mutex>
+
 #include "rf_common.h"
 
 namespace {
@@ -1090,8 +1092,20 @@ hipError_t launch_tiles_to_c64(const rf_plan &P, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int ncols, zd *Z,
-                              int64_t ldz, hipStream_t s, bool apply_b, const zd *colw) {
+namespace {
+
+// Work blocks of one application of G to ncols columns: B X staging (only when B is not
+// diagonal), per-pole forward results (tile precision) and per-pole weighted solutions.
+struct InnerBufs {
+    zd *rhs;
+    void *ypart;
+    zd *xpart;
+    bool profile;        // record the solve launch in the plan's kernel statistics
+};
+
+hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncols, zd *Z,
+                            int64_t ldz, hipStream_t s, bool apply_b, const zd *colw,
+                            const InnerBufs &buf) {
     SolveArgs a;
     a.n = int(P.n); a.nb = P.F.nb; a.nblk = P.F.nblk; a.p = P.opts.p;
     a.ncols = ncols;
@@ -1099,16 +1113,16 @@ hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int nc
     if (c64 && !P.F.tiles32) return hipErrorInvalidValue;
     a.tiles = c64 ? static_cast<const void *>(P.F.tiles32) : static_cast<const void *>(P.F.tiles);
     a.perm = P.F.perm; a.weights = P.d_weights; a.colw = colw;
-    a.ypart = P.ypart; a.xpart = P.xpart;
+    a.ypart = buf.ypart; a.xpart = buf.xpart;
     a.npad = int64_t(P.F.nblk) * P.F.nb;
     if (!apply_b) {
         a.X = X; a.ldx = ldx; a.bdiag = nullptr;
     } else if (P.B.diagonal) {
         a.X = X; a.ldx = ldx; a.bdiag = P.B.dval;
     } else {
-        hipError_t e = launch_spmm(P.B, ncols, X, ldx, P.rhs, a.npad, s);
+        hipError_t e = launch_spmm(P.B, ncols, X, ldx, buf.rhs, a.npad, s);
         if (e != hipSuccess) return e;
-        a.X = P.rhs; a.ldx = a.npad; a.bdiag = nullptr;
+        a.X = buf.rhs; a.ldx = a.npad; a.bdiag = nullptr;
     }
     int cw = P.opts.trsm_cols;
     if (cw <= 0) {
@@ -1122,7 +1136,7 @@ hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int nc
     while (cw > 1 && solve_lds(a.nb, cw, elem) > size_t(P.max_lds)) cw /= 2;
     hipError_t e;
     hipEvent_t ev0 = nullptr;
-    P.prof.record_begin(s, ev0);
+    if (buf.profile) P.prof.record_begin(s, ev0);
     if (c64) {
         switch (cw) {
             case 1: e = launch_solve_cw<1, zf>(a, s); break;
@@ -1137,9 +1151,94 @@ hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int nc
         }
     }
     if (e != hipSuccess) return e;
-    P.prof.record_end(s, ev0, ncols, 0);
+    if (buf.profile) P.prof.record_end(s, ev0, ncols, 0);
     int64_t tot = P.n * ncols;
-    hipLaunchKernelGGL(pole_sum_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, P.xpart, a.p,
+    hipLaunchKernelGGL(pole_sum_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, buf.xpart, a.p,
                        a.npad, P.n, ncols, Z, ldz);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int ncols, zd *Z,
+                              int64_t ldz, hipStream_t s, bool apply_b, const zd *colw) {
+    return inner_apply_core(P, X, ldx, ncols, Z, ldz, s, apply_b, colw,
+                            InnerBufs{P.rhs, P.ypart, P.xpart, true});
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free application of G: the work blocks live in one file-scope device
+// array instead of plan buffers.  Its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is passed to
+// kernels; the array's name in host code is not a device address.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+size_t inner_scratch_capacity() { return kScratchBytes; }
+
+size_t inner_scratch_per_column(const rf_plan &P) {
+    const int64_t npad = int64_t(P.F.nblk) * P.F.nb;
+    const size_t ye = P.opts.precision == 1 ? sizeof(zf) : sizeof(zd);
+    const size_t rhs = P.B.diagonal ? 0 : size_t(npad) * sizeof(zd);
+    return rhs + size_t(P.opts.p) * npad * (ye + sizeof(zd));
+}
+
+hipError_t launch_inner_apply_static(const rf_plan &P, const zd *X, int64_t ldx, int ncols,
+                                     zd *Z, int64_t ldz, hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void *ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            g_scratch_ptr[dev] = ptr;
+        }
+        base = g_scratch_ptr[dev];
+    }
+    const int64_t npad = int64_t(P.F.nblk) * P.F.nb;
+    const size_t ye = P.opts.precision == 1 ? sizeof(zf) : sizeof(zd);
+    // columns per chunk: the largest count whose three blocks (each 256-byte aligned) fit
+    int chunk = ncols;
+    auto need = [&](int k) {
+        const size_t rhs = P.B.diagonal ? 0 : align256(size_t(npad) * k * sizeof(zd));
+        return rhs + align256(size_t(P.opts.p) * npad * k * ye) +
+               align256(size_t(P.opts.p) * npad * k * sizeof(zd));
+    };
+    while (chunk > 0 && need(chunk) > kScratchBytes) --chunk;
+    if (chunk == 0) return hipErrorInvalidValue;          // one column does not fit
+    unsigned char *b = static_cast<unsigned char *>(base);
+    for (int c0 = 0; c0 < ncols; c0 += chunk) {
+        const int k = std::min(chunk, ncols - c0);
+        InnerBufs buf;
+        size_t off = 0;
+        buf.rhs = nullptr;
+        if (!P.B.diagonal) {
+            buf.rhs = reinterpret_cast<zd *>(b + off);
+            off += align256(size_t(npad) * k * sizeof(zd));
+        }
+        buf.ypart = b + off;
+        off += align256(size_t(P.opts.p) * npad * k * ye);
+        buf.xpart = reinterpret_cast<zd *>(b + off);
+        buf.profile = false;
+        e = inner_apply_core(P, X + int64_t(c0) * ldx, ldx, k, Z + int64_t(c0) * ldz, ldz, s, true,
+                             nullptr, buf);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }

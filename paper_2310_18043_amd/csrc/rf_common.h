@@ -192,6 +192,13 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s);
 hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int ncols,
                               zd *Z, int64_t ldz, hipStream_t s, bool apply_b = true,
                               const zd *colw = nullptr);
+// launch_inner_apply with its work blocks in the library's file-scope device array
+// instead of plan buffers (no allocation); columns go in chunks that fit the array.
+// hipErrorInvalidValue if a single column does not fit.
+hipError_t launch_inner_apply_static(const rf_plan &P, const zd *X, int64_t ldx, int ncols,
+                                     zd *Z, int64_t ldz, hipStream_t s);
+size_t inner_scratch_capacity();                    // bytes of that array
+size_t inner_scratch_per_column(const rf_plan &P);  // its bytes per column, unaligned
 // complex64 copy of the factor tiles (after the complex128 factorization)
 hipError_t launch_tiles_to_c64(const rf_plan &P, hipStream_t s);
 

@@ -91,6 +91,8 @@ _lib.rf_factor_shifts.argtypes = [_P]
 _lib.rf_factor_shifts.restype = ctypes.c_int
 _lib.rf_apply_inner.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int64]
 _lib.rf_apply_inner.restype = ctypes.c_int
+_lib.rf_apply_inner_noalloc.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int64]
+_lib.rf_apply_inner_noalloc.restype = ctypes.c_int
 _lib.rf_filter_apply.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int64,
                                  ctypes.POINTER(RfFilterInfo)]
 _lib.rf_filter_apply.restype = ctypes.c_int
@@ -331,6 +333,15 @@ class Plan:
         self._check(_lib.rf_apply_inner(self._h, _P(X.data_ptr()), _ld(X), k,
                                         _P(Z.data_ptr()), _ld(Z)))
         return Z
+
+    def apply_inner_noalloc(self, X, out):
+        """rf_apply_inner_noalloc: Z = G(X) into the caller's block ``out`` with the
+        library's static work array; enqueued on the plan stream, not synchronized."""
+        X = as_colmajor(X)
+        k = X.shape[1]
+        self._check(_lib.rf_apply_inner_noalloc(self._h, _P(X.data_ptr()), _ld(X), k,
+                                                _P(out.data_ptr()), _ld(out)))
+        return out
 
     def filter_apply(self, Y, out=None, allow_noconv=False):
         Y = as_colmajor(Y)
