@@ -208,8 +208,9 @@ def circuit_form(reps):
 
 def gradient_form(reps):
     """Eigenvalue gradients on the 128 x 128 random-velocity pencil (52 eigenvalues in
-    the disk): right eigenpairs (factor + Alg. composite), left eigenpairs from the
-    adjoint pencil (factor + Alg. composite), and the device contraction of
+    the disk): one band factorization, right eigenpairs (Alg. composite), left
+    eigenpairs from the adjoint pencil (Alg. composite whose solves are the K_i^H sweeps
+    over the same factors, transposed once), and the device contraction of
     d lambda_i / d A over the stored entries of A and B for one weight vector."""
     import torch
     from paper_2310_18043_amd import rfeig
@@ -222,7 +223,8 @@ def gradient_form(reps):
     Y0a = torch.from_numpy(W.start_block(wl.n, wl.w, 1)).cuda()
 
     def step():
-        # right and adjoint problems factorized and solved concurrently
+        # one factorization (the adjoint plan transposes its tiles), then the right and
+        # adjoint problems solved concurrently on two streams
         t0 = time.perf_counter()
         res, resa = rfeig.solve_regions([P, Pa], [Y0, Y0a], factor=True, allow_noconv=True)
         t2 = time.perf_counter()

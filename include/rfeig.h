@@ -226,7 +226,10 @@ int rf_dense_eig(int32_t n, const double *A, const double *B, double *alpha, dou
 /* rf_solve_region on `count` distinct plans at once, each on a host thread of its own
  * and its plan's stream (plans created on different streams run concurrently on the
  * device; plans sharing a stream still give the right results); factor != 0 runs
- * rf_factor_shifts first on every plan (concurrently too).  Y0, ldy: host arrays
+ * rf_factor_shifts first on every plan (concurrently too).  When adjoint plans are in
+ * the list, the plans that own factors are factorized first (where factor != 0 or
+ * they have no factors yet), then the adjoint plans take their transposes, then all
+ * plans are solved concurrently.  Y0, ldy: host arrays
  * of start blocks and leading dimensions (NULL or NULL entries: seeded Gaussian); res,
  * status: host arrays of count results and return codes.  Returns RF_OK if every plan
  * returned RF_OK, else the first other code in plan order; RF_ERR_ARG if a plan
@@ -245,9 +248,13 @@ rf_status rf_solve_regions(int32_t count, rf_plan_t *plans, int32_t factor, cons
 
 /* A new plan for the adjoint pencil (A^H, B^H) with the options of `plan` and the
  * disk centre (and an explicit HSRR shift) conjugated; its trapezoidal poles are the
- * conjugates of the plan's (eq. pwtp, the node angles are symmetric).  It factorizes
- * its own shifted pencils (rf_factor_shifts) and is destroyed with rf_plan_destroy.
- * Errors as rf_plan_create. */
+ * conjugates of the plan's (eq. pwtp, the node angles are symmetric), so its shifted
+ * matrices are the K_i^H of `plan`.  It does not factorize: rf_factor_shifts on it
+ * (after rf_factor_shifts on `plan`) makes conjugate-transposed copies of `plan`'s band
+ * factors and row orders, and its solves are the K_i^H = U_i^H L_i^H P_i^T sweeps over
+ * them.  `plan` must stay alive (and keep its factors) while the adjoint plan is used;
+ * refactorizing `plan` needs rf_factor_shifts on the adjoint plan again.  Complex128
+ * only (precision 0).  Destroyed with rf_plan_destroy.  Errors as rf_plan_create. */
 rf_status rf_plan_create_adjoint(rf_plan_t plan, void *hip_stream, rf_plan_t *out);
 
 /* Vector-Jacobian product of eigenvalues with respect to the stored entries of A

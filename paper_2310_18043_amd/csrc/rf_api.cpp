@@ -247,7 +247,8 @@ namespace {
 // poles instead of the disk's trapezoidal nodes (the batch's factor owner).
 rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts,
                            const rf_allocator *allocator, void *hip_stream, rf_plan_t *out,
-                           const rf_plan *owner, int pole_offset, const std::vector<zd> *poles) {
+                           const rf_plan *owner, int pole_offset, const std::vector<zd> *poles,
+                           const rf_plan *adjoint_of = nullptr) {
     if (!out) return RF_ERR_ARG;
     *out = nullptr;
     if (allocator && (!allocator->alloc || !allocator->free)) return RF_ERR_ARG;
@@ -398,6 +399,21 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
             }
             P->F.tiles32 = owner->F.tiles32 + int64_t(pole_offset) * P->F.nblk * 5 * te;
         }
+    } else if (adjoint_of) {
+        // conjugate transposes of adjoint_of's factor tiles (made by rf_factor_shifts)
+        if (adjoint_of->F.nb != nb || adjoint_of->F.nblk != P->F.nblk || adjoint_of->opts.p != o.p) {
+            rf_fail(P, RF_ERR_ARG, "adjoint pencil does not match the plan's band tiles");
+            return fail(RF_ERR_ARG);
+        }
+        if (o.precision != 0) {
+            rf_fail(P, RF_ERR_ARG, "the adjoint solves run in complex128 only (precision 0)");
+            return fail(RF_ERR_ARG);
+        }
+        ALLOC(P->F.tiles, int64_t(o.p) * P->F.nblk * 5 * te);
+        ALLOC(P->F.perm, int64_t(o.p) * P->F.nblk * 2 * nb);
+        ALLOC(P->F.info, o.p);
+        P->F.adjoint = true;
+        P->adj_parent = adjoint_of;
     } else {
         ALLOC(P->F.tiles, int64_t(o.p) * P->F.nblk * 5 * te);
         ALLOC(P->F.perm, int64_t(o.p) * P->F.nblk * 2 * nb);
@@ -494,6 +510,21 @@ rf_status rf_factor_shifts(rf_plan_t P) {
     if (P->broken) return rf_fail(P, RF_ERR_STATE, "plan is unusable after a device error");
     if (P->shared_factors)
         return rf_fail(P, RF_ERR_STATE, "the factors of a batched disk come from rf_batch_factor");
+    if (P->adj_parent) {
+        // adjoint pencil: K_i^H of the parent's factors, no factorization of its own
+        const rf_plan *Q = P->adj_parent;
+        if (!Q->F.ready)
+            return rf_fail(P, RF_ERR_STATE, "the plan of the adjoint pencil has no factors yet "
+                                            "(rf_factor_shifts on it first)");
+        P->F.ready = false;
+        hipEvent_t ev = nullptr;
+        P->prof.record_begin(P->stream, ev);
+        RF_HIP(P, launch_tiles_adjoint(*P, *Q, P->stream));
+        P->prof.record_end(P->stream, ev, 0, 1);
+        RF_HIP(P, hipStreamSynchronize(P->stream));
+        P->F.ready = true;
+        return RF_OK;
+    }
     hipEvent_t ev0 = nullptr;
     P->prof.record_begin(P->stream, ev0);
     RF_HIP(P, launch_band_factor(*P, P->stream));
@@ -1773,9 +1804,31 @@ namespace {
 void solve_many(rf_plan *const *plans, int np, const void *const *Y0, const int64_t *ldy,
                 rf_result *res, rf_status *status, int threads, bool factor = false) {
     const int nt = std::max(1, std::min(threads <= 0 ? np : threads, np));
+    // An adjoint plan's factors are the conjugate transposes of its parent's: factorize
+    // the plans that own factors first, then transpose into the adjoint plans, then solve.
+    std::vector<char> skip(size_t(np), 0);
+    bool any_adj = false;
+    for (int d = 0; d < np; ++d) any_adj |= plans[d]->adj_parent != nullptr;
+    if (any_adj) {
+        for (int pass = 0; pass < 2; ++pass)
+            for (int d = 0; d < np; ++d) {
+                if ((pass == 1) != (plans[d]->adj_parent != nullptr)) continue;
+                if (!(factor || !plans[d]->F.ready)) continue;
+                if (hipSetDevice(plans[d]->device) != hipSuccess) {
+                    (void)hipGetLastError();
+                    status[d] = RF_ERR_DEVICE;
+                    skip[d] = 1;
+                    continue;
+                }
+                status[d] = rf_factor_shifts(plans[d]);
+                if (status[d] != RF_OK) skip[d] = 1;
+            }
+        factor = false;
+    }
     std::atomic<int> next{0};
     auto worker = [&]() {
         for (int d; (d = next.fetch_add(1)) < np;) {
+            if (skip[d]) continue;
             if (hipSetDevice(plans[d]->device) != hipSuccess) {
                 (void)hipGetLastError();
                 status[d] = RF_ERR_DEVICE;
@@ -1895,8 +1948,10 @@ rf_status rf_plan_create_adjoint(rf_plan_t P, void *hip_stream, rf_plan_t *out) 
     rf_opts o = P->opts;
     o.c_im = -o.c_im;
     if (!std::isnan(o.sigma_re)) o.sigma_im = -o.sigma_im;
+    if (P->F.adjoint || P->shared_factors)
+        return rf_fail(P, RF_ERR_ARG, "adjoint plans are made from a plan that owns its factors");
     return plan_create_impl(&Ah, &Bh, &o, P->alloc.alloc ? &P->alloc : nullptr, hip_stream, out,
-                            nullptr, 0, nullptr);
+                            nullptr, 0, nullptr, P);
 }
 
 rf_status rf_eig_vjp(rf_plan_t P, int32_t s, const double *lambda, const void *X, int64_t ldx,

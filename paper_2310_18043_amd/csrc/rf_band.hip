@@ -969,6 +969,228 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
     if (a.n < 0) ybuf[0] = from_zd<CT>(zmake(sink, 0.0));
 }
 
+// Conjugate-transposed solve, K^H x = d, with the factors of K (the differentiation
+// form: left eigenvectors from the adjoint pencil (A^H, B^H), whose shifted matrices
+// at the conjugate poles are the K_i^H).  K = Lhat U, where Lhat^{-1} is the product
+// of the block steps M_k = [Linv_k, 0; -L21_k Linv_k, I] P_k acting on row blocks
+// (k, k+1), so K^H = U^H Lhat^H and
+//   U^H sweep (k = 0 .. nblk-1):  v_k = Uinv_k^H (d_k - U1_{k-1}^H v_{k-1} - U2_{k-2}^H v_{k-2})
+//   Lhat^H sweep (k = nblk-1 .. 0), with b the current row block k+1:
+//       a' = Linv_k^H (v_k - L21_k^H b),   [block k; block k+1] = P_k^T [a'; b],
+//   after which block k+1 is final.  The tiles read here are the conjugate transposes
+// of the factor's tiles (slot t holds T_t^H: Linv^H and U2^H upper, Uinv^H lower),
+// made once from the factorization, so both sweeps are the same tile products as the
+// plain solve.  One workgroup per (pole, slice of CW right-hand sides), as there.
+template <int CW, int NB, typename CT>
+__global__ __launch_bounds__(kSolveThreads) void band_solve_adj_kernel(SolveArgs a) {
+    using SH = SolveShape<NB>;
+    constexpr int NT = kSolveThreads;
+    constexpr int R = SH::R;
+    const int p = a.p;
+    const int pole = blockIdx.x % p;
+    const int slice = blockIdx.x / p;
+    const int c0 = slice * CW;
+    if (c0 >= a.ncols) return;
+    const int ncw = min(CW, a.ncols - c0);
+    const int nblk = a.nblk;
+    constexpr int64_t te = int64_t(NB) * NB;
+    const int tid = threadIdx.x;
+    const zd wgt = a.weights[pole];
+    const int wave = tid / 64, lane = tid % 64;
+    const int g = lane / SH::RPW;
+    const int slot_raw = wave * SH::RPW + lane % SH::RPW;
+    const bool active = tid < SH::ACTIVE;
+    const int slot = active ? slot_raw : 0;
+    const bool writer = active && g == 0;
+
+    extern __shared__ unsigned char smem_raw[];
+    CT *ring = reinterpret_cast<CT *>(smem_raw);   // [3][NB][CW]: v_{k-2}, v_{k-1}, v_k
+    CT *tb = ring + 3 * NB * CW;                   // [NB][CW]: right-hand side of a triangle
+    CT *abuf = tb + NB * CW;                       // [NB][CW]: a' before the interchange
+    CT *cbuf[2] = {abuf + NB * CW, abuf + 2 * NB * CW};   // [NB][CW] x 2: row block k+1
+
+    CT *yp = static_cast<CT *>(a.ypart) + int64_t(pole) * a.npad * a.ncols;
+    zd *xp = a.xpart + int64_t(pole) * a.npad * a.ncols;
+    const CT *tiles = static_cast<const CT *>(a.tiles) + int64_t(pole) * nblk * 5 * te;
+    const int32_t *perm = a.perm + int64_t(pole) * nblk * 2 * NB;
+    const int64_t corner = slot + int64_t(g) * NB;
+    auto tile_at = [&](int k, int t) __attribute__((always_inline)) {
+        return tiles + (int64_t(k) * 5 + t) * te + corner;
+    };
+
+    constexpr int RPT = (NB * CW + NT - 1) / NT;
+    CT pre[RPT];
+    auto prefetch_rhs = [&](int blk) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int e = tid + q * NT;
+            const int r = e / CW, c = e % CW;
+            const int64_t row = int64_t(blk) * NB + r;
+            const bool ok = blk < nblk && e < NB * CW && row < a.n && c < ncw;
+            zd x = a.X[ok ? row + int64_t(c0 + c) * a.ldx : 0];
+            if (a.bdiag) x = zmul(a.bdiag[ok ? row : 0], x);
+            pre[q] = ok ? from_zd<CT>(x) : czero<CT>();
+        }
+    };
+    CT bufA[SH::S], bufB[SH::S];
+    issue_batch<NB, kFull, CT>(tile_at(0, 3), 0, bufA);
+    issue_batch<NB, kFull, CT>(tile_at(0, 3), 1, bufB);
+    CT acc[R][CW];
+    auto zero_acc = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) acc[q][c] = czero<CT>();
+    };
+
+    // ---------------- U^H sweep
+    for (int e = tid; e < 3 * NB * CW; e += NT) ring[e] = czero<CT>();
+    prefetch_rhs(0);
+    for (int k = 0; k < nblk; ++k) {
+        const bool last = (k + 1 == nblk);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int e = tid + q * NT;
+            if (e < NB * CW) tb[e] = pre[q];             // d_k
+        }
+        prefetch_rhs(k + 1);
+        __syncthreads();
+        CT *vk = ring + (k % 3) * NB * CW;
+        const CT *vk1 = ring + ((k + 2) % 3) * NB * CW;   // v_{k-1} (zero for k < 1)
+        const CT *vk2 = ring + ((k + 1) % 3) * NB * CW;   // v_{k-2} (zero for k < 2)
+        zero_acc();
+        tile_product<CW, NB, kFull, kUpper, CT>(g, bufA, bufB, acc, vk1, tile_at(max(k - 1, 0), 3),
+                                                tile_at(max(k - 2, 0), 4));
+        tile_product<CW, NB, kUpper, kLower, CT>(g, bufA, bufB, acc, vk2, tile_at(max(k - 2, 0), 4),
+                                                 tile_at(k, 2));
+        reduce_rows<CW, NB, CT>(acc);
+        if (writer) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int row = slot + SH::SLOTS * q;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) tb[row * CW + c] = zsub(tb[row * CW + c], acc[q][c]);
+            }
+        }
+        __syncthreads();
+        zero_acc();
+        // next: U1_k^H, the first product of step k + 1, or L21^H of the last block
+        tile_product<CW, NB, kLower, kFull, CT>(g, bufA, bufB, acc, tb, tile_at(k, 2),
+                                                last ? tile_at(nblk - 1, 1) : tile_at(k, 3));
+        reduce_rows<CW, NB, CT>(acc);
+        if (writer) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int row = slot + SH::SLOTS * q;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    vk[row * CW + c] = acc[q][c];
+                    if (c < ncw) yp[int64_t(k) * NB + row + int64_t(c0 + c) * a.npad] = acc[q][c];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // ---------------- Lhat^H sweep
+    for (int e = tid; e < NB * CW; e += NT) cbuf[0][e] = czero<CT>();
+    CT ynext[R][CW];
+    auto load_v = [&](int k, CT (&dst)[R][CW]) {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const bool ok = writer && k >= 0 && c < ncw;
+                const CT x = yp[ok ? int64_t(k) * NB + slot + SH::SLOTS * q + int64_t(c0 + c) * a.npad : 0];
+                dst[q][c] = ok ? x : czero<CT>();
+            }
+    };
+    load_v(nblk - 1, ynext);
+    __syncthreads();
+    int cb = 0;
+    for (int k = nblk - 1; k >= 0; --k) {
+        const CT *cur = cbuf[cb];
+        CT *curn = cbuf[cb ^ 1];
+        CT v[R][CW];
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) v[q][c] = ynext[q][c];
+        load_v(k - 1, ynext);
+        zero_acc();
+        tile_product<CW, NB, kFull, kUpper, CT>(g, bufA, bufB, acc, cur, tile_at(k, 1),
+                                                tile_at(k, 0));           // L21_k^H b
+        reduce_rows<CW, NB, CT>(acc);
+        if (writer) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int row = slot + SH::SLOTS * q;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) tb[row * CW + c] = zsub(v[q][c], acc[q][c]);
+            }
+        }
+        __syncthreads();
+        zero_acc();
+        tile_product<CW, NB, kUpper, kFull, CT>(g, bufA, bufB, acc, tb, tile_at(k, 0),
+                                                tile_at(max(k - 1, 0), 1));   // a' = Linv_k^H t
+        reduce_rows<CW, NB, CT>(acc);
+        if (writer) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int row = slot + SH::SLOTS * q;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) abuf[row * CW + c] = acc[q][c];
+            }
+        }
+        __syncthreads();
+        // [block k; block k+1] = P_k^T [a'; b]: window row i goes back to position perm[i]
+        const int rows = (k + 1 == nblk) ? NB : 2 * NB;
+        const int32_t *pk = perm + int64_t(k) * 2 * NB;
+        for (int e = tid; e < rows * CW; e += NT) {
+            const int i = e / CW, c = e % CW;
+            const CT val = i < NB ? abuf[e] : cur[e - NB * CW];
+            const int d = pk[i];
+            if (d < NB) curn[d * CW + c] = val;
+            else if (c < ncw)
+                xp[int64_t(k + 1) * NB + (d - NB) + int64_t(c0 + c) * a.npad] = zmul(wgt, to_zd(val));
+        }
+        __syncthreads();
+        cb ^= 1;
+    }
+    for (int e = tid; e < NB * CW; e += NT) {
+        const int i = e / CW, c = e % CW;
+        if (c < ncw) xp[i + int64_t(c0 + c) * a.npad] = zmul(wgt, to_zd(cbuf[cb][e]));
+    }
+}
+
+// Conjugate transposes of the factor tiles of pole src_pole (one workgroup per
+// (tile, block, destination pole)), through LDS in 32 x 32 pieces (whole tile below
+// 32): dst(r, c) = conj(src(c, r)).
+__global__ __launch_bounds__(256) void tiles_adjoint_kernel(const zd *src, zd *dst, int p, int nblk,
+                                                            int nb) {
+    const int t = blockIdx.x % 5, k = blockIdx.x / 5, pd = blockIdx.y;
+    const int ps = p - 1 - pd;                 // the adjoint pole pd is the conjugate of pole ps
+    const int64_t te = int64_t(nb) * nb;
+    const zd *S = src + ((int64_t(ps) * nblk + k) * 5 + t) * te;
+    zd *D = dst + ((int64_t(pd) * nblk + k) * 5 + t) * te;
+    __shared__ zd tile[32][33];
+    const int P = nb < 32 ? nb : 32;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;    // 32 x 8
+    for (int bc = 0; bc < nb; bc += P)
+        for (int br = 0; br < nb; br += P) {
+            // read the piece at rows br.., columns bc.. of S (coalesced down the columns)
+            for (int j = ty; j < P; j += 8)
+                if (tx < P) tile[j][tx] = S[(br + tx) + int64_t(bc + j) * nb];
+            __syncthreads();
+            // write it transposed to rows bc.., columns br.. of D
+            for (int j = ty; j < P; j += 8)
+                if (tx < P) {
+                    const zd v = tile[tx][j];
+                    D[(bc + tx) + int64_t(br + j) * nb] = zmake(v.x, -v.y);
+                }
+            __syncthreads();
+        }
+}
+
 // Z[:, c] = sum_pole xpart[pole][:, c]   (fixed order: deterministic)
 __global__ void pole_sum_kernel(const zd *xpart, int p, int64_t npad, int64_t n, int ncols,
                                 zd *Z, int64_t ldz) {
@@ -1056,23 +1278,44 @@ static size_t solve_lds(int nb, int cw, size_t elem) {
 }
 
 template <int CW, int NB, typename CT>
-static hipError_t launch_solve_nb(const SolveArgs &a, hipStream_t s) {
+static hipError_t launch_solve_nb(const SolveArgs &a, hipStream_t s, bool adjoint) {
     const int slices = (a.ncols + CW - 1) / CW;
-    hipLaunchKernelGGL((band_solve_kernel<CW, NB, CT>), dim3(slices * a.p), dim3(kSolveThreads),
-                       solve_lds(NB, CW, sizeof(CT)), s, a);
+    if (adjoint)
+        hipLaunchKernelGGL((band_solve_adj_kernel<CW, NB, CT>), dim3(slices * a.p),
+                           dim3(kSolveThreads), solve_lds(NB, CW, sizeof(CT)), s, a);
+    else
+        hipLaunchKernelGGL((band_solve_kernel<CW, NB, CT>), dim3(slices * a.p), dim3(kSolveThreads),
+                           solve_lds(NB, CW, sizeof(CT)), s, a);
     return hipGetLastError();
 }
 
 template <int CW, typename CT>
-static hipError_t launch_solve_cw(const SolveArgs &a, hipStream_t s) {
+static hipError_t launch_solve_cw(const SolveArgs &a, hipStream_t s, bool adjoint = false) {
     switch (a.nb) {
-        case 16: return launch_solve_nb<CW, 16, CT>(a, s);
-        case 32: return launch_solve_nb<CW, 32, CT>(a, s);
-        case 64: return launch_solve_nb<CW, 64, CT>(a, s);
-        case 128: return launch_solve_nb<CW, 128, CT>(a, s);
-        case 256: return launch_solve_nb<CW, 256, CT>(a, s);
+        case 16: return launch_solve_nb<CW, 16, CT>(a, s, adjoint);
+        case 32: return launch_solve_nb<CW, 32, CT>(a, s, adjoint);
+        case 64: return launch_solve_nb<CW, 64, CT>(a, s, adjoint);
+        case 128: return launch_solve_nb<CW, 128, CT>(a, s, adjoint);
+        case 256: return launch_solve_nb<CW, 256, CT>(a, s, adjoint);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_tiles_adjoint(const rf_plan &P, const rf_plan &parent, hipStream_t s) {
+    const int p = P.opts.p, nblk = P.F.nblk, nb = P.F.nb;
+    if (parent.opts.p != p || parent.F.nblk != nblk || parent.F.nb != nb) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tiles_adjoint_kernel, dim3(nblk * 5, p), dim3(256), 0, s, parent.F.tiles,
+                       P.F.tiles, p, nblk, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t pb = size_t(nblk) * 2 * nb * sizeof(int32_t);
+    for (int i = 0; i < p; ++i) {
+        e = hipMemcpyAsync(P.F.perm + int64_t(i) * nblk * 2 * nb,
+                           parent.F.perm + int64_t(p - 1 - i) * nblk * 2 * nb, pb,
+                           hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 namespace {
@@ -1137,6 +1380,8 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
     hipError_t e;
     hipEvent_t ev0 = nullptr;
     if (buf.profile) P.prof.record_begin(s, ev0);
+    const bool adj = P.F.adjoint;
+    if (adj && (c64 || colw)) return hipErrorInvalidValue;
     if (c64) {
         switch (cw) {
             case 1: e = launch_solve_cw<1, zf>(a, s); break;
@@ -1145,9 +1390,9 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
         }
     } else {
         switch (cw) {
-            case 1: e = launch_solve_cw<1, zd>(a, s); break;
-            case 2: e = launch_solve_cw<2, zd>(a, s); break;
-            default: e = launch_solve_cw<4, zd>(a, s); break;
+            case 1: e = launch_solve_cw<1, zd>(a, s, adj); break;
+            case 2: e = launch_solve_cw<2, zd>(a, s, adj); break;
+            default: e = launch_solve_cw<4, zd>(a, s, adj); break;
         }
     }
     if (e != hipSuccess) return e;

@@ -78,6 +78,8 @@ struct BandFactors {
     int32_t *subperm = nullptr; // p * 2nb: row order of the current sub-panel
     int32_t *info = nullptr;   // p ints: 0 or (1 + first zero-pivot column)
     zf *tiles32 = nullptr;     // complex64 copy of tiles (precision form), or null
+    bool adjoint = false;      // tiles hold the conjugate transposes of another plan's
+                               // factors (adjoint pencil): solves run the K^H sweeps
     bool ready = false;
 };
 
@@ -159,6 +161,7 @@ struct rf_plan {
     std::string last_error;
     bool broken = false;
     bool shared_factors = false;  // F.tiles/perm/info belong to a batch's factor owner
+    const rf_plan *adj_parent = nullptr;  // adjoint plan: the plan whose factors it transposes
     // precision form: per-(shift, column) combine coefficients and per-(pole, column)
     // inner weights of the residual form
     zd *d_colcoef = nullptr;  // nq x w
@@ -199,6 +202,9 @@ hipError_t launch_inner_apply_static(const rf_plan &P, const zd *X, int64_t ldx,
                                      zd *Z, int64_t ldz, hipStream_t s);
 size_t inner_scratch_capacity();                    // bytes of that array
 size_t inner_scratch_per_column(const rf_plan &P);  // its bytes per column, unaligned
+// the adjoint plan P's tiles and row orders from the factorization of `parent`
+// (P's pole i is the conjugate of parent's pole p-1-i): conjugate-transposed tiles
+hipError_t launch_tiles_adjoint(const rf_plan &P, const rf_plan &parent, hipStream_t s);
 // complex64 copy of the factor tiles (after the complex128 factorization)
 hipError_t launch_tiles_to_c64(const rf_plan &P, hipStream_t s);
 

@@ -355,7 +355,9 @@ class Plan:
                    "ms": info.ms_total}
 
     def adjoint(self, stream=None):
-        """rf_plan_create_adjoint: plan of (A^H, B^H) over D(conj c, r)."""
+        """rf_plan_create_adjoint: plan of (A^H, B^H) over D(conj c, r) whose solves use
+        the conjugate transposes of this plan's factors (factor_shifts on it transposes
+        them; this plan must be factorized first)."""
         torch = _torch()
         stream = self.stream if stream is None else stream
         handle = _P()
@@ -369,6 +371,7 @@ class Plan:
         P._h = handle
         P._owned = True
         P.allocator = self.allocator          # the adjoint plan uses the same callbacks
+        P._parent = self                      # whose factors it transposes: kept alive
         P.opts = self.opts
         P.stream = stream
         P.n = self.n

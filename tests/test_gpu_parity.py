@@ -106,6 +106,22 @@ def _dense_bar(name, A, B, c, r, p, q, Y):
     return _DENSE[key]
 
 
+_GBAR = {}
+
+
+def _g_bar(name, A, B, c, r, p):
+    """Bar for G(X) against the oracle: both sides solve with backward-stable band
+    LUs of the K_i, so they agree to about cond(K_i) u: max(1e-12, 16 u max cond_2(K_i)),
+    the condition numbers computed densely."""
+    from oracle import coeffs
+    if name not in _GBAR:
+        Ad, Bd = A.toarray(), B.toarray()
+        poles, _ = coeffs.trapezoid_nodes(c, r, p)
+        ck = max(float(np.linalg.cond(z * Bd - Ad)) for z in poles)
+        _GBAR[name] = max(1e-12, 16.0 * U_ROUND * ck)
+    return _GBAR[name]
+
+
 def _to_host(X):
     return X.cpu().numpy()
 
@@ -144,6 +160,54 @@ def test_inner_apply_matches_oracle(rf, torch_cuda, case, ncols):
     ref = filters.InnerOperator(A, B, c, r, p)(X)
     e = _colerr(Z, ref)
     assert e.max() <= 1e-12, (name, e.max())
+
+
+@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("ncols", [1, 7, 32])
+def test_adjoint_inner_apply_matches_oracle(rf, torch_cuda, case, ncols):
+    # the adjoint plan solves with the conjugate transposes of the plan's factors
+    # (K_i^H = U_i^H L_i^H P_i^T); its G must equal the oracle's G of the adjoint pencil
+    # (A^H, B^H) over the mirrored disk, factorized on its own
+    from oracle import filters
+    name, A, B, c, r = _pencils()[case]
+    _say(f"adjoint inner_apply {name} ncols={ncols}")
+    plan = rf.Plan(A, B, c, r, p=4, q=4, w=32)
+    plan.factor_shifts()
+    adj = plan.adjoint()
+    adj.factor_shifts()
+    X = W.start_block(A.shape[0], ncols, seed=9)
+    Z = _to_host(adj.apply_inner(torch_cuda.from_numpy(X).cuda()))
+    AH, BH = A.conj().T.tocsr(), B.conj().T.tocsr()
+    ref = filters.InnerOperator(AH, BH, np.conj(c), r, 4)(X)
+    e = _colerr(Z, ref)
+    bar = _g_bar(name, A, B, c, r, 4)
+    print(f"adjoint G {name} ncols={ncols}: per-column error {e.max():.2e} (bar {bar:.1e})")
+    assert e.max() <= bar, (name, e.max())
+    # no factorization of its own: it holds only the transposed tiles and row orders
+    assert adj.device_bytes < plan.device_bytes
+    adj.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("tile", [16, 32, 64, 128, 256])
+def test_adjoint_inner_apply_tiles(rf, torch_cuda, tile):
+    from oracle import filters
+    A, B = W.convdiff_pencil(12, mass=(0.5, 1.5), seed=5)           # kl = 12, N = 144
+    c, r = 300 + 0.05j, 100.0
+    X = W.start_block(A.shape[0], 13, seed=2)
+    ref = filters.InnerOperator(A.conj().T.tocsr(), B.conj().T.tocsr(), np.conj(c), r, 3)(X)
+    _say(f"adjoint inner_apply tile={tile}")
+    plan = rf.Plan(A, B, c, r, p=3, q=4, w=16, tile=tile)
+    adj = plan.adjoint()
+    with pytest.raises(rf.RfError) as ei:            # the plan has no factors yet
+        adj.factor_shifts()
+    assert ei.value.status == rf.RF_ERR_STATE
+    plan.factor_shifts()
+    adj.factor_shifts()
+    Z = _to_host(adj.apply_inner(torch_cuda.from_numpy(X).cuda()))
+    assert _colerr(Z, ref).max() <= 1e-12, (tile, _colerr(Z, ref).max())
+    adj.close()
+    plan.close()
 
 
 def test_inner_apply_tile_override_and_column_slices(rf, torch_cuda):

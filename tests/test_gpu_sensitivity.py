@@ -195,7 +195,17 @@ def test_velocity_gradient_small(rf, torch_cuda):
 
 
 def test_full_size_velocity_gradient_fd(rf, torch_cuda):
+    # the differentiation workload: 128 x 128 grid, per-cell velocity U[-20, 20]^2, 52
+    # eigenvalues in the disk; loss L = sum_i |lambda_i - t_i|^2 with targets
+    # t_i = lambda_i(v0) + 0.01 xi_i (xi seeded complex Gaussian); dL/dv from the adjoint
+    # solves (K_i^H sweeps over the right problem's factors) and rf_eig_vjp, against
+    # central differences of re-solved eigenvalues on 32 random cells.  Step sweep:
+    # h = 2e-3 and 1e-3 and their Richardson combination (4 D(h/2) - D(h)) / 3 (the
+    # eigenvalues are smooth in v away from the upwind switch at v = 0, so cells have
+    # |v| > 10 h); the best of the three must be within 1e-6.  h = 1e-6 is printed as
+    # measured: there the rounding of the eigenvalues (about 1e-12 absolute) dominates.
     import torch
+    from scipy.optimize import linear_sum_assignment
     wl = W.random_velocity_workload()
     n = 128
     sys.path.insert(0, __file__.rsplit("/", 1)[0])
@@ -207,13 +217,16 @@ def test_full_size_velocity_gradient_fd(rf, torch_cuda):
     b_vals = torch.from_numpy(wl.B.data.copy())
     v = wl.vfield
     vt = torch.from_numpy(v.copy()).requires_grad_(True)
-    _say("velocity gradient convdiff128 random field (52 inside)")
+    _say("velocity gradient convdiff128 random field (52 inside), target loss")
     lam = rf.disk_eigenvalues(asm.values(vt), b_vals, wl.A, wl.B, wl.c, wl.r, Y0, Y0a,
                               p=wl.p, q=wl.q, w=wl.w, expected_count=wl.s_expected,
                               max_krylov_blocks=60)
     assert len(lam) == wl.s_expected
-    # loss: the real part of the eigenvalue sum (the trace of the projected pencil)
-    loss = torch.sum(lam.real)
+    rng = np.random.default_rng(21)
+    xi = rng.standard_normal(len(lam)) + 1j * rng.standard_normal(len(lam))
+    lam0 = lam.detach().numpy().copy()
+    tgt = lam0 + 0.01 * xi
+    loss = torch.sum(torch.abs(lam - torch.from_numpy(tgt)) ** 2)
     loss.backward()
     grad = vt.grad.numpy()
 
@@ -224,18 +237,32 @@ def test_full_size_velocity_gradient_fd(rf, torch_cuda):
         res = P.solve_region(Y0)
         P.close()
         assert res["count"] == wl.s_expected
-        return float(np.sum(res["lam"].real))
+        # the perturbed eigenvalues, matched to the base ones by minimum-cost assignment
+        cost = np.abs(lam0[:, None] - res["lam"][None, :])
+        r_, c_ = linear_sum_assignment(cost)
+        lam1 = np.empty_like(lam0)
+        lam1[r_] = res["lam"][c_]
+        return float(np.sum(np.abs(lam1 - tgt) ** 2))
 
-    rng = np.random.default_rng(11)
-    h = 1e-3
-    # cells where the gradient is not negligible and |v| > 10 h (away from the upwind switch)
-    mag = np.abs(grad)
-    cand = np.argwhere((mag > 1e-3 * mag.max()) & (np.abs(v) > 10 * h))
-    picks = cand[rng.choice(len(cand), size=3, replace=False)]
-    for comp, iy, ix in picks:
+    def fd(comp, iy, ix, h):
         vp = v.copy(); vp[comp, iy, ix] += h
         vm = v.copy(); vm[comp, iy, ix] -= h
-        fd = (L(vp) - L(vm)) / (2 * h)
-        rel = abs(fd - grad[comp, iy, ix]) / abs(grad[comp, iy, ix])
-        _say(f"  cell {(int(comp), int(iy), int(ix))} grad {grad[comp, iy, ix]:.6e} fd {fd:.6e} rel {rel:.2e}")
-        assert rel <= 1e-4
+        return (L(vp) - L(vm)) / (2 * h)
+
+    mag = np.abs(grad)
+    hmax = 2e-3
+    cand = np.argwhere((mag >= 0.05 * mag.max()) & (np.abs(v) > 10 * hmax))
+    picks = cand[rng.choice(len(cand), size=32, replace=False)]
+    best = []
+    for comp, iy, ix in picks:
+        g = grad[comp, iy, ix]
+        d1, d2 = fd(comp, iy, ix, 2e-3), fd(comp, iy, ix, 1e-3)
+        rich = (4.0 * d2 - d1) / 3.0
+        errs = [abs(d - g) / abs(g) for d in (d1, d2, rich)]
+        tiny = abs(fd(comp, iy, ix, 1e-6) - g) / abs(g)
+        best.append(min(errs))
+        _say(f"  cell {(int(comp), int(iy), int(ix))} grad {g:.6e}: rel err h=2e-3 {errs[0]:.1e}, "
+             f"h=1e-3 {errs[1]:.1e}, Richardson {errs[2]:.1e}; h=1e-6 {tiny:.1e}")
+    best = np.array(best)
+    print(f"32 cells: best-of-sweep relative error max {best.max():.2e} median {np.median(best):.2e}")
+    assert best.max() <= 1e-6, best.max()
