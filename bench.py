@@ -59,6 +59,35 @@ def solve_bytes_per_launch(n, kl, ku, p, cols):
     return factor + cols * n * 16 * (1 + p)
 
 
+def host_cpu():
+    """(model name, logical CPUs available to this process)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    return model, ncpu
+
+
+def _oracle_pole_term(args):
+    """One pole's term w_i K_i^{-1} B X of the oracle's inner operator (a worker of the
+    all-cores CPU baseline)."""
+    name, idx, seed, width = args
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    from oracle import filters
+    from paper_2310_18043_amd import workloads as W
+    wl = W.convdiff_workload()
+    X = W.start_block(wl.n, width, seed)
+    return filters.simple_filter_terms(wl.A, wl.B, wl.c, wl.r, wl.p, X, idx)
+
+
 def cpu_baseline(wl, cols_per_step):
     """Time the CPU oracle on a bounded sample of the workload and scale it to
     eigenpairs/s.
@@ -91,15 +120,121 @@ def cpu_baseline(wl, cols_per_step):
                 cols_per_step = sum(json.loads(line.split("inner_applications=")[1].strip()))
                 src = "the oracle's own full run, tests/golden/convdiff128_eigs.txt"
     est = t_fact + cols_per_step * t_col
+    model, ncpu = host_cpu()
+    # all cores: the p poles' factorizations and solves in p worker processes (the
+    # oracle's band LU and solves are single-threaded C), timed end to end
+    nproc = max(1, min(wl.p, ncpu))
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(nproc) as pool:
+        pool.map(_oracle_pole_term, [("w", [0], 1, 1)] * nproc)          # start the workers
+        t2 = time.time()
+        pool.map(_oracle_pole_term, [("w", [i], wl.seed, X.shape[1]) for i in range(wl.p)])
+        t_par = time.time() - t2
+    # per pole: one factorization + one application to the whole block
+    t_col_par = max(t_par - t_fact / wl.p * np.ceil(wl.p / nproc), 1e-9) / X.shape[1]
+    est_par = t_fact / wl.p * np.ceil(wl.p / nproc) + cols_per_step * t_col_par
     return {
         "value": float(wl.s_expected / est), "unit": "eigenpairs/s", "cores": 1,
-        "kind": "oracle",
+        "kind": "oracle", "cpu": model, "cpus_available": ncpu,
         "sample": (f"oracle band LU of the {wl.p} shifted pencils ({t_fact:.1f} s) and {reps} "
                    f"applications of G to the {X.shape[1]}-column start block ({t_apply:.1f} s each), "
                    f"one thread; scaled to {wl.p} factorizations + {cols_per_step:.0f} G columns "
                    f"per solve ({src}) = {est:.0f} s for {wl.s_expected} pairs; "
                    f"orthogonalisation, least squares and projection not included"),
+        "all_cores": {"value": float(wl.s_expected / est_par), "unit": "eigenpairs/s",
+                      "cores": nproc,
+                      "sample": (f"the same sample with the {wl.p} poles in {nproc} processes "
+                                 f"({t_par:.1f} s for factorization + one application), scaled the "
+                                 f"same way = {est_par:.0f} s; the oracle parallelizes over poles only")},
     }
+
+
+def toeplitz_form(balanced, reps):
+    """The tridiagonal Toeplitz pencil (n = 2000, a = 0, b = 1, c = 0.5 e^{i pi/3}, B = I),
+    disk c = 0.3 + 0.2i enclosing 20 eigenvalues, p = q = 4, w = 32.  The balanced
+    variant (normal) is checked against the closed-form eigenvalues; the literal one is
+    exponentially non-normal (kappa(X) ~ 2^1000), so its pairs are pseudo-eigenpairs
+    that can meet the residual bar while missing the closed form: reported as measured."""
+    import torch
+    from paper_2310_18043_amd import rfeig
+    from paper_2310_18043_amd import workloads as W
+    wl = W.toeplitz_workload(n=2000, balanced=balanced, w=32, count=20)
+    exact = W.toeplitz_eigs(wl.n, 0, 1, W.TOEPLITZ_C)
+    inside = exact[np.abs(exact - wl.c) < wl.r]
+    P = rfeig.Plan(wl.A, wl.B, wl.c, wl.r, p=4, q=4, w=32, expected_count=20)
+    Y0 = torch.from_numpy(W.start_block(wl.n, 32, 0)).cuda()
+
+    def step():
+        P.factor_shifts()
+        return P.solve_region(Y0, allow_noconv=True)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / reps
+    good = (np.abs(res["lam"] - wl.c) < wl.r) & (res["err"] <= 1e-10)
+    matched = 0
+    if len(res["lam"]):
+        d = np.abs(res["lam"][:, None] - inside[None, :]).min(axis=1)
+        matched = int(np.sum(good & (d <= 1e-10 * np.abs(res["lam"]))))
+    P.close()
+    return {"workload": f"toeplitz_n2000_{'balanced' if balanced else 'literal'}_p4_q4_w32",
+            "ms_per_step": round(ms, 3), "converged_count": int(good.sum()),
+            "closed_form_matched": matched, "closed_form_inside": int(len(inside)),
+            "sweeps": res["sweeps"], "krylov_steps": res["krylov_steps"],
+            "value": round(int(good.sum()) / (ms / 1000.0), 3), "unit": "eigenpairs/s"}
+
+
+def convdiff256_form(reps):
+    """The 256 x 256 random-velocity workload (N = 65536, bandwidth 256, 187 eigenvalues
+    in the disk, p = q = 8, w = 256): plain complex128 against the precision form
+    (complex64 band solves, complex128 outer solves, residual form from the second
+    sweep), same start block; band-solve rates of both."""
+    import torch
+    from paper_2310_18043_amd import rfeig
+    from paper_2310_18043_amd import workloads as W
+    wl = W.convdiff256_workload()
+    Y0 = torch.from_numpy(W.start_block(wl.n, wl.w, wl.seed)).cuda()
+    fl_col = solve_flops_per_column(wl.n, 256, 256, wl.p)
+    out = {"workload": "convdiff256_randv_p8_q8_w256", "n": wl.n, "bandwidth": 256,
+           "expected_count": wl.s_expected}
+    for key, prec in (("plain_c128", 0), ("precision_c64", 1)):
+        P = rfeig.Plan(wl.A, wl.B, wl.c, wl.r, p=wl.p, q=wl.q, w=wl.w,
+                       expected_count=wl.s_expected, max_krylov_blocks=60, precision=prec)
+
+        def step():
+            P.factor_shifts()
+            return P.solve_region(Y0, allow_noconv=True)
+
+        step()
+        torch.cuda.synchronize()
+        P.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / reps
+        st = P.profile_read()
+        P.profile_enable(False)
+        good = (np.abs(res["lam"] - wl.c) < wl.r) & (res["err"] <= 1e-10)
+        t = fl_col * st["solve_columns"] / (st["solve_ms"] * 1e-3) / 1e12
+        peak = PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP32_TFLOPS
+        out[key] = {"ms_per_step": round(ms, 3), "converged_count": int(good.sum()),
+                    "value": round(int(good.sum()) / (ms / 1000.0), 3), "unit": "eigenpairs/s",
+                    "sweeps": res["sweeps"], "krylov_steps": res["krylov_steps"],
+                    "max_err": float(res["err"].max()) if len(res["err"]) else None,
+                    "factor_ms": round(st["factor_ms"] / reps, 3),
+                    "band_solve": {"avg_launch_ms": round(st["solve_ms"] / max(st["solve_launches"], 1), 4),
+                                   "avg_columns_per_launch": round(st["solve_columns"] / max(st["solve_launches"], 1), 2),
+                                   "achieved": round(t, 3), "peak": peak, "unit": "TFLOP/s",
+                                   "frac": round(t / peak, 4)}}
+        P.close()
+    out["precision_speedup"] = round(out["plain_c128"]["ms_per_step"] / out["precision_c64"]["ms_per_step"], 3)
+    return out
 
 
 def batched_form(ndisks, reps):
@@ -274,6 +409,10 @@ def main():
                     help="skip the precision-form (complex64 band solves) measurement")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the differentiation-form measurement")
+    ap.add_argument("--no-convdiff256", action="store_true",
+                    help="skip the 256 x 256 workload (plain and precision form)")
+    ap.add_argument("--no-toeplitz", action="store_true",
+                    help="skip the Toeplitz workload (balanced and literal)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -475,6 +614,16 @@ def main():
         grad = gradient_form(min(args.steps, 2))
         log(f"gradient: {grad}")
 
+    cd256 = None
+    if not args.no_convdiff256:
+        cd256 = convdiff256_form(min(args.steps, 2))
+        log(f"convdiff256: {cd256}")
+
+    toep = None
+    if not args.no_toeplitz:
+        toep = [toeplitz_form(True, min(args.steps, 2)), toeplitz_form(False, min(args.steps, 2))]
+        log(f"toeplitz: {toep}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -504,6 +653,8 @@ def main():
         "batched": bt,
         "gradient": grad,
         "circuit": circ,
+        "convdiff256": cd256,
+        "toeplitz": toep,
         "phases_ms": {"factor": round(stats["factor_ms"] / max(args.steps, 1), 3),
                       "filter": round(res["ms_filter"], 3), "hsrr": round(res["ms_hsrr"], 3)},
     }

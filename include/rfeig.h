@@ -78,6 +78,9 @@ typedef struct {
                                 (complex128) factors for every band solve, the outer GMRES to
                                 max(gmres_tol, 1e-6), and from the second sweep of rf_solve_region on
                                 the filter applied through the complex128 residual of the Ritz pairs */
+    int32_t refine;          /* precision form: FP64 iterative-refinement steps of every shifted solve
+                                K_i x = b (0..4): r = b - K_i x in complex128 from the sparse A and B,
+                                x += K_i^{-1} r with the complex64 factors; 0 with precision 0 */
 } rf_opts;
 
 /* Per-call statistics of a filter application. */

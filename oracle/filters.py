@@ -51,3 +51,20 @@ class InnerOperator:
 def simple_filter(A, B, c: complex, r: float, k: int, Y: np.ndarray) -> np.ndarray:
     """R_{c,r,k}(B^{-1}A) Y by k independent direct band solves."""
     return InnerOperator(A, B, c, r, k)(Y)
+
+
+def simple_filter_terms(A, B, c: complex, r: float, k: int, Y: np.ndarray, indices) -> np.ndarray:
+    """The terms i in ``indices`` of the simple rule, sum_i w_i (p_i B - A)^{-1} B Y,
+    summed in the given order (the poles one at a time, so that the k terms can be
+    formed in separate processes and added afterwards)."""
+    A, B = A.tocsr(), B.tocsr()
+    poles, weights = coeffs.trapezoid_nodes(c, r, k)
+    kl, ku = pencil_bandwidths(A, B)
+    BY = B @ np.asarray(Y, dtype=np.complex128)
+    out = np.zeros_like(BY)
+    for i in indices:
+        f = banded.band_lu(poles[i] * B - A, kl, ku)
+        if f.info != 0:
+            raise ZeroDivisionError(f"exact zero pivot at pole {poles[i]}")
+        out = out + weights[i] * f.solve(BY)
+    return out

@@ -267,6 +267,7 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
     if (o.trsm_cols < 0 || o.trsm_cols > 8) return RF_ERR_ARG;
     if (o.q_max < 0 || o.q_max > 256) return RF_ERR_ARG;
     if (o.precision < 0 || o.precision > 1) return RF_ERR_ARG;
+    if (o.refine < 0 || o.refine > 4 || (o.refine > 0 && o.precision != 1)) return RF_ERR_ARG;
 
     rf_plan *P = new rf_plan();
     if (allocator) P->alloc = *allocator;
@@ -430,6 +431,7 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
     ALLOC(P->rhs, npad * w);
     ALLOC(P->ypart, int64_t(o.p) * npad * w);
     ALLOC(P->xpart, int64_t(o.p) * npad * w);
+    if (o.refine > 0) ALLOC(P->refres, int64_t(o.p) * npad * w);
     ALLOC(P->ytil, n * w);
     ALLOC(P->tmp, n * w);
     ALLOC(P->Wk, n * w);

@@ -556,6 +556,10 @@ struct SolveArgs {
     void *ypart;             // [pole][npad x ncols]  forward results (tile precision)
     zd *xpart;               // [pole][npad x ncols]  weight * K_i^{-1} B X
     int64_t npad;
+    int64_t x_pole_stride;   // 0: one right-hand side block for all poles; else pole i's
+                             // block starts at X + i * x_pole_stride (refinement residuals)
+    int unit_weight;         // 1: no pole weight (the solution of K_i d = r itself)
+    int accumulate;          // 1: xpart += solution (refinement correction), else xpart =
 };
 
 // complex64 helpers for the single-precision tiles
@@ -813,6 +817,7 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
     };
 
     // right-hand sides: rows of block blk, element e of the [NB][CW] block
+    const zd *Xp = a.X + int64_t(pole) * a.x_pole_stride;
     constexpr int RPT = (NB * CW + NT - 1) / NT;
     CT pre[RPT];
     auto prefetch_rhs = [&](int blk) __attribute__((always_inline)) {
@@ -822,7 +827,7 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
             const int r = e / CW, c = e % CW;
             const int64_t row = int64_t(blk) * NB + r;
             const bool ok = blk < nblk && e < NB * CW && row < a.n && c < ncw;
-            zd x = a.X[ok ? row + int64_t(c0 + c) * a.ldx : 0];
+            zd x = Xp[ok ? row + int64_t(c0 + c) * a.ldx : 0];
             if (a.bdiag) x = zmul(a.bdiag[ok ? row : 0], x);
             pre[q] = ok ? from_zd<CT>(x) : czero<CT>();
         }
@@ -957,8 +962,11 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
                 for (int c = 0; c < CW; ++c) {
                     xk[row * CW + c] = acc[q][c];
                     if (c < ncw) {
-                        const zd wc = a.colw ? a.colw[int64_t(pole) * a.ncols + c0 + c] : wgt;
-                        xp[int64_t(k) * NB + row + int64_t(c0 + c) * a.npad] = zmul(wc, to_zd(acc[q][c]));
+                        const zd wc = a.unit_weight ? zmake(1.0, 0.0)
+                                    : a.colw ? a.colw[int64_t(pole) * a.ncols + c0 + c] : wgt;
+                        zd *dst = xp + int64_t(k) * NB + row + int64_t(c0 + c) * a.npad;
+                        const zd val = zmul(wc, to_zd(acc[q][c]));
+                        *dst = a.accumulate ? zadd(*dst, val) : val;
                     }
                 }
             }
@@ -1191,6 +1199,38 @@ __global__ __launch_bounds__(256) void tiles_adjoint_kernel(const zd *src, zd *d
         }
 }
 
+// FP64 residual of the shifted solves for iterative refinement, every pole at once:
+// res_i = w b - K_i x_i = w b - p_i B x_i + A x_i, with x_i = xpart[pole] (which holds
+// w K_i^{-1} b from the complex64 solve) and b = B X (bdiag: diagonal B; rhsb: B X
+// already formed; neither: b = X).  w is the pole weight, or the per-(pole, column)
+// weight of the residual form (colw).  One thread per (row, column, pole).
+__global__ void refine_residual_kernel(int n, int ncols, int p, int64_t npad, const zd *X, int64_t ldx,
+                                       const zd *bdiag, const zd *rhsb, const int32_t *arow,
+                                       const int32_t *acol, const zd *aval, const int32_t *brow,
+                                       const int32_t *bcol, const zd *bval, const zd *poles,
+                                       const zd *weights, const zd *colw, const zd *xpart, zd *res) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = int64_t(n) * ncols;
+    if (e >= per * p) return;
+    const int pole = int(e / per);
+    const int64_t rc = e % per;
+    const int row = int(rc % n), c = int(rc / n);
+    const zd *x = xpart + int64_t(pole) * npad * ncols + int64_t(c) * npad;
+    zd b;
+    if (rhsb) b = rhsb[row + int64_t(c) * npad];
+    else {
+        b = X[row + int64_t(c) * ldx];
+        if (bdiag) b = zmul(bdiag[row], b);
+    }
+    const zd w = colw ? colw[int64_t(pole) * ncols + c] : weights[pole];
+    zd r = zmul(w, b);
+    zd bx = zmake(0, 0);
+    for (int q = brow[row]; q < brow[row + 1]; ++q) zfma(bx, bval[q], x[bcol[q]]);
+    zfms(r, poles[pole], bx);
+    for (int q = arow[row]; q < arow[row + 1]; ++q) zfma(r, aval[q], x[acol[q]]);
+    res[int64_t(pole) * npad * ncols + int64_t(c) * npad + row] = r;
+}
+
 // Z[:, c] = sum_pole xpart[pole][:, c]   (fixed order: deterministic)
 __global__ void pole_sum_kernel(const zd *xpart, int p, int64_t npad, int64_t n, int ncols,
                                 zd *Z, int64_t ldz) {
@@ -1343,6 +1383,7 @@ struct InnerBufs {
     zd *rhs;
     void *ypart;
     zd *xpart;
+    zd *refres;          // refinement residuals (plans with refine > 0)
     bool profile;        // record the solve launch in the plan's kernel statistics
 };
 
@@ -1358,6 +1399,7 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
     a.perm = P.F.perm; a.weights = P.d_weights; a.colw = colw;
     a.ypart = buf.ypart; a.xpart = buf.xpart;
     a.npad = int64_t(P.F.nblk) * P.F.nb;
+    a.x_pole_stride = 0; a.unit_weight = 0; a.accumulate = 0;
     if (!apply_b) {
         a.X = X; a.ldx = ldx; a.bdiag = nullptr;
     } else if (P.B.diagonal) {
@@ -1382,20 +1424,42 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
     if (buf.profile) P.prof.record_begin(s, ev0);
     const bool adj = P.F.adjoint;
     if (adj && (c64 || colw)) return hipErrorInvalidValue;
-    if (c64) {
-        switch (cw) {
-            case 1: e = launch_solve_cw<1, zf>(a, s); break;
-            case 2: e = launch_solve_cw<2, zf>(a, s); break;
-            default: e = launch_solve_cw<4, zf>(a, s); break;
+    auto solve = [&](const SolveArgs &sa) -> hipError_t {
+        if (c64) {
+            switch (cw) {
+                case 1: return launch_solve_cw<1, zf>(sa, s);
+                case 2: return launch_solve_cw<2, zf>(sa, s);
+                default: return launch_solve_cw<4, zf>(sa, s);
+            }
         }
-    } else {
         switch (cw) {
-            case 1: e = launch_solve_cw<1, zd>(a, s, adj); break;
-            case 2: e = launch_solve_cw<2, zd>(a, s, adj); break;
-            default: e = launch_solve_cw<4, zd>(a, s, adj); break;
+            case 1: return launch_solve_cw<1, zd>(sa, s, adj);
+            case 2: return launch_solve_cw<2, zd>(sa, s, adj);
+            default: return launch_solve_cw<4, zd>(sa, s, adj);
         }
-    }
+    };
+    e = solve(a);
     if (e != hipSuccess) return e;
+    // FP64 iterative refinement of every shifted solve: residual in complex128 from the
+    // sparse A and B, correction with the complex64 factors, added to the solution
+    const int nref = c64 ? P.opts.refine : 0;
+    if (nref > 0 && !buf.refres) return hipErrorInvalidValue;
+    for (int it = 0; it < nref; ++it) {
+        const int64_t tot = int64_t(P.n) * ncols * a.p;
+        hipLaunchKernelGGL(refine_residual_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, int(P.n),
+                           ncols, a.p, a.npad, X, ldx, (apply_b && P.B.diagonal) ? P.B.dval : nullptr,
+                           (apply_b && !P.B.diagonal) ? buf.rhs : nullptr, P.A.rowptr, P.A.colind,
+                           P.A.val, P.B.rowptr, P.B.colind, P.B.val, P.d_poles, P.d_weights, colw,
+                           buf.xpart, buf.refres);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        SolveArgs ra = a;
+        ra.X = buf.refres; ra.ldx = a.npad; ra.bdiag = nullptr;
+        ra.x_pole_stride = a.npad * ncols;
+        ra.unit_weight = 1; ra.accumulate = 1;
+        e = solve(ra);
+        if (e != hipSuccess) return e;
+    }
     if (buf.profile) P.prof.record_end(s, ev0, ncols, 0);
     int64_t tot = P.n * ncols;
     hipLaunchKernelGGL(pole_sum_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, buf.xpart, a.p,
@@ -1408,7 +1472,7 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
 hipError_t launch_inner_apply(const rf_plan &P, const zd *X, int64_t ldx, int ncols, zd *Z,
                               int64_t ldz, hipStream_t s, bool apply_b, const zd *colw) {
     return inner_apply_core(P, X, ldx, ncols, Z, ldz, s, apply_b, colw,
-                            InnerBufs{P.rhs, P.ypart, P.xpart, true});
+                            InnerBufs{P.rhs, P.ypart, P.xpart, P.refres, true});
 }
 
 // ---------------------------------------------------------------------------
@@ -1436,7 +1500,8 @@ size_t inner_scratch_per_column(const rf_plan &P) {
     const int64_t npad = int64_t(P.F.nblk) * P.F.nb;
     const size_t ye = P.opts.precision == 1 ? sizeof(zf) : sizeof(zd);
     const size_t rhs = P.B.diagonal ? 0 : size_t(npad) * sizeof(zd);
-    return rhs + size_t(P.opts.p) * npad * (ye + sizeof(zd));
+    const size_t ref = P.opts.precision == 1 && P.opts.refine > 0 ? sizeof(zd) : 0;
+    return rhs + size_t(P.opts.p) * npad * (ye + sizeof(zd) + ref);
 }
 
 hipError_t launch_inner_apply_static(const rf_plan &P, const zd *X, int64_t ldx, int ncols,
@@ -1460,10 +1525,12 @@ hipError_t launch_inner_apply_static(const rf_plan &P, const zd *X, int64_t ldx,
     const size_t ye = P.opts.precision == 1 ? sizeof(zf) : sizeof(zd);
     // columns per chunk: the largest count whose three blocks (each 256-byte aligned) fit
     int chunk = ncols;
+    const bool ref = P.opts.precision == 1 && P.opts.refine > 0;
     auto need = [&](int k) {
         const size_t rhs = P.B.diagonal ? 0 : align256(size_t(npad) * k * sizeof(zd));
         return rhs + align256(size_t(P.opts.p) * npad * k * ye) +
-               align256(size_t(P.opts.p) * npad * k * sizeof(zd));
+               align256(size_t(P.opts.p) * npad * k * sizeof(zd)) +
+               (ref ? align256(size_t(P.opts.p) * npad * k * sizeof(zd)) : 0);
     };
     while (chunk > 0 && need(chunk) > kScratchBytes) --chunk;
     if (chunk == 0) return hipErrorInvalidValue;          // one column does not fit
@@ -1480,6 +1547,8 @@ hipError_t launch_inner_apply_static(const rf_plan &P, const zd *X, int64_t ldx,
         buf.ypart = b + off;
         off += align256(size_t(P.opts.p) * npad * k * ye);
         buf.xpart = reinterpret_cast<zd *>(b + off);
+        off += align256(size_t(P.opts.p) * npad * k * sizeof(zd));
+        buf.refres = ref ? reinterpret_cast<zd *>(b + off) : nullptr;
         buf.profile = false;
         e = inner_apply_core(P, X + int64_t(c0) * ldx, ldx, k, Z + int64_t(c0) * ldz, ldz, s, true,
                              nullptr, buf);

@@ -118,6 +118,7 @@ struct rf_plan {
     zd *rhs = nullptr;        // B X staging: n_pad x w
     zd *ypart = nullptr;      // per-pole forward results: p x n_pad x w
     zd *xpart = nullptr;      // per-pole solutions: p x n_pad x w
+    zd *refres = nullptr;     // per-pole refinement residuals: p x n_pad x w (refine > 0)
     // Krylov
     int b = 0, nsub = 0, mmax = 0;
     zd *V = nullptr;          // nsub x (mmax+1) blocks of n x b

@@ -45,7 +45,7 @@ class RfOpts(ctypes.Structure):
                 ("subblock", ctypes.c_int32), ("expected_count", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("trsm_cols", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("q_max", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("refine", ctypes.c_int32)]
 
 
 class RfFilterInfo(ctypes.Structure):
@@ -270,8 +270,17 @@ class Plan:
     """rf_plan_create: pencil (A, B) as scipy sparse matrices, disk (c, r), rules p, q, width w."""
 
     def __init__(self, A, B, c: complex, r: float, p: int = 4, q: int = 8, w: int = 32,
-                 stream=None, allocator="torch", **opts):
+                 stream=None, allocator="torch", tuned=True, **opts):
         torch = _torch()
+        if tuned:
+            # launch shapes from the autotuner's table (tune.py) where the caller left
+            # them automatic
+            from . import tune
+            entry = tune.lookup(A, B, p, q, w, int(opts.get("precision", 0)))
+            if entry:
+                for key in ("tile", "trsm_cols", "subblock"):
+                    if not opts.get(key):
+                        opts[key] = int(entry[key])
         o = make_opts(c, r, p, q, w, **opts)
         self.opts = o
         self._owned = True

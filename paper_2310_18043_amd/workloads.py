@@ -248,6 +248,42 @@ def tile_disks(lam: np.ndarray, counts, start: int = 0, slack: int = 3):
     return out
 
 
+def strip_disks(lam: np.ndarray, counts, start: float, slack: int = 3, density_guess=None):
+    """Adjacent disks centred on the real axis along a thin horizontal strip of
+    eigenvalues (|Im| small against the radii), left to right from ``start``.
+
+    Disk d is centred at L_d + r with L_d the previous disk's right edge (``start`` for
+    the first): for every candidate count s within +-slack of counts[d] the radius is
+    the one centred between the s-th and (s+1)-th nearest eigenvalues of a centre
+    placed for about counts[d] eigenvalues (density from ``lam`` or ``density_guess``),
+    and the candidate with the largest ratio of those two distances is kept.  ``lam``
+    must hold every eigenvalue of the region the disks reach.  Returns a list of
+    (c, r, count)."""
+    lam = np.asarray(lam)
+    x = np.sort(lam.real)
+    dens = density_guess or (len(x) - 1) / (x[-1] - x[0])
+    out = []
+    left = float(start)
+    for want in counts:
+        half = 0.5 * want / dens
+        best = None
+        for shift in np.linspace(-0.3, 0.3, 13):
+            cx = left + half * (1.0 + shift)
+            d = np.sort(np.abs(lam - cx))
+            for s in range(max(1, want - slack), want + slack + 1):
+                r = 0.5 * (d[s - 1] + d[s])
+                if cx - r < left - 1e-9 * abs(left):
+                    continue                      # would reach back into the previous disk
+                ratio = d[s] / d[s - 1]
+                if best is None or ratio > best[3]:
+                    best = (complex(cx, 0.0), float(r), int(s), float(ratio))
+        if best is None:
+            raise ValueError("no disk fits after %g" % left)
+        out.append(best[:3])
+        left = best[0].real + best[1]
+    return out
+
+
 def disk_batch(n: int = 128, ndisks: int = 16, lo: int = 12, hi: int = 48,
                seed: int = 0, velocity=(20.0, 10.0)):
     """Several adjacent disks at the low-|lambda| end of the constant-velocity
@@ -293,6 +329,15 @@ CONVDIFF128_DISK = (2525.0 + 0.0494j, 661.5612524628755, 100)
 # halfway between the two.
 RANDOMV128_DISK = (1564.0 + 0.0495j, 350.8144063398522, 52)
 
+# Disk for the 256 x 256 pencil with a per-cell velocity field v ~ U[-30, 30]^2
+# (random_vfield seed 3), D = 1, +0.05i, B = diag U[0.5, 1.5] (seed 0).  Recipe
+# (tests/golden/make_convdiff256.py): the 400 eigenvalues of B^{-1}A nearest 2000
+# (ARPACK shift-invert, oracle.reference.nearest_eigenvalues; Re 20..5426, Im +-10.5);
+# centres on the grid Re 1200..2795 step 5, Im -6..6 step 1, counts 185..215, keeping
+# the disk (inside the computed set with 20% margin) with the largest ratio of the
+# (count+1)-th to the count-th distance (1.045); radius halfway between the two.
+CONVDIFF256_DISK = (2605.0 + 0.0j, 1255.9810842394086, 187)
+
 _DISKS = {
     (128, (20.0, 10.0), 0, (0.5, 1.5)): CONVDIFF128_DISK,
 }
@@ -337,6 +382,20 @@ def random_velocity_workload(n: int = 128, w: int = 64, p: int = 4, q: int = 8,
         disk = RANDOMV128_DISK
     c, r, count = disk
     wl = Workload(f"convdiff{n}_randv{vseed}", A, B, complex(c), float(r), p, q, w, count, 0)
+    wl.vfield = v
+    return wl
+
+
+def convdiff256_workload(w: int = 256, p: int = 8, q: int = 8, vseed: int = 3,
+                         vmax: float = 30.0) -> Workload:
+    """The precision-form workload: 256 x 256 convection-diffusion pencil (N = 65536,
+    bandwidth 256) with a per-cell velocity field U[-30, 30]^2 (seed 3), B = diag
+    U[0.5, 1.5] (seed 0), +0.05i on the diagonal; disk with 187 eigenvalues
+    (CONVDIFF256_DISK); p = q = 8, w = 256."""
+    v = random_vfield(256, vmax, vseed)
+    A, B = convdiff_pencil(256, 1.0, vfield=v, shift=0.05j, mass=(0.5, 1.5), seed=0)
+    c, r, count = CONVDIFF256_DISK
+    wl = Workload("convdiff256_randv3", A, B, complex(c), float(r), p, q, w, count, 0)
     wl.vfield = v
     return wl
 

@@ -46,6 +46,36 @@ def _relerr(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("mass", ["diagonal", "tridiagonal"])
+def test_inner_apply_refinement_converges_to_fp64(rf, torch_cuda, mass):
+    # FP64 iterative refinement of every shifted solve: each step multiplies the error
+    # of the complex64 solve by about cond(K_i) u_32, so G approaches the complex128 G
+    # of the oracle step by step; three steps reach the complex128 bar
+    import scipy.sparse as sp
+    from oracle import filters
+    A, B = W.convdiff_pencil(20, mass=(0.5, 1.5), seed=1)
+    if mass == "tridiagonal":
+        rng = np.random.default_rng(3)
+        n = A.shape[0]
+        e = 0.1 * rng.uniform(-1, 1, n - 1)
+        B = sp.diags([e, B.diagonal(), e], [-1, 0, 1], format="csr", dtype=np.complex128)
+    c, r = 900 + 0.05j, 250.0
+    X = W.start_block(A.shape[0], 9, seed=7)
+    ref = filters.InnerOperator(A, B, c, r, 4)(X)
+    errs = []
+    for steps in range(4):
+        _say(f"apply_inner c64 refine={steps} ({mass} B)")
+        plan = rf.Plan(A, B, c, r, p=4, q=4, w=16, precision=1, refine=steps)
+        plan.factor_shifts()
+        Z = plan.apply_inner(torch_cuda.from_numpy(X).cuda()).cpu().numpy()
+        errs.append(float((np.linalg.norm(Z - ref, axis=0) / np.linalg.norm(ref, axis=0)).max()))
+        plan.close()
+    print(f"{mass} B: per-column G error by refinement steps 0..3: " + ", ".join(f"{e:.1e}" for e in errs))
+    assert errs[0] <= 1e-5 and errs[0] >= 1e-10          # really complex64
+    assert errs[1] <= 1e-2 * errs[0] and errs[2] <= 1e-2 * errs[1]
+    assert errs[3] <= 1e-12
+
+
 @pytest.mark.parametrize("ncols", [1, 7, 32])
 def test_inner_apply_c64_vs_oracle(rf, torch_cuda, ncols):
     from oracle import filters
