@@ -312,6 +312,82 @@ def batched_form(ndisks, reps):
                            "value": round(found_s / (ms_s / 1000.0), 3)}}
 
 
+def batched_form_256(wave, with_sequential=True):
+    """The batched configuration: 64 disks along the real axis of the 256 x 256
+    random-velocity pencil (10..200 eigenvalues each, block widths 16..256, p = 4,
+    q cycling through 4, 8, 16; tests/golden/convdiff256_disks.txt).  The disks go
+    through the HBM in waves of `wave` disks: per wave one batch (all its poles
+    factorized in one launch sequence, its disks solved concurrently on their own
+    streams), destroyed before the next.  A pair counts when it is converged
+    (inside, e <= 1e-10) and matches the oracle's reference eigenvalue of its disk
+    to 1e-10 relative (tests/golden/convdiff256_disk_eigs.txt).  Against the same
+    disks solved one after another, one plan each."""
+    import torch
+    from scipy.optimize import linear_sum_assignment
+    from paper_2310_18043_amd import rfeig
+    from paper_2310_18043_amd import workloads as W
+    gdir = os.path.join(HERE, "tests", "golden")
+    disks = W.read_disk_table(os.path.join(gdir, "convdiff256_disks.txt"))
+    ref = np.loadtxt(os.path.join(gdir, "convdiff256_disk_eigs.txt"))
+    wl = W.convdiff256_workload()
+    A, B = wl.A, wl.B
+    common = dict(p=4, max_krylov_blocks=40)
+
+    def good(res, d):
+        lam_ref = ref[ref[:, 0] == d][:, 1] + 1j * ref[ref[:, 0] == d][:, 2]
+        ok = res["err"] <= 1e-10
+        lam = res["lam"][ok]
+        if len(lam) == 0 or len(lam_ref) == 0:
+            return 0
+        cost = np.abs(lam[:, None] - lam_ref[None, :])
+        r_, c_ = linear_sum_assignment(cost)
+        return int(np.sum(cost[r_, c_] <= 1e-10 * np.abs(lam_ref[c_])))
+
+    def y0(d):
+        return torch.from_numpy(W.start_block(wl.n, disks[d]["w"], 100 + d)).cuda()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    found_b, sweeps, peak = 0, [], 0
+    for w0 in range(0, len(disks), wave):
+        idx = list(range(w0, min(w0 + wave, len(disks))))
+        specs = [{"c": disks[d]["c"], "r": disks[d]["r"], "w": disks[d]["w"], "q": disks[d]["q"],
+                  "expected_count": disks[d]["count"]} for d in idx]
+        bt = rfeig.Batch(A, B, specs, **common)
+        peak = max(peak, bt.device_bytes)
+        bt.factor()
+        outs = bt.solve([y0(d) for d in idx], allow_noconv=True)
+        for d, r in zip(idx, outs):
+            found_b += good(r, d)
+            sweeps.append(r["sweeps"])
+        bt.close()
+        del bt
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) * 1000.0
+    expected = int(sum(d["count"] for d in disks))
+    out = {"workload": f"convdiff256_randv_{len(disks)}disks_p4_q4-8-16", "disks": len(disks),
+           "wave": wave, "widths": [d["w"] for d in disks], "expected_count": expected,
+           "ms_per_step": round(ms_b, 3), "value": round(found_b / (ms_b / 1000.0), 3),
+           "unit": "eigenpairs/s", "converged_count": found_b, "sweeps": sweeps,
+           "peak_batch_device_gb": round(peak / 1e9, 2)}
+    if with_sequential:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        found_s = 0
+        for d, dk in enumerate(disks):
+            P = rfeig.Plan(A, B, dk["c"], dk["r"], w=dk["w"], q=dk["q"], expected_count=dk["count"],
+                           **common)
+            P.factor_shifts()
+            found_s += good(P.solve_region(y0(d), allow_noconv=True), d)
+            P.close()
+        torch.cuda.synchronize()
+        ms_s = (time.perf_counter() - t0) * 1000.0
+        out["sequential"] = {"ms_per_step": round(ms_s, 3), "converged_count": found_s,
+                             "value": round(found_s / (ms_s / 1000.0), 3)}
+        out["batched_speedup"] = round(ms_s / ms_b, 3)
+    return out
+
+
 def circuit_form(reps):
     """The paper's circuit pencil (App. B) at n_x = 10 (N = 1220), its solver shape
     (k1 = k2 = 8, n_col = 24) and a disk with 17 eigenvalues: Alg. composite."""
@@ -413,6 +489,8 @@ def main():
                     help="skip the 256 x 256 workload (plain and precision form)")
     ap.add_argument("--no-toeplitz", action="store_true",
                     help="skip the Toeplitz workload (balanced and literal)")
+    ap.add_argument("--batch256-wave", type=int, default=8,
+                    help="disks per wave of the 64-disk 256 x 256 batched workload (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -495,6 +573,9 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(achieved_tflops / PEAK_FP64_TFLOPS, 4),
         "traffic": traffic,
+        "traffic_source": ("stored: profiles/band_solve_convdiff128_traffic.json, rocprofv3 FETCH_SIZE "
+                           "and WRITE_SIZE passes of this bench command on the same kernel, scaled "
+                           "by a 1 GiB copy") if traffic is not None else None,
         "avg_launch_ms": round(stats["solve_ms"] / max(stats["solve_launches"], 1), 4),
         "launches": stats["solve_launches"],
         "avg_columns_per_launch": round(avg_cols, 2),
@@ -614,6 +695,12 @@ def main():
         grad = gradient_form(min(args.steps, 2))
         log(f"gradient: {grad}")
 
+    bt256 = None
+    if args.batch256_wave > 0 and os.path.exists(os.path.join(HERE, "tests", "golden",
+                                                              "convdiff256_disks.txt")):
+        bt256 = batched_form_256(args.batch256_wave)
+        log(f"batched 256: { {k: v for k, v in bt256.items() if k not in ('widths', 'sweeps')} }")
+
     cd256 = None
     if not args.no_convdiff256:
         cd256 = convdiff256_form(min(args.steps, 2))
@@ -654,6 +741,7 @@ def main():
         "gradient": grad,
         "circuit": circ,
         "convdiff256": cd256,
+        "batched_256": bt256,
         "toeplitz": toep,
         "phases_ms": {"factor": round(stats["factor_ms"] / max(args.steps, 1), 3),
                       "filter": round(res["ms_filter"], 3), "hsrr": round(res["ms_hsrr"], 3)},

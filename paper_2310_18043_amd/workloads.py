@@ -400,6 +400,20 @@ def convdiff256_workload(w: int = 256, p: int = 8, q: int = 8, vseed: int = 3,
     return wl
 
 
+def read_disk_table(path: str):
+    """Disks of a batched workload from a text table (disk, Re c, Im c, r, count, w),
+    as written by tests/golden/make_convdiff256_batch.py.  Outer node counts cycle
+    through 4, 8, 16.  Returns a list of dicts c, r, count, w, q."""
+    disks = []
+    for line in open(path):
+        if not line.strip() or line.startswith("#"):
+            continue
+        d, cr, ci, r, count, w = line.split()
+        disks.append({"c": complex(float(cr), float(ci)), "r": float(r), "count": int(count),
+                      "w": int(w), "q": (4, 8, 16)[int(d) % 3]})
+    return disks
+
+
 # --------------------------------------------------------------------------
 # the paper's circuit pencil (App. B, construction of the matrix)
 # --------------------------------------------------------------------------

@@ -7,7 +7,7 @@
    20x; the counts are drawn, the radii follow.)
 2. Every eigenvalue of the strip's low end, by shift-invert Arnoldi in overlapping
    windows (oracle.reference.nearest_eigenvalues, 400 eigenvalues each, centres 2000,
-   7000, 12000, ...), merged.
+   6000, 10000, ..., overlapping), merged.
 3. Adjacent disks along the real axis from Re = 0 (workloads.strip_disks: rims in the
    widest relative gaps, counts within +-3 of the request), block width the smallest
    power of two >= 1.25 x count.
@@ -61,7 +61,10 @@ def main():
     ctx = mp.get_context("spawn")
     found, covered = [], 0.0
     with ctx.Pool(4) as pool:
-        sig = [2000.0 + 5000.0 * j for j in range(int(np.ceil(need / 360.0)) + 1)]
+        # centres 4000 apart: each window reaches about 2450 on either side, so
+        # consecutive windows overlap by about 900 along the strip
+        top = need / 0.073 + 4000.0
+        sig = [2000.0 + 4000.0 * j for j in range(int(np.ceil((top - 2000.0) / 4000.0)) + 1)]
         for sigma, lam in pool.imap(_window, sig):
             d = np.abs(lam - sigma)
             # every eigenvalue within the window's 400th distance is found

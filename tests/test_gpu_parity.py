@@ -364,6 +364,51 @@ def test_solve_region_toeplitz_closed_form(rf, torch_cuda):
     assert res["err"].max() <= 1e-10
 
 
+def test_solve_region_literal_toeplitz(rf, torch_cuda):
+    # the literal Toeplitz pencil (a = 0, b = 1, c = 0.5 e^{i pi/3}) is exponentially
+    # non-normal: its eigenvalue condition numbers grow like (|b|/|c|)^{(n-1)/2}.  At
+    # n = 40 (kappa ~ 1e5..1e6, from dense left and right eigenvectors) the eigenvalues
+    # are defined in FP64 and the solver must find them all, each within the first-order
+    # bound kappa * residual norm of its returned pair (a pair with e <= 1e-10 is not
+    # closer than that); at n = 2000 no FP64 method can find them (sigma_min(z I - A) ~
+    # 1e-265 near the disk): the pairs returned are pseudo-eigenpairs whose residuals meet
+    # the bar, and their distance to the closed form is printed as measured
+    from oracle import hsrr, sensitivity
+    from scipy.optimize import linear_sum_assignment
+    wl = W.toeplitz_workload(n=40, balanced=False, w=8, count=4, c=0.3 + 0.2j)
+    exact = W.toeplitz_eigs(40, 0, 1, W.TOEPLITZ_C)
+    inside = exact[np.abs(exact - wl.c) < wl.r]
+    _say("solve_region literal toeplitz n=40")
+    plan = rf.Plan(wl.A, wl.B, wl.c, wl.r, p=4, q=4, w=8, expected_count=len(inside))
+    res = plan.solve_region(torch_cuda.from_numpy(W.start_block(40, 8, 0)).cuda())
+    assert res["converged"] and res["count"] == len(inside)
+    lam_d, X_d, Y_d = sensitivity.dense_left_right(wl.A, wl.B)
+    lam_d, X_d, Y_d = sensitivity.select(lam_d, X_d, Y_d, inside)
+    kap = np.linalg.norm(X_d, axis=0) * np.linalg.norm(Y_d, axis=0) / np.abs(
+        np.einsum("ij,ij->j", Y_d.conj(), X_d))
+    cost = np.abs(res["lam"][:, None] - inside[None, :])
+    r_, c_ = linear_sum_assignment(cost)
+    e = hsrr.rel_errors(wl.A, wl.B, res["lam"], _to_host(res["X"]), wl.c, wl.r)
+    rn = e * (abs(wl.c) + wl.r)                       # residual norms of the unit vectors (B = I)
+    bound = kap[c_] * rn[r_] + 1e-13 * np.abs(inside[c_])
+    print(f"literal toeplitz n=40: {len(inside)} eigenvalues, kappa {kap.min():.1e}..{kap.max():.1e}, "
+          f"max |dlambda|/|lambda| {(cost[r_, c_] / np.abs(inside[c_])).max():.2e}, max ratio to "
+          f"kappa * residual {(cost[r_, c_] / bound).max():.2f}")
+    assert e.max() <= 1e-10 and np.all(cost[r_, c_] <= bound)
+    wl = W.toeplitz_workload(n=2000, balanced=False, w=32, count=20)
+    _say("solve_region literal toeplitz n=2000")
+    plan = rf.Plan(wl.A, wl.B, wl.c, wl.r, p=4, q=4, w=32)
+    res = plan.solve_region(torch_cuda.from_numpy(W.start_block(wl.n, 32, 0)).cuda(),
+                            allow_noconv=True)
+    exact = W.toeplitz_eigs(wl.n, 0, 1, W.TOEPLITZ_C)
+    e = hsrr.rel_errors(wl.A, wl.B, res["lam"], _to_host(res["X"]), wl.c, wl.r)
+    d = (np.abs(res["lam"][:, None] - exact[None, :]).min(axis=1) if res["count"] else np.zeros(0))
+    print(f"literal toeplitz n=2000: {res['count']} pairs returned (20 closed-form eigenvalues in the "
+          f"disk), sweeps {res['sweeps']}, max residual {e.max() if len(e) else 0:.1e}, distance to the "
+          f"closed form {d.min() if len(d) else float('nan'):.1e}..{d.max() if len(d) else float('nan'):.1e}")
+    assert np.all(e <= 1e-10)
+
+
 def test_solve_region_small_convdiff_vs_oracle(rf, torch_cuda):
     from oracle import hsrr, solver
     import scipy.linalg as sl
