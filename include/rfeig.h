@@ -81,6 +81,8 @@ typedef struct {
     int32_t refine;          /* precision form: FP64 iterative-refinement steps of every shifted solve
                                 K_i x = b (0..4): r = b - K_i x in complex128 from the sparse A and B,
                                 x += K_i^{-1} r with the complex64 factors; 0 with precision 0 */
+    int32_t no_graph;        /* 0: rf_factor_shifts records its fixed launch sequence once in a HIP
+                                graph (on a non-null stream) and replays it; 1: plain launches */
 } rf_opts;
 
 /* Per-call statistics of a filter application. */

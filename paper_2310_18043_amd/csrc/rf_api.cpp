@@ -228,6 +228,7 @@ int64_t rf_plan_device_bytes(rf_plan_t plan) { return plan ? plan->device_bytes 
 void rf_plan_destroy(rf_plan_t plan) {
     if (!plan) return;
     if (!plan->broken) (void)hipStreamSynchronize(plan->stream);
+    if (plan->fac_graph) (void)hipGraphExecDestroy(plan->fac_graph);
     plan->prof.release();
     for (void *p : plan->allocations) {
         if (plan->alloc.alloc) plan->alloc.free(p, plan->alloc.ctx);
@@ -529,7 +530,28 @@ rf_status rf_factor_shifts(rf_plan_t P) {
     }
     hipEvent_t ev0 = nullptr;
     P->prof.record_begin(P->stream, ev0);
-    RF_HIP(P, launch_band_factor(*P, P->stream));
+    if (!P->opts.no_graph && P->stream) {
+        // the factorization is a fixed sequence of about 2 nb_steps launches that only
+        // depends on the plan's shapes and buffers: record it once, replay it after
+        if (!P->fac_graph) {
+            hipGraph_t g = nullptr;
+            RF_HIP(P, hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+            const hipError_t le = launch_band_factor(*P, P->stream);
+            const hipError_t ce = hipStreamEndCapture(P->stream, &g);
+            if (le != hipSuccess || ce != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                RF_HIP(P, le != hipSuccess ? le : ce);
+            }
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            RF_HIP(P, ie);
+            P->fac_graph = ex;
+        }
+        RF_HIP(P, hipGraphLaunch(P->fac_graph, P->stream));
+    } else {
+        RF_HIP(P, launch_band_factor(*P, P->stream));
+    }
     P->prof.record_end(P->stream, ev0, 0, 1);
     std::vector<int32_t> info(P->opts.p);
     {

@@ -163,6 +163,7 @@ struct rf_plan {
     bool broken = false;
     bool shared_factors = false;  // F.tiles/perm/info belong to a batch's factor owner
     const rf_plan *adj_parent = nullptr;  // adjoint plan: the plan whose factors it transposes
+    hipGraphExec_t fac_graph = nullptr;   // the factorization's launch sequence, recorded once
     // precision form: per-(shift, column) combine coefficients and per-(pole, column)
     // inner weights of the residual form
     zd *d_colcoef = nullptr;  // nq x w

@@ -45,7 +45,8 @@ class RfOpts(ctypes.Structure):
                 ("subblock", ctypes.c_int32), ("expected_count", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("trsm_cols", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("q_max", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("refine", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("no_graph", ctypes.c_int32)]
 
 
 class RfFilterInfo(ctypes.Structure):

@@ -263,6 +263,34 @@ def test_inner_apply_tile_256(rf, torch_cuda, precision):
         plan.close()
 
 
+def test_factorization_graph_replays_match_eager(rf, torch_cuda):
+    # on a non-null stream rf_factor_shifts records its launch sequence in a HIP graph
+    # once and replays it; every replay, with eager work and synchronizations of the
+    # program in between, must give the factors of plain launches bit for bit
+    A, B = W.convdiff_pencil(24, mass=(0.5, 1.5), seed=4)           # N = 576, 19 block steps
+    c, r = 1500 + 0.05j, 300.0
+    X = torch_cuda.from_numpy(W.start_block(A.shape[0], 16, seed=2)).cuda()
+    side = torch_cuda.cuda.Stream()
+    _say("factorization graph replays vs eager launches")
+    eager = rf.Plan(A, B, c, r, p=4, q=8, w=16, no_graph=1, stream=side)
+    eager.factor_shifts()
+    with torch_cuda.cuda.stream(side):
+        ref = eager.apply_inner(X).cpu().numpy()
+    graph = rf.Plan(A, B, c, r, p=4, q=8, w=16, stream=side)
+    for rep in range(4):
+        graph.factor_shifts()
+        with torch_cuda.cuda.stream(side):
+            Z = graph.apply_inner(X).cpu().numpy()
+        assert np.array_equal(Z, ref), rep
+        # eager work of the program between replays
+        Y = torch_cuda.randn(2048, 2048, device="cuda") @ torch_cuda.randn(2048, 2048, device="cuda")
+        torch_cuda.cuda.synchronize()
+        assert torch_cuda.isfinite(Y).all()
+        eager.factor_shifts()
+    graph.close()
+    eager.close()
+
+
 def test_pole_on_eigenvalue_is_reported_singular(rf, torch_cuda):
     # diagonal pencil with an eigenvalue exactly at a trapezoidal pole
     lam = np.linspace(-3, 3, 64) + 0.0j

@@ -52,3 +52,30 @@ def test_convdiff_const_cond_against_dense_left_right_vectors(v):
     for i in range(len(lam)):
         j = np.argmin(np.abs(cf_lam - lam[i]))
         assert abs(cf_kap[j] - kap[i]) <= 1e-6 * kap[i]
+
+
+def test_strip_disks_are_adjacent_and_hold_their_counts():
+    # eigenvalues on a thin strip (|Im| <= 2) with unit density along Re: each disk is
+    # centred on the real axis, starts at or after the previous disk's right edge, and
+    # holds exactly its reported count (its rim between two eigenvalues)
+    rng = np.random.default_rng(3)
+    lam = np.sort(rng.uniform(0, 2000, 2000)) + 1j * rng.uniform(-2, 2, 2000)
+    counts = [10, 40, 25, 100, 15]
+    disks = W.strip_disks(lam, counts, start=0.0)
+    left = 0.0
+    for (c, r, s), want in zip(disks, counts):
+        assert c.imag == 0.0 and abs(s - want) <= 3
+        assert c.real - r >= left - 1e-9
+        d = np.abs(lam - c)
+        assert int(np.sum(d < r)) == s
+        assert np.min(np.abs(d - r)) > 0.0          # no eigenvalue on the rim
+        left = c.real + r
+
+
+def test_read_disk_table_cycles_outer_nodes(tmp_path):
+    p = tmp_path / "disks.txt"
+    p.write_text("# header\n0 10.0 0.0 5.0 12 16\n1 30.0 0.0 7.5 20 32\n2 60.0 0.0 9.0 33 64\n"
+                 "3 90.0 0.5 3.0 10 16\n")
+    disks = W.read_disk_table(str(p))
+    assert [d["q"] for d in disks] == [4, 8, 16, 4]
+    assert disks[3]["c"] == complex(90.0, 0.5) and disks[1]["w"] == 32 and disks[2]["count"] == 33
