@@ -83,6 +83,13 @@ typedef struct {
                                 x += K_i^{-1} r with the complex64 factors; 0 with precision 0 */
     int32_t no_graph;        /* 0: rf_factor_shifts records its fixed launch sequence once in a HIP
                                 graph (on a non-null stream) and replays it; 1: plain launches */
+    int32_t solve_form;      /* complex128 band solves of eq. linearsolve2: 0 (automatic) = the
+                                cluster form wherever it applies (tile 64 or 128, precision 0,
+                                not an adjoint plan): the factorization also stores the products
+                                L21 Linv, Uinv Linv, Uinv U1, Uinv U2 of every block (4/5 of the
+                                factor storage again) and each solve runs clusters of nb/16
+                                workgroups per pole and 16 right-hand sides on the FP64 matrix
+                                cores; 1 = the per-slice form only (no product storage) */
 } rf_opts;
 
 /* Per-call statistics of a filter application. */

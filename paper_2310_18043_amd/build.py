@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librfeig.so")
-SOURCES = ["rf_api.cpp", "rf_qz.cpp", "rf_band.hip", "rf_dense.hip"]
+SOURCES = ["rf_api.cpp", "rf_qz.cpp", "rf_band.hip", "rf_dense.hip", "rf_cluster.hip"]
 ARCH = os.environ.get("RFEIG_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

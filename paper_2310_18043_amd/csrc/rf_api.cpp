@@ -186,6 +186,24 @@ rf_status rf_fail(rf_plan *plan, rf_status s, const std::string &msg) {
     return s;
 }
 
+// After the plan's stream has drained: did a cluster solve launched since the last check
+// give up a wait or run a member off its XCD?  Either voids that launch's results; the
+// plan then keeps to the per-slice solves.
+static rf_status cluster_check(rf_plan *P) {
+    if (!P->F.cerr || P->F.cepoch == P->F.cerr_seen) return RF_OK;
+    unsigned h[2] = {0, 0};
+    RF_HIP(P, hipMemcpy(h, P->F.cerr, sizeof(h), hipMemcpyDeviceToHost));
+    const unsigned seen = P->F.cerr_seen;
+    P->F.cerr_seen = P->F.cepoch;
+    if (h[0] > seen || h[1] > seen) {
+        P->F.cluster_ok = false;
+        return rf_fail(P, RF_ERR_DEVICE, h[1] > seen
+                       ? "band solve: a cluster workgroup did not run on the XCD its exchange assumes"
+                       : "band solve: a cluster handoff wait timed out");
+    }
+    return RF_OK;
+}
+
 extern "C" {
 
 void rf_default_opts(rf_opts *o) {
@@ -269,6 +287,7 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
     if (o.q_max < 0 || o.q_max > 256) return RF_ERR_ARG;
     if (o.precision < 0 || o.precision > 1) return RF_ERR_ARG;
     if (o.refine < 0 || o.refine > 4 || (o.refine > 0 && o.precision != 1)) return RF_ERR_ARG;
+    if (o.solve_form < 0 || o.solve_form > 1) return RF_ERR_ARG;
 
     rf_plan *P = new rf_plan();
     if (allocator) P->alloc = *allocator;
@@ -401,6 +420,8 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
             }
             P->F.tiles32 = owner->F.tiles32 + int64_t(pole_offset) * P->F.nblk * 5 * te;
         }
+        if (owner->F.ftiles && o.precision == 0 && o.solve_form == 0)
+            P->F.ftiles = owner->F.ftiles + int64_t(pole_offset) * P->F.nblk * 4 * te;
     } else if (adjoint_of) {
         // conjugate transposes of adjoint_of's factor tiles (made by rf_factor_shifts)
         if (adjoint_of->F.nb != nb || adjoint_of->F.nblk != P->F.nblk || adjoint_of->opts.p != o.p) {
@@ -424,6 +445,23 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
         ALLOC(P->F.rows, int64_t(o.p) * P->F.nblk * te * 3);
         ALLOC(P->F.subperm, int64_t(o.p) * 2 * nb);
         if (o.precision == 1) ALLOC(P->F.tiles32, int64_t(o.p) * P->F.nblk * 5 * te);
+        if (o.precision == 0 && o.solve_form == 0 && cluster_solve_supported(nb))
+            ALLOC(P->F.ftiles, int64_t(o.p) * P->F.nblk * 4 * te);
+    }
+    if (P->F.ftiles) {
+        // exchange area, sequence flags and error words of the cluster solve (per plan:
+        // the disks of a batch solve on their own streams)
+        ALLOC(P->F.xchg, cluster_xchg_elems(nb, P->num_cu));
+        ALLOC(P->F.cflags, cluster_flag_words(nb, P->num_cu));
+        ALLOC(P->F.cerr, 2);
+        if (hipMemsetAsync(P->F.cflags, 0, cluster_flag_words(nb, P->num_cu) * 8, P->stream) != hipSuccess ||
+            hipMemsetAsync(P->F.cerr, 0, 2 * sizeof(unsigned), P->stream) != hipSuccess ||
+            cluster_gate_init(dev) != hipSuccess) {
+            (void)hipGetLastError();
+            P->broken = true;
+            rf_fail(P, RF_ERR_DEVICE, "cluster solve set-up failed");
+            return fail(RF_ERR_DEVICE);
+        }
     }
     ALLOC(P->d_colcoef, int64_t(std::max(nq_alloc, 1)) * o.w);
     ALLOC(P->d_colw, int64_t(o.p) * o.w);
@@ -590,7 +628,7 @@ rf_status rf_apply_inner(rf_plan_t P, const void *X, int64_t ldx, int32_t ncols,
     RF_HIP(P, launch_inner_apply(*P, static_cast<const zd *>(X), ldx, ncols, static_cast<zd *>(Zp),
                                  ldz, P->stream));
     RF_HIP(P, hipStreamSynchronize(P->stream));
-    return RF_OK;
+    return cluster_check(P);
 }
 
 rf_status rf_apply_inner_noalloc(rf_plan_t P, const void *X, int64_t ldx, int32_t ncols, void *Zp,
@@ -996,7 +1034,7 @@ rf_status krylov_combine(rf_plan *P, KrylovState &K, zd *U, int64_t ldu) {
                                         n, Us, ldu, s));
     }
     RF_HIP(P, hipStreamSynchronize(s));
-    return RF_OK;
+    return cluster_check(P);
 }
 
 // U = sum_j c'_j (G - s_j I)^{-1} G(Y) (Alg. composite's filter): a fresh basis,

@@ -1309,7 +1309,12 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
     else
         hipLaunchKernelGGL(tri_inverse_kernel<16>, dim3(a.nblk, p, 2), dim3(kThreads),
                            size_t(nb) * 16 * sizeof(zd), s, P.F.tiles, nb, a.nblk);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the products of the cluster solve (its own tiles only: a batch owner forms them
+    // for every disk)
+    if (P.F.ftiles && !P.shared_factors) return launch_fused_tiles(P, s);
+    return hipSuccess;
 }
 
 static size_t solve_lds(int nb, int cw, size_t elem) {
@@ -1377,6 +1382,12 @@ hipError_t launch_tiles_to_c64(const rf_plan &P, hipStream_t s) {
 
 namespace {
 
+// complex128 solves of this plan run as clusters over the fused tiles
+bool cluster_path(const rf_plan &P) {
+    return P.opts.precision == 0 && !P.F.adjoint && P.F.ftiles && P.F.cluster_ok &&
+           cluster_solve_supported(P.F.nb);
+}
+
 // Work blocks of one application of G to ncols columns: B X staging (only when B is not
 // diagonal), per-pole forward results (tile precision) and per-pole weighted solutions.
 struct InnerBufs {
@@ -1424,6 +1435,19 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
     if (buf.profile) P.prof.record_begin(s, ev0);
     const bool adj = P.F.adjoint;
     if (adj && (c64 || colw)) return hipErrorInvalidValue;
+    if (cluster_path(P)) {
+        // complex128 solves over the fused tiles, a cluster of workgroups per pole and
+        // 16 right-hand sides
+        e = launch_cluster_solve(P, ClusterSolve{a.X, a.ldx, a.bdiag, buf.rhs, 0, colw,
+                                                 static_cast<zd *>(buf.ypart), buf.xpart, ncols,
+                                                 0, 0}, s);
+        if (e != hipSuccess) return e;
+        if (buf.profile) P.prof.record_end(s, ev0, ncols, 0);
+        int64_t tot = P.n * ncols;
+        hipLaunchKernelGGL(pole_sum_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, buf.xpart,
+                           a.p, a.npad, P.n, ncols, Z, ldz);
+        return hipGetLastError();
+    }
     auto solve = [&](const SolveArgs &sa) -> hipError_t {
         if (c64) {
             switch (cw) {
@@ -1499,7 +1523,7 @@ size_t inner_scratch_capacity() { return kScratchBytes; }
 size_t inner_scratch_per_column(const rf_plan &P) {
     const int64_t npad = int64_t(P.F.nblk) * P.F.nb;
     const size_t ye = P.opts.precision == 1 ? sizeof(zf) : sizeof(zd);
-    const size_t rhs = P.B.diagonal ? 0 : size_t(npad) * sizeof(zd);
+    const size_t rhs = (P.B.diagonal && !cluster_path(P)) ? 0 : size_t(npad) * sizeof(zd);
     const size_t ref = P.opts.precision == 1 && P.opts.refine > 0 ? sizeof(zd) : 0;
     return rhs + size_t(P.opts.p) * npad * (ye + sizeof(zd) + ref);
 }
@@ -1526,8 +1550,9 @@ hipError_t launch_inner_apply_static(const rf_plan &P, const zd *X, int64_t ldx,
     // columns per chunk: the largest count whose three blocks (each 256-byte aligned) fit
     int chunk = ncols;
     const bool ref = P.opts.precision == 1 && P.opts.refine > 0;
+    const bool staged = !P.B.diagonal || cluster_path(P);   // B X staging block
     auto need = [&](int k) {
-        const size_t rhs = P.B.diagonal ? 0 : align256(size_t(npad) * k * sizeof(zd));
+        const size_t rhs = staged ? align256(size_t(npad) * k * sizeof(zd)) : 0;
         return rhs + align256(size_t(P.opts.p) * npad * k * ye) +
                align256(size_t(P.opts.p) * npad * k * sizeof(zd)) +
                (ref ? align256(size_t(P.opts.p) * npad * k * sizeof(zd)) : 0);
@@ -1540,7 +1565,7 @@ hipError_t launch_inner_apply_static(const rf_plan &P, const zd *X, int64_t ldx,
         InnerBufs buf;
         size_t off = 0;
         buf.rhs = nullptr;
-        if (!P.B.diagonal) {
+        if (staged) {
             buf.rhs = reinterpret_cast<zd *>(b + off);
             off += align256(size_t(npad) * k * sizeof(zd));
         }

@@ -78,6 +78,16 @@ struct BandFactors {
     int32_t *subperm = nullptr; // p * 2nb: row order of the current sub-panel
     int32_t *info = nullptr;   // p ints: 0 or (1 + first zero-pivot column)
     zf *tiles32 = nullptr;     // complex64 copy of tiles (precision form), or null
+    // cluster solve (rf_cluster.hip): fused tiles M, W, V1, V2 per pole and block
+    // (p * nblk * 4 * nb*nb, or a batch owner's), the exchange area, the sequence flags
+    // and the error words {epoch of a timed-out wait, epoch of a misplaced workgroup}
+    zd *ftiles = nullptr;
+    zd *xchg = nullptr;
+    unsigned long long *cflags = nullptr;
+    unsigned *cerr = nullptr;
+    mutable unsigned cepoch = 0;   // epoch of the last cluster launch
+    unsigned cerr_seen = 0;        // launches up to this epoch have been checked
+    bool cluster_ok = true;        // false after a reported failure: per-slice solves
     bool adjoint = false;      // tiles hold the conjugate transposes of another plan's
                                // factors (adjoint pencil): solves run the K^H sweeps
     bool ready = false;
@@ -207,6 +217,26 @@ size_t inner_scratch_per_column(const rf_plan &P);  // its bytes per column, una
 // the adjoint plan P's tiles and row orders from the factorization of `parent`
 // (P's pole i is the conjugate of parent's pole p-1-i): conjugate-transposed tiles
 hipError_t launch_tiles_adjoint(const rf_plan &P, const rf_plan &parent, hipStream_t s);
+// cluster solve over fused tiles (rf_cluster.hip)
+struct ClusterSolve {
+    const zd *X; int64_t ldx;      // right-hand sides before B, or B X itself (bdiag null)
+    const zd *bdiag;               // diagonal of B, or null (then X holds B X)
+    zd *stage;                     // npad x ncols: B X when bdiag is set
+    int64_t x_pole_stride;         // 0: one block for all poles
+    const zd *colw;                // or null: [pole][ncols] weights
+    zd *zbuf, *xpart;              // [pole][npad x ncols] each
+    int ncols;
+    int unit_weight, accumulate;
+};
+bool cluster_solve_supported(int nb);              // tile sizes 64, 128, 256
+int cluster_slots_max(int nb, int num_cu);         // clusters in flight at most
+size_t cluster_xchg_elems(int nb, int num_cu);     // complex entries of the exchange area
+size_t cluster_flag_words(int nb, int num_cu);     // 64-bit sequence flags
+hipError_t cluster_gate_init(int device);          // once per device, before any launch
+// F.ftiles from F.tiles (complex128 factors of every pole): M, W, V1, V2
+hipError_t launch_fused_tiles(const rf_plan &P, hipStream_t s);
+// xpart_i = w_i K_i^{-1} (B X) for every pole (or the unit-weight / accumulating forms)
+hipError_t launch_cluster_solve(const rf_plan &P, const ClusterSolve &cs, hipStream_t s);
 // complex64 copy of the factor tiles (after the complex128 factorization)
 hipError_t launch_tiles_to_c64(const rf_plan &P, hipStream_t s);
 

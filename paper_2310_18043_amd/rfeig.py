@@ -18,7 +18,8 @@ import re
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librfeig.so")
+# RFEIG_LIBRARY names another build of the library (default: the in-tree one)
+LIB_PATH = os.environ.get("RFEIG_LIBRARY") or os.path.join(HERE, "librfeig.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "rfeig.h")
 
 if not os.path.exists(LIB_PATH):
@@ -46,7 +47,7 @@ class RfOpts(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("trsm_cols", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("q_max", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("no_graph", ctypes.c_int32)]
+                ("no_graph", ctypes.c_int32), ("solve_form", ctypes.c_int32)]
 
 
 class RfFilterInfo(ctypes.Structure):
