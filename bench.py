@@ -34,7 +34,11 @@ import numpy as np  # noqa: E402
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (complex64 band solves)
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "band_solve_convdiff128_traffic.json")
+# stored HBM traffic of the band-solve kernel that the headline plan runs (rocprofv3 passes)
+TRAFFIC_FILES = {
+    "band_solve_cluster_kernel": os.path.join(HERE, "profiles", "band_solve_cluster_convdiff128_traffic.json"),
+    "band_solve_kernel": os.path.join(HERE, "profiles", "band_solve_convdiff128_traffic.json"),
+}
 
 
 def log(msg):
@@ -474,6 +478,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--subblock", type=int, default=0)
     ap.add_argument("--trsm-cols", type=int, default=0)
+    ap.add_argument("--solve-form", type=int, default=0,
+                    help="band solves: 0 cluster form where it applies (tiles 64, 128), 1 per slice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adaptive-qmax", type=int, default=64,
                     help="also time Alg. composite2 up to this outer node count (0: skip)")
@@ -523,7 +529,7 @@ def main():
     log(f"workload {wl.name}: n={wl.n} p={wl.p} q={wl.q} w={wl.w} disk c={wl.c} r={wl.r:.3f}")
     plan = rfeig.Plan(wl.A, wl.B, wl.c, wl.r, p=wl.p, q=wl.q, w=wl.w,
                       expected_count=wl.s_expected, subblock=args.subblock,
-                      trsm_cols=args.trsm_cols)
+                      trsm_cols=args.trsm_cols, solve_form=args.solve_form)
     Y0 = torch.from_numpy(W.start_block(wl.n, wl.w, wl.seed)).cuda()
     Y0 = rfeig.as_colmajor(Y0)
     torch.cuda.synchronize()
@@ -559,21 +565,28 @@ def main():
     fl_col = solve_flops_per_column(wl.n, kl, ku, wl.p)
     achieved_tflops = fl_col * stats["solve_columns"] / (stats["solve_ms"] * 1e-3) / 1e12
     avg_cols = stats["solve_columns"] / max(stats["solve_launches"], 1)
+    # tiles 64 and 128 solve with the cluster kernel (FP64 matrix cores), others per slice
+    tile = 16
+    while tile < max(kl, ku):
+        tile *= 2
+    cluster = tile in (64, 128) and args.solve_form == 0
+    kname = "band_solve_cluster_kernel" if cluster else "band_solve_kernel"
+    tfile = TRAFFIC_FILES[kname]
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    if os.path.exists(tfile):
         try:
-            traffic = json.load(open(TRAFFIC_FILE)).get("bytes_per_launch")
+            traffic = json.load(open(tfile)).get("bytes_per_launch")
         except Exception:
             traffic = None
     roofline = {
-        "kernel": "band_solve_kernel",
-        "bound": "alu",
+        "kernel": kname,
+        "bound": "mfma" if cluster else "alu",
         "achieved": round(achieved_tflops, 3),
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved_tflops / PEAK_FP64_TFLOPS, 4),
         "traffic": traffic,
-        "traffic_source": ("stored: profiles/band_solve_convdiff128_traffic.json, rocprofv3 FETCH_SIZE "
+        "traffic_source": (f"stored: profiles/{os.path.basename(tfile)}, rocprofv3 FETCH_SIZE "
                            "and WRITE_SIZE passes of this bench command on the same kernel, scaled "
                            "by a 1 GiB copy") if traffic is not None else None,
         "avg_launch_ms": round(stats["solve_ms"] / max(stats["solve_launches"], 1), 4),

@@ -117,15 +117,20 @@ __device__ __attribute__((always_inline)) inline void cl_load(const zd *t,
 // result entry (4r + lane / 16, lane % 16) in slot r; the four real products of the
 // complex one accumulate separately.
 // NL of the tiles pa, pb (0, 1 or 2) are loaded into da, db while the product runs: entry
-// j of each right after the matrix-core instructions of step j, so that the loads' issue
-// overlaps the matrix cores
-template <int NB, int NL>
+// j of each right after the matrix-core instructions of step j, then ex(j), so that the
+// loads' address work and issue overlap the matrix cores
+struct ClNoExtra {
+    __device__ void operator()(int) const {}
+};
+
+template <int NB, int NL, typename EX = ClNoExtra>
 __device__ __attribute__((always_inline)) inline void cl_product(const dv2 (&t)[ClShape<NB>::KS],
                                                                  const zd *vec, zd *red, int wave,
                                                                  int lane, const zd *pa,
                                                                  dv2 (&da)[ClShape<NB>::KS],
                                                                  const zd *pb,
-                                                                 dv2 (&db)[ClShape<NB>::KS]) {
+                                                                 dv2 (&db)[ClShape<NB>::KS],
+                                                                 EX ex = EX()) {
     using S = ClShape<NB>;
     dv4 rr = {0.0, 0.0, 0.0, 0.0}, ii = rr, ri = rr, ir = rr;
     const zd *vb = vec + (wave * S::KW + (lane >> 4)) * kVecLd + (lane & 15);
@@ -138,6 +143,7 @@ __device__ __attribute__((always_inline)) inline void cl_product(const dv2 (&t)[
         ir = mfma64(t[j].y, b.x, ir);
         if (NL >= 1) da[j] = ld2(pa + int64_t(4 * j) * NB);
         if (NL >= 2) db[j] = ld2(pb + int64_t(4 * j) * NB);
+        ex(j);                                    // further loads of the caller
     }
     zd *dst = red + wave * S::RED + (lane >> 4) * kRedLd + (lane & 15);
 #pragma unroll
@@ -250,83 +256,107 @@ __global__ __launch_bounds__(kClThreads) void band_solve_cluster_kernel(ClusterA
         auto zload = [&](int k) __attribute__((always_inline)) -> zd {
             return (k >= 0 && colok) ? zb[int64_t(k) * NB + zoff] : zmake(0.0, 0.0);
         };
+        // this thread's weight: w_i, the per-column weight, or 1
+        const zd wc = a.unit_weight ? zmake(1.0, 0.0)
+                    : a.colw ? a.colw[int64_t(pole) * a.ncols + (colok ? col : 0)] : a.weights[pole];
         auto out = [&](int k, zd v) __attribute__((always_inline)) {
             if (!colok) return;
-            const zd wc = a.unit_weight ? zmake(1.0, 0.0)
-                        : a.colw ? a.colw[int64_t(pole) * a.ncols + col] : a.weights[pole];
             zd *dst = xp + int64_t(k) * NB + zoff;
             const zd val = zmul(wc, v);
-            *dst = a.accumulate ? zadd(*dst, val) : val;
+            if (a.accumulate) *dst = zadd(*dst, val);
+            else *dst = val;
         };
 
         // gathered entry q of w_k (rows(k) window rows: NB + 16 while a block follows,
         // else NB): e = tid + 256 q, window row i = e % rows(k) (i < NB: w_top row i; else
         // this member's w_bot row i - NB), column e / rows(k).  Consecutive lanes take
         // consecutive rows of one column, which are adjacent in X and in the exchange area.
-        int psrc[GQ];
-        dv2 gv[GQ];
+        // window rows of w_k (the permutation), B X entries and t_k entries per thread
+        int pa_[GQ], pb_[GQ];
+        dv2 gv[GQ], gt[GQ];
         // the two window heights as compile-time constants (cheap divisions by rows)
         using Full = std::integral_constant<int, NB + kClRows>;
         using Last = std::integral_constant<int, NB>;
-        auto load_perm_r = [&](auto R_, int k) __attribute__((always_inline)) {
-            constexpr int rows = decltype(R_)::value;
+        // full windows (a block follows): per entry q the window row index into the
+        // permutation and the B X column, fixed for the whole sweep
+        int fpi[GQ];
+        const zd *fxc[GQ];
 #pragma unroll
-            for (int q = 0; q < GQ; ++q) {
-                const int e = tid + q * kClThreads, i = e % rows;
-                const int pi = i < NB ? i : NB + 16 * m + (i - NB);
-                const int v = e < rows * kClCols ? perm[int64_t(k) * 2 * NB + pi] : 0;
-                psrc[q] = v < 0 ? 0 : v >= 2 * NB ? 2 * NB - 1 : v;   // window rows only
-            }
+        for (int q = 0; q < GQ; ++q) {
+            constexpr int rows = NB + kClRows;
+            const int e = tid + q * kClThreads, i = e % rows, cc = e / rows;
+            fpi[q] = i < NB ? i : NB + 16 * m + (i - NB);
+            fxc[q] = a.X + int64_t(min(c0 + cc, a.ncols - 1)) * a.npad;
+        }
+        // entry q of the permutation of block k, as stored (read where it is used through
+        // wrow, which keeps it to the window's rows, so no loaded value is tested here)
+        auto perm_q_r = [&](auto R_, int k, int q, int (&ps)[GQ]) __attribute__((always_inline)) {
+            constexpr int rows = decltype(R_)::value;
+            const int e = tid + q * kClThreads, i = e % rows;
+            const int pi = i < NB ? i : NB + 16 * m + (i - NB);
+            if (e < rows * kClCols) ps[q] = perm[int64_t(k) * 2 * NB + pi];
         };
+        auto wrow = [](int v) __attribute__((always_inline)) { return min(max(v, 0), 2 * NB - 1); };
         // entry q of w_k as if it came from b: window row src is row k NB + src of B X
         // (block k for src < NB, block k+1 after); for k > 0 the entries with src < NB are
         // replaced by rows of t_k.  While block k+1 exists no loaded value is tested, so
         // the loads are only waited for where the window is stored.
-        auto gather_b_q = [&](auto R_, int k, int q) __attribute__((always_inline)) {
+        auto gather_b_r = [&](auto R_, int k, int q, const int (&ps)[GQ]) __attribute__((always_inline)) {
             constexpr int rows = decltype(R_)::value;
             const int e = tid + q * kClThreads, cc = e / rows;
             if (e >= rows * kClCols) return;
-            const int src = psrc[q];
+            const int src = wrow(ps[q]);
             const int64_t row = int64_t(k) * NB + src;
             if (k + 2 <= nblk) gv[q] = rhs(row, cc);
             else gv[q] = src < NB ? rhs(row, cc) : dv2{0.0, 0.0};    // last block: no b_{k+1}
         };
-        // entries of w_k that come from t_k (published rows of every member)
-        auto gather_t_r = [&](auto R_, const zd *pub) __attribute__((always_inline)) {
+        // all entries of w_k that come from b; one branch around straight-line loads (a
+        // branch per entry would make the loads wait for each other)
+        auto gather_b = [&](int k, const int (&ps)[GQ]) __attribute__((always_inline)) {
+            if (k + 1 < nblk) {                                    // block k+1 exists
+#pragma unroll
+                for (int q = 0; q < GQ; ++q) gv[q] = ld2(fxc[q] + int64_t(k) * NB + wrow(ps[q]));
+            } else {
+#pragma unroll
+                for (int q = 0; q < GQ; ++q) gather_b_r(Last(), k, q, ps);
+            }
+        };
+        auto load_perm = [&](int k, int (&ps)[GQ]) __attribute__((always_inline)) {
+            if (k + 1 < nblk) {
+#pragma unroll
+                for (int q = 0; q < GQ; ++q) ps[q] = perm[int64_t(k) * 2 * NB + fpi[q]];
+            } else {
+#pragma unroll
+                for (int q = 0; q < GQ; ++q) perm_q_r(Last(), k, q, ps);
+            }
+        };
+        // the published rows of t_k at the window rows, loaded for every entry (rows of b
+        // read a harmless row of t) and chosen where the window is stored
+        auto gather_t_r = [&](auto R_, const zd *pub, const int (&ps)[GQ]) __attribute__((always_inline)) {
             constexpr int rows = decltype(R_)::value;
 #pragma unroll
             for (int q = 0; q < GQ; ++q) {
                 const int e = tid + q * kClThreads, cc = e / rows;
-                const int src = psrc[q];
-                if (e < rows * kClCols && src < NB)
-                    gv[q] = ld2(pub + (src >> 4) * SLOT + cc * 16 + (src & 15));
+                const int src = wrow(ps[q]) & (NB - 1);
+                if (e < rows * kClCols) gt[q] = ld2(pub + (src >> 4) * SLOT + cc * 16 + (src & 15));
             }
         };
-        auto store_w_r = [&](auto R_) __attribute__((always_inline)) {
+        auto store_w_r = [&](auto R_, bool with_t, const int (&ps)[GQ]) __attribute__((always_inline)) {
             constexpr int rows = decltype(R_)::value;
 #pragma unroll
             for (int q = 0; q < GQ; ++q) {
                 const int e = tid + q * kClThreads, i = e % rows, cc = e / rows;
                 if (e >= rows * kClCols) continue;
-                vec[i * kVecLd + cc] = zmake(gv[q].x, gv[q].y);   // rows NB.. : w_bot
+                const dv2 v = (with_t && wrow(ps[q]) < NB) ? gt[q] : gv[q];
+                vec[i * kVecLd + cc] = zmake(v.x, v.y);   // rows NB.. : w_bot
             }
         };
-        auto load_perm = [&](int k) __attribute__((always_inline)) {
-            if (k + 1 < nblk) load_perm_r(Full(), k); else load_perm_r(Last(), k);
-        };
-        auto gather_b1 = [&](int k, int q) __attribute__((always_inline)) {
-            if (k + 1 < nblk) gather_b_q(Full(), k, q); else gather_b_q(Last(), k, q);
-        };
-        auto gather_b = [&](int k) __attribute__((always_inline)) {
-#pragma unroll
-            for (int q = 0; q < GQ; ++q) gather_b1(k, q);
-        };
-        auto gather_t = [&](int k, const zd *pub) __attribute__((always_inline)) {
+        auto gather_t = [&](int k, const zd *pub, const int (&ps)[GQ]) __attribute__((always_inline)) {
             cl_inv_l1();
-            if (k + 1 < nblk) gather_t_r(Full(), pub); else gather_t_r(Last(), pub);
+            if (k + 1 < nblk) gather_t_r(Full(), pub, ps); else gather_t_r(Last(), pub, ps);
         };
-        auto store_w = [&](int k) __attribute__((always_inline)) {
-            if (k + 1 < nblk) store_w_r(Full()); else store_w_r(Last());
+        auto store_w = [&](int k, bool with_t, const int (&ps)[GQ]) __attribute__((always_inline)) {
+            if (k + 1 < nblk) store_w_r(Full(), with_t, ps); else store_w_r(Last(), with_t, ps);
         };
         auto load_x = [&](const zd *pub) __attribute__((always_inline)) {
             cl_inv_l1();
@@ -360,34 +390,37 @@ __global__ __launch_bounds__(kClThreads) void band_solve_cluster_kernel(ClusterA
         // stores then finds the previous step's loads long done).  The loops are unrolled
         // by two so that every buffer is a fixed register set.
         dv2 ta[S::KS], tb[S::KS], tc[S::KS];
-        load_perm(0);
-        gather_b(0);
-        store_w(0);
+        load_perm(0, pa_);
+        gather_b(0, pa_);
+        store_w(0, false, pa_);
         if (nblk > 1) cl_load<NB>(tile(0, 0), ta);    // M_0
         cl_load<NB>(tile(0, 1), tb);                  // W_0
-        if (nblk > 1) load_perm(1);
+        if (nblk > 1) load_perm(1, pb_);
         __syncthreads();
         zd pre = zmake(0.0, 0.0), zcur = zmake(0.0, 0.0);
 
         // forward step k < nblk - 1, second tile in tcur, the next one into tnext
-        auto fwd = [&](int k, dv2 (&tcur)[S::KS], dv2 (&tnext)[S::KS]) __attribute__((always_inline)) {
+        // pcur holds the permutation of block k+1; that of block k+2 goes into pnext
+        auto fwd = [&](int k, dv2 (&tcur)[S::KS], dv2 (&tnext)[S::KS], int (&pcur)[GQ],
+                       int (&pnext)[GQ]) __attribute__((always_inline)) {
             // t_{k+1} = w_bot - M_k w_top
             cl_product<NB, 0>(ta, vec, red0, wave, lane, nullptr, ta, nullptr, ta);
             __syncthreads();
             publish(zsub(wbot[lrow * kVecLd + oc], cl_sum<NB>(red0, lrow, oc)));
-            // z_k = W_k w_top, while M_{k+1} (or V1_{nblk-2}) and W_{k+1} are requested;
-            // then the rows of w_{k+1} that come from b
+            // the rows of w_{k+1} that come from b and the permutation of block k+2 are
+            // requested first (ahead of the tile stream in the CU's queue); then
+            // z_k = W_k w_top while M_{k+1} (or V1_{nblk-2}) and W_{k+1} are requested
+            gather_b(k + 1, pcur);
+            if (k + 2 < nblk) load_perm(k + 2, pnext);
             const zd *na = k + 2 < nblk ? tile(k + 1, 0) : tile(nblk - 2, 2);
             const zd *nw = tile(k + 1, 1);
             cl_product<NB, 2>(tcur, vec, red1, wave, lane, na, ta, nw, tnext);
-            gather_b(k + 1);
             __syncthreads();
             const zd zv = cl_sum<NB>(red1, lrow, oc);
             if (colok) zb[int64_t(k) * NB + zoff] = zv;
             wait_all();
-            gather_t(k + 1, pub());                                      // w_{k+1}: rows of t
-            store_w(k + 1);
-            if (k + 2 < nblk) load_perm(k + 2);
+            gather_t(k + 1, pub(), pcur);                                // w_{k+1}: rows of t
+            store_w(k + 1, true, pcur);
             __syncthreads();
         };
         // backward step k >= 1: ta = V1_k, tcur = V2_{k-1}, the next V2 into tnext
@@ -441,11 +474,11 @@ __global__ __launch_bounds__(kClThreads) void band_solve_cluster_kernel(ClusterA
         };
         int k = 0;
         for (; k + 2 < nblk; k += 2) {
-            fwd(k, tb, tc);
-            fwd(k + 1, tc, tb);
+            fwd(k, tb, tc, pb_, pa_);
+            fwd(k + 1, tc, tb, pa_, pb_);
         }
         if (k + 1 < nblk) {
-            fwd(k, tb, tc);
+            fwd(k, tb, tc, pb_, pa_);
 #pragma unroll
             for (int j = 0; j < S::KS; ++j) tb[j] = tc[j];   // W_{nblk-1} into tb (registers)
         }
