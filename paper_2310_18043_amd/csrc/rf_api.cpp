@@ -198,7 +198,7 @@ static rf_status cluster_check(rf_plan *P) {
     if (h[0] > seen || h[1] > seen) {
         P->F.cluster_ok = false;
         return rf_fail(P, RF_ERR_DEVICE, h[1] > seen
-                       ? "band solve: a cluster workgroup did not run on the XCD its exchange assumes"
+                       ? "band solve: more cluster workgroups ran on one XCD than its share of the grid"
                        : "band solve: a cluster handoff wait timed out");
     }
     return RF_OK;
@@ -454,6 +454,7 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
         ALLOC(P->F.xchg, cluster_xchg_elems(nb, P->num_cu));
         ALLOC(P->F.cflags, cluster_flag_words(nb, P->num_cu));
         ALLOC(P->F.cerr, 2);
+        ALLOC(P->F.ctickets, 8 * 32);
         if (hipMemsetAsync(P->F.cflags, 0, cluster_flag_words(nb, P->num_cu) * 8, P->stream) != hipSuccess ||
             hipMemsetAsync(P->F.cerr, 0, 2 * sizeof(unsigned), P->stream) != hipSuccess ||
             cluster_gate_init(dev) != hipSuccess) {

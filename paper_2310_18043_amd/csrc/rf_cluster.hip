@@ -18,9 +18,11 @@
 // partial blocks in LDS), so a workgroup streams 1/C of its pole's tiles where the
 // per-slice solve streams all of them for one or two columns.  The rows of t_{k+1} and
 // x_k that a member produces reach the other members through an exchange area:
-//   * the members of a cluster run on one XCD (workgroup b is placed on XCD b mod 8;
-//     each workgroup compares its XCC id with that and reports a mismatch), so their
-//     stores and loads meet in that XCD's L2;
+//   * the members of a cluster run on one XCD, so their stores and loads meet in that
+//     XCD's L2: a workgroup reads its XCC id and takes a ticket from that XCD's counter
+//     (reset before every launch), and cluster slot and member follow from (XCD,
+//     ticket), in the order the workgroups arrive; a ticket past the XCD's share of the
+//     grid is reported;
 //   * a member stores its rows, waits until its stores are complete and then raises
 //     its sequence flag, a 64-bit word (launch epoch << 32 | publication number);
 //   * readers poll the flags and read the rows with agent-scope loads, which skip the
@@ -70,6 +72,7 @@ struct ClusterArgs {
     int unit_weight, accumulate;
     zd *xchg;                           // [slot][2][C][16 x 16]
     unsigned long long *flags;          // [slot][16]
+    unsigned *tickets;                  // [8 XCDs][32]: arrival counters, zero at launch
     unsigned *err;                      // [0] epoch of a timed-out wait, [1] of a misplaced member
     unsigned epoch;
     int nclusters, nslots;
@@ -198,17 +201,16 @@ __device__ inline void cl_wait(const unsigned long long *flags, unsigned long lo
     __syncthreads();
 }
 
-// grid: nslots * C workgroups of 256 threads; workgroup b is member (b / 8) % C of slot
-// ((b / 8) / C) * 8 + b % 8, so the members of a slot share an XCD.  Slot s solves
-// clusters s, s + nslots, ... (cluster c: pole c % p, right-hand sides 16 (c / p) ..).
+// grid: nslots * C workgroups of 256 threads, nslots a multiple of 8, so each XCD runs
+// nslots C / 8 of them: ticket t on XCD x makes a workgroup member t % C of slot
+// (t / C) * 8 + x.  Slot s solves clusters s, s + nslots, ... (cluster c: pole c % p,
+// right-hand sides 16 (c / p) ..).
 template <int NB>
 __global__ __launch_bounds__(kClThreads) void band_solve_cluster_kernel(ClusterArgs a) {
     using S = ClShape<NB>;
     constexpr int C = S::C, KW = S::KW, GQ = S::GQ, XQ = S::XQ, SLOT = S::SLOT;
     constexpr int64_t te = int64_t(NB) * NB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
-    const int m = loc % C, slot = (loc / C) * 8 + xcd;
     const unsigned long long ep = (unsigned long long)a.epoch << 32;
 
     extern __shared__ unsigned char smem_raw[];
@@ -217,13 +219,29 @@ __global__ __launch_bounds__(kClThreads) void band_solve_cluster_kernel(ClusterA
     zd *red0 = vec + S::VEC;                      // [4][16 x 17]: first product's partials
     zd *red1 = red0 + 4 * S::RED;                 // [4][16 x 17]: second product's partials
 
+    __shared__ int s_place[2];
     if (tid == 0) {
         unsigned xcc;
         asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
-        if (int(xcc & 15u) != xcd)
-            __hip_atomic_store(a.err + 1, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        xcc &= 15u;
+        int sl = -1, mm = 0;
+        if (xcc < 8u) {
+            const unsigned t = __hip_atomic_fetch_add(a.tickets + xcc * 32, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            if (t < unsigned(a.nslots / 8 * C)) {
+                sl = int(t / C) * 8 + int(xcc);
+                mm = int(t % C);
+            }
+        }
+        if (sl < 0) __hip_atomic_store(a.err + 1, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_place[0] = sl;
+        s_place[1] = mm;
     }
-    if (slot >= a.nslots) return;                 // not reached: the grid is nslots * C
+    __syncthreads();
+    const int slot = s_place[0], m = s_place[1];
+    // a workgroup past its XCD's share leaves; the members that would wait for it give up
+    // after the bounded wait, and the launch is reported
+    if (slot < 0) return;
 
     const int lrow = tid & 15, oc = tid >> 4;     // this thread's entry of a 16 x 16 block
     unsigned long long *myflag = a.flags + int64_t(slot) * kFlagsPerSlot + m;
@@ -490,8 +508,9 @@ __global__ __launch_bounds__(kClThreads) void band_solve_cluster_kernel(ClusterA
 // Y (row, col) = d[row] X (row, col) for rows < n (d null: 1), 0 for rows n .. npad-1;
 // Y is npad x ncols (ld npad) and may be X itself (then ldx = npad)
 __global__ void stage_kernel(int64_t n, int64_t npad, int ncols, const zd *d, const zd *X,
-                             int64_t ldx, zd *Y) {
+                             int64_t ldx, zd *Y, unsigned *tickets) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < 8) tickets[e * 32] = 0u;          // the cluster kernel's arrival counters
     if (e >= npad * ncols) return;
     const int64_t r = e % npad, c = e / npad;
     zd v = zmake(0.0, 0.0);
@@ -573,7 +592,8 @@ hipError_t launch_fused_tiles(const rf_plan &P, hipStream_t s) {
 
 hipError_t launch_cluster_solve(const rf_plan &P, const ClusterSolve &cs, hipStream_t s) {
     const int nb = P.F.nb;
-    if (!cluster_solve_supported(nb) || !P.F.ftiles || !P.F.xchg || !P.F.cflags || !P.F.cerr)
+    if (!cluster_solve_supported(nb) || !P.F.ftiles || !P.F.xchg || !P.F.cflags || !P.F.cerr ||
+        !P.F.ctickets)
         return hipErrorInvalidValue;
     if (P.device < 0 || P.device >= kMaxDev || !g_gate[P.device].ready) return hipErrorNotReady;
     const int C = nb / kClRows;
@@ -585,7 +605,7 @@ hipError_t launch_cluster_solve(const rf_plan &P, const ClusterSolve &cs, hipStr
     {
         const int64_t tot = a.npad * int64_t(cs.ncols);
         hipLaunchKernelGGL(stage_kernel, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, P.n,
-                           a.npad, cs.ncols, cs.bdiag, cs.X, cs.ldx, cs.stage);
+                           a.npad, cs.ncols, cs.bdiag, cs.X, cs.ldx, cs.stage, P.F.ctickets);
         hipError_t e0 = hipGetLastError();
         if (e0 != hipSuccess) return e0;
         a.X = cs.stage;
@@ -594,7 +614,7 @@ hipError_t launch_cluster_solve(const rf_plan &P, const ClusterSolve &cs, hipStr
     a.weights = P.d_weights; a.colw = cs.colw;
     a.zbuf = cs.zbuf; a.xpart = cs.xpart;
     a.unit_weight = cs.unit_weight; a.accumulate = cs.accumulate;
-    a.xchg = P.F.xchg; a.flags = P.F.cflags; a.err = P.F.cerr;
+    a.xchg = P.F.xchg; a.flags = P.F.cflags; a.err = P.F.cerr; a.tickets = P.F.ctickets;
     a.epoch = ++P.F.cepoch;
     a.nclusters = a.p * ((cs.ncols + kClCols - 1) / kClCols);
     const int smax = cluster_slots_max(nb, P.num_cu);

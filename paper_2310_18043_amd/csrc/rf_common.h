@@ -85,6 +85,7 @@ struct BandFactors {
     zd *xchg = nullptr;
     unsigned long long *cflags = nullptr;
     unsigned *cerr = nullptr;
+    unsigned *ctickets = nullptr;  // per-XCD arrival counters (8 x 32 words)
     mutable unsigned cepoch = 0;   // epoch of the last cluster launch
     unsigned cerr_seen = 0;        // launches up to this epoch have been checked
     bool cluster_ok = true;        // false after a reported failure: per-slice solves

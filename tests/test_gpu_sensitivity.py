@@ -200,10 +200,12 @@ def test_full_size_velocity_gradient_fd(rf, torch_cuda):
     # t_i = lambda_i(v0) + 0.01 xi_i (xi seeded complex Gaussian); dL/dv from the adjoint
     # solves (K_i^H sweeps over the right problem's factors) and rf_eig_vjp, against
     # central differences of re-solved eigenvalues on 32 random cells.  Step sweep:
-    # h = 2e-3 and 1e-3 and their Richardson combination (4 D(h/2) - D(h)) / 3 (the
-    # eigenvalues are smooth in v away from the upwind switch at v = 0, so cells have
-    # |v| > 10 h); the best of the three must be within 1e-6.  h = 1e-6 is printed as
-    # measured: there the rounding of the eigenvalues (about 1e-12 absolute) dominates.
+    # h = 4e-3, 2e-3 and 1e-3 and the Richardson combinations (4 D(h/2) - D(h)) / 3 of
+    # neighbouring steps (the eigenvalues are smooth in v away from the upwind switch at
+    # v = 0, so cells have |v| > 10 h); the best of the five must be within 1e-6.  The
+    # re-solved loss carries rounding noise of about 1e-12 (h = 1e-6, printed as
+    # measured, is dominated by it), which is 1e-6 of a gradient of 1e-4 at h = 1e-3:
+    # the larger steps keep that term below the bar.
     import torch
     from scipy.optimize import linear_sum_assignment
     wl = W.random_velocity_workload()
@@ -250,19 +252,20 @@ def test_full_size_velocity_gradient_fd(rf, torch_cuda):
         return (L(vp) - L(vm)) / (2 * h)
 
     mag = np.abs(grad)
-    hmax = 2e-3
+    hmax = 4e-3
     cand = np.argwhere((mag >= 0.05 * mag.max()) & (np.abs(v) > 10 * hmax))
     picks = cand[rng.choice(len(cand), size=32, replace=False)]
     best = []
     for comp, iy, ix in picks:
         g = grad[comp, iy, ix]
-        d1, d2 = fd(comp, iy, ix, 2e-3), fd(comp, iy, ix, 1e-3)
-        rich = (4.0 * d2 - d1) / 3.0
-        errs = [abs(d - g) / abs(g) for d in (d1, d2, rich)]
+        d0, d1, d2 = fd(comp, iy, ix, 4e-3), fd(comp, iy, ix, 2e-3), fd(comp, iy, ix, 1e-3)
+        r01, r12 = (4.0 * d1 - d0) / 3.0, (4.0 * d2 - d1) / 3.0
+        errs = [abs(d - g) / abs(g) for d in (d0, d1, d2, r01, r12)]
         tiny = abs(fd(comp, iy, ix, 1e-6) - g) / abs(g)
         best.append(min(errs))
-        _say(f"  cell {(int(comp), int(iy), int(ix))} grad {g:.6e}: rel err h=2e-3 {errs[0]:.1e}, "
-             f"h=1e-3 {errs[1]:.1e}, Richardson {errs[2]:.1e}; h=1e-6 {tiny:.1e}")
+        _say(f"  cell {(int(comp), int(iy), int(ix))} grad {g:.6e}: rel err h=4e-3 {errs[0]:.1e}, "
+             f"2e-3 {errs[1]:.1e}, 1e-3 {errs[2]:.1e}, Richardson {errs[3]:.1e} {errs[4]:.1e}; "
+             f"h=1e-6 {tiny:.1e}")
     best = np.array(best)
     print(f"32 cells: best-of-sweep relative error max {best.max():.2e} median {np.median(best):.2e}")
     assert best.max() <= 1e-6, best.max()
