@@ -320,9 +320,9 @@ def batched_form_256(wave, with_sequential=True):
     """The batched configuration: 64 disks along the real axis of the 256 x 256
     random-velocity pencil (10..200 eigenvalues each, block widths 16..256, p = 4,
     q cycling through 4, 8, 16; tests/golden/convdiff256_disks.txt).  The disks go
-    through the HBM in waves of `wave` disks: per wave one batch (all its poles
-    factorized in one launch sequence, its disks solved concurrently on their own
-    streams), destroyed before the next.  A pair counts when it is converged
+    through the HBM in waves of `wave` disks of similar block width: per wave one batch
+    (all its poles factorized in one launch sequence, its disks solved concurrently on
+    their own streams), destroyed before the next.  A pair counts when it is converged
     (inside, e <= 1e-10) and matches the oracle's reference eigenvalue of its disk
     to 1e-10 relative (tests/golden/convdiff256_disk_eigs.txt).  Against the same
     disks solved one after another, one plan each."""
@@ -353,8 +353,10 @@ def batched_form_256(wave, with_sequential=True):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     found_b, sweeps, peak = 0, [], 0
+    # waves of disks of similar block width (a wave lasts as long as its slowest disk)
+    order = sorted(range(len(disks)), key=lambda d: (-disks[d]["w"], d))
     for w0 in range(0, len(disks), wave):
-        idx = list(range(w0, min(w0 + wave, len(disks))))
+        idx = order[w0:w0 + wave]
         specs = [{"c": disks[d]["c"], "r": disks[d]["r"], "w": disks[d]["w"], "q": disks[d]["q"],
                   "expected_count": disks[d]["count"]} for d in idx]
         bt = rfeig.Batch(A, B, specs, **common)
