@@ -213,7 +213,9 @@ __global__ __launch_bounds__(kClThreads) void band_solve_cluster_kernel(ClusterA
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const unsigned long long ep = (unsigned long long)a.epoch << 32;
 
-    extern __shared__ unsigned char smem_raw[];
+    // 16-byte aligned: the static placement words below come first in LDS, and every
+    // array here is read and written 16 bytes (one complex double) at a time
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     zd *vec = reinterpret_cast<zd *>(smem_raw);   // [NB][17]: w_top, later x_{k+1}
     zd *wbot = vec + NB * kVecLd;                 // [16][17]: this member's rows of w_bot
     zd *red0 = vec + S::VEC;                      // [4][16 x 17]: first product's partials
@@ -238,7 +240,8 @@ __global__ __launch_bounds__(kClThreads) void band_solve_cluster_kernel(ClusterA
         s_place[1] = mm;
     }
     __syncthreads();
-    const int slot = s_place[0], m = s_place[1];
+    const int slot = __builtin_amdgcn_readfirstlane(s_place[0]);
+    const int m = __builtin_amdgcn_readfirstlane(s_place[1]);
     // a workgroup past its XCD's share leaves; the members that would wait for it give up
     // after the bounded wait, and the launch is reported
     if (slot < 0) return;
