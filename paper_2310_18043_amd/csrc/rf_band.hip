@@ -165,10 +165,12 @@ struct PivotCand {
 // the position of its row, and the pivot row and the row at the pivot position trade
 // positions, so row interchanges of the whole sub-panel (the multipliers of earlier
 // columns included) come for free.  Per column: the candidate of each wave (DPP max,
-// ballot) writes its key and its row from the pivot column on to LDS, one barrier,
-// every thread picks the winner among the waves' candidates and updates its own row.
-// Candidates and pivot rows are double-buffered by column parity, so one barrier per
-// column suffices.  The rows are written back at their new positions, with the
+// ballot) writes a record (key, thread, position) to LDS, one barrier, every thread
+// picks the winner among the waves' records, the winning thread stores its row from the
+// pivot column on, a second barrier, and every thread updates its own row.  (Every wave
+// storing its candidate's row before a single barrier costs more: a wave's LDS stores
+// issue one at a time, some tens of cycles each, so four waves' rows took longer than
+// one row and a barrier.)  The rows are written back at their new positions, with the
 // sub-panel's row order (subperm) and the running permutation of the block step.
 template <int SW, int NT>
 __global__ __launch_bounds__(NT) void band_panel_kernel(FactorArgs a, int k, int buf, int c0) {
@@ -180,8 +182,8 @@ __global__ __launch_bounds__(NT) void band_panel_kernel(FactorArgs a, int k, int
     const int nw = int(blockDim.x) >> 6;
     const int R = (k + 1 < nblk) ? 2 * nb : nb;
     const bool live = tid < R;
-    __shared__ PivotCand cand[2][NWMAX];
-    __shared__ zd urow[2][NWMAX][SW];
+    __shared__ PivotCand cand[NWMAX];
+    __shared__ zd urow[SW];
     __shared__ int s_pm[NT];
     int32_t *pm = a.perm + (int64_t(pole) * nblk + k) * (2 * nb);
     // the running permutation is read before the first barrier and written after the
@@ -190,13 +192,13 @@ __global__ __launch_bounds__(NT) void band_panel_kernel(FactorArgs a, int k, int
     zd x[SW];
 #pragma unroll
     for (int j = 0; j < SW; ++j) x[j] = live ? W[tid + int64_t(c0 + j) * ldw] : zmake(0, 0);
-    // the pivot-row buffers start finite (a singular column reads one, times zero)
-    for (int e = tid; e < 2 * NWMAX * SW; e += int(blockDim.x)) (&urow[0][0][0])[e] = zmake(0, 0);
+    // the pivot row starts finite (a singular column reads it, times zero)
+    if (tid < SW) urow[tid] = zmake(0, 0);
     // waves that do not exist never offer a candidate
-    if (tid < 2 * NWMAX && (tid % NWMAX) >= nw) {
-        cand[tid / NWMAX][tid % NWMAX].key = 0;
-        cand[tid / NWMAX][tid % NWMAX].tid = -1;
-        cand[tid / NWMAX][tid % NWMAX].pos = -1;
+    if (tid < NWMAX && tid >= nw) {
+        cand[tid].key = 0;
+        cand[tid].tid = -1;
+        cand[tid].pos = -1;
     }
     // the initialisation above must land before the first candidates are written
     __syncthreads();
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(NT) void band_panel_kernel(FactorArgs a, int k, int
     int info = 0;
 #pragma unroll
     for (int j = 0; j < SW; ++j) {
-        const int gj = c0 + j, par = j & 1;
+        const int gj = c0 + j;
         const bool is_cand = live && pos >= gj;
         const double m = zabs2(x[j]);
         const uint64_t mine = (is_cand && m > 0.0) ? uint64_t(__double_as_longlong(m)) : 0;
@@ -216,31 +218,34 @@ __global__ __launch_bounds__(NT) void band_panel_kernel(FactorArgs a, int k, int
         if (hit != 0 && lane == int(__builtin_ctzll(hit))) {
             PivotCand c;
             c.key = wmax; c.tid = tid; c.pos = pos;
-            cand[par][wave] = c;
-#pragma unroll
-            for (int q = j; q < SW; ++q) urow[par][wave][q] = x[q];
+            cand[wave] = c;
         } else if (hit == 0 && lane == 0) {
             PivotCand c;
             c.key = 0; c.tid = -1; c.pos = -1;
-            cand[par][wave] = c;
+            cand[wave] = c;
         }
         __syncthreads();
         // winner: largest nonzero key, ties to the lowest wave (so the lowest thread);
         // none: singular column (no interchange, zero multipliers)
         PivotCand cw[NWMAX];
 #pragma unroll
-        for (int w = 0; w < NWMAX; ++w) cw[w] = cand[par][w];
+        for (int w = 0; w < NWMAX; ++w) cw[w] = cand[w];
         uint64_t bk = 0;
-        int tw = -1, pw = gj, bw = 0;
+        int tw = -1, pw = gj;
 #pragma unroll
         for (int w = 0; w < NWMAX; ++w)
-            if (cw[w].key > bk) { bk = cw[w].key; tw = cw[w].tid; pw = cw[w].pos; bw = w; }
+            if (cw[w].key > bk) { bk = cw[w].key; tw = cw[w].tid; pw = cw[w].pos; }
         tw = __builtin_amdgcn_readfirstlane(tw);
         pw = __builtin_amdgcn_readfirstlane(pw);
-        bw = __builtin_amdgcn_readfirstlane(bw);
         const bool sing = tw < 0;
         if (sing && info == 0) info = k * nb + gj + 1;
-        const zd *ur = urow[par][bw];
+        // only the winning row goes through LDS (a wave's LDS stores issue one at a time)
+        if (tid == tw) {
+#pragma unroll
+            for (int q = j; q < SW; ++q) urow[q] = x[q];
+        }
+        __syncthreads();
+        const zd *ur = urow;
         const zd uj = ur[j];
         // 1 / u_j = conj(u_j) / |u_j|^2 (the pivot is the column's largest entry)
         const double sc = 1.0 / zabs2(uj);
