@@ -1233,15 +1233,57 @@ struct Projected {
     int w = 0;
     zd *V = nullptr, *AV = nullptr, *BV = nullptr;   // the basis and its products (device)
     std::vector<zd> A, B, al, be, vr;
+    std::complex<double> sigma{0.0, 0.0};             // W = orth(AV - sigma BV)
     int qz_status = 0;
     double qz_ms = 0.0;           // host time of the last QZ (reported by RFEIG_TRACE)
+    double lower_rel = 0.0;       // strict lower part of A - sigma B, relative (reported)
+    bool swapped = false;         // the QZ ran on (B, A - sigma B)
     QzStats qz_stats{};
+    // The eigenpairs of (A, B).  W comes from a QR of AV - sigma BV, so R = A - sigma B =
+    // W^* (AV - sigma BV) is upper triangular up to rounding; the pencil (B, R) has the
+    // same eigenvectors and the eigenvalues mu = 1 / (lambda - sigma), and its second
+    // matrix is already triangular, so its QZ skips the QR of step 1 (and, measured, needs
+    // fewer sweeps: 383-415 against 433-459 on the 128 x 128 workload's pencils).  It is
+    // used when R's strict lower part is at the rounding level (else the QZ runs on (A, B)).
     void run_qz() {
+        typedef std::complex<double> cd;
         const auto t0 = std::chrono::steady_clock::now();
-        qz_status = host_qz_eig(w, reinterpret_cast<const double *>(A.data()),
-                                reinterpret_cast<const double *>(B.data()),
-                                reinterpret_cast<double *>(al.data()), reinterpret_cast<double *>(be.data()),
-                                reinterpret_cast<double *>(vr.data()));
+        const cd *Ac = reinterpret_cast<const cd *>(A.data());
+        const cd *Bc = reinterpret_cast<const cd *>(B.data());
+        std::vector<cd> R(size_t(w) * w);
+        double lmax = 0.0, scale = 0.0;
+        for (int j = 0; j < w; ++j)
+            for (int i = 0; i < w; ++i) {
+                const size_t e = i + size_t(j) * w;
+                R[e] = Ac[e] - sigma * Bc[e];
+                scale = std::max(scale, std::abs(Ac[e]) + std::abs(sigma) * std::abs(Bc[e]));
+                if (i > j) lmax = std::max(lmax, std::abs(R[e]));
+            }
+        lower_rel = scale > 0.0 ? lmax / scale : 0.0;
+        // the entries of A and B are sums over the n rows of the blocks, whose rounding
+        // is of the order of 1e-14 of the largest entry (observed: 4e-14 .. 9e-14 at
+        // n = 16384); a lower part up to 1e-12 of it is treated as rounding
+        swapped = scale > 0.0 && std::isfinite(lmax) && lower_rel <= 1e-12;
+        if (swapped) {
+            std::vector<cd> a2(w), b2(w);
+            qz_status = host_qz_eig_ex(w, reinterpret_cast<const double *>(Bc),
+                                       reinterpret_cast<const double *>(R.data()), true,
+                                       reinterpret_cast<double *>(a2.data()),
+                                       reinterpret_cast<double *>(b2.data()),
+                                       reinterpret_cast<double *>(vr.data()));
+            // mu = a2 / b2, lambda = sigma + b2 / a2 = (sigma a2 + b2) / a2
+            for (int i = 0; i < w; ++i) {
+                const cd a = sigma * a2[i] + b2[i];
+                al[i] = zmake(a.real(), a.imag());
+                be[i] = zmake(a2[i].real(), a2[i].imag());
+            }
+        } else {
+            qz_status = host_qz_eig_ex(w, reinterpret_cast<const double *>(Ac),
+                                       reinterpret_cast<const double *>(Bc), false,
+                                       reinterpret_cast<double *>(al.data()),
+                                       reinterpret_cast<double *>(be.data()),
+                                       reinterpret_cast<double *>(vr.data()));
+        }
         qz_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         qz_stats = host_qz_last_stats;
     }
@@ -1279,6 +1321,7 @@ rf_status hsrr_project(rf_plan *P, zd *U, Projected &pr, int buf = 0) {
     RF_HIP(P, launch_gemm_cn(n, w, w, Z(1), P->hW, n, 0, pr.BV, n, 0, Z(0), Bh, w, 0, 1, P->partial,
                              P->partial_elems, s));
     pr.w = w;
+    pr.sigma = sigma;
     pr.A.resize(size_t(w) * w);
     pr.B.resize(size_t(w) * w);
     pr.al.resize(w);
@@ -1479,8 +1522,10 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
                 fin = hsrr_finish(P, pr, lam, err);
                 if (trace_on())
                     std::fprintf(stderr, "[rfeig] sweep %d: host QZ %.1f ms (QR %.1f, HT %.1f, QZ %.1f in %d "
-                                         "sweeps, vectors %.1f)\n", t, pr.qz_ms, pr.qz_stats.qr_ms,
-                                 pr.qz_stats.ht_ms, pr.qz_stats.qz_ms, pr.qz_stats.sweeps, pr.qz_stats.vec_ms);
+                                         "sweeps, vectors %.1f; pencil %s, lower part %.1e)\n",
+                                 t, pr.qz_ms, pr.qz_stats.qr_ms, pr.qz_stats.ht_ms, pr.qz_stats.qz_ms,
+                                 pr.qz_stats.sweeps, pr.qz_stats.vec_ms,
+                                 pr.swapped ? "(B, A - sigma B)" : "(A, B)", pr.lower_rel);
                 decided = true;
                 ms_hsrr += now_ms() - t3;
                 if (fin == RF_OK) converged = judge(t, 0.0);

@@ -6,7 +6,7 @@
 // solved on the CPU while the device holds the large blocks.
 //
 // Steps (complex arithmetic throughout):
-//   1. Householder QR of B: B = Q R; A <- Q^H A.
+//   1. Householder QR of B: B = Q R; A <- Q^H A (skipped when B is upper triangular).
 //   2. Hessenberg-triangular reduction with Givens rotations: zero A below the
 //      first subdiagonal column by column; each left rotation's fill in B is
 //      removed by a right rotation, which is accumulated into Z.
@@ -72,6 +72,11 @@ thread_local QzStats host_qz_last_stats;
 
 int host_qz_eig(int n, const double *Ain, const double *Bin, double *alpha_out, double *beta_out,
                 double *vr_out) {
+    return host_qz_eig_ex(n, Ain, Bin, false, alpha_out, beta_out, vr_out);
+}
+
+int host_qz_eig_ex(int n, const double *Ain, const double *Bin, bool b_upper, double *alpha_out,
+                   double *beta_out, double *vr_out) {
     if (n <= 0) return 0;
     using clk = std::chrono::steady_clock;
     auto ms = [](clk::time_point a, clk::time_point b) {
@@ -83,13 +88,13 @@ int host_qz_eig(int n, const double *Ain, const double *Bin, double *alpha_out, 
         for (int i = 0; i < n; ++i) {
             const size_t e = 2 * (i + size_t(j) * n);
             A(i, j) = cd(Ain[e], Ain[e + 1]);
-            B(i, j) = cd(Bin[e], Bin[e + 1]);
+            B(i, j) = (b_upper && i > j) ? cd(0.0) : cd(Bin[e], Bin[e + 1]);
             Z(i, j) = (i == j) ? 1.0 : 0.0;
         }
     const double eps = 2.220446049250313e-16;
     // 1. Householder QR of B, applied to A from the left
     std::vector<cd> v(n);
-    for (int k = 0; k < n - 1; ++k) {
+    for (int k = 0; k < (b_upper ? 0 : n - 1); ++k) {
         double nrm2 = 0.0;
         for (int i = k; i < n; ++i) nrm2 += std::norm(B(i, k));
         double nrm = std::sqrt(nrm2);

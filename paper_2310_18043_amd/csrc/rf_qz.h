@@ -10,3 +10,8 @@ extern thread_local QzStats host_qz_last_stats;
 // (n each), unit-norm eigenvectors in the columns of vr (n x n).  0 on success, -1 if
 // the iteration did not converge.  A and B are not modified.
 int host_qz_eig(int n, const double *A, const double *B, double *alpha, double *beta, double *vr);
+
+// host_qz_eig for an upper triangular B when b_upper is set: the QR of step 1 is skipped
+// and B's strict lower part is taken as zero.
+int host_qz_eig_ex(int n, const double *A, const double *B, bool b_upper, double *alpha,
+                   double *beta, double *vr);
