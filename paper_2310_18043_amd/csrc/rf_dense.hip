@@ -286,14 +286,17 @@ __global__ __launch_bounds__(GT) void gemm_nn_mfma_kernel(int64_t n, int m, int 
 // pivot is not positive; dratio[t] = min_i R_ii / max_i R_ii (condition estimate).
 // ---------------------------------------------------------------------------
 // Register version for k <= K (K = 32 or 64): thread (i = tid % K, g = tid / K) holds
-// row i, columns g CPT .. g CPT + CPT - 1 of the matrix being reduced.
+// row i, columns g CPT .. g CPT + CPT - 1 of the matrix being reduced and of X.
 //   Cholesky, right-looking: before step j every thread reads column j (published in
 //   LDS by its owners at the end of step j - 1), scales its element of column j by
 //   1 / sqrt(d_j) and takes the rank-one update of its elements right of column j;
-//   the owners of column j + 1 then publish it.  Column buffers alternate by step
-//   parity, so one barrier per column suffices.
-//   X = L^{-1}, right-looking forward substitution on the identity: the owners of row
-//   r scale it by 1 / L_rr and publish it, every row below subtracts L_ir times it.
+//   the owners of column j + 1 then publish it.
+//   X = L^{-1} in the same steps (right-looking forward substitution on the identity):
+//   row j of X is final once the steps before j have been taken, so its owners
+//   publish it beside column j; step j scales it by 1 / L_jj and every row below
+//   subtracts L_ij times it.  Per element these are the operations, in the order, of a
+//   separate substitution pass after the factorization, which would take K more
+//   steps.  Column and row buffers alternate by step parity: one barrier per step.
 // Rows and columns past k are the identity and take no part.
 template <int K, int NT>
 __global__ __launch_bounds__(NT) void chol_inv_reg_kernel(int k, const zd *S, int64_t sS,
@@ -307,21 +310,26 @@ __global__ __launch_bounds__(NT) void chol_inv_reg_kernel(int k, const zd *S, in
     zd *Rg = Rout + bidx(map, flags, kMapB, bt) * sR;
     zd *Rig = Rinv + bidx(map, flags, kMapC, bt) * sRi;
     const int tid = threadIdx.x, i = tid % K, g = tid / K, c0 = g * CPT;
-    __shared__ zd colb[2][K];
-    __shared__ zd Ls[K][K + 1];              // Ls[c][r] = L[r][c]
-    __shared__ double rdiag[K], sdiag[K];    // 1 / L_jj, L_jj
+    __shared__ zd colb[2][K];                // column j of the matrix being reduced
+    __shared__ zd rowb[2][K];                // row j of X
+    __shared__ double sdiag[K];              // L_jj
     __shared__ double s_shift;
     __shared__ int s_bad;
-    zd a[CPT];
+    zd a[CPT], x[CPT];
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
         const int l = c0 + q;
         a[q] = (i < k && l < k) ? Sg[i + int64_t(l) * k] : zmake(i == l ? 1.0 : 0.0, 0.0);
+        x[q] = zmake(l == i ? 1.0 : 0.0, 0.0);
     }
     // the diagonal for the shift (one element per thread, read in parallel)
     if (tid < K) sdiag[tid] = (tid < k) ? Sg[tid + int64_t(tid) * k].x : 0.0;
-    // column 0 published by its owners
+    // column 0 and row 0 of X published by their owners
     if (g == 0) colb[0][i] = a[0];
+    if (i == 0) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) rowb[0][c0 + q] = x[q];
+    }
     __syncthreads();
     if (tid == 0) {
         double mx = 0.0;
@@ -339,17 +347,18 @@ __global__ __launch_bounds__(NT) void chol_inv_reg_kernel(int k, const zd *S, in
         for (int jj = 0; jj < CPT; ++jj) {
             const int j = jb * CPT + jj, par = jj & 1;     // CPT is even: parity of j
             const zd *cj = colb[par];
+            const zd *xj = rowb[par];
             double d = cj[j].x + (j < k ? shift : 0.0);
             if (!(d > 0.0)) {
                 if (tid == 0 && s_bad == 0) s_bad = j + 1;
                 d = 1.0;
             }
             const double sq = sqrt(d), rs = 1.0 / sq, rd = 1.0 / d;
-            if (tid == 0) { rdiag[j] = rs; sdiag[j] = sq; }
+            if (tid == 0) sdiag[j] = sq;
             const zd ci = cj[i];
-            zd cl[CPT];                                // all reads issued before any use
+            zd cl[CPT], xr[CPT];                       // all reads issued before any use
 #pragma unroll
-            for (int q = 0; q < CPT; ++q) cl[q] = cj[c0 + q];
+            for (int q = 0; q < CPT; ++q) { cl[q] = cj[c0 + q]; xr[q] = xj[c0 + q]; }
             const zd cir = zmake(ci.x * rd, ci.y * rd);
 #pragma unroll
             for (int q = 0; q < CPT; ++q) {
@@ -361,48 +370,27 @@ __global__ __launch_bounds__(NT) void chol_inv_reg_kernel(int k, const zd *S, in
                     a[q].y -= cir.y * cl[q].x - cir.x * cl[q].y;
                 }
             }
-            if (g == jb)
-                a[jj] = (i == j) ? zmake(sq, 0.0) : (i > j ? zmake(ci.x * rs, ci.y * rs) : zmake(0, 0));
-            // publish column j + 1
+            const zd lij = (i > j) ? zmake(ci.x * rs, ci.y * rs) : zmake(0, 0);
+            if (g == jb) a[jj] = (i == j) ? zmake(sq, 0.0) : lij;
+            // X: row j scaled by 1 / L_jj; the rows below subtract L_ij times it (the
+            // rows at or above j take it times zero)
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                const zd xs = zmake(xr[q].x * rs, xr[q].y * rs);
+                if (i == j) x[q] = xs;
+                else zfms(x[q], lij, xs);
+            }
+            // publish column j + 1 and row j + 1 of X
             if (jj + 1 < CPT) {
                 if (g == jb) colb[par ^ 1][i] = a[jj + 1 < CPT ? jj + 1 : 0];
             } else if (g == jb + 1) {
                 colb[par ^ 1][i] = a[0];
             }
-            __syncthreads();
-        }
-    }
-    // L to LDS (lower triangle, zeros above); the identity starts X
+            if (i == j + 1) {
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int l = c0 + q;
-        Ls[l][i] = (l <= i) ? a[q] : zmake(0, 0);
-        a[q] = zmake(l == i ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
-    // X = L^{-1}: step r fixes row r and removes it from the rows below
-#pragma unroll 1
-    for (int rb = 0; rb < NCG; ++rb) {
-#pragma unroll
-        for (int rr = 0; rr < CPT; ++rr) {
-            const int r = rb * CPT + rr, par = rr & 1;
-            if (i == r) {
-                const double rq = rdiag[r];
-#pragma unroll
-                for (int q = 0; q < CPT; ++q) {
-                    a[q] = zmake(a[q].x * rq, a[q].y * rq);
-                    colb[par][c0 + q] = a[q];
-                }
+                for (int q = 0; q < CPT; ++q) rowb[par ^ 1][c0 + q] = x[q];
             }
             __syncthreads();
-            // rows below r: subtract L_ir x_r (x_r is zero right of column r, so the
-            // update is taken everywhere; rows at or above r take it times zero)
-            const zd lir = (i > r) ? Ls[r][i] : zmake(0, 0);
-            zd xr[CPT];
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) xr[q] = colb[par][c0 + q];
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) zfms(a[q], lir, xr[q]);
         }
     }
     // R = L^H (upper), Rinv = X^H
@@ -411,8 +399,8 @@ __global__ __launch_bounds__(NT) void chol_inv_reg_kernel(int k, const zd *S, in
         for (int q = 0; q < CPT; ++q) {
             const int l = c0 + q;
             if (l < k) {
-                Rg[l + int64_t(i) * k] = (l <= i) ? zconj(Ls[l][i]) : zmake(0, 0);
-                Rig[l + int64_t(i) * k] = (l <= i) ? zconj(a[q]) : zmake(0, 0);
+                Rg[l + int64_t(i) * k] = (l <= i) ? zconj(a[q]) : zmake(0, 0);
+                Rig[l + int64_t(i) * k] = (l <= i) ? zconj(x[q]) : zmake(0, 0);
             }
         }
     }
@@ -1126,7 +1114,7 @@ hipError_t launch_chol_inv(int k, zd *S, int64_t sS, zd *Rout, int64_t sR, zd *R
         hipLaunchKernelGGL((chol_inv_reg_kernel<32, 256>), dim3(batch), dim3(256), 0, s, k, S, sS, Rout, sR,
                            Rinv, sRi, status, dratio, shift_rel, map, flags);
     } else if (k <= 64) {
-        hipLaunchKernelGGL((chol_inv_reg_kernel<64, 512>), dim3(batch), dim3(512), 0, s, k, S, sS, Rout, sR,
+        hipLaunchKernelGGL((chol_inv_reg_kernel<64, 1024>), dim3(batch), dim3(1024), 0, s, k, S, sS, Rout, sR,
                            Rinv, sRi, status, dratio, shift_rel, map, flags);
     } else {
         if (map) return hipErrorInvalidValue;
