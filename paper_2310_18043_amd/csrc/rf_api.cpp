@@ -1442,7 +1442,7 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
     std::vector<int> flags(w);
     rf_filter_info fi{};
     // the stopping rule of Alg. composite on sweep t's Ritz pairs
-    auto judge = [&](int sweep, double ms_f) {
+    auto stopping_rule = [&](int sweep, double ms_f) {
         int count = 0;
         bool all_small = true;
         for (int i = 0; i < w; ++i) {
@@ -1486,7 +1486,7 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
             const double t2 = now_ms();
             RF_TRY(hsrr(P, P->ytil, lam, err));
             ms_hsrr += now_ms() - t2;
-            if (judge(t, 0.0)) { converged = true; break; }
+            if (stopping_rule(t, 0.0)) { converged = true; break; }
         }
     } else {
         // Sweep t + 1 filters the orthonormal basis V_t of sweep t's HSRR (P->hV) instead of
@@ -1528,7 +1528,7 @@ rf_status rf_solve_region(rf_plan_t P, const void *Y0, int64_t ldy, rf_result *r
                                  pr.swapped ? "(B, A - sigma B)" : "(A, B)", pr.lower_rel);
                 decided = true;
                 ms_hsrr += now_ms() - t3;
-                if (fin == RF_OK) converged = judge(t, 0.0);
+                if (fin == RF_OK) converged = stopping_rule(t, 0.0);
                 return fin == RF_OK && converged;
             };
             if (t < P->opts.max_subspace_it) {
@@ -1604,7 +1604,7 @@ rf_status rf_solve_region_adaptive(rf_plan_t P, const void *Y0, int64_t ldy, rf_
         ms_filter += now_ms() - ta;
         return RF_OK;
     };
-    auto judge = [&](int level) {
+    auto stopping_rule = [&](int level) {
         int count = 0;
         bool all_small = true;
         for (int i = 0; i < w; ++i) {
@@ -1620,7 +1620,7 @@ rf_status rf_solve_region_adaptive(rf_plan_t P, const void *Y0, int64_t ldy, rf_
     };
     // Levels are pipelined: while the host QZ of level t runs on its own thread, the
     // device computes level t + 1's filter and projection into the second basis set, and
-    // level t + 1's QZ starts on another thread; level t is then finished and judged, and
+    // level t + 1's QZ starts on another thread; level t is then finished and tested, and
     // a converged level discards the one behind it.
     const int nlevels = [&] { int m = 0; for (int k2 = P->opts.q; k2 <= P->opts.q_max; k2 *= 2) ++m; return m; }();
     struct Flight {
@@ -1661,7 +1661,7 @@ rf_status rf_solve_region_adaptive(rf_plan_t P, const void *Y0, int64_t ldy, rf_
         rf_status fin = (out == RF_OK) ? hsrr_finish(P, cur.pr, lam, err) : out;
         ms_hsrr += now_ms() - tb;
         if (fin != RF_OK) { out = fin; nxt.wait(); break; }
-        if (judge(t)) {
+        if (stopping_rule(t)) {
             converged = true;
             nxt.wait();
             ++t;
