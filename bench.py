@@ -476,8 +476,10 @@ def W_start_block(wl):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    # five timed steps: the host QZ of the last sweep is on the step's critical path and
+    # its time varies with the host's load, so a few more steps steady the average
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--subblock", type=int, default=0)
     ap.add_argument("--trsm-cols", type=int, default=0)
     ap.add_argument("--solve-form", type=int, default=0,
