@@ -112,11 +112,18 @@ rf_status upload_csr(rf_plan *P, const rf_csr *M, DevCsr &D) {
     RF_TRY(dalloc(P, &D.rowptr, size_t(M->n) + 1));
     RF_TRY(dalloc(P, &D.colind, size_t(std::max<int64_t>(M->nnz, 1))));
     RF_TRY(dalloc(P, &D.val, size_t(std::max<int64_t>(M->nnz, 1))));
-    RF_HIP(P, hipMemcpy(D.rowptr, M->rowptr, sizeof(int32_t) * (M->n + 1), hipMemcpyHostToDevice));
+    // copies on the plan's stream, never the legacy stream: a legacy-stream operation would
+    // depend on every blocking stream, and so fail while another thread records a graph
+    // on one of its own
+    RF_HIP(P, hipMemcpyAsync(D.rowptr, M->rowptr, sizeof(int32_t) * (M->n + 1),
+                             hipMemcpyHostToDevice, P->stream));
     if (M->nnz > 0) {
-        RF_HIP(P, hipMemcpy(D.colind, M->colind, sizeof(int32_t) * M->nnz, hipMemcpyHostToDevice));
-        RF_HIP(P, hipMemcpy(D.val, M->val, sizeof(zd) * M->nnz, hipMemcpyHostToDevice));
+        RF_HIP(P, hipMemcpyAsync(D.colind, M->colind, sizeof(int32_t) * M->nnz,
+                                 hipMemcpyHostToDevice, P->stream));
+        RF_HIP(P, hipMemcpyAsync(D.val, M->val, sizeof(zd) * M->nnz, hipMemcpyHostToDevice,
+                                 P->stream));
     }
+    RF_HIP(P, hipStreamSynchronize(P->stream));
     // diagonal fast path: exactly one stored entry per row, on the diagonal
     bool diag = (M->nnz == M->n);
     for (int32_t i = 0; diag && i < M->n; ++i)
@@ -192,7 +199,8 @@ rf_status rf_fail(rf_plan *plan, rf_status s, const std::string &msg) {
 static rf_status cluster_check(rf_plan *P) {
     if (!P->F.cerr || P->F.cepoch == P->F.cerr_seen) return RF_OK;
     unsigned h[2] = {0, 0};
-    RF_HIP(P, hipMemcpy(h, P->F.cerr, sizeof(h), hipMemcpyDeviceToHost));
+    RF_HIP(P, hipMemcpyAsync(h, P->F.cerr, sizeof(h), hipMemcpyDeviceToHost, P->stream));
+    RF_HIP(P, hipStreamSynchronize(P->stream));
     const unsigned seen = P->F.cerr_seen;
     P->F.cerr_seen = P->F.cepoch;
     if (h[0] > seen || h[1] > seen) {
@@ -398,10 +406,15 @@ rf_status plan_create_impl(const rf_csr *A, const rf_csr *B, const rf_opts *opts
     ALLOC(P->d_weights, o.p);
     ALLOC(P->d_shifts, std::max(nq_alloc, 1));
     ALLOC(P->d_oweights, std::max(nq_alloc, 1));
-    if (hipMemcpy(P->d_poles, P->poles.data(), sizeof(zd) * o.p, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->d_weights, P->weights.data(), sizeof(zd) * o.p, hipMemcpyHostToDevice) != hipSuccess ||
-        (nq > 0 && hipMemcpy(P->d_shifts, P->shifts.data(), sizeof(zd) * nq, hipMemcpyHostToDevice) != hipSuccess) ||
-        (nq > 0 && hipMemcpy(P->d_oweights, P->oweights.data(), sizeof(zd) * nq, hipMemcpyHostToDevice) != hipSuccess)) {
+    if (hipMemcpyAsync(P->d_poles, P->poles.data(), sizeof(zd) * o.p, hipMemcpyHostToDevice,
+                       P->stream) != hipSuccess ||
+        hipMemcpyAsync(P->d_weights, P->weights.data(), sizeof(zd) * o.p, hipMemcpyHostToDevice,
+                       P->stream) != hipSuccess ||
+        (nq > 0 && hipMemcpyAsync(P->d_shifts, P->shifts.data(), sizeof(zd) * nq,
+                                  hipMemcpyHostToDevice, P->stream) != hipSuccess) ||
+        (nq > 0 && hipMemcpyAsync(P->d_oweights, P->oweights.data(), sizeof(zd) * nq,
+                                  hipMemcpyHostToDevice, P->stream) != hipSuccess) ||
+        hipStreamSynchronize(P->stream) != hipSuccess) {
         P->broken = true;
         rf_fail(P, RF_ERR_DEVICE, "copy of the rule coefficients failed");
         return fail(RF_ERR_DEVICE);
@@ -1876,8 +1889,9 @@ rf_status rf_batch_factor(rf_batch_t Bt) {
         if (st == RF_ERR_SINGULAR) {
             // name the disk of the first singular pole
             std::vector<int32_t> info(Bt->owner->opts.p);
-            if (hipMemcpy(info.data(), Bt->owner->F.info, sizeof(int32_t) * info.size(),
-                          hipMemcpyDeviceToHost) == hipSuccess) {
+            if (hipMemcpyAsync(info.data(), Bt->owner->F.info, sizeof(int32_t) * info.size(),
+                               hipMemcpyDeviceToHost, Bt->owner->stream) == hipSuccess &&
+                hipStreamSynchronize(Bt->owner->stream) == hipSuccess) {
                 int off = 0;
                 for (size_t d = 0; d < Bt->disks.size(); ++d) {
                     bool bad = false;
