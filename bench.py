@@ -316,13 +316,111 @@ def batched_form(ndisks, reps):
                            "value": round(found_s / (ms_s / 1000.0), 3)}}
 
 
-def batched_form_256(wave, with_sequential=True):
+def batched_window_256(slots, capacity=64):
+    """The batched configuration (as batched_form_256) with a sliding window instead of
+    waves: `slots` host threads, each with its own stream, take the next disk (widest
+    first) as soon as their previous one is done and the window has room for it, one
+    plan per disk (its own band factorization, then Alg. composite), so no disk waits for
+    the slowest of a wave.  A disk of block width w takes max(w, 64) / 32 of `capacity`
+    units: eight disks of width 256 at a time (223 GB), up to `slots` narrow ones.  Eight
+    threads: with sixteen, the HIP runtime ran out of resources for the scratch memory of
+    the tile-256 solve kernel on that many streams (the process aborted)."""
+    import queue
+    import threading
+    import torch
+    from scipy.optimize import linear_sum_assignment
+    from paper_2310_18043_amd import rfeig
+    from paper_2310_18043_amd import workloads as W
+    gdir = os.path.join(HERE, "tests", "golden")
+    disks = W.read_disk_table(os.path.join(gdir, "convdiff256_disks.txt"))
+    ref = np.loadtxt(os.path.join(gdir, "convdiff256_disk_eigs.txt"))
+    wl = W.convdiff256_workload()
+    A, B = wl.A, wl.B
+    common = dict(p=4, max_krylov_blocks=40)
+
+    def good(res, d):
+        lam_ref = ref[ref[:, 0] == d][:, 1] + 1j * ref[ref[:, 0] == d][:, 2]
+        ok = res["err"] <= 1e-10
+        lam = res["lam"][ok]
+        if len(lam) == 0 or len(lam_ref) == 0:
+            return 0
+        cost = np.abs(lam[:, None] - lam_ref[None, :])
+        r_, c_ = linear_sum_assignment(cost)
+        return int(np.sum(cost[r_, c_] <= 1e-10 * np.abs(lam_ref[c_])))
+
+    todo = queue.Queue()
+    for d in sorted(range(len(disks)), key=lambda d: (-disks[d]["w"], d)):
+        todo.put(d)
+    found, sweeps, errors = {}, {}, []
+    lock = threading.Lock()
+    room = threading.Condition(lock)
+    live = [0, 0, 0]                               # bytes of the plans alive, peak, units in use
+
+    def worker():
+        st = torch.cuda.Stream()
+        while True:
+            try:
+                d = todo.get_nowait()
+            except queue.Empty:
+                return
+            dk = disks[d]
+            units = max(dk["w"], 64) // 32
+            with room:
+                while live[2] + units > capacity:
+                    room.wait()
+                live[2] += units
+            try:
+                with torch.cuda.stream(st):
+                    P = rfeig.Plan(A, B, dk["c"], dk["r"], w=dk["w"], q=dk["q"],
+                                   expected_count=dk["count"], stream=st, **common)
+                    nb = P.device_bytes
+                    with lock:
+                        live[0] += nb
+                        live[1] = max(live[1], live[0])
+                    P.factor_shifts()
+                    y = torch.from_numpy(W.start_block(wl.n, dk["w"], 100 + d)).cuda()
+                    r = P.solve_region(y, allow_noconv=True)
+                    found[d] = good(r, d)
+                    sweeps[d] = r["sweeps"]
+                    P.close()
+                    with lock:
+                        live[0] -= nb
+            except Exception as e:                 # reported in the result
+                errors.append((d, repr(e)))
+            with room:
+                live[2] -= units
+                room.notify_all()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    threads = [threading.Thread(target=worker) for _ in range(slots)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0
+    total = int(sum(found.values()))
+    out = {"workload": f"convdiff256_randv_{len(disks)}disks_p4_q4-8-16", "disks": len(disks),
+           "slots": slots, "capacity_units": capacity,
+           "expected_count": int(sum(d["count"] for d in disks)),
+           "ms_per_step": round(ms, 3), "value": round(total / (ms / 1000.0), 3),
+           "unit": "eigenpairs/s", "converged_count": total,
+           "sweeps": [sweeps.get(d) for d in range(len(disks))],
+           "peak_device_gb": round(live[1] / 1e9, 2)}
+    if errors:
+        out["errors"] = errors[:4]
+    return out
+
+
+def batched_form_256(wave, with_sequential=True, mode="window"):
     """The batched configuration: 64 disks along the real axis of the 256 x 256
     random-velocity pencil (10..200 eigenvalues each, block widths 16..256, p = 4,
-    q cycling through 4, 8, 16; tests/golden/convdiff256_disks.txt).  The disks go
-    through the HBM in waves of `wave` disks of similar block width: per wave one batch
-    (all its poles factorized in one launch sequence, its disks solved concurrently on
-    their own streams), destroyed before the next.  A pair counts when it is converged
+    q cycling through 4, 8, 16; tests/golden/convdiff256_disks.txt).  mode "window": a
+    sliding window of `wave` disks in flight (batched_window_256); mode "wave": the
+    disks go through the HBM in waves of `wave` disks of similar block width, per wave
+    one batch (all its poles factorized in one launch sequence, its disks solved
+    concurrently on their own streams), destroyed before the next.  A pair counts when it is converged
     (inside, e <= 1e-10) and matches the oracle's reference eigenvalue of its disk
     to 1e-10 relative (tests/golden/convdiff256_disk_eigs.txt).  Against the same
     disks solved one after another, one plan each."""
@@ -355,7 +453,7 @@ def batched_form_256(wave, with_sequential=True):
     found_b, sweeps, peak = 0, [], 0
     # waves of disks of similar block width (a wave lasts as long as its slowest disk)
     order = sorted(range(len(disks)), key=lambda d: (-disks[d]["w"], d))
-    for w0 in range(0, len(disks), wave):
+    for w0 in (range(0, len(disks), wave) if mode == "wave" else []):
         idx = order[w0:w0 + wave]
         specs = [{"c": disks[d]["c"], "r": disks[d]["r"], "w": disks[d]["w"], "q": disks[d]["q"],
                   "expected_count": disks[d]["count"]} for d in idx]
@@ -370,9 +468,14 @@ def batched_form_256(wave, with_sequential=True):
         del bt
     torch.cuda.synchronize()
     ms_b = (time.perf_counter() - t0) * 1000.0
+    if mode == "window":
+        win = batched_window_256(wave)
+        ms_b, found_b, sweeps = win["ms_per_step"], win["converged_count"], win["sweeps"]
+        peak = win["peak_device_gb"] * 1e9
     expected = int(sum(d["count"] for d in disks))
     out = {"workload": f"convdiff256_randv_{len(disks)}disks_p4_q4-8-16", "disks": len(disks),
-           "wave": wave, "widths": [d["w"] for d in disks], "expected_count": expected,
+           "mode": mode, ("slots" if mode == "window" else "wave"): wave,
+           "widths": [d["w"] for d in disks], "expected_count": expected,
            "ms_per_step": round(ms_b, 3), "value": round(found_b / (ms_b / 1000.0), 3),
            "unit": "eigenpairs/s", "converged_count": found_b, "sweeps": sweeps,
            "peak_batch_device_gb": round(peak / 1e9, 2)}
@@ -500,7 +603,11 @@ def main():
     ap.add_argument("--no-toeplitz", action="store_true",
                     help="skip the Toeplitz workload (balanced and literal)")
     ap.add_argument("--batch256-wave", type=int, default=8,
-                    help="disks per wave of the 64-disk 256 x 256 batched workload (0: skip)")
+                    help="disks in flight (window) or per wave of the 64-disk 256 x 256 "
+                         "batched workload (0: skip)")
+    ap.add_argument("--batch256-mode", choices=("window", "wave"), default="window",
+                    help="the batched 256 x 256 workload: a sliding window of disks in flight, "
+                         "or waves of batches")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -715,7 +822,7 @@ def main():
     bt256 = None
     if args.batch256_wave > 0 and os.path.exists(os.path.join(HERE, "tests", "golden",
                                                               "convdiff256_disks.txt")):
-        bt256 = batched_form_256(args.batch256_wave)
+        bt256 = batched_form_256(args.batch256_wave, mode=args.batch256_mode)
         log(f"batched 256: { {k: v for k, v in bt256.items() if k not in ('widths', 'sweeps')} }")
 
     cd256 = None
