@@ -392,6 +392,7 @@ def batched_window_256(slots, capacity=64):
                 room.notify_all()
 
     torch.cuda.synchronize()
+    retries0 = torch.cuda.memory_stats().get("num_alloc_retries", 0)
     t0 = time.perf_counter()
     threads = [threading.Thread(target=worker) for _ in range(slots)]
     for t in threads:
@@ -407,7 +408,8 @@ def batched_window_256(slots, capacity=64):
            "ms_per_step": round(ms, 3), "value": round(total / (ms / 1000.0), 3),
            "unit": "eigenpairs/s", "converged_count": total,
            "sweeps": [sweeps.get(d) for d in range(len(disks))],
-           "peak_device_gb": round(live[1] / 1e9, 2)}
+           "peak_device_gb": round(live[1] / 1e9, 2),
+           "alloc_retries": int(torch.cuda.memory_stats().get("num_alloc_retries", 0) - retries0)}
     if errors:
         out["errors"] = errors[:4]
     return out
@@ -479,6 +481,8 @@ def batched_form_256(wave, with_sequential=True, mode="window"):
            "ms_per_step": round(ms_b, 3), "value": round(found_b / (ms_b / 1000.0), 3),
            "unit": "eigenpairs/s", "converged_count": found_b, "sweeps": sweeps,
            "peak_batch_device_gb": round(peak / 1e9, 2)}
+    if mode == "window":
+        out["alloc_retries"] = win["alloc_retries"]     # caching-allocator frees and retries
     if with_sequential:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
