@@ -316,7 +316,7 @@ def batched_form(ndisks, reps):
                            "value": round(found_s / (ms_s / 1000.0), 3)}}
 
 
-def batched_window_256(slots, capacity=64):
+def batched_window_256(slots, capacity=64, trsm_cols=8):
     """The batched configuration (as batched_form_256) with a sliding window instead of
     waves: `slots` host threads, each with its own stream, take the next disk (widest
     first) as soon as their previous one is done and the window has room for it, one
@@ -324,7 +324,11 @@ def batched_window_256(slots, capacity=64):
     the slowest of a wave.  A disk of block width w takes max(w, 64) / 32 of `capacity`
     units: eight disks of width 256 at a time (223 GB), up to `slots` narrow ones.  Eight
     threads: with sixteen, the HIP runtime ran out of resources for the scratch memory of
-    the tile-256 solve kernel on that many streams (the process aborted)."""
+    the tile-256 solve kernel on that many streams (the process aborted).  The band solves
+    take `trsm_cols` right-hand sides per workgroup, eight by default: the plans in flight
+    share the compute units, so the fewest workgroups per column win, where a lone plan's
+    automatic choice (one plan after another below) takes the narrowest slices that still
+    run at once, the shortest launch."""
     import queue
     import threading
     import torch
@@ -336,7 +340,7 @@ def batched_window_256(slots, capacity=64):
     ref = np.loadtxt(os.path.join(gdir, "convdiff256_disk_eigs.txt"))
     wl = W.convdiff256_workload()
     A, B = wl.A, wl.B
-    common = dict(p=4, max_krylov_blocks=40)
+    common = dict(p=4, max_krylov_blocks=40, trsm_cols=trsm_cols)
 
     def good(res, d):
         lam_ref = ref[ref[:, 0] == d][:, 1] + 1j * ref[ref[:, 0] == d][:, 2]

@@ -604,11 +604,11 @@ __device__ inline zd to_zd(zf v) { return zmake(double(v.x), double(v.y)); }
 // The workgroups of a pole also touch the next block's tiles so that they are in L2.
 constexpr int kSolveThreads = 512;
 
-template <int NB>
+template <int NB, int NT = kSolveThreads>
 struct SolveShape {
     static constexpr int R = NB >= 64 ? NB / 64 : 1;                  // rows per thread
     static constexpr int SLOTS = NB / R;
-    static constexpr int G0 = kSolveThreads / SLOTS;
+    static constexpr int G0 = NT / SLOTS;
     static constexpr int G = G0 < NB / 2 ? G0 : NB / 2;               // lanes per slot
     static constexpr int KL = NB / G;                                 // columns per thread
     static constexpr int L = R * KL;                                  // tile elements per thread
@@ -616,7 +616,7 @@ struct SolveShape {
     static constexpr int NBAT = L / S;                                // batches per tile (even)
     static constexpr int RPW = 64 / G;                                // slots per wave
     static constexpr int ACTIVE = SLOTS * G;                          // threads with rows
-    static_assert(NBAT % 2 == 0 && S >= 1 && ACTIVE <= kSolveThreads, "solve shape");
+    static_assert(NBAT % 2 == 0 && S >= 1 && ACTIVE <= NT, "solve shape");
 };
 
 // Shape of a tile: full, or triangular with structural zeros (Linv and U2 lower,
@@ -624,37 +624,37 @@ struct SolveShape {
 // and columns [j G, j G + G) of the tile; it is skipped when all of it is zero.
 enum : int { kFull = 0, kLower = 1, kUpper = 2 };
 
-template <int NB, int SHAPE>
+template <int NB, int NT, int SHAPE>
 __device__ constexpr bool piece_zero(int q, int j) {
-    using SH = SolveShape<NB>;
+    using SH = SolveShape<NB, NT>;
     return SHAPE == kLower ? ((q + 1) * SH::SLOTS - 1 < j * SH::G)
          : SHAPE == kUpper ? (q * SH::SLOTS > j * SH::G + SH::G - 1) : false;
 }
 
 // Load batch b of this thread's piece of tile T (thread corner tp = T + slot + g NB;
 // the element offsets are compile-time constants).
-template <int NB, int SHAPE, typename CT>
+template <int NB, int NT, int SHAPE, typename CT>
 __device__ __attribute__((always_inline)) inline void issue_batch(const CT *tp, int b,
-                                                                  CT (&t)[SolveShape<NB>::S]) {
-    using SH = SolveShape<NB>;
+                                                                  CT (&t)[SolveShape<NB, NT>::S]) {
+    using SH = SolveShape<NB, NT>;
 #pragma unroll
     for (int e = 0; e < SH::S; ++e) {
         const int E = b * SH::S + e, j = E / SH::R, q = E % SH::R;
-        if (!piece_zero<NB, SHAPE>(q, j)) t[e] = tp[SH::SLOTS * q + j * SH::G * NB];
+        if (!piece_zero<NB, NT, SHAPE>(q, j)) t[e] = tp[SH::SLOTS * q + j * SH::G * NB];
     }
 }
 
 // acc[q][c] += sum over batch b of a tile of T[row_q, k] v[k, c]
-template <int CW, int NB, int SHAPE, typename CT>
+template <int CW, int NB, int NT, int SHAPE, typename CT>
 __device__ __attribute__((always_inline)) inline void consume(int g, int b,
-                                                              const CT (&t)[SolveShape<NB>::S],
+                                                              const CT (&t)[SolveShape<NB, NT>::S],
                                                               const CT *v,
-                                                              CT (&acc)[SolveShape<NB>::R][CW]) {
-    using SH = SolveShape<NB>;
+                                                              CT (&acc)[SolveShape<NB, NT>::R][CW]) {
+    using SH = SolveShape<NB, NT>;
 #pragma unroll
     for (int e = 0; e < SH::S; ++e) {
         const int E = b * SH::S + e, j = E / SH::R, q = E % SH::R;
-        if (piece_zero<NB, SHAPE>(q, j)) continue;
+        if (piece_zero<NB, NT, SHAPE>(q, j)) continue;
         const CT *vr = v + (j * SH::G + g) * CW;
 #pragma unroll
         for (int c = 0; c < CW; ++c) zfma(acc[q][c], t[e], vr[c]);
@@ -665,28 +665,28 @@ __device__ __attribute__((always_inline)) inline void consume(int g, int b,
 // (even / odd batches) and request, batch by batch, the rest of it and then the
 // first batches of the next tile, read as shape SN.  A consumer never uses an
 // element its producer skipped: SN is the next tile's shape or kFull.
-template <int CW, int NB, int SC, int SN, typename CT>
+template <int CW, int NB, int NT, int SC, int SN, typename CT>
 __device__ __attribute__((always_inline)) inline void run_phase(
-        int g, CT (&bufA)[SolveShape<NB>::S], CT (&bufB)[SolveShape<NB>::S],
-        CT (&acc)[SolveShape<NB>::R][CW], const CT *v, const CT *tcur, const CT *tnext) {
-    using SH = SolveShape<NB>;
+        int g, CT (&bufA)[SolveShape<NB, NT>::S], CT (&bufB)[SolveShape<NB, NT>::S],
+        CT (&acc)[SolveShape<NB, NT>::R][CW], const CT *v, const CT *tcur, const CT *tnext) {
+    using SH = SolveShape<NB, NT>;
 #pragma unroll
     for (int bp = 0; bp < SH::NBAT; bp += 2) {
-        consume<CW, NB, SC, CT>(g, bp, bufA, v, acc);
-        if (bp + 2 < SH::NBAT) issue_batch<NB, SC, CT>(tcur, bp + 2, bufA);
-        else issue_batch<NB, SN, CT>(tnext, bp + 2 - SH::NBAT, bufA);
-        consume<CW, NB, SC, CT>(g, bp + 1, bufB, v, acc);
-        if (bp + 3 < SH::NBAT) issue_batch<NB, SC, CT>(tcur, bp + 3, bufB);
-        else issue_batch<NB, SN, CT>(tnext, bp + 3 - SH::NBAT, bufB);
+        consume<CW, NB, NT, SC, CT>(g, bp, bufA, v, acc);
+        if (bp + 2 < SH::NBAT) issue_batch<NB, NT, SC, CT>(tcur, bp + 2, bufA);
+        else issue_batch<NB, NT, SN, CT>(tnext, bp + 2 - SH::NBAT, bufA);
+        consume<CW, NB, NT, SC, CT>(g, bp + 1, bufB, v, acc);
+        if (bp + 3 < SH::NBAT) issue_batch<NB, NT, SC, CT>(tcur, bp + 3, bufB);
+        else issue_batch<NB, NT, SN, CT>(tnext, bp + 3 - SH::NBAT, bufB);
     }
 }
 
 // the entries of v that batch b of a tile piece multiplies: columns j G + g for the
 // batch's S / R values of j
-template <int CW, int NB, typename CT>
+template <int CW, int NB, int NT, typename CT>
 __device__ __attribute__((always_inline)) inline void load_v(
-        int g, int b, const CT *v, CT (&vb)[SolveShape<NB>::S / SolveShape<NB>::R][CW]) {
-    using SH = SolveShape<NB>;
+        int g, int b, const CT *v, CT (&vb)[SolveShape<NB, NT>::S / SolveShape<NB, NT>::R][CW]) {
+    using SH = SolveShape<NB, NT>;
     constexpr int JB = SH::S / SH::R;
 #pragma unroll
     for (int jj = 0; jj < JB; ++jj) {
@@ -697,16 +697,16 @@ __device__ __attribute__((always_inline)) inline void load_v(
 }
 
 // consume with the batch's entries of v already in registers
-template <int CW, int NB, int SHAPE, typename CT>
+template <int CW, int NB, int NT, int SHAPE, typename CT>
 __device__ __attribute__((always_inline)) inline void consume_v(
-        int b, const CT (&t)[SolveShape<NB>::S],
-        const CT (&vb)[SolveShape<NB>::S / SolveShape<NB>::R][CW],
-        CT (&acc)[SolveShape<NB>::R][CW]) {
-    using SH = SolveShape<NB>;
+        int b, const CT (&t)[SolveShape<NB, NT>::S],
+        const CT (&vb)[SolveShape<NB, NT>::S / SolveShape<NB, NT>::R][CW],
+        CT (&acc)[SolveShape<NB, NT>::R][CW]) {
+    using SH = SolveShape<NB, NT>;
 #pragma unroll
     for (int e = 0; e < SH::S; ++e) {
         const int E = b * SH::S + e, j = E / SH::R, q = E % SH::R;
-        if (piece_zero<NB, SHAPE>(q, j)) continue;
+        if (piece_zero<NB, NT, SHAPE>(q, j)) continue;
         const int jj = j - (b * SH::S) / SH::R;
 #pragma unroll
         for (int c = 0; c < CW; ++c) zfma(acc[q][c], t[e], vb[jj][c]);
@@ -714,45 +714,45 @@ __device__ __attribute__((always_inline)) inline void consume_v(
 }
 
 // run_phase with the entries of v read one batch ahead into two register sets
-template <int CW, int NB, int SC, int SN, typename CT>
+template <int CW, int NB, int NT, int SC, int SN, typename CT>
 __device__ __attribute__((always_inline)) inline void run_phase_vpre(
-        int g, CT (&bufA)[SolveShape<NB>::S], CT (&bufB)[SolveShape<NB>::S],
-        CT (&acc)[SolveShape<NB>::R][CW], const CT *v, const CT *tcur, const CT *tnext) {
-    using SH = SolveShape<NB>;
+        int g, CT (&bufA)[SolveShape<NB, NT>::S], CT (&bufB)[SolveShape<NB, NT>::S],
+        CT (&acc)[SolveShape<NB, NT>::R][CW], const CT *v, const CT *tcur, const CT *tnext) {
+    using SH = SolveShape<NB, NT>;
     constexpr int JB = SH::S / SH::R;
     static_assert(SH::S % SH::R == 0, "batch covers whole columns");
     CT vA[JB][CW], vB[JB][CW];
-    load_v<CW, NB, CT>(g, 0, v, vA);
-    load_v<CW, NB, CT>(g, 1, v, vB);
+    load_v<CW, NB, NT, CT>(g, 0, v, vA);
+    load_v<CW, NB, NT, CT>(g, 1, v, vB);
 #pragma unroll
     for (int bp = 0; bp < SH::NBAT; bp += 2) {
-        consume_v<CW, NB, SC, CT>(bp, bufA, vA, acc);
-        if (bp + 2 < SH::NBAT) issue_batch<NB, SC, CT>(tcur, bp + 2, bufA);
-        else issue_batch<NB, SN, CT>(tnext, bp + 2 - SH::NBAT, bufA);
-        if (bp + 2 < SH::NBAT) load_v<CW, NB, CT>(g, bp + 2, v, vA);
-        consume_v<CW, NB, SC, CT>(bp + 1, bufB, vB, acc);
-        if (bp + 3 < SH::NBAT) issue_batch<NB, SC, CT>(tcur, bp + 3, bufB);
-        else issue_batch<NB, SN, CT>(tnext, bp + 3 - SH::NBAT, bufB);
-        if (bp + 3 < SH::NBAT) load_v<CW, NB, CT>(g, bp + 3, v, vB);
+        consume_v<CW, NB, NT, SC, CT>(bp, bufA, vA, acc);
+        if (bp + 2 < SH::NBAT) issue_batch<NB, NT, SC, CT>(tcur, bp + 2, bufA);
+        else issue_batch<NB, NT, SN, CT>(tnext, bp + 2 - SH::NBAT, bufA);
+        if (bp + 2 < SH::NBAT) load_v<CW, NB, NT, CT>(g, bp + 2, v, vA);
+        consume_v<CW, NB, NT, SC, CT>(bp + 1, bufB, vB, acc);
+        if (bp + 3 < SH::NBAT) issue_batch<NB, NT, SC, CT>(tcur, bp + 3, bufB);
+        else issue_batch<NB, NT, SN, CT>(tnext, bp + 3 - SH::NBAT, bufB);
+        if (bp + 3 < SH::NBAT) load_v<CW, NB, NT, CT>(g, bp + 3, v, vB);
     }
 }
 
 // The tile products of the solve: the v-prefetching form where its two register
 // sets fit beside the accumulators (complex128 up to two columns, complex64 up to
 // four), the plain form otherwise.
-template <int CW, int NB, int SC, int SN, typename CT>
+template <int CW, int NB, int NT, int SC, int SN, typename CT>
 __device__ __attribute__((always_inline)) inline void tile_product(
-        int g, CT (&bufA)[SolveShape<NB>::S], CT (&bufB)[SolveShape<NB>::S],
-        CT (&acc)[SolveShape<NB>::R][CW], const CT *v, const CT *tcur, const CT *tnext) {
+        int g, CT (&bufA)[SolveShape<NB, NT>::S], CT (&bufB)[SolveShape<NB, NT>::S],
+        CT (&acc)[SolveShape<NB, NT>::R][CW], const CT *v, const CT *tcur, const CT *tnext) {
     if constexpr (CW * sizeof(CT) <= 32)
-        run_phase_vpre<CW, NB, SC, SN, CT>(g, bufA, bufB, acc, v, tcur, tnext);
+        run_phase_vpre<CW, NB, NT, SC, SN, CT>(g, bufA, bufB, acc, v, tcur, tnext);
     else
-        run_phase<CW, NB, SC, SN, CT>(g, bufA, bufB, acc, v, tcur, tnext);
+        run_phase<CW, NB, NT, SC, SN, CT>(g, bufA, bufB, acc, v, tcur, tnext);
 }
 
-template <int CW, int NB, typename CT>
-__device__ inline void reduce_rows(CT (&acc)[SolveShape<NB>::R][CW]) {
-    using SH = SolveShape<NB>;
+template <int CW, int NB, int NT, typename CT>
+__device__ inline void reduce_rows(CT (&acc)[(SolveShape<NB, NT>::R)][CW]) {
+    using SH = SolveShape<NB, NT>;
 #pragma unroll
     for (int off = SH::G / 2; off > 0; off >>= 1) {
 #pragma unroll
@@ -765,10 +765,9 @@ __device__ inline void reduce_rows(CT (&acc)[SolveShape<NB>::R][CW]) {
     }
 }
 
-template <int CW, int NB, typename CT>
-__global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) {
-    using SH = SolveShape<NB>;
-    constexpr int NT = kSolveThreads;
+template <int CW, int NB, int NT, typename CT>
+__global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
+    using SH = SolveShape<NB, NT>;
     constexpr int R = SH::R;
     const int p = a.p;
     const int pole = blockIdx.x % p;             // slices of one pole share an XCD
@@ -787,11 +786,15 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
     const int slot = active ? slot_raw : 0;                  // idle threads read row 0
     const bool writer = active && g == 0;
 
+    // The 256-thread form (eight columns at tile 256) keeps its forward window in three
+    // nb-row buffers (see the forward sweep): a second 2nb-row window would not fit the
+    // LDS.  Its ring of backward blocks reuses those buffers.
+    constexpr bool inplace = NT < kSolveThreads;
     extern __shared__ unsigned char smem_raw[];
-    CT *win = reinterpret_cast<CT *>(smem_raw);   // [2NB][CW]
-    CT *win2 = win + 2 * NB * CW;                 // [2NB][CW]
-    CT *ybuf = win2 + 2 * NB * CW;                // [NB][CW]
-    CT *ring = ybuf + NB * CW;                    // [3][NB][CW]
+    CT *win = reinterpret_cast<CT *>(smem_raw);   // [2NB][CW] (256 threads: [3][NB][CW])
+    CT *win2 = inplace ? win : win + 2 * NB * CW; // [2NB][CW]: the permuted window
+    CT *ybuf = inplace ? win + 3 * NB * CW : win2 + 2 * NB * CW;   // [NB][CW]
+    CT *ring = inplace ? win : ybuf + NB * CW;    // [3][NB][CW]
 
     CT *yp = static_cast<CT *>(a.ypart) + int64_t(pole) * a.npad * a.ncols;
     zd *xp = a.xpart + int64_t(pole) * a.npad * a.ncols;
@@ -849,8 +852,8 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
     // being consumed; each consumed batch is replaced by the one two places further
     // down the sequence (the same tile, or the next one)
     CT bufA[SH::S], bufB[SH::S];
-    issue_batch<NB, kFull, CT>(tile_at(0, 0), 0, bufA);
-    issue_batch<NB, kFull, CT>(tile_at(0, 0), 1, bufB);
+    issue_batch<NB, NT, kFull, CT>(tile_at(0, 0), 0, bufA);
+    issue_batch<NB, NT, kFull, CT>(tile_at(0, 0), 1, bufB);
     CT acc[R][CW];
     auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
@@ -860,31 +863,52 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
     };
 
     // ---------------- forward sweep
-    constexpr int GPT = (2 * NB * CW + NT - 1) / NT;     // gathered elements per thread
+    // Window of step k: [t_k; b_{k+1}], permuted by P_k.  The 512-thread form keeps it in
+    // win (2nb rows) and its permuted copy in win2.  The 256-thread form has three
+    // nb-row buffers in turn: t_k, b_{k+1} and a free one, which receives the permuted top
+    // half (w_top) and, once that has been consumed, t_{k+1}; the bottom half (w_bot) is
+    // read through the permutation where it is used.
+    constexpr int GROWS = inplace ? 1 : 2;                 // window halves gathered
+    constexpr int GPT = (GROWS * NB * CW + NT - 1) / NT;  // gathered elements per thread
+    auto third = [&](int i) __attribute__((always_inline)) {
+        return win + ((i % 3 + 3) % 3) * NB * CW;
+    };
     prefetch_rhs(0);
-    store_rhs(win);
+    store_rhs(win);                                      // b_0 (the t-buffer of step 0)
     prefetch_rhs(1);
     for (int k = 0; k < nblk; ++k) {
         const bool last = (k + 1 == nblk);
-        if (!last) store_rhs(win + NB * CW);                 // b_{k+1}
+        CT *tb = inplace ? third(-k) : win;                  // t_k
+        CT *bb = inplace ? third(1 - k) : win + NB * CW;     // b_{k+1}
+        CT *gb = inplace ? third(2 - k) : win2;              // permuted window
+        if (!last) store_rhs(bb);                            // b_{k+1}
         prefetch_rhs(k + 2);                                 // b_{k+2}, used next step
         touch(tiles + int64_t(min(k + 1, nblk - 1)) * 5 * te, 2 * te);   // Linv, L21 of step k+1
-        const int rows = last ? NB : 2 * NB;
+        const int rows = (last || inplace) ? NB : 2 * NB;
         const int32_t *pk = perm + int64_t(k) * 2 * NB;
         int pr[GPT];
 #pragma unroll
         for (int q = 0; q < GPT; ++q) pr[q] = pk[min(tid + q * NT, rows * CW - 1) / CW];
+        int pb[inplace ? R : 1];                             // window rows of w_bot (writers)
+        if constexpr (inplace) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) pb[q] = (writer && !last) ? pk[NB + slot + SH::SLOTS * q] : 0;
+        }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < GPT; ++q) {
             const int e = min(tid + q * NT, rows * CW - 1);  // past the end: same value again
-            win2[e] = win[pr[q] * CW + e % CW];
+            const int src = pr[q];
+            if constexpr (inplace)
+                gb[e] = src < NB ? tb[src * CW + e % CW] : bb[(src - NB) * CW + e % CW];
+            else
+                gb[e] = win[src * CW + e % CW];
         }
         __syncthreads();
         zero_acc();
-        tile_product<CW, NB, kLower, kFull, CT>(g, bufA, bufB, acc, win2, tile_at(k, 0),
+        tile_product<CW, NB, NT, kLower, kFull, CT>(g, bufA, bufB, acc, gb, tile_at(k, 0),
                                                 tile_at(k, 1));          // y_k = Linv w_top
-        reduce_rows<CW, NB, CT>(acc);
+        reduce_rows<CW, NB, NT, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -899,15 +923,22 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         __syncthreads();
         zero_acc();
         // next: Linv_{k+1}, or U1 of the last block to start the backward sweep
-        tile_product<CW, NB, kFull, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 1),
+        tile_product<CW, NB, NT, kFull, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 1),
                                                last ? tile_at(k, 3) : tile_at(k + 1, 0));   // t_{k+1} = w_bot - L21 y_k
-        reduce_rows<CW, NB, CT>(acc);
+        reduce_rows<CW, NB, NT, CT>(acc);
         if (writer && !last) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const int row = slot + SH::SLOTS * q;
+                if constexpr (inplace) {
+                    const int src = pb[q];
+                    const CT *wb = src < NB ? tb + src * CW : bb + (src - NB) * CW;
 #pragma unroll
-                for (int c = 0; c < CW; ++c) win[row * CW + c] = zsub(win2[(NB + row) * CW + c], acc[q][c]);
+                    for (int c = 0; c < CW; ++c) gb[row * CW + c] = zsub(wb[c], acc[q][c]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CW; ++c) win[row * CW + c] = zsub(win2[(NB + row) * CW + c], acc[q][c]);
+                }
             }
         }
         __syncthreads();
@@ -926,26 +957,32 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
                 dst[q][c] = ok ? x : czero<CT>();
             }
     };
-    load_y(nblk - 1, ynext);
+    // y_k is read one step ahead, or (the 256-thread form, whose registers hold
+    // 8-column blocks) at the start of its own step, in flight during the first products
+    if constexpr (!inplace) load_y(nblk - 1, ynext);
     __syncthreads();
     for (int k = nblk - 1; k >= 0; --k) {
         CT *xk = ring + (k % 3) * NB * CW;
         const CT *xk1 = ring + ((k + 1) % 3) * NB * CW;
         const CT *xk2 = ring + ((k + 2) % 3) * NB * CW;
         CT y[R][CW];
+        if constexpr (inplace) {
+            load_y(k, y);
+        } else {
 #pragma unroll
-        for (int q = 0; q < R; ++q)
+            for (int q = 0; q < R; ++q)
 #pragma unroll
-            for (int c = 0; c < CW; ++c) y[q][c] = ynext[q][c];
-        load_y(k - 1, ynext);                                       // y_{k-1}, used next step
+                for (int c = 0; c < CW; ++c) y[q][c] = ynext[q][c];
+            load_y(k - 1, ynext);                                   // y_{k-1}, used next step
+        }
         touch(tiles + int64_t(max(k - 1, 0)) * 5 * te + 2 * te, 3 * te);   // Uinv, U1, U2 of k-1
         // v = y_k - U1 x_{k+1} - U2 x_{k+2}
         zero_acc();
-        tile_product<CW, NB, kFull, kLower, CT>(g, bufA, bufB, acc, xk1, tile_at(k, 3),
+        tile_product<CW, NB, NT, kFull, kLower, CT>(g, bufA, bufB, acc, xk1, tile_at(k, 3),
                                                 tile_at(k, 4));
-        tile_product<CW, NB, kLower, kUpper, CT>(g, bufA, bufB, acc, xk2, tile_at(k, 4),
+        tile_product<CW, NB, NT, kLower, kUpper, CT>(g, bufA, bufB, acc, xk2, tile_at(k, 4),
                                                  tile_at(k, 2));
-        reduce_rows<CW, NB, CT>(acc);
+        reduce_rows<CW, NB, NT, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -956,9 +993,9 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
         }
         __syncthreads();
         zero_acc();
-        tile_product<CW, NB, kUpper, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 2),
+        tile_product<CW, NB, NT, kUpper, kFull, CT>(g, bufA, bufB, acc, ybuf, tile_at(k, 2),
                                                 tile_at(max(k - 1, 0), 3));   // x_k = Uinv v
-        reduce_rows<CW, NB, CT>(acc);
+        reduce_rows<CW, NB, NT, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -994,10 +1031,9 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_kernel(SolveArgs a) 
 // of the factor's tiles (slot t holds T_t^H: Linv^H and U2^H upper, Uinv^H lower),
 // made once from the factorization, so both sweeps are the same tile products as the
 // plain solve.  One workgroup per (pole, slice of CW right-hand sides), as there.
-template <int CW, int NB, typename CT>
-__global__ __launch_bounds__(kSolveThreads) void band_solve_adj_kernel(SolveArgs a) {
-    using SH = SolveShape<NB>;
-    constexpr int NT = kSolveThreads;
+template <int CW, int NB, int NT, typename CT>
+__global__ __launch_bounds__(NT) void band_solve_adj_kernel(SolveArgs a) {
+    using SH = SolveShape<NB, NT>;
     constexpr int R = SH::R;
     const int p = a.p;
     const int pole = blockIdx.x % p;
@@ -1046,8 +1082,8 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_adj_kernel(SolveArgs
         }
     };
     CT bufA[SH::S], bufB[SH::S];
-    issue_batch<NB, kFull, CT>(tile_at(0, 3), 0, bufA);
-    issue_batch<NB, kFull, CT>(tile_at(0, 3), 1, bufB);
+    issue_batch<NB, NT, kFull, CT>(tile_at(0, 3), 0, bufA);
+    issue_batch<NB, NT, kFull, CT>(tile_at(0, 3), 1, bufB);
     CT acc[R][CW];
     auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
@@ -1072,11 +1108,11 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_adj_kernel(SolveArgs
         const CT *vk1 = ring + ((k + 2) % 3) * NB * CW;   // v_{k-1} (zero for k < 1)
         const CT *vk2 = ring + ((k + 1) % 3) * NB * CW;   // v_{k-2} (zero for k < 2)
         zero_acc();
-        tile_product<CW, NB, kFull, kUpper, CT>(g, bufA, bufB, acc, vk1, tile_at(max(k - 1, 0), 3),
+        tile_product<CW, NB, NT, kFull, kUpper, CT>(g, bufA, bufB, acc, vk1, tile_at(max(k - 1, 0), 3),
                                                 tile_at(max(k - 2, 0), 4));
-        tile_product<CW, NB, kUpper, kLower, CT>(g, bufA, bufB, acc, vk2, tile_at(max(k - 2, 0), 4),
+        tile_product<CW, NB, NT, kUpper, kLower, CT>(g, bufA, bufB, acc, vk2, tile_at(max(k - 2, 0), 4),
                                                  tile_at(k, 2));
-        reduce_rows<CW, NB, CT>(acc);
+        reduce_rows<CW, NB, NT, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -1088,9 +1124,9 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_adj_kernel(SolveArgs
         __syncthreads();
         zero_acc();
         // next: U1_k^H, the first product of step k + 1, or L21^H of the last block
-        tile_product<CW, NB, kLower, kFull, CT>(g, bufA, bufB, acc, tb, tile_at(k, 2),
+        tile_product<CW, NB, NT, kLower, kFull, CT>(g, bufA, bufB, acc, tb, tile_at(k, 2),
                                                 last ? tile_at(nblk - 1, 1) : tile_at(k, 3));
-        reduce_rows<CW, NB, CT>(acc);
+        reduce_rows<CW, NB, NT, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -1130,9 +1166,9 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_adj_kernel(SolveArgs
             for (int c = 0; c < CW; ++c) v[q][c] = ynext[q][c];
         load_v(k - 1, ynext);
         zero_acc();
-        tile_product<CW, NB, kFull, kUpper, CT>(g, bufA, bufB, acc, cur, tile_at(k, 1),
+        tile_product<CW, NB, NT, kFull, kUpper, CT>(g, bufA, bufB, acc, cur, tile_at(k, 1),
                                                 tile_at(k, 0));           // L21_k^H b
-        reduce_rows<CW, NB, CT>(acc);
+        reduce_rows<CW, NB, NT, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -1143,9 +1179,9 @@ __global__ __launch_bounds__(kSolveThreads) void band_solve_adj_kernel(SolveArgs
         }
         __syncthreads();
         zero_acc();
-        tile_product<CW, NB, kUpper, kFull, CT>(g, bufA, bufB, acc, tb, tile_at(k, 0),
+        tile_product<CW, NB, NT, kUpper, kFull, CT>(g, bufA, bufB, acc, tb, tile_at(k, 0),
                                                 tile_at(max(k - 1, 0), 1));   // a' = Linv_k^H t
-        reduce_rows<CW, NB, CT>(acc);
+        reduce_rows<CW, NB, NT, CT>(acc);
         if (writer) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
@@ -1322,20 +1358,36 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
     return hipSuccess;
 }
 
-static size_t solve_lds(int nb, int cw, size_t elem) {
-    // win + win2 (2nb each) + ybuf (nb) + ring (3nb), all x cw
+// Threads per solve workgroup: 512, or 256 for eight complex128 right-hand sides at
+// tile 256, where a wave then has the whole register file for its 4 x 8 accumulators
+// and the longer load batches (and the window is permuted in place, see the kernel).
+template <int CW, int NB, typename CT>
+constexpr int solve_threads() {
+    return (NB == 256 && CW == 8 && sizeof(CT) == sizeof(zd)) ? 256 : kSolveThreads;
+}
+
+static size_t solve_lds(int nb, int cw, size_t elem, bool inplace) {
+    // in place: ring (its first 2nb rows hold the window) + ybuf; otherwise
+    // win + win2 (2nb each) + ybuf (nb) + ring (3nb); all x cw
+    if (inplace) return size_t(4 * nb * cw) * elem;
     return size_t(2 * nb * cw * 2 + nb * cw + 3 * nb * cw) * elem;
 }
 
 template <int CW, int NB, typename CT>
 static hipError_t launch_solve_nb(const SolveArgs &a, hipStream_t s, bool adjoint) {
     const int slices = (a.ncols + CW - 1) / CW;
-    if (adjoint)
-        hipLaunchKernelGGL((band_solve_adj_kernel<CW, NB, CT>), dim3(slices * a.p),
-                           dim3(kSolveThreads), solve_lds(NB, CW, sizeof(CT)), s, a);
-    else
-        hipLaunchKernelGGL((band_solve_kernel<CW, NB, CT>), dim3(slices * a.p), dim3(kSolveThreads),
-                           solve_lds(NB, CW, sizeof(CT)), s, a);
+    constexpr int NT = solve_threads<CW, NB, CT>();
+    if constexpr (NT == kSolveThreads) {
+        if (adjoint) {
+            hipLaunchKernelGGL((band_solve_adj_kernel<CW, NB, NT, CT>), dim3(slices * a.p), dim3(NT),
+                               solve_lds(NB, CW, sizeof(CT), false), s, a);
+            return hipGetLastError();
+        }
+    } else {
+        if (adjoint) return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((band_solve_kernel<CW, NB, NT, CT>), dim3(slices * a.p), dim3(NT),
+                       solve_lds(NB, CW, sizeof(CT), NT < kSolveThreads), s, a);
     return hipGetLastError();
 }
 
@@ -1425,20 +1477,23 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
         if (e != hipSuccess) return e;
         a.X = buf.rhs; a.ldx = a.npad; a.bdiag = nullptr;
     }
+    const bool adj = P.F.adjoint;
+    // eight right-hand sides per workgroup: complex128 solves at tile 256 only
+    const bool cw8 = !c64 && !adj && a.nb == 256;
     int cw = P.opts.trsm_cols;
     if (cw <= 0) {
         // the narrowest slices whose workgroups all run at once, one per compute unit
         // (a second workgroup on a unit only queues behind the first's tile stream)
         cw = 1;
-        while (cw < 4 && (int64_t(ncols + cw - 1) / cw) * a.p > P.num_cu) cw *= 2;
+        while (cw < (cw8 ? 8 : 4) && (int64_t(ncols + cw - 1) / cw) * a.p > P.num_cu) cw *= 2;
     }
-    if (cw > 2) cw = 4;
+    if (cw > 4) cw = cw8 ? 8 : 4;
+    else if (cw > 2) cw = 4;
     const size_t elem = c64 ? sizeof(zf) : sizeof(zd);
-    while (cw > 1 && solve_lds(a.nb, cw, elem) > size_t(P.max_lds)) cw /= 2;
+    while (cw > 1 && solve_lds(a.nb, cw, elem, cw == 8) > size_t(P.max_lds)) cw /= 2;
     hipError_t e;
     hipEvent_t ev0 = nullptr;
     if (buf.profile) P.prof.record_begin(s, ev0);
-    const bool adj = P.F.adjoint;
     if (adj && (c64 || colw)) return hipErrorInvalidValue;
     if (cluster_path(P)) {
         // complex128 solves over the fused tiles, a cluster of workgroups per pole and
@@ -1464,6 +1519,7 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
         switch (cw) {
             case 1: return launch_solve_cw<1, zd>(sa, s, adj);
             case 2: return launch_solve_cw<2, zd>(sa, s, adj);
+            case 8: return launch_solve_nb<8, 256, zd>(sa, s, adj);     // cw8: tile 256
             default: return launch_solve_cw<4, zd>(sa, s, adj);
         }
     };

@@ -263,6 +263,29 @@ def test_inner_apply_tile_256(rf, torch_cuda, precision):
         plan.close()
 
 
+def test_inner_apply_tile_256_eight_columns(rf, torch_cuda):
+    # eight right-hand sides per solve workgroup at tile 256 (256 threads, the forward
+    # window in three nb-row buffers in turn): against the oracle and against four
+    # columns per workgroup.  21 columns give a ragged last slice; N = 1089 gives five
+    # block steps (the buffers go round more than once) with a ragged last block.
+    from oracle import filters
+    A, B = W.convdiff_pencil(33, mass=(0.5, 1.5), seed=4)           # kl = 33
+    X = W.start_block(A.shape[0], 21, seed=6)
+    ref = filters.InnerOperator(A, B, 3000 + 0.05j, 400.0, 2)(X)
+    out = {}
+    for cols in (4, 8):
+        _say(f"inner_apply tile=256 trsm_cols={cols} (21 columns)")
+        plan = rf.Plan(A, B, 3000 + 0.05j, 400.0, p=2, q=4, w=24, tile=256, trsm_cols=cols)
+        plan.factor_shifts()
+        out[cols] = _to_host(plan.apply_inner(torch_cuda.from_numpy(X).cuda()))
+        plan.close()
+    e = _colerr(out[8], ref).max()
+    d = _colerr(out[8], out[4]).max()
+    _say(f"  eight columns per workgroup: {e:.1e} from the oracle, {d:.1e} from four")
+    assert e <= 1e-12, e
+    assert d <= 1e-14, d
+
+
 def test_factorization_graph_replays_match_eager(rf, torch_cuda):
     # on a non-null stream rf_factor_shifts records its launch sequence in a HIP graph
     # once and replays it; every replay, with eager work and synchronizations of the
