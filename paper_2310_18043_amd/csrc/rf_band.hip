@@ -1358,12 +1358,12 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
     return hipSuccess;
 }
 
-// Threads per solve workgroup: 512, or 256 for eight complex128 right-hand sides at
-// tile 256, where a wave then has the whole register file for its 4 x 8 accumulators
-// and the longer load batches (and the window is permuted in place, see the kernel).
+// Threads per solve workgroup: 512, or 256 for eight right-hand sides at tile 256,
+// where a wave then has the whole register file for its 4 x 8 accumulators (and the
+// forward window sits in three nb-row buffers, see the kernel).
 template <int CW, int NB, typename CT>
 constexpr int solve_threads() {
-    return (NB == 256 && CW == 8 && sizeof(CT) == sizeof(zd)) ? 256 : kSolveThreads;
+    return (NB == 256 && CW == 8) ? 256 : kSolveThreads;
 }
 
 static size_t solve_lds(int nb, int cw, size_t elem, bool inplace) {
@@ -1478,14 +1478,17 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
         a.X = buf.rhs; a.ldx = a.npad; a.bdiag = nullptr;
     }
     const bool adj = P.F.adjoint;
-    // eight right-hand sides per workgroup: complex128 solves at tile 256 only
-    const bool cw8 = !c64 && !adj && a.nb == 256;
+    // eight right-hand sides per workgroup: solves at tile 256 only (not the adjoint's);
+    // the automatic choice takes them in complex128 only (in complex64 four per workgroup
+    // were faster on the 256 x 256 workload)
+    const bool cw8 = !adj && a.nb == 256;
     int cw = P.opts.trsm_cols;
     if (cw <= 0) {
         // the narrowest slices whose workgroups all run at once, one per compute unit
         // (a second workgroup on a unit only queues behind the first's tile stream)
         cw = 1;
-        while (cw < (cw8 ? 8 : 4) && (int64_t(ncols + cw - 1) / cw) * a.p > P.num_cu) cw *= 2;
+        const int cwmax = (cw8 && !c64) ? 8 : 4;
+        while (cw < cwmax && (int64_t(ncols + cw - 1) / cw) * a.p > P.num_cu) cw *= 2;
     }
     if (cw > 4) cw = cw8 ? 8 : 4;
     else if (cw > 2) cw = 4;
@@ -1513,6 +1516,7 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
             switch (cw) {
                 case 1: return launch_solve_cw<1, zf>(sa, s);
                 case 2: return launch_solve_cw<2, zf>(sa, s);
+                case 8: return launch_solve_nb<8, 256, zf>(sa, s, false);   // cw8: tile 256
                 default: return launch_solve_cw<4, zf>(sa, s);
             }
         }

@@ -5,8 +5,7 @@ rf_factor_shifts + rf_solve_region on the device -- for every combination of
 
 * tile      the band tile nb (the smallest power of two >= the bandwidth, and twice it
             when that is still <= 256),
-* trsm_cols right-hand sides per band-solve workgroup (1, 2, 4; also 8 at tile 256 in
-            complex128),
+* trsm_cols right-hand sides per band-solve workgroup (1, 2, 4; also 8 at tile 256),
 * subblock  the Krylov sub-block width b (16, 32, dividing w),
 
 keeps the fastest combination whose run converged with the expected count, and
@@ -79,7 +78,7 @@ def tune(name: str, precision: int = 0, reps: int = 1, log=print):
     Y0 = torch.from_numpy(W.start_block(wl.n, wl.w, wl.seed)).cuda()
     rows = []
     for tile in tiles:
-        for cw in ((1, 2, 4, 8) if tile == 256 and precision == 0 else (1, 2, 4)):
+        for cw in ((1, 2, 4, 8) if tile == 256 else (1, 2, 4)):
             for b in (16, 32):
                 if wl.w % b:
                     continue

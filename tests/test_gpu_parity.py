@@ -263,27 +263,32 @@ def test_inner_apply_tile_256(rf, torch_cuda, precision):
         plan.close()
 
 
-def test_inner_apply_tile_256_eight_columns(rf, torch_cuda):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_inner_apply_tile_256_eight_columns(rf, torch_cuda, precision):
     # eight right-hand sides per solve workgroup at tile 256 (256 threads, the forward
     # window in three nb-row buffers in turn): against the oracle and against four
-    # columns per workgroup.  21 columns give a ragged last slice; N = 1089 gives five
-    # block steps (the buffers go round more than once) with a ragged last block.
+    # columns per workgroup (512 threads), which splits each row's inner products over 8
+    # lanes instead of 4, so the two agree to the rounding of the tile precision: 1e-14
+    # in complex128, the oracle's own bar in complex64.  21 columns give a ragged last
+    # slice; N = 1089 gives five block steps (the buffers go round more than once) with a
+    # ragged last block.
     from oracle import filters
     A, B = W.convdiff_pencil(33, mass=(0.5, 1.5), seed=4)           # kl = 33
     X = W.start_block(A.shape[0], 21, seed=6)
     ref = filters.InnerOperator(A, B, 3000 + 0.05j, 400.0, 2)(X)
     out = {}
     for cols in (4, 8):
-        _say(f"inner_apply tile=256 trsm_cols={cols} (21 columns)")
-        plan = rf.Plan(A, B, 3000 + 0.05j, 400.0, p=2, q=4, w=24, tile=256, trsm_cols=cols)
+        _say(f"inner_apply tile=256 trsm_cols={cols} precision={precision} (21 columns)")
+        plan = rf.Plan(A, B, 3000 + 0.05j, 400.0, p=2, q=4, w=24, tile=256, trsm_cols=cols,
+                       precision=precision)
         plan.factor_shifts()
         out[cols] = _to_host(plan.apply_inner(torch_cuda.from_numpy(X).cuda()))
         plan.close()
     e = _colerr(out[8], ref).max()
     d = _colerr(out[8], out[4]).max()
     _say(f"  eight columns per workgroup: {e:.1e} from the oracle, {d:.1e} from four")
-    assert e <= 1e-12, e
-    assert d <= 1e-14, d
+    assert e <= (1e-12 if precision == 0 else 1e-5), e
+    assert d <= (1e-14 if precision == 0 else 1e-5), d
 
 
 def test_factorization_graph_replays_match_eager(rf, torch_cuda):

@@ -12,9 +12,8 @@ def test_table_entries_are_well_formed():
     for key, e in table.items():
         assert key.startswith("n=") and "precision=" in key
         assert e["tile"] in (16, 32, 64, 128, 256)
-        # eight columns per workgroup exist at tile 256 in complex128 only
-        assert e["trsm_cols"] in ((1, 2, 4, 8) if e["tile"] == 256 and key.endswith("precision=0")
-                                  else (1, 2, 4))
+        # eight columns per workgroup exist at tile 256 only
+        assert e["trsm_cols"] in ((1, 2, 4, 8) if e["tile"] == 256 else (1, 2, 4))
         assert e["subblock"] in (1, 2, 4, 8, 16, 32)
         # the chosen entry is the fastest converged candidate it records
         ok = [c for c in e["candidates"] if c["converged"]]
