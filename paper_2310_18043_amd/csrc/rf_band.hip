@@ -790,6 +790,7 @@ __global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
     // nb-row buffers (see the forward sweep): a second 2nb-row window would not fit the
     // LDS.  Its ring of backward blocks reuses those buffers.
     constexpr bool inplace = NT < kSolveThreads;
+    constexpr bool late_y = CW >= 8;              // see the backward sweep
     extern __shared__ unsigned char smem_raw[];
     CT *win = reinterpret_cast<CT *>(smem_raw);   // [2NB][CW] (256 threads: [3][NB][CW])
     CT *win2 = inplace ? win : win + 2 * NB * CW; // [2NB][CW]: the permuted window
@@ -957,16 +958,16 @@ __global__ __launch_bounds__(NT) void band_solve_kernel(SolveArgs a) {
                 dst[q][c] = ok ? x : czero<CT>();
             }
     };
-    // y_k is read one step ahead, or (the 256-thread form, whose registers hold
-    // 8-column blocks) at the start of its own step, in flight during the first products
-    if constexpr (!inplace) load_y(nblk - 1, ynext);
+    // y_k is read one step ahead, or (eight columns, whose 4 x 8 blocks would take two
+    // register sets) at the start of its own step, in flight during the first products
+    if constexpr (!late_y) load_y(nblk - 1, ynext);
     __syncthreads();
     for (int k = nblk - 1; k >= 0; --k) {
         CT *xk = ring + (k % 3) * NB * CW;
         const CT *xk1 = ring + ((k + 1) % 3) * NB * CW;
         const CT *xk2 = ring + ((k + 2) % 3) * NB * CW;
         CT y[R][CW];
-        if constexpr (inplace) {
+        if constexpr (late_y) {
             load_y(k, y);
         } else {
 #pragma unroll
@@ -1358,12 +1359,13 @@ hipError_t launch_band_factor(const rf_plan &P, hipStream_t s) {
     return hipSuccess;
 }
 
-// Threads per solve workgroup: 512, or 256 for eight right-hand sides at tile 256,
-// where a wave then has the whole register file for its 4 x 8 accumulators (and the
-// forward window sits in three nb-row buffers, see the kernel).
+// Threads per solve workgroup: 512, or 256 for eight complex128 right-hand sides at tile
+// 256, where a wave then has the whole register file for its 4 x 8 accumulators (and the
+// forward window sits in three nb-row buffers, see the kernel); eight complex64 ones fit
+// the registers of 512 threads.
 template <int CW, int NB, typename CT>
 constexpr int solve_threads() {
-    return (NB == 256 && CW == 8) ? 256 : kSolveThreads;
+    return (NB == 256 && CW == 8 && sizeof(CT) == sizeof(zd)) ? 256 : kSolveThreads;
 }
 
 static size_t solve_lds(int nb, int cw, size_t elem, bool inplace) {
@@ -1478,17 +1480,14 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
         a.X = buf.rhs; a.ldx = a.npad; a.bdiag = nullptr;
     }
     const bool adj = P.F.adjoint;
-    // eight right-hand sides per workgroup: solves at tile 256 only (not the adjoint's);
-    // the automatic choice takes them in complex128 only (in complex64 four per workgroup
-    // were faster on the 256 x 256 workload)
+    // eight right-hand sides per workgroup: solves at tile 256 only (not the adjoint's)
     const bool cw8 = !adj && a.nb == 256;
     int cw = P.opts.trsm_cols;
     if (cw <= 0) {
         // the narrowest slices whose workgroups all run at once, one per compute unit
         // (a second workgroup on a unit only queues behind the first's tile stream)
         cw = 1;
-        const int cwmax = (cw8 && !c64) ? 8 : 4;
-        while (cw < cwmax && (int64_t(ncols + cw - 1) / cw) * a.p > P.num_cu) cw *= 2;
+        while (cw < (cw8 ? 8 : 4) && (int64_t(ncols + cw - 1) / cw) * a.p > P.num_cu) cw *= 2;
     }
     if (cw > 4) cw = cw8 ? 8 : 4;
     else if (cw > 2) cw = 4;

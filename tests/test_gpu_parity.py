@@ -265,13 +265,12 @@ def test_inner_apply_tile_256(rf, torch_cuda, precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_inner_apply_tile_256_eight_columns(rf, torch_cuda, precision):
-    # eight right-hand sides per solve workgroup at tile 256 (256 threads, the forward
-    # window in three nb-row buffers in turn): against the oracle and against four
-    # columns per workgroup (512 threads), which splits each row's inner products over 8
-    # lanes instead of 4, so the two agree to the rounding of the tile precision: 1e-14
-    # in complex128, the oracle's own bar in complex64.  21 columns give a ragged last
-    # slice; N = 1089 gives five block steps (the buffers go round more than once) with a
-    # ragged last block.
+    # eight right-hand sides per solve workgroup at tile 256 (complex128: 256 threads,
+    # the forward window in three nb-row buffers in turn; complex64: 512 threads), against
+    # the oracle and against four columns per workgroup.  In complex128 four columns split
+    # each row's inner products over 8 lanes instead of 4, so the two agree to rounding;
+    # in complex64 the split is the same.  21 columns give a ragged last slice; N = 1089
+    # gives five block steps (the buffers go round more than once) with a ragged last block.
     from oracle import filters
     A, B = W.convdiff_pencil(33, mass=(0.5, 1.5), seed=4)           # kl = 33
     X = W.start_block(A.shape[0], 21, seed=6)
@@ -288,7 +287,7 @@ def test_inner_apply_tile_256_eight_columns(rf, torch_cuda, precision):
     d = _colerr(out[8], out[4]).max()
     _say(f"  eight columns per workgroup: {e:.1e} from the oracle, {d:.1e} from four")
     assert e <= (1e-12 if precision == 0 else 1e-5), e
-    assert d <= (1e-14 if precision == 0 else 1e-5), d
+    assert d <= (1e-14 if precision == 0 else 1e-6), d
 
 
 def test_factorization_graph_replays_match_eager(rf, torch_cuda):
