@@ -323,8 +323,10 @@ def batched_window_256(slots, capacity=64, trsm_cols=8):
     plan per disk (its own band factorization, then Alg. composite), so no disk waits for
     the slowest of a wave.  A disk of block width w takes max(w, 64) / 32 of `capacity`
     units: eight disks of width 256 at a time (223 GB), up to `slots` narrow ones.  Eight
-    threads: with sixteen, the HIP runtime ran out of resources for the scratch memory of
-    the tile-256 solve kernel on that many streams (the process aborted).  The band solves
+    threads: with sixteen and four columns per solve workgroup, the HIP runtime ran out of
+    resources for the scratch memory of that tile-256 solve kernel on that many streams
+    (the process aborted); the eight-column kernel uses no scratch, and twelve threads ran
+    but were not faster (more caching-allocator retries, 239 GB).  The band solves
     take `trsm_cols` right-hand sides per workgroup, eight by default: the plans in flight
     share the compute units, so the fewest workgroups per column win, where a lone plan's
     automatic choice (one plan after another below) takes the narrowest slices that still

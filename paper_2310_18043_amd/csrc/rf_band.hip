@@ -1379,7 +1379,7 @@ template <int CW, int NB, typename CT>
 static hipError_t launch_solve_nb(const SolveArgs &a, hipStream_t s, bool adjoint) {
     const int slices = (a.ncols + CW - 1) / CW;
     constexpr int NT = solve_threads<CW, NB, CT>();
-    if constexpr (NT == kSolveThreads) {
+    if constexpr (NT == kSolveThreads && CW <= 4) {       // adjoint solves: up to four columns
         if (adjoint) {
             hipLaunchKernelGGL((band_solve_adj_kernel<CW, NB, NT, CT>), dim3(slices * a.p), dim3(NT),
                                solve_lds(NB, CW, sizeof(CT), false), s, a);
