@@ -1492,7 +1492,8 @@ hipError_t inner_apply_core(const rf_plan &P, const zd *X, int64_t ldx, int ncol
     if (cw > 4) cw = cw8 ? 8 : 4;
     else if (cw > 2) cw = 4;
     const size_t elem = c64 ? sizeof(zf) : sizeof(zd);
-    while (cw > 1 && solve_lds(a.nb, cw, elem, cw == 8) > size_t(P.max_lds)) cw /= 2;
+    // (the three-buffer window: eight complex128 columns, the 256-thread form)
+    while (cw > 1 && solve_lds(a.nb, cw, elem, cw == 8 && !c64) > size_t(P.max_lds)) cw /= 2;
     hipError_t e;
     hipEvent_t ev0 = nullptr;
     if (buf.profile) P.prof.record_begin(s, ev0);
