@@ -622,7 +622,7 @@ def main():
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
               "(the per-GPU shard is the whole problem); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
