@@ -23,11 +23,13 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("tile", [64, 128])
-def test_plans_on_threads_with_their_own_streams(torch_cuda, tile):
+@pytest.mark.parametrize("tile,cols", [(64, 0), (128, 0), (256, 8)])
+def test_plans_on_threads_with_their_own_streams(torch_cuda, tile, cols):
+    # tile 256 with eight right-hand sides per solve workgroup: the 256-thread form that
+    # the batched configuration's concurrent plans run
     from paper_2310_18043_amd import rfeig
     torch = torch_cuda
-    print(f"[gpu-case] plans on 8 threads, tile {tile}", flush=True)
+    print(f"[gpu-case] plans on 8 threads, tile {tile}, trsm_cols {cols}", flush=True)
     sys.stdout.flush()
     m = 30
     A, B = W.convdiff_pencil(m, mass=(0.5, 1.5), seed=2)
@@ -39,8 +41,8 @@ def test_plans_on_threads_with_their_own_streams(torch_cuda, tile):
     def one(t, stream):
         s = stream if stream is not None else torch.cuda.current_stream()
         with torch.cuda.stream(s):
-            P = rfeig.Plan(A, B, c + 3.0 * t, r, p=4, q=4, w=ncols, tile=tile, tuned=False,
-                           stream=s)
+            P = rfeig.Plan(A, B, c + 3.0 * t, r, p=4, q=4, w=ncols, tile=tile, trsm_cols=cols,
+                           tuned=False, stream=s)
             P.factor_shifts()
             Z = P.apply_inner(torch.from_numpy(Xs[t]).cuda())
             s.synchronize()
