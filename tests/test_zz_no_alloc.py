@@ -57,17 +57,21 @@ def _tridiag_mass_pencil():
     return A, B, 700 + 0.05j, 200.0
 
 
-@pytest.mark.parametrize("case", ["diagonal_mass", "tridiagonal_mass"])
+@pytest.mark.parametrize("case", ["diagonal_mass", "tridiagonal_mass", "tile256_eight_columns"])
 def test_noalloc_matches_apply_inner_twice(rf, torch_cuda, case):
     from oracle import filters
+    p, extra = 4, {}
     if case == "diagonal_mass":
         A, B = W.convdiff_pencil(20, mass=(0.5, 1.5), seed=1)
         c, r = 900 + 0.05j, 250.0
-    else:
+    elif case == "tridiagonal_mass":
         A, B, c, r = _tridiag_mass_pencil()
-    plan = rf.Plan(A, B, c, r, p=4, q=8, w=16)
+    else:                                        # the 256-thread solve form
+        A, B = W.convdiff_pencil(33, mass=(0.5, 1.5), seed=4)
+        c, r, p, extra = 3000 + 0.05j, 400.0, 2, dict(tile=256, trsm_cols=8)
+    plan = rf.Plan(A, B, c, r, p=p, q=8, w=16, **extra)
     plan.factor_shifts()
-    G = filters.InnerOperator(A, B, c, r, 4)
+    G = filters.InnerOperator(A, B, c, r, p)
     for k, seed in ((16, 2), (5, 3)):            # the second call is smaller
         _say(f"noalloc {case} ncols={k}")
         X = W.start_block(A.shape[0], k, seed=seed)
